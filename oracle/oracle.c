@@ -1,0 +1,620 @@
+/*
+ * WCSPH CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, scalar FP64 implementation of the weakly-compressible SPH
+ * step of Amaro Junior, Cheng & Buruchenko (2023), Section 2.2: the Wendland
+ * kernel (eq. sphw), the momentum equation with Monaghan artificial viscosity
+ * (eqs. sphu, pi, cpmu), the delta-SPH continuity equation (eq. sphrho), the
+ * Tait equation of state (eq. tait), the Verlet scheme with an Euler reset
+ * every N_s steps (eqs. sphu1-sphrho1, sphu2-sphrho2), the adaptive time step
+ * (eq. sphdt) and dynamic boundary particles.  Probe pressures follow the
+ * Shepard filter of eq. sphpa (Section 3.1).
+ *
+ * Only the test-suite, the package's smoke check and the benchmark's CPU
+ * baseline may load this library.  It shares no code with the HIP library.
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp (no FMA
+ * contraction, IEEE round-to-nearest).  OpenMP is used over target particles
+ * only; every particle writes only its own outputs, so results do not depend
+ * on the thread count.
+ *
+ * Readings of the paper taken here (where it is silent or garbled):
+ *  - kernel constant: 21/(16 pi h^3) in 3D (the printed constant is garbled;
+ *    this is the value for which the kernel integrates to one);
+ *  - neighbour iff |r_ij|^2 < 4h^2 (strict) and j != i; the kernel and its
+ *    gradient vanish at q = 2, so this equals the inclusive reading;
+ *  - first continuity term m_j (u_i - u_j) . grad_i W_ij (the sign under
+ *    which compression raises the density, as the dynamic-boundary text
+ *    requires); the delta term as printed with r_ij = r_j - r_i; its factor
+ *    r_ij . grad W / |r_ij|^2 is the radial factor F of the gradient, which
+ *    is also its limit at r = 0;
+ *  - sound speed in the viscosity average: the Tait sound speed
+ *    c_i = c0 (rho_i/rho0)^((gamma-1)/2), or c0 for every particle when
+ *    c_const is set;
+ *  - fluid i sums over all neighbours; the delta term only over fluid j
+ *    (all j when delta_all is set); boundary i sums the first continuity
+ *    term over fluid j only and has no acceleration;
+ *  - step 0 is an Euler step, and every step n with n mod N_s == 0;
+ *  - time step: max_j |mu_ij| in the viscous bound; |f_i| includes gravity;
+ *    boundary accelerations do not enter.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+typedef struct {
+    double h, rho0, c0, gamma, alpha, delta, mass, eta2_coef, cfl;
+    double gx, gy, gz;
+    double ox, oy, oz, cs;
+    int32_t nx, ny, nz;
+    int32_t c_const;   /* 1: c_i = c0 for every particle */
+    int32_t delta_all; /* 1: delta term over boundary j too */
+    int32_t verlet_ns; /* Euler reset period N_s */
+} orc_par;
+
+/* ---------------------------------------------------------------- kernel */
+
+/* Wendland C2 kernel in 3D, eq. sphw: W = w_D (1 - q/2)^4 (2q + 1), q <= 2,
+ * with w_D = 21 / (16 pi h^3). */
+double orc_kernel_w(double q, double h)
+{
+    if (q >= 2.0 || q < 0.0)
+        return 0.0;
+    double wd = 21.0 / (16.0 * ORC_PI * h * h * h);
+    double t = 1.0 - 0.5 * q;
+    return wd * t * t * t * t * (2.0 * q + 1.0);
+}
+
+/* Radial factor of the kernel gradient: grad_i W_ij = F(q) (r_j - r_i) with
+ * F = 5 w_D (1 - q/2)^3 / h^2 (derivative of eq. sphw; dW/dq = -5 q w_D
+ * (1-q/2)^3). */
+double orc_kernel_f(double q, double h)
+{
+    if (q >= 2.0 || q < 0.0)
+        return 0.0;
+    double wd = 21.0 / (16.0 * ORC_PI * h * h * h);
+    double t = 1.0 - 0.5 * q;
+    return 5.0 * wd * t * t * t / (h * h);
+}
+
+/* ------------------------------------------------------ equation of state */
+
+/* Tait equation, eq. tait: P = (rho0 c0^2 / gamma) [(rho/rho0)^gamma - 1]. */
+double orc_pressure(const orc_par *p, double rho)
+{
+    double B = p->rho0 * p->c0 * p->c0 / p->gamma;
+    return B * (pow(rho / p->rho0, p->gamma) - 1.0);
+}
+
+/* Sound speed entering the viscosity average c_ij = (c_i + c_j)/2: the Tait
+ * sound speed sqrt(dP/drho) = c0 (rho/rho0)^((gamma-1)/2), or c0. */
+double orc_sound(const orc_par *p, double rho)
+{
+    if (p->c_const)
+        return p->c0;
+    return p->c0 * pow(rho / p->rho0, 0.5 * (p->gamma - 1.0));
+}
+
+/* ------------------------------------------------------------ cell list */
+
+static int64_t orc_ncells(const orc_par *p)
+{
+    return (int64_t)p->nx * p->ny * p->nz;
+}
+
+static int32_t orc_axis_cell(double v, double o, double cs, int32_t n)
+{
+    double f = floor((v - o) / cs);
+    if (!(f >= 0.0)) /* also NaN */
+        return 0;
+    if (f > (double)(n - 1))
+        return n - 1;
+    return (int32_t)f;
+}
+
+/* Cell of every particle (clamped to the grid), and a stable counting sort:
+ * order[] lists particles cell by cell, in increasing index within a cell;
+ * start[c] .. start[c+1] is cell c's slice.  start has ncells + 1 entries. */
+int orc_cells(const orc_par *p, int64_t n, const double *x, const double *y,
+              const double *z, int32_t *cx, int32_t *cy, int32_t *cz,
+              int64_t *start, int64_t *order)
+{
+    int64_t nc = orc_ncells(p);
+    for (int64_t c = 0; c <= nc; ++c)
+        start[c] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        cx[i] = orc_axis_cell(x[i], p->ox, p->cs, p->nx);
+        cy[i] = orc_axis_cell(y[i], p->oy, p->cs, p->ny);
+        cz[i] = orc_axis_cell(z[i], p->oz, p->cs, p->nz);
+        int64_t c = cx[i] + (int64_t)p->nx * (cy[i] + (int64_t)p->ny * cz[i]);
+        start[c + 1] += 1;
+    }
+    for (int64_t c = 0; c < nc; ++c)
+        start[c + 1] += start[c];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc > 0 ? nc : 1));
+    if (!fill)
+        return -1;
+    for (int64_t c = 0; c < nc; ++c)
+        fill[c] = start[c];
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = cx[i] + (int64_t)p->nx * (cy[i] + (int64_t)p->ny * cz[i]);
+        order[fill[c]++] = i;
+    }
+    free(fill);
+    return 0;
+}
+
+typedef struct {
+    int32_t *cx, *cy, *cz;
+    int64_t *start, *order;
+} orc_grid;
+
+static int orc_grid_build(const orc_par *p, int64_t n, const double *x,
+                          const double *y, const double *z, orc_grid *g)
+{
+    int64_t nc = orc_ncells(p);
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    g->cx = (int32_t *)malloc(sizeof(int32_t) * nn);
+    g->cy = (int32_t *)malloc(sizeof(int32_t) * nn);
+    g->cz = (int32_t *)malloc(sizeof(int32_t) * nn);
+    g->start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc + 1));
+    g->order = (int64_t *)malloc(sizeof(int64_t) * nn);
+    if (!g->cx || !g->cy || !g->cz || !g->start || !g->order)
+        return -1;
+    return orc_cells(p, n, x, y, z, g->cx, g->cy, g->cz, g->start, g->order);
+}
+
+static void orc_grid_free(orc_grid *g)
+{
+    free(g->cx);
+    free(g->cy);
+    free(g->cz);
+    free(g->start);
+    free(g->order);
+}
+
+/* The squared distance used as the neighbour predicate: d = r_j - r_i,
+ * r^2 = (dx dx + dy dy) + dz dz, evaluated in this order without contraction. */
+static double orc_r2(double dx, double dy, double dz)
+{
+    double a = dx * dx;
+    double b = dy * dy;
+    double c = dz * dz;
+    return (a + b) + c;
+}
+
+/* Number of neighbours of every particle (|r_ij|^2 < 4h^2, j != i) and,
+ * optionally, the ordered pair list (i, j) sorted by i then by the search
+ * order.  Returns the total number of ordered pairs, or -1 on allocation
+ * failure; pairs are written only while the total fits max_pairs. */
+int64_t orc_neighbours(const orc_par *p, int64_t n, const double *x,
+                       const double *y, const double *z, int64_t *count,
+                       int64_t *pairs, int64_t max_pairs)
+{
+    orc_grid g;
+    if (orc_grid_build(p, n, x, y, z, &g) != 0) {
+        orc_grid_free(&g);
+        return -1;
+    }
+    const double r2max = 4.0 * p->h * p->h;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t k = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int32_t ax = g.cx[i] + dx, ay = g.cy[i] + dy, az = g.cz[i] + dz;
+                    if (ax < 0 || ay < 0 || az < 0 || ax >= p->nx || ay >= p->ny || az >= p->nz)
+                        continue;
+                    int64_t c = ax + (int64_t)p->nx * (ay + (int64_t)p->ny * az);
+                    for (int64_t s = g.start[c]; s < g.start[c + 1]; ++s) {
+                        int64_t j = g.order[s];
+                        if (j == i)
+                            continue;
+                        if (orc_r2(x[j] - x[i], y[j] - y[i], z[j] - z[i]) < r2max)
+                            ++k;
+                    }
+                }
+        count[i] = k;
+    }
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; ++i)
+        total += count[i];
+    if (pairs && total <= max_pairs) {
+        int64_t w = 0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int32_t ax = g.cx[i] + dx, ay = g.cy[i] + dy, az = g.cz[i] + dz;
+                        if (ax < 0 || ay < 0 || az < 0 || ax >= p->nx || ay >= p->ny || az >= p->nz)
+                            continue;
+                        int64_t c = ax + (int64_t)p->nx * (ay + (int64_t)p->ny * az);
+                        for (int64_t s = g.start[c]; s < g.start[c + 1]; ++s) {
+                            int64_t j = g.order[s];
+                            if (j == i)
+                                continue;
+                            if (orc_r2(x[j] - x[i], y[j] - y[i], z[j] - z[i]) < r2max) {
+                                pairs[2 * w] = i;
+                                pairs[2 * w + 1] = j;
+                                ++w;
+                            }
+                        }
+                    }
+    }
+    orc_grid_free(&g);
+    return total;
+}
+
+/* ------------------------------------------------------------ interaction */
+
+/* Rates of change at one state (Section 2.2):
+ *   fluid i:    a_i = - sum_j m [(P_i + P_j)/(rho_i rho_j) + Pi_ij] grad_i W_ij + g
+ *               drho_i = sum_j m (u_i - u_j) . grad_i W_ij
+ *                      + 2 delta h c0 sum_{j fluid} (rho_j - rho_i) F_ij m / rho_j
+ *   boundary i: drho_i = sum_{j fluid} m (u_i - u_j) . grad_i W_ij, a_i = 0
+ * with Pi_ij = -alpha cbar_ij mu_ij / rhobar_ij when u_ij . r_ij < 0, else 0,
+ * mu_ij = h u_ij . r_ij / (|r_ij|^2 + eta^2), eta^2 = eta2_coef h^2,
+ * r_ij = r_j - r_i, u_ij = u_j - u_i.  mumax_i = max_j |mu_ij| over the same
+ * pairs (the time-step bound).  Optional pair counters (nullable): nff =
+ * fluid-fluid, nfb = fluid i with boundary j, nbf = boundary i with fluid j. */
+int orc_rates(const orc_par *p, int64_t n, const double *x, const double *y,
+              const double *z, const double *ux, const double *uy,
+              const double *uz, const double *rho, const uint8_t *is_bnd,
+              double *ax, double *ay, double *az, double *drho, double *mumax,
+              int64_t *npairs3)
+{
+    orc_grid g;
+    if (orc_grid_build(p, n, x, y, z, &g) != 0) {
+        orc_grid_free(&g);
+        return -1;
+    }
+    double *P = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *C = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!P || !C) {
+        free(P);
+        free(C);
+        orc_grid_free(&g);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        P[i] = orc_pressure(p, rho[i]);
+        C[i] = orc_sound(p, rho[i]);
+    }
+    const double h = p->h, m = p->mass;
+    const double r2max = 4.0 * h * h;
+    const double eta2 = p->eta2_coef * h * h;
+    const double kdelta = 2.0 * p->delta * h * p->c0;
+    int64_t tff = 0, tfb = 0, tbf = 0;
+
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : tff, tfb, tbf)
+    for (int64_t i = 0; i < n; ++i) {
+        const int bi = is_bnd[i] != 0;
+        double sax = 0.0, say = 0.0, saz = 0.0, sdr = 0.0, mum = 0.0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int32_t cxn = g.cx[i] + dx, cyn = g.cy[i] + dy, czn = g.cz[i] + dz;
+                    if (cxn < 0 || cyn < 0 || czn < 0 || cxn >= p->nx || cyn >= p->ny || czn >= p->nz)
+                        continue;
+                    int64_t c = cxn + (int64_t)p->nx * (cyn + (int64_t)p->ny * czn);
+                    for (int64_t s = g.start[c]; s < g.start[c + 1]; ++s) {
+                        int64_t j = g.order[s];
+                        if (j == i)
+                            continue;
+                        const int bj = is_bnd[j] != 0;
+                        if (bi && bj)
+                            continue;
+                        double rx = x[j] - x[i], ry = y[j] - y[i], rz = z[j] - z[i];
+                        double r2 = orc_r2(rx, ry, rz);
+                        if (!(r2 < r2max))
+                            continue;
+                        double q = sqrt(r2) / h;
+                        double F = orc_kernel_f(q, h);
+                        double gx = F * rx, gy = F * ry, gz = F * rz; /* grad_i W_ij */
+                        double vx = ux[j] - ux[i], vy = uy[j] - uy[i], vz = uz[j] - uz[i];
+                        double vr = (vx * rx + vy * ry) + vz * rz; /* u_ij . r_ij */
+                        double mu = h * vr / (r2 + eta2);
+                        double amu = fabs(mu);
+                        if (amu > mum)
+                            mum = amu;
+                        /* first continuity term: m (u_i - u_j) . grad W */
+                        sdr += m * (-((vx * gx + vy * gy) + vz * gz));
+                        if (bi) {
+                            ++tbf;
+                            continue;
+                        }
+                        if (bj)
+                            ++tfb;
+                        else
+                            ++tff;
+                        if (!bj || p->delta_all)
+                            sdr += kdelta * (rho[j] - rho[i]) * F * m / rho[j];
+                        double visc = 0.0;
+                        if (vr < 0.0) {
+                            double cbar = 0.5 * (C[i] + C[j]);
+                            double rbar = 0.5 * (rho[i] + rho[j]);
+                            visc = -p->alpha * cbar * mu / rbar;
+                        }
+                        double coef = m * ((P[i] + P[j]) / (rho[i] * rho[j]) + visc);
+                        sax -= coef * gx;
+                        say -= coef * gy;
+                        saz -= coef * gz;
+                    }
+                }
+        if (bi) {
+            ax[i] = 0.0;
+            ay[i] = 0.0;
+            az[i] = 0.0;
+        } else {
+            ax[i] = sax + p->gx;
+            ay[i] = say + p->gy;
+            az[i] = saz + p->gz;
+        }
+        drho[i] = sdr;
+        mumax[i] = mum;
+    }
+    if (npairs3) {
+        npairs3[0] = tff;
+        npairs3[1] = tfb;
+        npairs3[2] = tbf;
+    }
+    free(P);
+    free(C);
+    orc_grid_free(&g);
+    return 0;
+}
+
+/* Adaptive time step, eq. sphdt:
+ * dt = Cr min{ min_{i fluid} sqrt(h/|a_i|), min_i h/(c0 + mumax_i) }. */
+double orc_dt_cfl(const orc_par *p, int64_t n, const double *ax,
+                  const double *ay, const double *az, const double *mumax,
+                  const uint8_t *is_bnd)
+{
+    double best = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_bnd[i]) {
+            double a = sqrt((ax[i] * ax[i] + ay[i] * ay[i]) + az[i] * az[i]);
+            if (a > 0.0) {
+                double t = sqrt(p->h / a);
+                if (t < best)
+                    best = t;
+            }
+        }
+        double t2 = p->h / (p->c0 + mumax[i]);
+        if (t2 < best)
+            best = t2;
+    }
+    return p->cfl * best;
+}
+
+/* Time update (eqs. sphu1-sphrho1; Euler reset eqs. sphu2-sphrho2).  Fluid
+ * particles update r, u, rho; boundary particles only rho.  Afterwards the
+ * previous level holds the old current level. */
+void orc_update(const orc_par *p, int64_t n, int euler, double dt, double *x,
+                double *y, double *z, double *ux, double *uy, double *uz,
+                double *uxm, double *uym, double *uzm, double *rho,
+                double *rhom, const double *ax, const double *ay,
+                const double *az, const double *drho, const uint8_t *is_bnd)
+{
+    (void)p;
+    const double hdt2 = 0.5 * dt * dt;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double rn;
+        if (euler)
+            rn = rho[i] + dt * drho[i];
+        else
+            rn = rhom[i] + 2.0 * dt * drho[i];
+        rhom[i] = rho[i];
+        rho[i] = rn;
+        if (is_bnd[i])
+            continue;
+        double vx, vy, vz;
+        if (euler) {
+            vx = ux[i] + dt * ax[i];
+            vy = uy[i] + dt * ay[i];
+            vz = uz[i] + dt * az[i];
+        } else {
+            vx = uxm[i] + 2.0 * dt * ax[i];
+            vy = uym[i] + 2.0 * dt * ay[i];
+            vz = uzm[i] + 2.0 * dt * az[i];
+        }
+        x[i] = x[i] + dt * ux[i] + hdt2 * ax[i];
+        y[i] = y[i] + dt * uy[i] + hdt2 * ay[i];
+        z[i] = z[i] + dt * uz[i] + hdt2 * az[i];
+        uxm[i] = ux[i];
+        uym[i] = uy[i];
+        uzm[i] = uz[i];
+        ux[i] = vx;
+        uy[i] = vy;
+        uz[i] = vz;
+    }
+}
+
+/* Run nsteps steps from step index step0.  dt_mode: 0 = fixed dt taken from
+ * dt_in[k] (one value per step), 1 = CFL from the current rates, 2 = CFL
+ * lagged (step k uses the bound computed at step k-1; the first step uses
+ * its own).  The dt used at each step is written to dt_out (nullable).
+ * If rates_out is non-null, the rates of the last step are kept there as
+ * 5 arrays of n: ax, ay, az, drho, mumax. */
+int orc_run(const orc_par *p, int64_t n, double *x, double *y, double *z,
+            double *ux, double *uy, double *uz, double *uxm, double *uym,
+            double *uzm, double *rho, double *rhom, const uint8_t *is_bnd,
+            int64_t step0, int64_t nsteps, int dt_mode, const double *dt_in,
+            double *dt_out, double *rates_out)
+{
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double *buf = (double *)malloc(sizeof(double) * nn * 5);
+    if (!buf)
+        return -1;
+    double *ax = buf, *ay = buf + nn, *az = buf + 2 * nn, *dr = buf + 3 * nn,
+           *mm = buf + 4 * nn;
+    double lag = 0.0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (orc_rates(p, n, x, y, z, ux, uy, uz, rho, is_bnd, ax, ay, az, dr, mm, 0) != 0) {
+            free(buf);
+            return -1;
+        }
+        double dt;
+        if (dt_mode == 0) {
+            dt = dt_in[k];
+        } else {
+            double now = orc_dt_cfl(p, n, ax, ay, az, mm, is_bnd);
+            dt = (dt_mode == 2 && k > 0) ? lag : now;
+            lag = now;
+        }
+        if (dt_out)
+            dt_out[k] = dt;
+        int64_t step = step0 + k;
+        int euler = p->verlet_ns <= 0 ? 0 : (step % p->verlet_ns) == 0;
+        orc_update(p, n, euler, dt, x, y, z, ux, uy, uz, uxm, uym, uzm, rho, rhom,
+                   ax, ay, az, dr, is_bnd);
+    }
+    if (rates_out)
+        memcpy(rates_out, buf, sizeof(double) * nn * 5);
+    free(buf);
+    return 0;
+}
+
+/* ------------------------------------------------------------ diagnostics */
+
+/* Internal energy per unit mass with de/drho = P/rho^2 and e(rho0) = 0:
+ * e = (B/rho0) [ (rho/rho0)^(gamma-1)/(gamma-1) + rho0/rho - gamma/(gamma-1) ]. */
+double orc_internal_energy(const orc_par *p, double rho)
+{
+    double B = p->rho0 * p->c0 * p->c0 / p->gamma;
+    double gm1 = p->gamma - 1.0;
+    return (B / p->rho0) * (pow(rho / p->rho0, gm1) / gm1 + p->rho0 / rho - p->gamma / gm1);
+}
+
+/* out[0] mass, out[1..3] fluid momentum, out[4] kinetic, out[5] potential
+ * (-m g.r), out[6] internal, out[7] max |u| over fluid, out[8] surge front
+ * (max x over fluid particles with at least one fluid neighbour, -inf if
+ * none), out[9] number of non-finite values in (r, u, rho), out[10] number of
+ * particles outside the grid (binned by clamping). */
+int orc_diagnostics(const orc_par *p, int64_t n, const double *x,
+                    const double *y, const double *z, const double *ux,
+                    const double *uy, const double *uz, const double *rho,
+                    const uint8_t *is_bnd, double *out)
+{
+    double M = 0, px = 0, py = 0, pz = 0, ek = 0, ep = 0, ei = 0, umax = 0;
+    double nonfinite = 0, outside = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        M += p->mass;
+        ei += p->mass * orc_internal_energy(p, rho[i]);
+        double vals[7] = {x[i], y[i], z[i], ux[i], uy[i], uz[i], rho[i]};
+        for (int k = 0; k < 7; ++k)
+            if (!isfinite(vals[k]))
+                nonfinite += 1;
+        double fx = floor((x[i] - p->ox) / p->cs), fy = floor((y[i] - p->oy) / p->cs),
+               fz = floor((z[i] - p->oz) / p->cs);
+        if (!(fx >= 0 && fx < p->nx && fy >= 0 && fy < p->ny && fz >= 0 && fz < p->nz))
+            outside += 1;
+        if (is_bnd[i])
+            continue;
+        px += p->mass * ux[i];
+        py += p->mass * uy[i];
+        pz += p->mass * uz[i];
+        double u2 = (ux[i] * ux[i] + uy[i] * uy[i]) + uz[i] * uz[i];
+        ek += 0.5 * p->mass * u2;
+        ep -= p->mass * ((p->gx * x[i] + p->gy * y[i]) + p->gz * z[i]);
+        double um = sqrt(u2);
+        if (um > umax)
+            umax = um;
+    }
+    /* surge front */
+    orc_grid g;
+    if (orc_grid_build(p, n, x, y, z, &g) != 0) {
+        orc_grid_free(&g);
+        return -1;
+    }
+    const double r2max = 4.0 * p->h * p->h;
+    double front = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        if (is_bnd[i] || !(x[i] > front))
+            continue;
+        int found = 0;
+        for (int dz = -1; dz <= 1 && !found; ++dz)
+            for (int dy = -1; dy <= 1 && !found; ++dy)
+                for (int dx = -1; dx <= 1 && !found; ++dx) {
+                    int32_t cxn = g.cx[i] + dx, cyn = g.cy[i] + dy, czn = g.cz[i] + dz;
+                    if (cxn < 0 || cyn < 0 || czn < 0 || cxn >= p->nx || cyn >= p->ny || czn >= p->nz)
+                        continue;
+                    int64_t c = cxn + (int64_t)p->nx * (cyn + (int64_t)p->ny * czn);
+                    for (int64_t s = g.start[c]; s < g.start[c + 1]; ++s) {
+                        int64_t j = g.order[s];
+                        if (j == i || is_bnd[j])
+                            continue;
+                        if (orc_r2(x[j] - x[i], y[j] - y[i], z[j] - z[i]) < r2max) {
+                            found = 1;
+                            break;
+                        }
+                    }
+                }
+        if (found)
+            front = x[i];
+    }
+    orc_grid_free(&g);
+    out[0] = M;
+    out[1] = px;
+    out[2] = py;
+    out[3] = pz;
+    out[4] = ek;
+    out[5] = ep;
+    out[6] = ei;
+    out[7] = umax;
+    out[8] = front;
+    out[9] = nonfinite;
+    out[10] = outside;
+    return 0;
+}
+
+/* Shepard-filtered probe pressure (eq. sphpa):
+ * P_a = sum_b P_b W_ab / sum_b W_ab over fluid b with |r_b - a|^2 < 4h^2;
+ * 0 for a probe with no fluid in range.  Brute force over all particles. */
+void orc_probes(const orc_par *p, int64_t n, const double *x, const double *y,
+                const double *z, const double *rho, const uint8_t *is_bnd,
+                int32_t np, const double *pts, double *out)
+{
+    const double r2max = 4.0 * p->h * p->h;
+    for (int32_t a = 0; a < np; ++a) {
+        double num = 0.0, den = 0.0;
+        for (int64_t b = 0; b < n; ++b) {
+            if (is_bnd[b])
+                continue;
+            double r2 = orc_r2(x[b] - pts[3 * a], y[b] - pts[3 * a + 1], z[b] - pts[3 * a + 2]);
+            if (!(r2 < r2max))
+                continue;
+            double w = orc_kernel_w(sqrt(r2) / p->h, p->h);
+            num += orc_pressure(p, rho[b]) * w;
+            den += w;
+        }
+        out[a] = den > 0.0 ? num / den : 0.0;
+    }
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0)
+        omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
