@@ -1,0 +1,187 @@
+"""Throughput of the WCSPH step on one MI355X.
+
+One step = cell hash + stable radix sort + reorder (cell list), the pair
+interaction (continuity, momentum with Tait pressure and Monaghan viscosity),
+the device-side adaptive time step and the Verlet update, on the synthetic
+dam break at dp = 0.01 m (146,752 particles: 72,000 fluid + 74,752 dynamic
+boundary), mixed precision (FP32 pair arithmetic on cell + offset positions,
+FP64 integration).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: particle-steps/s of the mixed step, the FP64 step on the
+same workload for the ratio, the interaction kernel's roofline (achieved
+algorithmic FP32 FLOP/s over HIP-event kernel time) and the FP64 CPU oracle
+timed on this host.
+"""
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic FLOPs per interacting ordered pair (FMA = 2, sqrt/rcp = 1 each):
+# fluid i with fluid j, fluid i with boundary j (no delta term), boundary i
+# with fluid j (continuity only)
+FLOP_FF, FLOP_FB, FLOP_BF = 50, 44, 24
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32, dual-issue (packed) figure
+PEAK_FP32_SCALAR_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+HBM_TBS = 8.0
+
+
+def hip_runtime():
+    import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+    return C.CDLL("libamdhip64.so.7")
+
+
+class Events:
+    """Arrays of hipEvent_t for per-launch kernel timing."""
+
+    def __init__(self, hip, n):
+        self.hip = hip
+        self.n = n
+        self.begin = (C.c_void_p * n)()
+        self.end = (C.c_void_p * n)()
+        for arr in (self.begin, self.end):
+            for k in range(n):
+                h = C.c_void_p()
+                assert hip.hipEventCreate(C.byref(h)) == 0
+                arr[k] = h
+        hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+
+    def mean_ms(self):
+        tot = 0.0
+        ms = C.c_float()
+        for k in range(self.n):
+            assert self.hip.hipEventElapsedTime(C.byref(ms), self.begin[k], self.end[k]) == 0
+            tot += ms.value
+        return tot / self.n
+
+    def close(self):
+        for arr in (self.begin, self.end):
+            for k in range(self.n):
+                self.hip.hipEventDestroy(C.c_void_p(arr[k]))
+
+
+def time_gpu(scene_obj, precision, steps, warmup, hip):
+    import torch
+    from paper_2306_01959_amd import lib
+    sim = lib.Simulation(scene_obj, precision)
+    sim.run(warmup, -1.0, 0)
+    d0, _ = sim.diagnostics()
+    ev = Events(hip, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run_profiled(steps, -1.0, warmup, ev.begin, ev.end)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d1, _ = sim.diagnostics()
+    kern_ms = ev.mean_ms()
+    ev.close()
+    pairs = [(d1[k] - d0[k]) / steps for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
+    flop = FLOP_FF * pairs[0] + FLOP_FB * pairs[1] + FLOP_BF * pairs[2]
+    assert d1["n_nonfinite"] == 0, "non-finite state"
+    return dict(wall_s=t1 - t0, ms_per_step=(t1 - t0) / steps * 1e3, interact_ms=kern_ms,
+                pairs_per_step=pairs, flop_per_launch=flop, sim_time=d1["time"] - d0["time"],
+                umax=d1["umax"], x_front=d1["x_front"])
+
+
+def cpu_baseline(scene_obj, seconds=10.0):
+    """The FP64 oracle on this host's cores: 2 warm-up steps, then steps of
+    the same workload until `seconds` elapse (at least 3)."""
+    from oracle import orc
+    orc.build(force=False)
+    p = orc.par(scene_obj.params)
+    st = orc.State(scene_obj)
+    orc.run(p, st, 2, dt_mode=1)
+    k = 0
+    t0 = time.perf_counter()
+    while True:
+        orc.run(p, st, 1, dt_mode=1)
+        k += 1
+        el = time.perf_counter() - t0
+        if (el >= seconds and k >= 3) or k >= 2000:
+            break
+    return dict(value=scene_obj.n * k / el, unit="particle-steps/s", cores=orc.max_threads(),
+                kind="oracle",
+                sample=f"{k} steps of the same dam break (dp=0.01 m, {scene_obj.n} particles) "
+                       f"after 2 warm-up steps, FP64 C oracle, OpenMP over particles, "
+                       f"{el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2306_01959_amd import scene
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    hip = hip_runtime()
+
+    sc = scene.config_scene(2)
+    mixed = time_gpu(sc, "mixed", args.steps, args.warmup, hip)
+    fp64 = None if args.no_fp64 else time_gpu(sc, "fp64", args.steps, args.warmup, hip)
+    value = sc.n * args.steps / mixed["wall_s"]
+    achieved = mixed["flop_per_launch"] / (mixed["interact_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": "particle-steps/s of WCSPH step, mixed-FP32 vs FP64 on 1 GPU, + ensemble batch",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "3D dam break, tank 1.6x0.6x0.6 m, water 0.4x0.6x0.3 m, dp=0.01 m, "
+                        "h=1.2*sqrt(3)*dp, Wendland C2, alpha=0.01, delta=0.1, CFL 0.2 "
+                        "(device-side adaptive dt), hydrostatic start, mixed FP32 "
+                        "interaction + FP64 integration",
+            "particles": sc.n, "fluid": sc.n_fluid, "boundary": sc.n_boundary,
+            "precision": "mixed", "parallelism": "single GPU",
+        },
+        "roofline": {
+            "kernel": "k_interact_mixed",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "kernel_ms": mixed["interact_ms"],
+            "flop_per_launch": mixed["flop_per_launch"],
+            "pairs_per_launch": {"ff": mixed["pairs_per_step"][0],
+                                 "fb": mixed["pairs_per_step"][1],
+                                 "bf": mixed["pairs_per_step"][2]},
+            "frac_of_scalar_issue_peak": achieved / PEAK_FP32_SCALAR_TFLOPS,
+        },
+    }
+    if fp64 is not None:
+        v64 = sc.n * args.steps / fp64["wall_s"]
+        out["fp64"] = {"value": v64, "ms_per_step": fp64["ms_per_step"],
+                       "interact_ms": fp64["interact_ms"]}
+        out["mixed_over_fp64"] = value / v64
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

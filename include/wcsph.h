@@ -1,0 +1,278 @@
+/*
+ * wcsph.h -- C ABI of the MI355X (gfx950) WCSPH step library.
+ *
+ * The library advances a weakly-compressible SPH (WCSPH) particle system by
+ * the step of Amaro Junior, Cheng & Buruchenko, "A comparison between
+ * weakly-compressible SPH and moving particle semi-implicit methods for 3D
+ * dam-break flows", Section 2.2:
+ *   - neighbours: all j with |r_j - r_i| < 2h, j != i (compact support of
+ *     the Wendland kernel, eq. sphw), found through a cell-linked list;
+ *   - momentum (eq. sphu) with Tait pressure (eq. tait) and Monaghan
+ *     artificial viscosity (eqs. pi, cpmu);
+ *   - delta-SPH continuity (eq. sphrho);
+ *   - Verlet update with an Euler reset every N_s steps (eqs. sphu1-sphrho1,
+ *     sphu2-sphrho2), adaptive time step (eq. sphdt);
+ *   - dynamic boundary particles: they obey continuity and the equation of
+ *     state but do not move.
+ *
+ * Conventions for every entry point:
+ *   - extern "C"; the return value is an sph_status (0 = success).  On
+ *     failure sph_last_error() returns a message for the calling thread.
+ *     Arguments are validated before anything is launched; a rejected call
+ *     launches nothing and changes nothing.
+ *   - Device pointers are HIP device addresses (HBM) owned by the caller.  The
+ *     library never allocates or frees device memory in these calls and holds
+ *     no device state between calls; everything it needs lives in the caller's
+ *     workspace buffer (size from sph_workspace_bytes, 256-byte aligned).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *     asynchronous on that stream except sph_diagnostics, which
+ *     synchronises it.
+ *   - Particle arrays are structure-of-arrays of length n.  After
+ *     sph_build_cells the arrays are in cell order; id[] carries each
+ *     particle's original index.
+ *   - One state/workspace pair must not be used by two overlapping calls.
+ */
+#ifndef WCSPH_H
+#define WCSPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPH_ABI_VERSION 1
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_E_INVAL = -1,  /* bad argument: null/misaligned pointer, bad size or parameter */
+    SPH_E_HIP = -2,    /* a HIP runtime call or kernel launch failed */
+    SPH_E_RANGE = -3,  /* a size does not fit the 32-bit index space */
+    SPH_E_STATE = -4,  /* call out of order (e.g. interact before build_cells) */
+    SPH_E_SIZE = -5    /* workspace too small for (params, n) */
+} sph_status;
+
+/* Arithmetic of the pair interaction. */
+typedef enum {
+    SPH_FP64 = 0,  /* FP64 everywhere; density stored as double rho */
+    SPH_MIXED = 1  /* FP32 pair arithmetic on (integer cell, FP32 offset)
+                      positions; FP64 position/velocity accumulators; density
+                      stored as float (rho - rho0) */
+} sph_precision;
+
+/* Sound speed c_i in the viscosity average (eq. pi, cpmu). */
+typedef enum {
+    SPH_C_TAIT = 0,  /* c_i = c0 (rho_i/rho0)^((gamma-1)/2), the Tait sound speed */
+    SPH_C_CONST = 1  /* c_i = c0 */
+} sph_c_mode;
+
+/* Pairs that carry the delta-SPH diffusive term (eq. sphrho). */
+typedef enum {
+    SPH_DELTA_FLUID = 0,  /* fluid i with fluid j only */
+    SPH_DELTA_ALL = 1     /* fluid i with every neighbour j */
+} sph_delta_pairs;
+
+/*
+ * Problem parameters (Section 2.2 and Section 3 of the paper).  All lengths in
+ * metres, SI units.  Validation (SPH_E_INVAL): dp > 0, h > 0, rho0 > 0,
+ * c0 > 0, gamma >= 1, alpha >= 0, 0 <= delta <= 1, eta2_coef >= 0,
+ * 0 < cfl <= 1, mass > 0, cell_size >= 2h, dims[k] >= 1 and
+ * dims[0]*dims[1]*dims[2] < 2^31, finite values, enums in range.
+ */
+typedef struct sph_params {
+    double dp;         /* initial particle spacing l0 */
+    double h;          /* smoothing length (h = k_SPH l0) */
+    double rho0;       /* reference density */
+    double c0;         /* artificial speed of sound */
+    double gamma;      /* Tait polytropic index */
+    double alpha;      /* artificial viscosity coefficient */
+    double delta;      /* delta-SPH coefficient */
+    double g[3];       /* body force per unit mass (gravity) */
+    double eta2_coef;  /* eta^2 = eta2_coef * h^2 (the paper: 0.01) */
+    double cfl;        /* Courant number Cr of eq. sphdt */
+    double mass;       /* particle mass (fluid and boundary) */
+    double origin[3];  /* lower corner of the cell grid */
+    double cell_size;  /* cell edge, >= 2h (2h(1 + 2^-20) recommended) */
+    int32_t dims[3];   /* cells per axis; positions outside are binned to the
+                          nearest cell (never dropped) and counted */
+    int32_t verlet_ns; /* Euler reset period N_s (40); <= 0: Euler only at step 0 */
+    int32_t precision; /* sph_precision */
+    int32_t c_mode;    /* sph_c_mode */
+    int32_t delta_pairs; /* sph_delta_pairs */
+    int32_t reserved;  /* must be 0 */
+} sph_params;
+
+/*
+ * Particle state, structure of arrays of length n, all device pointers.
+ * Two Verlet levels: (u, rho) at t and (um, rhom) at t - dt.
+ * rho/rhom: double rho when precision == SPH_FP64; float (rho - rho0) when
+ * SPH_MIXED (use sph_set_density / sph_get_density to convert).
+ * id: original index in bits 0..30, bit 31 set for a boundary particle.
+ * The *_alt arrays are second buffers of the same sizes: sph_build_cells
+ * gathers the state into them in cell order and swaps the pointer pairs in
+ * this struct, and sph_step swaps (u, um) and (rho, rhom); read the pointers
+ * back after each call.
+ */
+typedef struct sph_state {
+    int64_t n;
+    double *x, *y, *z;
+    double *ux, *uy, *uz;
+    double *uxm, *uym, *uzm;
+    void *rho, *rhom;
+    uint32_t *id;
+    double *x_alt, *y_alt, *z_alt;
+    double *ux_alt, *uy_alt, *uz_alt;
+    double *uxm_alt, *uym_alt, *uzm_alt;
+    void *rho_alt, *rhom_alt;
+    uint32_t *id_alt;
+    int32_t cells_valid; /* set by sph_build_cells; cleared when positions change */
+    int32_t reserved;
+} sph_state;
+
+/* Host-side results of sph_diagnostics, all FP64 (sums in a fixed order). */
+typedef struct sph_diag {
+    double mass;        /* sum of m over all particles */
+    double mom[3];      /* sum of m u over fluid particles */
+    double e_kin;       /* sum of m |u|^2 / 2 over fluid */
+    double e_pot;       /* sum of -m g . r over fluid */
+    double e_int;       /* sum of m e(rho), e = (B/rho0)[(rho/rho0)^(gamma-1)/(gamma-1)
+                           + rho0/rho - gamma/(gamma-1)], B = rho0 c0^2/gamma */
+    double umax;        /* max |u| over fluid */
+    double x_front;     /* max x over fluid particles with a fluid neighbour
+                           (-inf if none) */
+    double dt_cfl;      /* time-step bound of eq. sphdt at the last interaction */
+    double dt_last;     /* dt used by the last sph_step */
+    double time;        /* accumulated simulated time of sph_step calls */
+    int64_t n;          /* particles */
+    int64_t n_fluid;    /* fluid particles */
+    int64_t n_outside;  /* particles outside the grid (binned by clamping) */
+    int64_t n_nonfinite;/* non-finite values in r, u, rho */
+    int64_t steps;      /* steps taken since sph_workspace_init */
+    int64_t pairs_ff;   /* interacting ordered pairs evaluated since
+                           sph_workspace_init: fluid i with fluid j, */
+    int64_t pairs_fb;   /* fluid i with boundary j, */
+    int64_t pairs_bf;   /* boundary i with fluid j */
+    uint32_t flags;     /* SPH_FLAG_* */
+    uint32_t reserved;
+} sph_diag;
+
+#define SPH_FLAG_NONFINITE 1u   /* n_nonfinite > 0 */
+#define SPH_FLAG_OUTSIDE 2u     /* n_outside > 0 */
+#define SPH_FLAG_DENSITY 4u     /* some |rho - rho0| / rho0 > 0.1 */
+#define SPH_FLAG_DT_CFL 8u      /* dt_last exceeded dt_cfl */
+
+/* Library ABI version (SPH_ABI_VERSION). */
+int sph_version(void);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *sph_last_error(void);
+
+/* Validate params (see sph_params) without touching the device. */
+int sph_check_params(const sph_params *p);
+
+/* Bytes of workspace needed for (p, n particles); 0 < n < 2^31. */
+int sph_workspace_bytes(const sph_params *p, int64_t n, size_t *bytes);
+
+/*
+ * Prepare a fresh workspace: clears its device scalars (simulated time, step
+ * counter, time-step bound).  Call once before the first use of a workspace;
+ * calling it again restarts the clock.  SPH_E_SIZE if ws_bytes is too small.
+ */
+int sph_workspace_init(const sph_params *p, int64_t n, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/*
+ * Convert an FP64 density array (device, n values, in the state's current
+ * order) into the state's density storage: which = 0 -> rho, 1 -> rhom.
+ * sph_get_density does the reverse into an FP64 device array.
+ */
+int sph_set_density(const sph_params *p, sph_state *s, const double *rho, int32_t which,
+                    void *stream);
+int sph_get_density(const sph_params *p, const sph_state *s, double *rho, int32_t which,
+                    void *stream);
+
+/*
+ * Cell-linked list (neighbour search set-up).  Hashes every position to its
+ * cell (clamped to the grid), sorts the particles stably by cell (LSD radix
+ * sort of 32-bit cell keys), gathers every state array into cell order (the
+ * *_alt buffers, then swaps the pointers) and builds the cell table and the
+ * interaction view (per-particle pressure, sound speed, 1/rho, and for
+ * SPH_MIXED the FP32 offset of each particle from its cell centre).
+ * Stable: particles of one cell keep their previous relative order, so the
+ * result is deterministic.
+ */
+int sph_build_cells(const sph_params *p, sph_state *s, void *ws, void *stream);
+
+/*
+ * Rates of change at the current state (eqs. sphu, pi, cpmu, sphw, sphrho,
+ * tait):
+ *   fluid i:    a_i = -sum_j m [(P_i+P_j)/(rho_i rho_j) + Pi_ij] grad_i W_ij + g
+ *               drho_i = sum_j m (u_i - u_j).grad_i W_ij
+ *                        + 2 delta h c0 sum_j (rho_j - rho_i) F_ij m / rho_j
+ *   boundary i: drho_i = sum_{j fluid} m (u_i - u_j).grad_i W_ij, a_i = 0
+ * with grad_i W_ij = F_ij (r_j - r_i).  mumax_i = max_j |mu_ij|.
+ * Requires sph_build_cells since the positions last changed (SPH_E_STATE).
+ * Outputs are FP64 device arrays of n values in the current (cell) order;
+ * mumax may be NULL.
+ */
+int sph_interact(const sph_params *p, const sph_state *s, void *ws, double *ax, double *ay,
+                 double *az, double *drho, double *mumax, void *stream);
+
+/*
+ * Neighbour statistics at the current state, as decided by the interaction's
+ * own pair predicate (see sph_interact): per particle, the number of fluid
+ * neighbours, the number of boundary neighbours (boundary particles count
+ * fluid neighbours only), and the sum modulo 2^32 of H(id_j) over the
+ * neighbour set, H being the 32-bit MurmurHash3 finaliser of the original
+ * index.  The hash identifies the set independently of visit order (test and
+ * accounting aid).  int32/uint32 device arrays of n values, current order.
+ * Requires current cells (SPH_E_STATE).
+ */
+int sph_neighbour_stats(const sph_params *p, const sph_state *s, void *ws, int32_t *n_fluid_nbrs,
+                        int32_t *n_boundary_nbrs, uint32_t *id_hash, void *stream);
+
+/*
+ * One time step of the method: (sph_build_cells if the cells are stale) ->
+ * interaction -> time step -> Verlet update.  dt > 0: use it; dt <= 0: use
+ * the bound of eq. sphdt computed on the device from this step's rates (no
+ * host synchronisation).  step_index n selects the Euler reset
+ * (n mod verlet_ns == 0, and n == 0) or the two-level Verlet update.  Fluid
+ * particles update r, u, rho; boundary particles rho only.  Afterwards the
+ * positions have moved and cells_valid is 0.
+ */
+int sph_step(const sph_params *p, sph_state *s, void *ws, double dt, int64_t step_index,
+             void *stream);
+
+/*
+ * nsteps calls of sph_step with step indices step0 .. step0+nsteps-1 and the
+ * same dt rule, with every launch enqueued back to back on the stream.
+ */
+int sph_run(const sph_params *p, sph_state *s, void *ws, int64_t nsteps, double dt,
+            int64_t step0, void *stream);
+
+/*
+ * sph_run that also records caller-created hipEvent_t handles on the stream
+ * immediately before (ev_begin[k]) and after (ev_end[k]) the interaction
+ * kernel of step k, for timing that kernel alone.  Both arrays hold nsteps
+ * handles, or both are NULL (then it is sph_run).
+ */
+int sph_run_profiled(const sph_params *p, sph_state *s, void *ws, int64_t nsteps, double dt,
+                     int64_t step0, void *const *ev_begin, void *const *ev_end, void *stream);
+
+/*
+ * FP64 global diagnostics of the current state and Shepard-filtered probe
+ * pressures (eq. sphpa): P_a = sum_b P_b W_ab / sum_b W_ab over fluid b with
+ * |r_b - a| < 2h; 0 for a probe with no fluid in range.  probes_xyz: host
+ * array of 3*np doubles (may be NULL when np == 0); probe_p: host array of np
+ * doubles.  Requires current cells (call after sph_build_cells; sph_step
+ * leaves them stale).  Synchronises the stream.
+ */
+int sph_diagnostics(const sph_params *p, const sph_state *s, void *ws, const double *probes_xyz,
+                    int32_t np, sph_diag *out, double *probe_p, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WCSPH_H */

@@ -1,0 +1,327 @@
+"""ctypes binding of libwcsph.so (the C ABI in include/wcsph.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch supplies device memory (tensors) and the stream.  The library must be
+built (python -m paper_2306_01959_amd.build); importing this module on a
+machine without it, or calling into it without a GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libwcsph.so")
+
+SPH_OK, SPH_E_INVAL, SPH_E_HIP, SPH_E_RANGE, SPH_E_STATE, SPH_E_SIZE = 0, -1, -2, -3, -4, -5
+SPH_FP64, SPH_MIXED = 0, 1
+SPH_C_TAIT, SPH_C_CONST = 0, 1
+SPH_DELTA_FLUID, SPH_DELTA_ALL = 0, 1
+FLAG_NONFINITE, FLAG_OUTSIDE, FLAG_DENSITY, FLAG_DT_CFL = 1, 2, 4, 8
+BOUNDARY_BIT = np.uint32(1 << 31)
+
+#: every symbol include/wcsph.h declares
+EXPORTS = ("sph_version", "sph_last_error", "sph_check_params", "sph_workspace_bytes",
+           "sph_workspace_init", "sph_set_density", "sph_get_density", "sph_build_cells",
+           "sph_interact", "sph_neighbour_stats", "sph_step", "sph_run", "sph_run_profiled",
+           "sph_diagnostics")
+
+
+class SphParams(C.Structure):
+    _fields_ = [
+        ("dp", C.c_double), ("h", C.c_double), ("rho0", C.c_double), ("c0", C.c_double),
+        ("gamma", C.c_double), ("alpha", C.c_double), ("delta", C.c_double),
+        ("g", C.c_double * 3), ("eta2_coef", C.c_double), ("cfl", C.c_double),
+        ("mass", C.c_double), ("origin", C.c_double * 3), ("cell_size", C.c_double),
+        ("dims", C.c_int32 * 3), ("verlet_ns", C.c_int32), ("precision", C.c_int32),
+        ("c_mode", C.c_int32), ("delta_pairs", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+_P = C.c_void_p
+
+
+class SphState(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(k, _P) for k in (
+        "x", "y", "z", "ux", "uy", "uz", "uxm", "uym", "uzm", "rho", "rhom", "id",
+        "x_alt", "y_alt", "z_alt", "ux_alt", "uy_alt", "uz_alt", "uxm_alt", "uym_alt",
+        "uzm_alt", "rho_alt", "rhom_alt", "id_alt")] + [
+        ("cells_valid", C.c_int32), ("reserved", C.c_int32)]
+
+
+class SphDiag(C.Structure):
+    _fields_ = [
+        ("mass", C.c_double), ("mom", C.c_double * 3), ("e_kin", C.c_double),
+        ("e_pot", C.c_double), ("e_int", C.c_double), ("umax", C.c_double),
+        ("x_front", C.c_double), ("dt_cfl", C.c_double), ("dt_last", C.c_double),
+        ("time", C.c_double), ("n", C.c_int64), ("n_fluid", C.c_int64),
+        ("n_outside", C.c_int64), ("n_nonfinite", C.c_int64), ("steps", C.c_int64),
+        ("pairs_ff", C.c_int64), ("pairs_fb", C.c_int64), ("pairs_bf", C.c_int64),
+        ("flags", C.c_uint32), ("reserved", C.c_uint32),
+    ]
+
+    def as_dict(self) -> Dict[str, object]:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("mom", "reserved")}
+        d["mom"] = tuple(self.mom)
+        return d
+
+
+class SphError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libwcsph error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libwcsph.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_2306_01959_amd.build")
+    # torch first: the library then binds to the HIP runtime torch already
+    # loaded (same soname), so both share one runtime and one device context
+    import torch  # noqa: F401
+    L = C.CDLL(path)
+    PP, PS, PD = C.POINTER(SphParams), C.POINTER(SphState), C.POINTER(SphDiag)
+    L.sph_version.restype = C.c_int
+    L.sph_last_error.restype = C.c_char_p
+    L.sph_check_params.argtypes = [PP]
+    L.sph_workspace_bytes.argtypes = [PP, C.c_int64, C.POINTER(C.c_size_t)]
+    L.sph_workspace_init.argtypes = [PP, C.c_int64, _P, C.c_size_t, _P]
+    L.sph_set_density.argtypes = [PP, PS, _P, C.c_int32, _P]
+    L.sph_get_density.argtypes = [PP, PS, _P, C.c_int32, _P]
+    L.sph_build_cells.argtypes = [PP, PS, _P, _P]
+    L.sph_interact.argtypes = [PP, PS, _P, _P, _P, _P, _P, _P, _P]
+    L.sph_neighbour_stats.argtypes = [PP, PS, _P, _P, _P, _P, _P]
+    L.sph_step.argtypes = [PP, PS, _P, C.c_double, C.c_int64, _P]
+    L.sph_run.argtypes = [PP, PS, _P, C.c_int64, C.c_double, C.c_int64, _P]
+    L.sph_run_profiled.argtypes = [PP, PS, _P, C.c_int64, C.c_double, C.c_int64, _P, _P, _P]
+    L.sph_diagnostics.argtypes = [PP, PS, _P, _P, C.c_int32, PD, _P, _P]
+    for name in EXPORTS[2:]:
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int) -> None:
+    if rc != SPH_OK:
+        raise SphError(rc, load().sph_last_error().decode())
+
+
+def make_params(prm: Dict[str, object], precision: str = "mixed", *,
+                c_mode: int = SPH_C_TAIT, delta_pairs: int = SPH_DELTA_FLUID) -> SphParams:
+    p = SphParams()
+    for k in ("dp", "h", "rho0", "c0", "gamma", "alpha", "delta", "eta2_coef", "cfl", "mass"):
+        setattr(p, k, float(prm[k]))
+    p.g[:] = [float(v) for v in prm["g"]]
+    p.origin[:] = [float(v) for v in prm["origin"]]
+    p.cell_size = float(prm["cell_size"])
+    p.dims[:] = [int(v) for v in prm["dims"]]
+    p.verlet_ns = int(prm["verlet_ns"])
+    p.precision = SPH_MIXED if precision == "mixed" else SPH_FP64
+    p.c_mode = c_mode
+    p.delta_pairs = delta_pairs
+    p.reserved = 0
+    return p
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Simulation:
+    """Device state, workspace and stream for one particle system.
+
+    Owns two copies of every state array (the library ping-pongs between
+    them) and one workspace tensor.  Arrays come back in original particle
+    order via :meth:`fetch`.
+    """
+
+    def __init__(self, scene, precision: str = "mixed", device: str = "cuda:0",
+                 stream=None, c_mode: int = SPH_C_TAIT, delta_pairs: int = SPH_DELTA_FLUID):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.dev = torch.device(device)
+        self.precision = precision
+        self.params = make_params(scene.params, precision, c_mode=c_mode,
+                                  delta_pairs=delta_pairs)
+        check(self.lib.sph_check_params(C.byref(self.params)))
+        n = scene.n
+        self.n = n
+        self.stream = stream
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        rdt = torch.float32 if precision == "mixed" else torch.float64
+        self._buf = {}
+        for k in ("x", "y", "z", "ux", "uy", "uz", "uxm", "uym", "uzm"):
+            for suffix in ("", "_alt"):
+                self._buf[k + suffix] = torch.zeros(n, **f64)
+        for k in ("rho", "rhom"):
+            for suffix in ("", "_alt"):
+                self._buf[k + suffix] = torch.zeros(n, dtype=rdt, device=self.dev)
+        for suffix in ("", "_alt"):
+            self._buf["id" + suffix] = torch.zeros(n, dtype=torch.int32, device=self.dev)
+        nbytes = C.c_size_t(0)
+        check(self.lib.sph_workspace_bytes(C.byref(self.params), n, C.byref(nbytes)))
+        self.ws_bytes = int(nbytes.value)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        st = SphState()
+        st.n = n
+        for name, t in self._buf.items():
+            setattr(st, name, t.data_ptr())
+        st.cells_valid = 0
+        st.reserved = 0
+        self.state = st
+        check(self.lib.sph_workspace_init(C.byref(self.params), n, self.ws_ptr,
+                                          self.ws_bytes, self._s()))
+        self.upload(scene)
+
+    # -- plumbing ---------------------------------------------------------
+    def _s(self):
+        return _stream_ptr(self.stream)
+
+    def _cur(self, name: str):
+        """Tensor currently behind state field `name`."""
+        ptr = getattr(self.state, name)
+        for t in self._buf.values():
+            if t.data_ptr() == ptr:
+                return t
+        raise KeyError(name)
+
+    def upload(self, scene, prev=None) -> None:
+        """Load a scene (original order).  `prev` optionally gives the
+        previous Verlet level as a dict with ux, uy, uz, rho; by default it
+        equals the current level."""
+        torch = self.torch
+        ids = np.arange(scene.n, dtype=np.uint32)
+        ids[scene.is_boundary] |= BOUNDARY_BIT
+        pv = prev if prev is not None else dict(ux=scene.ux, uy=scene.uy, uz=scene.uz,
+                                                rho=scene.rho)
+        vals = dict(x=scene.x, y=scene.y, z=scene.z, ux=scene.ux, uy=scene.uy, uz=scene.uz,
+                    uxm=pv["ux"], uym=pv["uy"], uzm=pv["uz"])
+        for k, v in vals.items():
+            self._cur(k).copy_(torch.from_numpy(np.ascontiguousarray(v, np.float64)))
+        self._cur("id").copy_(torch.from_numpy(ids.view(np.int32)))
+        for which, r in ((0, scene.rho), (1, pv["rho"])):
+            rho = torch.from_numpy(np.ascontiguousarray(r, np.float64)).to(self.dev)
+            check(self.lib.sph_set_density(C.byref(self.params), C.byref(self.state),
+                                           rho.data_ptr(), which, self._s()))
+            self.sync()
+        self.state.cells_valid = 0
+
+    def sync(self) -> None:
+        self.torch.cuda.synchronize(self.dev)
+
+    # -- the four verbs ---------------------------------------------------
+    def build_cells(self) -> None:
+        check(self.lib.sph_build_cells(C.byref(self.params), C.byref(self.state), self.ws_ptr,
+                                       self._s()))
+
+    def interact(self, want_mumax: bool = True):
+        """Rates at the current state, FP64 tensors in current (cell) order."""
+        torch = self.torch
+        if not self.state.cells_valid:
+            self.build_cells()
+        outs = [torch.empty(self.n, dtype=torch.float64, device=self.dev) for _ in range(5)]
+        check(self.lib.sph_interact(C.byref(self.params), C.byref(self.state), self.ws_ptr,
+                                    *[o.data_ptr() for o in outs[:4]],
+                                    outs[4].data_ptr() if want_mumax else None, self._s()))
+        return outs
+
+    def neighbour_stats(self):
+        """(fluid-neighbour count, boundary-neighbour count, id-set hash) per
+        particle, numpy arrays in original particle order."""
+        torch = self.torch
+        if not self.state.cells_valid:
+            self.build_cells()
+        nf = torch.empty(self.n, dtype=torch.int32, device=self.dev)
+        nb = torch.empty(self.n, dtype=torch.int32, device=self.dev)
+        hs = torch.empty(self.n, dtype=torch.int32, device=self.dev)
+        check(self.lib.sph_neighbour_stats(C.byref(self.params), C.byref(self.state),
+                                           self.ws_ptr, nf.data_ptr(), nb.data_ptr(),
+                                           hs.data_ptr(), self._s()))
+        self.sync()
+        ids = self.ids()
+        out = []
+        for t, dt in ((nf, np.int64), (nb, np.int64), (hs, np.uint32)):
+            a = np.empty(self.n, dtype=dt)
+            v = t.cpu().numpy()
+            a[ids] = v.view(np.uint32) if dt is np.uint32 else v
+            out.append(a)
+        return tuple(out)
+
+    def step(self, dt: float, step_index: int) -> None:
+        check(self.lib.sph_step(C.byref(self.params), C.byref(self.state), self.ws_ptr,
+                                float(dt), int(step_index), self._s()))
+
+    def run(self, nsteps: int, dt: float, step0: int) -> None:
+        check(self.lib.sph_run(C.byref(self.params), C.byref(self.state), self.ws_ptr,
+                               int(nsteps), float(dt), int(step0), self._s()))
+
+    def run_profiled(self, nsteps: int, dt: float, step0: int, ev_begin, ev_end) -> None:
+        """run() recording hipEvent_t handles (ctypes arrays of c_void_p)
+        around every interaction kernel."""
+        check(self.lib.sph_run_profiled(C.byref(self.params), C.byref(self.state), self.ws_ptr,
+                                        int(nsteps), float(dt), int(step0), ev_begin, ev_end,
+                                        self._s()))
+
+    def diagnostics(self, probes: Optional[Sequence[Sequence[float]]] = None):
+        if not self.state.cells_valid:
+            self.build_cells()
+        pts = np.ascontiguousarray(np.asarray(probes if probes is not None else np.zeros((0, 3)),
+                                              np.float64).reshape(-1))
+        npts = pts.size // 3
+        out = SphDiag()
+        pp = np.zeros(max(npts, 1))
+        check(self.lib.sph_diagnostics(
+            C.byref(self.params), C.byref(self.state), self.ws_ptr,
+            pts.ctypes.data if npts else None, npts, C.byref(out),
+            pp.ctypes.data if npts else None, self._s()))
+        return out.as_dict(), pp[:npts]
+
+    # -- read-back ----------------------------------------------------------
+    def ids(self) -> np.ndarray:
+        raw = self._cur("id").cpu().numpy().view(np.uint32)
+        return (raw & np.uint32(0x7FFFFFFF)).astype(np.int64)
+
+    def density(self, which: int = 0):
+        out = self.torch.empty(self.n, dtype=self.torch.float64, device=self.dev)
+        check(self.lib.sph_get_density(C.byref(self.params), C.byref(self.state),
+                                       out.data_ptr(), which, self._s()))
+        return out
+
+    def fetch(self) -> Dict[str, np.ndarray]:
+        """All state arrays in original particle order (numpy, FP64)."""
+        self.sync()
+        ids = self.ids()
+        inv = np.empty_like(ids)
+        inv[ids] = np.arange(ids.size)
+        out = {}
+        for k in ("x", "y", "z", "ux", "uy", "uz", "uxm", "uym", "uzm"):
+            out[k] = self._cur(k).cpu().numpy()[inv]
+        out["rho"] = self.density(0).cpu().numpy()[inv]
+        out["rhom"] = self.density(1).cpu().numpy()[inv]
+        return out
+
+    def rates_by_id(self):
+        """(ax, ay, az, drho, mumax) in original particle order."""
+        outs = self.interact()
+        self.sync()
+        ids = self.ids()
+        res = []
+        for o in outs:
+            a = np.empty(self.n)
+            a[ids] = o.cpu().numpy()
+            res.append(a)
+        return tuple(res)

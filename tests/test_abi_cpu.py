@@ -1,0 +1,148 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+symbol the header declares, and rejects bad arguments before any launch."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2306_01959_amd import lib, scene
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wcsph.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(lib.LIB_PATH):
+        from paper_2306_01959_amd import build
+        build.build()
+    return lib.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(sph_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_what_binding_exports():
+    assert declared_functions() == sorted(lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    syms = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    for name in declared_functions():
+        assert name in syms, name
+        assert hasattr(L, name)
+
+
+def test_version(L):
+    assert L.sph_version() == 1
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """sizeof/offsetof of the three structs, compiled from the header with
+    gcc, equal the binding's ctypes mirrors."""
+    prog = tmp_path / "layout.c"
+    checks = []
+    for cname, py in (("sph_params", lib.SphParams), ("sph_state", lib.SphState),
+                      ("sph_diag", lib.SphDiag)):
+        checks.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            checks.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "wcsph.h"\n'
+                    "int main(void){" + "".join(checks) + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(prog)],
+                   check=True)
+    got = dict(ln.split() for ln in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    for cname, py in (("sph_params", lib.SphParams), ("sph_state", lib.SphState),
+                      ("sph_diag", lib.SphDiag)):
+        assert int(got[cname]) == C.sizeof(py)
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def params(**over):
+    p = lib.make_params(scene.make_params(0.02), "mixed")
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value", [
+    ("h", 0.0), ("h", -1.0), ("dp", 0.0), ("rho0", 0.0), ("c0", -1.0), ("gamma", 0.5),
+    ("alpha", -0.1), ("delta", 1.5), ("cfl", 0.0), ("cfl", 1.5), ("mass", 0.0),
+    ("cell_size", 0.01), ("precision", 7), ("c_mode", 3), ("delta_pairs", 2),
+    ("reserved", 1), ("h", float("nan")), ("eta2_coef", -1.0),
+])
+def test_bad_params_rejected(L, field, value):
+    p = params(**{field: value})
+    assert L.sph_check_params(C.byref(p)) == lib.SPH_E_INVAL
+    assert L.sph_last_error().decode() != ""
+
+
+def test_grid_too_large(L):
+    p = params()
+    p.dims[:] = [2048, 2048, 1024]
+    assert L.sph_check_params(C.byref(p)) == lib.SPH_E_RANGE
+
+
+def test_workspace_bytes(L):
+    p = params()
+    nb = C.c_size_t(0)
+    assert L.sph_workspace_bytes(C.byref(p), 28392, C.byref(nb)) == 0
+    assert nb.value > 28392 * 70 and nb.value % 256 == 0
+    assert L.sph_workspace_bytes(C.byref(p), 0, C.byref(nb)) == lib.SPH_E_INVAL
+    assert L.sph_workspace_bytes(C.byref(p), 1 << 31, C.byref(nb)) == lib.SPH_E_RANGE
+    assert L.sph_workspace_bytes(None, 10, C.byref(nb)) == lib.SPH_E_INVAL
+    p64 = lib.make_params(scene.make_params(0.02), "fp64")
+    nb64 = C.c_size_t(0)
+    L.sph_workspace_bytes(C.byref(p64), 28392, C.byref(nb64))
+    assert nb64.value > nb.value
+
+
+def test_calls_rejected_before_launch(L):
+    """Null state, null workspace, misaligned workspace, stale cells: every
+    entry point answers with an error code and launches nothing (no GPU is
+    needed to see that)."""
+    p = params()
+    st = lib.SphState()
+    assert L.sph_build_cells(C.byref(p), None, None, None) == lib.SPH_E_INVAL
+    assert L.sph_build_cells(C.byref(p), C.byref(st), None, None) == lib.SPH_E_INVAL  # n = 0
+    st.n = 100
+    assert L.sph_build_cells(C.byref(p), C.byref(st), None, None) == lib.SPH_E_INVAL  # null arrays
+    # fake but aligned non-null pointers: validation only, nothing is dereferenced
+    fake = 1 << 20
+    for k, _ in lib.SphState._fields_:
+        if k not in ("n", "cells_valid", "reserved"):
+            setattr(st, k, fake)
+            fake += 1 << 20
+    assert L.sph_build_cells(C.byref(p), C.byref(st), None, None) == lib.SPH_E_INVAL  # ws null
+    assert L.sph_build_cells(C.byref(p), C.byref(st), 1 << 30 | 8, None) == lib.SPH_E_INVAL
+    st.cells_valid = 0
+    outs = [1 << 33] * 4
+    assert L.sph_interact(C.byref(p), C.byref(st), 1 << 30, *outs, None, None) == lib.SPH_E_STATE
+    assert L.sph_diagnostics(C.byref(p), C.byref(st), 1 << 30, None, 0, None, None,
+                             None) == lib.SPH_E_INVAL
+    d = lib.SphDiag()
+    assert L.sph_diagnostics(C.byref(p), C.byref(st), 1 << 30, None, 0, C.byref(d), None,
+                             None) == lib.SPH_E_STATE
+    assert L.sph_diagnostics(C.byref(p), C.byref(st), 1 << 30, None, 5000, C.byref(d), None,
+                             None) == lib.SPH_E_INVAL
+    assert L.sph_step(C.byref(p), C.byref(st), 1 << 30, float("nan"), 0, None) == lib.SPH_E_INVAL
+    assert L.sph_step(C.byref(p), C.byref(st), 1 << 30, 1e-4, -1, None) == lib.SPH_E_INVAL
+    assert L.sph_run(C.byref(p), C.byref(st), 1 << 30, -1, 1e-4, 0, None) == lib.SPH_E_INVAL
+    st.x = (1 << 20) + 4          # misaligned double array
+    assert L.sph_build_cells(C.byref(p), C.byref(st), 1 << 30, None) == lib.SPH_E_INVAL
+    assert "misaligned" in L.sph_last_error().decode()
+
+
+def test_workspace_init_size_check(L):
+    p = params()
+    assert L.sph_workspace_init(C.byref(p), 100, 1 << 30, 64, None) == lib.SPH_E_SIZE

@@ -1,0 +1,277 @@
+"""HIP path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Tolerances: the FP64 path within 1e-12 relative L2 of the oracle; the mixed
+FP32 path within 1e-5 relative L2 for accelerations and drho/dt.  Neighbour
+sets are compared bit-exactly, each against the brute-force definition taken
+in the precision the path decides it in.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2306_01959_amd import scene
+from tests import bruteforce
+from tests.gpu_helpers import rel_l2, scene_from_oracle, set_stats
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_01959_amd import lib
+    lib.load()
+    return lib
+
+
+@pytest.fixture(scope="module")
+def developed(oracle_lib):
+    """Configuration-1 dam break advanced 60 steps by the oracle (CFL dt):
+    a state with real flow, pressure and viscosity."""
+    orc = oracle_lib
+    s = scene.config_scene(1)
+    p = orc.par(s.params)
+    st = orc.State(s)
+    orc.run(p, st, 60, dt_mode=1)
+    return s.params, st
+
+
+def _sim(gpu, sc, precision, prev=None, **kw):
+    sim = gpu.Simulation(sc, precision, **kw)
+    if prev is not None:
+        sim.upload(sc, prev)
+    return sim
+
+
+# ---------------------------------------------------------------- cells
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_build_cells_invariants(gpu, precision):
+    s = scene.config_scene(1)
+    sim = _sim(gpu, s, precision)
+    sim.build_cells()
+    sim.sync()
+    ids = sim.ids()
+    assert np.array_equal(np.sort(ids), np.arange(s.n))
+    x = sim._cur("x").cpu().numpy()
+    y = sim._cur("y").cpu().numpy()
+    z = sim._cur("z").cpu().numpy()
+    prm = s.params
+    (cx, cy, cz), _ = bruteforce.cells_and_offsets(x, y, z, prm["origin"], prm["cell_size"],
+                                                   prm["dims"])
+    nx, ny = prm["dims"][0], prm["dims"][1]
+    key = cx + nx * (cy + ny * cz)
+    assert np.all(np.diff(key) >= 0)
+    # stable: inside a cell the original order is kept
+    same = np.diff(key) == 0
+    assert np.all(np.diff(ids)[same] > 0)
+    # positions travelled with their ids
+    assert np.array_equal(x, s.x[ids]) and np.array_equal(z, s.z[ids])
+
+
+# ----------------------------------------------------------- neighbours
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_neighbour_sets_bit_exact(gpu, precision, seed):
+    prm = scene.make_params(0.02, lo=(0, 0, 0), hi=(0.5, 0.45, 0.4))
+    x, y, z = bruteforce.adversarial_cloud(seed, prm)
+    n = x.size
+    rng = np.random.default_rng(seed + 10)
+    isb = rng.uniform(size=n) < 0.3
+    zero = np.zeros(n)
+    sc = scene.Scene("adv", x, y, z, zero.copy(), zero.copy(), zero.copy(),
+                     np.full(n, 1000.0), isb, prm)
+    sim = _sim(gpu, sc, precision)
+    nf, nb, hs = sim.neighbour_stats()
+    if precision == "fp64":
+        ref = bruteforce.pairs_fp64(x, y, z, prm["h"])
+    else:
+        ref = bruteforce.pairs_mixed(x, y, z, prm["h"], prm["origin"], prm["cell_size"],
+                                     prm["dims"])
+    rf, rb, rh = set_stats(ref, n, isb)
+    assert np.array_equal(nf, rf)
+    assert np.array_equal(nb, rb)
+    assert np.array_equal(hs, rh)
+
+
+# ---------------------------------------------------------------- rates
+
+def _oracle_rates(orc, params, st):
+    p = orc.par(params)
+    return orc.rates(p, st.x, st.y, st.z, st.ux, st.uy, st.uz, st.rho, st.is_bnd)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_rates_developed_state(gpu, oracle_lib, developed, precision, tol):
+    params, st = developed
+    sc, prev = scene_from_oracle(st, params)
+    ref = _oracle_rates(oracle_lib, params, st)
+    sim = _sim(gpu, sc, precision, prev)
+    got = sim.rates_by_id()
+    f = ~sc.is_boundary
+    g = np.asarray(params["g"])
+    for k in range(3):
+        assert rel_l2(got[k], ref[k]) < tol, (k, rel_l2(got[k], ref[k]))
+    # interaction-only norm (gravity removed)
+    a_got = np.stack([got[k][f] - g[k] for k in range(3)])
+    a_ref = np.stack([ref[k][f] - g[k] for k in range(3)])
+    assert rel_l2(a_got, a_ref) < 10 * tol
+    assert rel_l2(got[3], ref[3]) < tol
+    assert rel_l2(got[4], ref[4]) < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_config2_first_steps_lockstep(gpu, oracle_lib, precision):
+    """Configuration 2 (dp = 0.01, hydrostatic start): for each of the first
+    10 steps, the GPU's rates at its own state against the oracle's rates at
+    the oracle's state, both advanced with the oracle's dt sequence."""
+    orc = oracle_lib
+    s = scene.config_scene(2)
+    p = orc.par(s.params)
+    st = orc.State(s)
+    sim = _sim(gpu, s, precision)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    worst = 0.0
+    for k in range(10):
+        ref = orc.rates(p, st.x, st.y, st.z, st.ux, st.uy, st.uz, st.rho, st.is_bnd)
+        got = sim.rates_by_id()
+        for c in range(4):
+            worst = max(worst, rel_l2(got[c], ref[c]))
+        dt = orc.dt_cfl(p, ref[0], ref[1], ref[2], ref[4], st.is_bnd)
+        orc.update(p, st, k % 40 == 0, dt, ref)
+        sim.step(dt, k)
+    assert worst < tol, worst
+    out = sim.fetch()
+    scale = s.params["dp"]
+    assert np.abs(out["x"] - st.x).max() < (1e-12 if precision == "fp64" else 1e-7) * scale * 100
+
+
+def test_dt_bound_matches_oracle(gpu, oracle_lib, developed):
+    params, st = developed
+    sc, prev = scene_from_oracle(st, params)
+    ref = _oracle_rates(oracle_lib, params, st)
+    p = oracle_lib.par(params)
+    dt_ref = oracle_lib.dt_cfl(p, ref[0], ref[1], ref[2], ref[4], st.is_bnd)
+    for precision, tol in (("fp64", 1e-13), ("mixed", 1e-5)):
+        sim = _sim(gpu, sc, precision, prev)
+        sim.step(-1.0, 1)     # device CFL time step, Verlet branch
+        d, _ = sim.diagnostics()
+        assert d["dt_last"] == pytest.approx(dt_ref, rel=tol)
+        assert d["dt_cfl"] == pytest.approx(dt_ref, rel=tol)
+
+
+# ---------------------------------------------------------- trajectories
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_trajectory_matches_oracle(gpu, oracle_lib, developed, precision):
+    """45 steps (crossing the Euler reset at step 40) with the oracle's dt
+    sequence from a developed state."""
+    orc = oracle_lib
+    params, st0 = developed
+    sc, prev = scene_from_oracle(st0, params)
+    p = orc.par(params)
+    st = orc.State(sc)
+    st.uxm, st.uym, st.uzm, st.rhom = (prev["ux"].copy(), prev["uy"].copy(),
+                                       prev["uz"].copy(), prev["rho"].copy())
+    st.step = 60
+    dts, _ = orc.run(p, st, 45, dt_mode=1)
+    sim = _sim(gpu, sc, precision, prev)
+    for k in range(45):
+        sim.step(float(dts[k]), 60 + k)
+    out = sim.fetch()
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    for key, ref in (("ux", st.ux), ("uz", st.uz)):
+        assert rel_l2(out[key], ref) < tol, (key, rel_l2(out[key], ref))
+    assert rel_l2(out["rho"] - 1000.0, st.rho - 1000.0) < tol
+    assert np.abs(out["x"] - st.x).max() < 1e-6 * params["dp"]
+
+
+def test_determinism_bitwise(gpu):
+    s = scene.config_scene(1)
+    outs = []
+    for _ in range(2):
+        sim = _sim(gpu, s, "mixed")
+        sim.run(25, -1.0, 0)
+        outs.append(sim.fetch())
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+# ----------------------------------------------------------- diagnostics
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_diagnostics_match_oracle(gpu, oracle_lib, developed, precision):
+    params, st = developed
+    sc, prev = scene_from_oracle(st, params)
+    sim = _sim(gpu, sc, precision, prev)
+    probes = np.array([[0.2, 0.3, 0.05], [0.5, 0.3, 0.02], [1.5, 0.3, 0.5]])
+    d, pp = sim.diagnostics(probes)
+    p = oracle_lib.par(params)
+    od = oracle_lib.diagnostics(p, st)
+    op = oracle_lib.probes(p, st, probes)
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert d["mass"] == pytest.approx(od["mass"], rel=1e-12)
+    assert d["e_kin"] == pytest.approx(od["e_kin"], rel=tol)
+    assert d["e_pot"] == pytest.approx(od["e_pot"], rel=1e-12)
+    assert d["e_int"] == pytest.approx(od["e_int"], rel=1e-4 if precision == "mixed" else 1e-10)
+    assert d["umax"] == pytest.approx(od["umax"], rel=1e-12)
+    assert d["x_front"] == od["x_front"]
+    for k, key in enumerate(("px", "py", "pz")):
+        assert d["mom"][k] == pytest.approx(od[key], rel=1e-9, abs=1e-12)
+    assert d["n_fluid"] == sc.n_fluid and d["n"] == sc.n
+    assert d["n_nonfinite"] == 0
+    assert np.allclose(pp, op, rtol=1e-6 if precision == "mixed" else 1e-12, atol=1e-9)
+    assert pp[2] == 0.0          # dry probe
+
+
+def test_pair_totals_match_oracle(gpu, oracle_lib, developed):
+    params, st = developed
+    sc, prev = scene_from_oracle(st, params)
+    p = oracle_lib.par(params)
+    _, cnt = oracle_lib.rates(p, st.x, st.y, st.z, st.ux, st.uy, st.uz, st.rho, st.is_bnd,
+                              want_counts=True)
+    sim = _sim(gpu, sc, "fp64", prev)
+    sim.interact()
+    d, _ = sim.diagnostics()
+    assert (d["pairs_ff"], d["pairs_fb"], d["pairs_bf"]) == cnt
+
+
+def test_nan_is_flagged(gpu):
+    s = scene.config_scene(1)
+    s.rho[5] = float("nan")
+    sim = _sim(gpu, s, "fp64")
+    d, _ = sim.diagnostics()
+    assert d["n_nonfinite"] >= 1 and d["flags"] & gpu.FLAG_NONFINITE
+
+
+def test_outside_particle_clamped_and_counted(gpu):
+    s = scene.config_scene(1)
+    s.z[0] = 5.0                       # far above the grid top (1.2 m)
+    s.x[1] = -1.0                      # left of the grid
+    sim = _sim(gpu, s, "mixed")
+    d, _ = sim.diagnostics()
+    assert d["n_outside"] == 2 and d["flags"] & gpu.FLAG_OUTSIDE
+    sim.run(3, -1.0, 0)
+    out = sim.fetch()
+    assert np.all(np.isfinite(out["x"])) and out["z"][0] < 5.0
+
+
+# ------------------------------------------------------------ hydrostatics
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_hydrostatic_column(gpu, precision):
+    """The settling case of the oracle pins, on the GPU path."""
+    s = scene.resting_column(0.02, 0, tank=(0.2, 0.2, 0.4), H=0.3, alpha=0.1, delta=0.0)
+    sim = _sim(gpu, s, precision)
+    h, c0, H = s.params["h"], s.params["c0"], 0.3
+    dt = s.params["cfl"] * h / c0
+    sim.run(int(0.6 / dt), -1.0, 0)
+    zs = np.array([2 * h + 0.001, 0.1, 0.15, 0.2, H - 2 * h])
+    d, pp = sim.diagnostics([[0.1, 0.1, zz] for zz in zs])
+    err = (pp - 1000.0 * 9.81 * (H - zs)) / (1000.0 * 9.81 * H)
+    assert np.abs(err).max() < 0.01, err
+    assert d["umax"] < 0.1
