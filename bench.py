@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
+    ap.add_argument("--retune", action="store_true", help="ignore the autotune cache")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -131,9 +132,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     hip = hip_runtime()
 
+    from paper_2306_01959_amd import autotune
     sc = scene.config_scene(2)
+    splits = {"mixed": autotune.tune(sc, "mixed", use_cache=not args.retune,
+                                     verbose=args.retune)}
     mixed = time_gpu(sc, "mixed", args.steps, args.warmup, hip)
-    fp64 = None if args.no_fp64 else time_gpu(sc, "fp64", args.steps, args.warmup, hip)
+    fp64 = None
+    if not args.no_fp64:
+        splits["fp64"] = autotune.tune(sc, "fp64", use_cache=not args.retune,
+                                       verbose=args.retune)
+        fp64 = time_gpu(sc, "fp64", args.steps, args.warmup, hip)
     value = sc.n * args.steps / mixed["wall_s"]
     achieved = mixed["flop_per_launch"] / (mixed["interact_ms"] * 1e-3) / 1e12
     out = {
@@ -156,9 +164,10 @@ def main():
                         "interaction + FP64 integration",
             "particles": sc.n, "fluid": sc.n_fluid, "boundary": sc.n_boundary,
             "precision": "mixed", "parallelism": "single GPU",
+            "waves_per_chunk": splits,
         },
         "roofline": {
-            "kernel": "k_interact_mixed",
+            "kernel": f"k_interact<Mixed, {splits['mixed']}, false>",
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,

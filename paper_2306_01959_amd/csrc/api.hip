@@ -190,6 +190,28 @@ const char *sph_last_error(void) { return g_err.c_str(); }
 
 int sph_check_params(const sph_params *p) { return check_params(p); }
 
+int sph_set_tuning(const sph_tuning *t) {
+    if (!t) return fail(SPH_E_INVAL, "tuning is NULL");
+    for (int k = 0; k < 6; ++k)
+        if (t->reserved[k] != 0) return fail(SPH_E_INVAL, "tuning reserved must be 0");
+    const int ok = (t->split_fp64 == 0 || t->split_fp64 == 1 || t->split_fp64 == 3 ||
+                    t->split_fp64 == 9) &&
+                   (t->split_mixed == 0 || t->split_mixed == 1 || t->split_mixed == 3 ||
+                    t->split_mixed == 9);
+    if (!ok) return fail(SPH_E_INVAL, "split must be 0, 1, 3 or 9");
+    set_split(SPH_FP64, t->split_fp64);
+    set_split(SPH_MIXED, t->split_mixed);
+    return SPH_OK;
+}
+
+int sph_get_split(const sph_params *p, int64_t n, int32_t *split) {
+    if (int rc = check_params(p)) return rc;
+    if (int rc = check_n(n)) return rc;
+    if (!split) return fail(SPH_E_INVAL, "split is NULL");
+    *split = split_for(*p, make_layout(*p, n).max_chunks);
+    return SPH_OK;
+}
+
 int sph_workspace_bytes(const sph_params *p, int64_t n, size_t *bytes) {
     if (int rc = check_params(p)) return rc;
     if (int rc = check_n(n)) return rc;

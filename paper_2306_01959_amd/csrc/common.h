@@ -123,6 +123,8 @@ int launch_set_density(const sph_params &p, sph_state &s, const double *rho, int
 int launch_get_density(const sph_params &p, const sph_state &s, double *rho, int which,
                        hipStream_t st);
 int launch_ws_init(const Ws &w, hipStream_t st);
+int set_split(int precision, int split);
+int split_for(const sph_params &p, int64_t max_chunks);
 
 // Cell id layout: linear = cx + nx * (cy + ny * cz).
 __host__ __device__ inline int64_t lin_cell(int cx, int cy, int cz, int nx, int ny) {

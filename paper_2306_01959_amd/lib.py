@@ -24,7 +24,8 @@ FLAG_NONFINITE, FLAG_OUTSIDE, FLAG_DENSITY, FLAG_DT_CFL = 1, 2, 4, 8
 BOUNDARY_BIT = np.uint32(1 << 31)
 
 #: every symbol include/wcsph.h declares
-EXPORTS = ("sph_version", "sph_last_error", "sph_check_params", "sph_workspace_bytes",
+EXPORTS = ("sph_version", "sph_last_error", "sph_check_params", "sph_set_tuning",
+           "sph_get_split", "sph_workspace_bytes",
            "sph_workspace_init", "sph_set_density", "sph_get_density", "sph_build_cells",
            "sph_interact", "sph_neighbour_stats", "sph_step", "sph_run", "sph_run_profiled",
            "sph_diagnostics")
@@ -42,6 +43,11 @@ class SphParams(C.Structure):
 
 
 _P = C.c_void_p
+
+
+class SphTuning(C.Structure):
+    _fields_ = [("split_fp64", C.c_int32), ("split_mixed", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class SphState(C.Structure):
@@ -93,6 +99,8 @@ def load(path: str = LIB_PATH):
     L.sph_version.restype = C.c_int
     L.sph_last_error.restype = C.c_char_p
     L.sph_check_params.argtypes = [PP]
+    L.sph_set_tuning.argtypes = [C.POINTER(SphTuning)]
+    L.sph_get_split.argtypes = [PP, C.c_int64, C.POINTER(C.c_int32)]
     L.sph_workspace_bytes.argtypes = [PP, C.c_int64, C.POINTER(C.c_size_t)]
     L.sph_workspace_init.argtypes = [PP, C.c_int64, _P, C.c_size_t, _P]
     L.sph_set_density.argtypes = [PP, PS, _P, C.c_int32, _P]
@@ -113,6 +121,20 @@ def load(path: str = LIB_PATH):
 def check(rc: int) -> None:
     if rc != SPH_OK:
         raise SphError(rc, load().sph_last_error().decode())
+
+
+def set_tuning(split_fp64: int = 0, split_mixed: int = 0) -> None:
+    """Process-wide interaction launch shape (0 = the library's choice)."""
+    t = SphTuning()
+    t.split_fp64 = int(split_fp64)
+    t.split_mixed = int(split_mixed)
+    check(load().sph_set_tuning(C.byref(t)))
+
+
+def get_split(params: "SphParams", n: int) -> int:
+    v = C.c_int32(0)
+    check(load().sph_get_split(C.byref(params), int(n), C.byref(v)))
+    return int(v.value)
 
 
 def make_params(prm: Dict[str, object], precision: str = "mixed", *,

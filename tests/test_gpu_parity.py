@@ -275,3 +275,31 @@ def test_hydrostatic_column(gpu, precision):
     err = (pp - 1000.0 * 9.81 * (H - zs)) / (1000.0 * 9.81 * H)
     assert np.abs(err).max() < 0.01, err
     assert d["umax"] < 0.1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_every_split_matches(gpu, oracle_lib, developed, precision):
+    """The launch shapes the autotuner may pick (1, 3 or 9 waves per chunk)
+    give bit-identical neighbour sets and oracle-parity rates."""
+    params, st = developed
+    sc, prev = scene_from_oracle(st, params)
+    ref = _oracle_rates(oracle_lib, params, st)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    stats = []
+    try:
+        for split in (1, 3, 9):
+            if precision == "fp64":
+                gpu.set_tuning(split_fp64=split)
+            else:
+                gpu.set_tuning(split_mixed=split)
+            sim = _sim(gpu, sc, precision, prev)
+            assert gpu.get_split(sim.params, sim.n) == split
+            got = sim.rates_by_id()
+            for k in range(4):
+                assert rel_l2(got[k], ref[k]) < tol, (split, k)
+            stats.append(sim.neighbour_stats())
+    finally:
+        gpu.set_tuning(0, 0)
+    for s_ in stats[1:]:
+        for a_, b_ in zip(s_, stats[0]):
+            assert np.array_equal(a_, b_)
