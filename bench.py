@@ -167,7 +167,7 @@ def main():
             "waves_per_chunk": splits,
         },
         "roofline": {
-            "kernel": f"k_interact<Mixed, {splits['mixed']}, false>",
+            "kernel": "k_interact<Mixed, %d, %d, false>" % tuple(splits["mixed"]),
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,

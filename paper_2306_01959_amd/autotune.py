@@ -1,9 +1,10 @@
 """Autotuner for the interaction launch shape.
 
 For a given scene and precision it times whole steps for every supported
-split (waves per 64-target chunk: 1, 3, 9), keeps the fastest, sets it in the
-library (sph_set_tuning) and caches the choice in a JSON file keyed by the
-problem shape (precision, particle count, grid).  The cache path comes from
+shape -- waves per 64-target chunk (1, 3, 9) x targets per group (8, 16,
+64) -- keeps the fastest, sets it in the library (sph_set_tuning) and caches
+the choice in a JSON file keyed by the problem shape (precision, particle
+count, grid).  The cache path comes from
 WCSPH_TUNE_CACHE (default: tune_cache.json next to this file).
 """
 from __future__ import annotations
@@ -16,6 +17,7 @@ from typing import Dict, Optional
 from . import lib
 
 SPLITS = (1, 3, 9)
+GROUPS = (8, 16, 64)
 CACHE = os.environ.get("WCSPH_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json"))
 
@@ -40,50 +42,46 @@ def _save(tab: Dict[str, dict]) -> None:
     os.replace(tmp, CACHE)
 
 
-def current() -> Dict[str, int]:
-    return dict(_state)
+_state = {"fp64": (0, 0), "mixed": (0, 0)}
 
 
-_state = {"fp64": 0, "mixed": 0}
-
-
-def apply(precision: str, split: int) -> None:
-    _state[precision] = int(split)
-    lib.set_tuning(split_fp64=_state["fp64"], split_mixed=_state["mixed"])
+def apply(precision: str, shape) -> None:
+    _state[precision] = (int(shape[0]), int(shape[1]))
+    lib.set_tuning(split_fp64=_state["fp64"][0], split_mixed=_state["mixed"][0],
+                   group_fp64=_state["fp64"][1], group_mixed=_state["mixed"][1])
 
 
 def tune(scene, precision: str = "mixed", steps: int = 30, warmup: int = 5,
-         use_cache: bool = True, verbose: bool = False) -> int:
-    """Pick the split for (scene, precision); returns it (and applies it)."""
+         use_cache: bool = True, verbose: bool = False):
+    """Pick (split, group) for (scene, precision); returns it (and applies it)."""
     import torch
     key = _key(precision, scene)
     tab = _load() if use_cache else {}
-    if key in tab:
-        apply(precision, tab[key]["split"])
-        return tab[key]["split"]
+    if key in tab and "shape" in tab[key]:
+        apply(precision, tab[key]["shape"])
+        return tuple(tab[key]["shape"])
     times = {}
     for split in SPLITS:
-        apply(precision, split)
-        sim = lib.Simulation(scene, precision)
-        sim.run(warmup, -1.0, 0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim.run(steps, -1.0, warmup)
-        torch.cuda.synchronize()
-        times[split] = (time.perf_counter() - t0) / steps
-        del sim
-        if verbose:
-            print(f"autotune {key} split={split}: {times[split] * 1e3:.3f} ms/step", flush=True)
+        for group in GROUPS:
+            apply(precision, (split, group))
+            sim = lib.Simulation(scene, precision)
+            sim.run(warmup, -1.0, 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.run(steps, -1.0, warmup)
+            torch.cuda.synchronize()
+            times[(split, group)] = (time.perf_counter() - t0) / steps
+            del sim
+            if verbose:
+                print(f"autotune {key} split={split} group={group}: "
+                      f"{times[(split, group)] * 1e3:.3f} ms/step", flush=True)
     best = min(times, key=times.get)
     apply(precision, best)
     tab = _load()
-    tab[key] = {"split": best, "ms_per_step": {str(k): v * 1e3 for k, v in times.items()}}
+    tab[key] = {"shape": list(best),
+                "ms_per_step": {f"{k[0]}x{k[1]}": v * 1e3 for k, v in times.items()}}
     try:
         _save(tab)
     except OSError:
         pass
     return best
-
-
-def tuned_split(scene, precision: str) -> Optional[int]:
-    return _load().get(_key(precision, scene), {}).get("split")

@@ -192,23 +192,27 @@ int sph_check_params(const sph_params *p) { return check_params(p); }
 
 int sph_set_tuning(const sph_tuning *t) {
     if (!t) return fail(SPH_E_INVAL, "tuning is NULL");
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 4; ++k)
         if (t->reserved[k] != 0) return fail(SPH_E_INVAL, "tuning reserved must be 0");
-    const int ok = (t->split_fp64 == 0 || t->split_fp64 == 1 || t->split_fp64 == 3 ||
-                    t->split_fp64 == 9) &&
-                   (t->split_mixed == 0 || t->split_mixed == 1 || t->split_mixed == 3 ||
-                    t->split_mixed == 9);
-    if (!ok) return fail(SPH_E_INVAL, "split must be 0, 1, 3 or 9");
+    auto split_ok = [](int v) { return v == 0 || v == 1 || v == 3 || v == 9; };
+    auto group_ok = [](int v) { return v == 0 || v == 8 || v == 16 || v == 64; };
+    if (!split_ok(t->split_fp64) || !split_ok(t->split_mixed))
+        return fail(SPH_E_INVAL, "split must be 0, 1, 3 or 9");
+    if (!group_ok(t->group_fp64) || !group_ok(t->group_mixed))
+        return fail(SPH_E_INVAL, "group must be 0, 8, 16 or 64");
     set_split(SPH_FP64, t->split_fp64);
     set_split(SPH_MIXED, t->split_mixed);
+    set_group(SPH_FP64, t->group_fp64);
+    set_group(SPH_MIXED, t->group_mixed);
     return SPH_OK;
 }
 
-int sph_get_split(const sph_params *p, int64_t n, int32_t *split) {
+int sph_get_split(const sph_params *p, int64_t n, int32_t *split, int32_t *group) {
     if (int rc = check_params(p)) return rc;
     if (int rc = check_n(n)) return rc;
-    if (!split) return fail(SPH_E_INVAL, "split is NULL");
+    if (!split || !group) return fail(SPH_E_INVAL, "output is NULL");
     *split = split_for(*p, make_layout(*p, n).max_chunks);
+    *group = group_for(*p);
     return SPH_OK;
 }
 

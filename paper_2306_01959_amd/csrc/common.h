@@ -124,7 +124,9 @@ int launch_get_density(const sph_params &p, const sph_state &s, double *rho, int
                        hipStream_t st);
 int launch_ws_init(const Ws &w, hipStream_t st);
 int set_split(int precision, int split);
+int set_group(int precision, int group);
 int split_for(const sph_params &p, int64_t max_chunks);
+int group_for(const sph_params &p);
 
 // Cell id layout: linear = cx + nx * (cy + ny * cz).
 __host__ __device__ inline int64_t lin_cell(int cx, int cy, int cz, int nx, int ny) {

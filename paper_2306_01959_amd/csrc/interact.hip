@@ -2,22 +2,26 @@
 // sphrho, tait) and the per-particle time-step bound (eq. sphdt).
 //
 // Work decomposition.  A chunk is up to 64 consecutive sorted particles of
-// one cell row (fixed cy, cz; cells are numbered x-fastest), one target per
-// lane.  Its candidates are the nine stencil rows (cy+dy, cz+dz) over cells
-// [cx_first - 1, cx_last + 1], each a contiguous range of the sorted arrays.
-// A workgroup of kSplit waves (1, 3 or 9) owns a chunk; each wave takes 9 /
-// kSplit of the rows, and the waves' partial sums are added in a fixed order
-// at the end, so more waves cover the chip on small problems without changing
-// results between runs.
+// one cell row (fixed cy, cz; cells are numbered x-fastest).  Its candidates
+// are the nine stencil rows (cy+dy, cz+dz) over cells [cx_first - 1,
+// cx_last + 1], each a contiguous range of the sorted arrays.  A workgroup of
+// kSplit waves (1, 3 or 9) owns a chunk; each wave takes 9 / kSplit of the
+// rows, and the waves' partial sums are added in a fixed order at the end.
 //
 // Per wave, candidates stream through in batches of 64: the next batch is
 // loaded into registers while the current one is processed; a batch is
 // culled against the chunk's bounding box (conservatively: 2h plus a relative
-// margin), compacted into LDS with a ballot and a popcount, and every lane
-// then sweeps the compacted records by LDS broadcast, accumulating only its
-// own target's sums (gather form: no atomics, deterministic).  Quantities that
-// depend on the candidate alone (P_j/rho_j, the delta-term factors) are
-// computed once at staging instead of once per lane.
+// margin) and compacted into LDS with a ballot and a popcount.  The chunk's
+// targets are split into groups of kT consecutive particles (64 / kT groups),
+// each with its own bounding box; every group keeps the staged records that
+// can reach it (one ballot per group).  Lane l then works on target
+// (l mod kT) of a group and on every (64 / kT)-th of that group's records, so
+// a wave evaluates 64 (target, record) pairs per step; small groups are
+// compact, which raises the share of evaluated pairs that lie inside the 2h
+// support.  Each lane accumulates per group; at the end the lanes that share
+// a target are summed with a fixed shuffle tree (gather form: no atomics,
+// deterministic).  Candidate-only quantities (P_j/rho_j, the delta-term
+// factors) are computed once at staging.
 //
 // Mixed precision: positions are an integer cell plus an FP32 offset from the
 // cell centre.  The displacement r_j - r_i along an axis is
@@ -25,8 +29,7 @@
 // and r^2 = ((dx dx + dy dy) + dz dz) rounded after every operation, so the
 // neighbour decision does not depend on how particles are grouped.  Densities
 // enter as rho - rho0, which keeps the delta-SPH differences and the pressure
-// accurate in FP32; pair terms are summed per staged batch before they enter
-// the running sums.  FP64: absolute positions, d = r_j - r_i, the same r^2.
+// accurate in FP32.  FP64: absolute positions, d = r_j - r_i, the same r^2.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -70,10 +73,10 @@ __device__ __forceinline__ double sq_sum_f64(double dx, double dy, double dz) {
     return (a + b) + c;
 }
 
+// min / max over aligned groups of `width` lanes (width a power of 2)
 template <class T>
-__device__ __forceinline__ T wave_min(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+__device__ __forceinline__ T group_min(T v, int width) {
+    for (int off = 1; off < width; off <<= 1) {
         T o = __shfl_xor(v, off, kWave);
         v = o < v ? o : v;
     }
@@ -81,9 +84,8 @@ __device__ __forceinline__ T wave_min(T v) {
 }
 
 template <class T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+__device__ __forceinline__ T group_max(T v, int width) {
+    for (int off = 1; off < width; off <<= 1) {
         T o = __shfl_xor(v, off, kWave);
         v = o > v ? o : v;
     }
@@ -123,47 +125,35 @@ __device__ __forceinline__ uint32_t xcd_chunk(uint32_t b, uint32_t nb) {
     return (b % 8) * per + b / 8;
 }
 
-// Per-lane sums of one target.
+// Per-lane sums of one (target, record subset).
 template <class R>
 struct Acc {
-    R ax = 0, ay = 0, az = 0, dr = 0;
+    R ax = 0, ay = 0, az = 0, dr = 0, mu = 0;
 };
 
-// Scalar (wave-uniform) pair counters and per-lane statistics.
+// Wave-uniform pair counters, and per-lane neighbour statistics of a group.
 struct Counters {
     uint32_t ff = 0, fb = 0, bf = 0;
-    int32_t st_f = 0, st_b = 0;
-    uint32_t st_h = 0;
 };
-
-__device__ __forceinline__ void count_pairs(Counters &cn, uint64_t inm, uint64_t fmask_bits,
-                                            bool fj) {
-    const uint32_t nin = (uint32_t)__popcll(inm);
-    const uint32_t nfin = (uint32_t)__popcll(inm & fmask_bits);
-    cn.ff += fj ? nfin : 0u;
-    cn.bf += fj ? nin - nfin : 0u;
-    cn.fb += fj ? 0u : nin;
-}
+struct Stats {
+    int32_t f = 0, b = 0;
+    uint32_t h = 0;
+};
 
 // ================================================================ policies
 //
-// A policy supplies the target registers, the raw candidate registers, the
-// LDS record (four vectors of 4) written at staging, and the pair term.
+// A policy supplies the target record (three vectors of 4 in LDS), the raw
+// candidate registers, the candidate record (four vectors of 4 in LDS)
+// written at staging, and the pair term.
 
 struct Mixed {
     using R = float;
     using V4 = float4;
-    struct Target {
-        float ox, oy, oz, cixf;  // offset from own cell centre, own cell x
-        float ux, uy, uz;
-        float P, invr;           // invr = 1/rho_i for fluid, 0 for boundary
-        float dr;                // rho_i - rho0
-        float rsum;              // 2 rho0 + (rho_i - rho0)
-        float c;                 // |c_i|
-        float nalpha;            // -alpha for fluid, 0 for boundary
-        float fmask;             // 1 for fluid, 0 for boundary
-        bool act, fi;
-        int i;
+    // target: {o_x, o_y, o_z, own cell x}, {u, P}, {1/rho (0 for boundary),
+    // rho - rho0, |c|, -}
+    struct T {
+        float4 a, b, c;
+        __device__ bool fluid() const { return c.x > 0.f; }
     };
     struct Cand {
         float4 v0, v1;
@@ -171,12 +161,9 @@ struct Mixed {
         int cx;
         bool ok;
     };
-    // frame for the chunk bounding box: cell (cxa, cy, cz)
-    __device__ static Target target(const InteractArgs &a, int i, bool act, int rowbase, int cxa,
-                                    float &bx, float &by, float &bz) {
-        Target t{};
-        t.act = act;
-        t.i = i;
+    __device__ static void target(const InteractArgs &a, int i, bool act, int rowbase, int cxa,
+                                  V4 &t0, V4 &t1, V4 &t2, float &bx, float &by, float &bz,
+                                  bool &fi) {
         float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
         float2 v2 = make_float2(1.f, 1.f);
         int cix = cxa;
@@ -186,26 +173,14 @@ struct Mixed {
             v2 = static_cast<const float2 *>(a.v2)[i];
             cix = (int)a.keys[i] - rowbase;
         }
-        t.fi = act && v2.y > 0.f;
-        t.ox = v0.x;
-        t.oy = v0.y;
-        t.oz = v0.z;
-        t.dr = v0.w;
-        t.cixf = (float)cix;
-        t.ux = v1.x;
-        t.uy = v1.y;
-        t.uz = v1.z;
-        t.P = v1.w;
-        t.invr = t.fi ? v2.x : 0.f;
-        t.rsum = (float)(2.0 * a.rho0) + v0.w;
-        t.c = fabsf(v2.y);
-        t.nalpha = t.fi ? -(float)a.alpha : 0.f;
-        t.fmask = t.fi ? 1.f : 0.f;
+        fi = act && v2.y > 0.f;
+        t0 = make_float4(v0.x, v0.y, v0.z, (float)cix);
+        t1 = v1;
+        t2 = make_float4(fi ? v2.x : 0.f, v0.w, fabsf(v2.y), 0.f);
         const float csf = (float)a.cs;
         bx = v0.x + (float)(cix - cxa) * csf;
         by = v0.y;
         bz = v0.z;
-        return t;
     }
     __device__ static void load(const InteractArgs &a, int j, int je, int nbase, Cand &c) {
         c.ok = j < je;
@@ -221,7 +196,8 @@ struct Mixed {
             c.cx = 0;
         }
     }
-    // position of the candidate in the chunk frame, for culling only
+    // position of a candidate in the chunk frame (cell cxa of the chunk's
+    // row), for culling only
     __device__ static void cull_pos(const InteractArgs &a, const Cand &c, int cxa, int dy, int dz,
                                     float &qx, float &qy, float &qz) {
         const float csf = (float)a.cs;
@@ -229,7 +205,14 @@ struct Mixed {
         qy = c.v0.y + (float)dy * csf;
         qz = c.v0.z + (float)dz * csf;
     }
+    __device__ static void rec_pos(const InteractArgs &a, const float4 &r0, int cxa, float &qx,
+                                   float &qy, float &qz) {
+        qx = r0.x + (r0.y - (float)cxa) * (float)a.cs;
+        qy = r0.z;
+        qz = r0.w;
+    }
     __device__ static bool cand_fluid(const Cand &c) { return c.v2.y > 0.f; }
+    __device__ static bool rec_fluid(const float4 &r3) { return r3.y > 0.f; }
     // record: {o_x, c_x, o_y + dy cs, o_z + dz cs}, {u, P/rho}, {index bits,
     // 1/rho, (rho - rho0) B, B} with B = 2 delta h c0 / rho (0 when the pair
     // carries no delta term), {rho - rho0, +-c (- = boundary), -, -}
@@ -246,50 +229,58 @@ struct Mixed {
         *rec2 = make_float4(__int_as_float(j), invr, c.v0.w * B, B);
         *rec3 = make_float4(c.v0.w, c.v2.y, 0.f, 0.f);
     }
+    // one (target, record) pair; `valid` is false for idle lanes
     template <bool kStats>
-    __device__ static void pair(const InteractArgs &a, const Target &t, const float4 &r0,
-                                const float4 &r1, const float4 &r2, const float4 &r3,
-                                uint64_t fmask_bits, Acc<float> &acc, float &mum, Counters &cn) {
+    __device__ static void pair(const InteractArgs &a, const T &t, int ti, bool valid,
+                                const float4 &r0, const float4 &r1, const float4 &r2,
+                                const float4 &r3, Acc<float> &acc, Counters &cn, Stats &st) {
         const float csf = (float)a.cs;
-        const bool fj = uni(__float_as_int(r3.y)) > 0;  // record is wave-uniform
-        const float sx = fmaf(r0.y - t.cixf, csf, r0.x);
-        const float dx = sx - t.ox;
-        const float dy = r0.z - t.oy;
-        const float dz = r0.w - t.oz;
+        const bool fi = t.fluid();
+        const bool fj = r3.y > 0.f;
+        const float sx = fmaf(r0.y - t.a.w, csf, r0.x);
+        const float dx = sx - t.a.x;
+        const float dy = r0.z - t.a.y;
+        const float dz = r0.w - t.a.z;
         const float rr = sq_sum_f32(dx, dy, dz);
         const int j = __float_as_int(r2.x);
-        const bool in = t.act && rr < (float)a.r2max && j != t.i && (t.fi || fj);
+        const bool in = valid && rr < (float)a.r2max && j != ti && (fi || fj);
         const uint64_t inm = __ballot(in);
         if (inm == 0) return;
-        count_pairs(cn, inm, fmask_bits, fj);
+        const uint64_t fim = __ballot(fi);
+        const uint64_t fjm = __ballot(fj);
+        cn.ff += (uint32_t)__popcll(inm & fim & fjm);
+        cn.fb += (uint32_t)__popcll(inm & fim & ~fjm);
+        cn.bf += (uint32_t)__popcll(inm & ~fim & fjm);
         if (kStats && in) {
             if (fj)
-                ++cn.st_f;
+                ++st.f;
             else
-                ++cn.st_b;
-            cn.st_h += id_hash(a.id[j] & 0x7fffffffu);
+                ++st.b;
+            st.h += id_hash(a.id[j] & 0x7fffffffu);
         }
         const float r = __builtin_amdgcn_sqrtf(rr);
         const float q2 = fmaf(r, -0.5f * (float)a.invh, 1.f);  // 1 - q/2
         const float F = in ? (float)a.Fm * q2 * q2 * q2 : 0.f;   // m 5 w_D/h^2 (1-q/2)^3
-        const float vx = r1.x - t.ux, vy = r1.y - t.uy, vz = r1.z - t.uz;
+        const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const float vr = vx * dx + vy * dy + vz * dz;               // u_ij . r_ij
         const float mu = (float)a.h * vr * __builtin_amdgcn_rcpf(rr + (float)a.eta2);
-        mum = in ? fmaxf(mum, fabsf(mu)) : mum;
-        acc.dr -= F * vr;                                     // m (u_i - u_j) . grad_i W_ij
-        acc.dr += fmaf(-t.dr, r2.w, r2.z) * (F * t.fmask);    // delta term
-        const float visc = vr < 0.f ? t.nalpha * (t.c + fabsf(r3.y)) * mu *
-                                          __builtin_amdgcn_rcpf(t.rsum + r3.x)
-                                    : 0.f;
-        const float s = (fmaf(t.P, r2.y, r1.w) * t.invr + visc) * F;
+        acc.mu = in ? fmaxf(acc.mu, fabsf(mu)) : acc.mu;
+        acc.dr -= F * vr;                                    // m (u_i - u_j) . grad_i W_ij
+        const float Fd = fi ? F : 0.f;
+        acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;             // delta term
+        const float visc =
+            vr < 0.f ? -(float)a.alpha * (t.c.z + fabsf(r3.y)) * mu *
+                           __builtin_amdgcn_rcpf((float)(2.0 * a.rho0) + t.c.y + r3.x)
+                     : 0.f;
+        const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
         acc.az -= s * dz;
     }
-    __device__ static void store(const InteractArgs &a, int i, const Target &t, float ax, float ay,
+    __device__ static void store(const InteractArgs &a, int i, bool fi, float ax, float ay,
                                  float az, float dr, float mum, double &bound) {
         float fax = 0.f, fay = 0.f, faz = 0.f;
-        if (t.fi) {
+        if (fi) {
             fax = ax + (float)a.gx;
             fay = ay + (float)a.gy;
             faz = az + (float)a.gz;
@@ -300,7 +291,7 @@ struct Mixed {
         static_cast<float *>(a.drho)[i] = dr;
         static_cast<float *>(a.mumax)[i] = mum;
         bound = a.h / (a.c0 + (double)mum);
-        if (t.fi) {
+        if (fi) {
             const double am = sqrt((double)fax * fax + (double)fay * fay + (double)faz * faz);
             if (am > 0.0) bound = fmin(bound, sqrt(a.h / am));
         }
@@ -310,23 +301,21 @@ struct Mixed {
 struct Fp64 {
     using R = double;
     using V4 = double4;
-    struct Target {
-        double x, y, z, ux, uy, uz, P, invr, rho, c, nalpha, fmask;
-        bool act, fi;
-        int i;
+    // target: {x, y, z, -}, {u, P}, {1/rho (0 for boundary), rho, |c|, -}
+    struct T {
+        double4 a, b, c;
+        __device__ bool fluid() const { return c.x > 0.0; }
     };
     struct Cand {
         double4 v0, v1;
         double2 v2;
         bool ok;
     };
-    __device__ static Target target(const InteractArgs &a, int i, bool act, int rowbase, int cxa,
-                                    double &bx, double &by, double &bz) {
+    __device__ static void target(const InteractArgs &a, int i, bool act, int rowbase, int cxa,
+                                  V4 &t0, V4 &t1, V4 &t2, double &bx, double &by, double &bz,
+                                  bool &fi) {
         (void)rowbase;
         (void)cxa;
-        Target t{};
-        t.act = act;
-        t.i = i;
         double4 v0 = make_double4(0, 0, 0, 1), v1 = make_double4(0, 0, 0, 0);
         double2 v2 = make_double2(1, 1);
         if (act) {
@@ -334,23 +323,13 @@ struct Fp64 {
             v1 = static_cast<const double4 *>(a.v1)[i];
             v2 = static_cast<const double2 *>(a.v2)[i];
         }
-        t.fi = act && v2.y > 0.0;
-        t.x = v0.x;
-        t.y = v0.y;
-        t.z = v0.z;
-        t.rho = v0.w;
-        t.ux = v1.x;
-        t.uy = v1.y;
-        t.uz = v1.z;
-        t.P = v1.w;
-        t.invr = t.fi ? v2.x : 0.0;
-        t.c = fabs(v2.y);
-        t.nalpha = t.fi ? -a.alpha : 0.0;
-        t.fmask = t.fi ? 1.0 : 0.0;
+        fi = act && v2.y > 0.0;
+        t0 = make_double4(v0.x, v0.y, v0.z, 0.0);
+        t1 = v1;
+        t2 = make_double4(fi ? v2.x : 0.0, v0.w, fabs(v2.y), 0.0);
         bx = v0.x;
         by = v0.y;
         bz = v0.z;
-        return t;
     }
     __device__ static void load(const InteractArgs &a, int j, int je, int nbase, Cand &c) {
         (void)nbase;
@@ -375,58 +354,73 @@ struct Fp64 {
         qy = c.v0.y;
         qz = c.v0.z;
     }
+    __device__ static void rec_pos(const InteractArgs &a, const double4 &r0, int cxa, double &qx,
+                                   double &qy, double &qz) {
+        (void)a;
+        (void)cxa;
+        qx = r0.x;
+        qy = r0.y;
+        qz = r0.z;
+    }
     __device__ static bool cand_fluid(const Cand &c) { return c.v2.y > 0.0; }
-    // record: {x, y, z, index}, {u, P/rho}, {1/rho, B, rho, +-c}, unused
+    __device__ static bool rec_fluid(const double4 &r3) { return r3.y > 0.0; }
+    // record: {x, y, z, index}, {u, P/rho}, {1/rho, B, rho, -}, {-, +-c, -, -}
     __device__ static void stage(const InteractArgs &a, const Cand &c, int j, int dy, int dz,
                                  double4 *rec0, double4 *rec1, double4 *rec2, double4 *rec3) {
         (void)dy;
         (void)dz;
-        (void)rec3;
         const double invr = c.v2.x;
         const bool fj = c.v2.y > 0.0;
         const double B = (fj || a.delta_all) ? a.kdelta * invr : 0.0;
         *rec0 = make_double4(c.v0.x, c.v0.y, c.v0.z, (double)j);
         *rec1 = make_double4(c.v1.x, c.v1.y, c.v1.z, c.v1.w * invr);
-        *rec2 = make_double4(invr, B, c.v0.w, c.v2.y);
+        *rec2 = make_double4(invr, B, c.v0.w, 0.0);
+        *rec3 = make_double4(0.0, c.v2.y, 0.0, 0.0);
     }
     template <bool kStats>
-    __device__ static void pair(const InteractArgs &a, const Target &t, const double4 &r0,
-                                const double4 &r1, const double4 &r2, const double4 &r3,
-                                uint64_t fmask_bits, Acc<double> &acc, double &mum, Counters &cn) {
-        (void)r3;
-        const bool fj = uni(__double2hiint(r2.w)) > 0;  // record is wave-uniform
-        const double dx = r0.x - t.x, dy = r0.y - t.y, dz = r0.z - t.z;
+    __device__ static void pair(const InteractArgs &a, const T &t, int ti, bool valid,
+                                const double4 &r0, const double4 &r1, const double4 &r2,
+                                const double4 &r3, Acc<double> &acc, Counters &cn, Stats &st) {
+        const bool fi = t.fluid();
+        const bool fj = r3.y > 0.0;
+        const double dx = r0.x - t.a.x, dy = r0.y - t.a.y, dz = r0.z - t.a.z;
         const double rr = sq_sum_f64(dx, dy, dz);
         const int j = (int)r0.w;
-        const bool in = t.act && rr < a.r2max && j != t.i && (t.fi || fj);
+        const bool in = valid && rr < a.r2max && j != ti && (fi || fj);
         const uint64_t inm = __ballot(in);
         if (inm == 0) return;
-        count_pairs(cn, inm, fmask_bits, fj);
+        const uint64_t fim = __ballot(fi);
+        const uint64_t fjm = __ballot(fj);
+        cn.ff += (uint32_t)__popcll(inm & fim & fjm);
+        cn.fb += (uint32_t)__popcll(inm & fim & ~fjm);
+        cn.bf += (uint32_t)__popcll(inm & ~fim & fjm);
         if (kStats && in) {
             if (fj)
-                ++cn.st_f;
+                ++st.f;
             else
-                ++cn.st_b;
-            cn.st_h += id_hash(a.id[j] & 0x7fffffffu);
+                ++st.b;
+            st.h += id_hash(a.id[j] & 0x7fffffffu);
         }
         const double q2 = 1.0 - 0.5 * (sqrt(rr) * a.invh);
         const double F = in ? a.Fm * q2 * q2 * q2 : 0.0;
-        const double vx = r1.x - t.ux, vy = r1.y - t.uy, vz = r1.z - t.uz;
+        const double vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const double vr = vx * dx + vy * dy + vz * dz;
         const double mu = a.h * vr / (rr + a.eta2);
-        mum = in ? fmax(mum, fabs(mu)) : mum;
+        acc.mu = in ? fmax(acc.mu, fabs(mu)) : acc.mu;
         acc.dr -= F * vr;
-        acc.dr += (r2.z - t.rho) * r2.y * (F * t.fmask);
-        const double visc = vr < 0.0 ? t.nalpha * (t.c + fabs(r2.w)) * mu / (t.rho + r2.z) : 0.0;
-        const double s = (fma(t.P, r2.x, r1.w) * t.invr + visc) * F;
+        const double Fd = fi ? F : 0.0;
+        acc.dr += (r2.z - t.c.y) * r2.y * Fd;
+        const double visc =
+            vr < 0.0 ? -a.alpha * (t.c.z + fabs(r3.y)) * mu / (t.c.y + r2.z) : 0.0;
+        const double s = (fma(t.b.w, r2.x, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
         acc.az -= s * dz;
     }
-    __device__ static void store(const InteractArgs &a, int i, const Target &t, double ax,
-                                 double ay, double az, double dr, double mum, double &bound) {
+    __device__ static void store(const InteractArgs &a, int i, bool fi, double ax, double ay,
+                                 double az, double dr, double mum, double &bound) {
         double fax = 0, fay = 0, faz = 0;
-        if (t.fi) {
+        if (fi) {
             fax = ax + a.gx;
             fay = ay + a.gy;
             faz = az + a.gz;
@@ -437,7 +431,7 @@ struct Fp64 {
         static_cast<double *>(a.drho)[i] = dr;
         static_cast<double *>(a.mumax)[i] = mum;
         bound = a.h / (a.c0 + mum);
-        if (t.fi) {
+        if (fi) {
             const double am = sqrt(fax * fax + fay * fay + faz * faz);
             if (am > 0.0) bound = fmin(bound, sqrt(a.h / am));
         }
@@ -446,16 +440,27 @@ struct Fp64 {
 
 // ================================================================ skeleton
 
-template <class P, int kSplit, bool kStats>
+template <class P, int kSplit, int kT, bool kStats>
 __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     using R = typename P::R;
     using V4 = typename P::V4;
     constexpr int kRows = 9 / kSplit;
-    // per-wave staging; after its loop a wave reuses its own region for the
-    // cross-wave reduction (5 sums of R and 3 int32 per lane fit in 4 V4)
-    __shared__ V4 stg[kSplit][4][kWave];
+    constexpr int kG = kWave / kT;  // target groups per chunk = records per step
+    __shared__ V4 stg[kSplit][4][kWave];          // staged candidate records (per wave)
+    __shared__ V4 tgt[3][kWave];                  // the chunk's targets
+    __shared__ R gbox[kG][6];                     // group bounding boxes, chunk frame
+    __shared__ uint8_t glist[kSplit][kG][kWave];  // per group: staged records that reach it
     __shared__ int4 rows[kSplit][kRows];
+    // after its loop a wave reuses its own staging region for its per-target
+    // sums (5 values of R and 3 int32 per target fit in 4 V4 per lane)
     static_assert(sizeof(R) * 5 + 4 * 3 <= sizeof(V4) * 4, "reduction fits the staging region");
+    auto red = [&](int wave, int f, int idx) -> R & {
+        return reinterpret_cast<R *>(&stg[wave][0][0])[f * kWave + idx];
+    };
+    auto redi = [&](int wave, int f, int idx) -> int32_t & {
+        return reinterpret_cast<int32_t *>(reinterpret_cast<R *>(&stg[wave][0][0]) +
+                                           5 * kWave)[f * kWave + idx];
+    };
 
     const int w = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
@@ -464,20 +469,45 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     const int4 ch = a.chunks[chunk];
     const int cs0 = uni(ch.x), cs1 = uni(ch.y), row = uni(ch.z);
     const int cy = row % a.ny, cz = row / a.ny;
-    const int i = cs0 + lane;
-    const bool act = i < cs1;
+    const int ntgt = cs1 - cs0;
     const int rowbase = row * a.nx;
     const int cxa = uni((int)a.keys[cs0] - rowbase);
     const int cxb = uni((int)a.keys[cs1 - 1] - rowbase);
 
+    // targets (lane = target index in the chunk) and their group boxes
+    const int it = cs0 + lane;
+    const bool act = lane < ntgt;
     R bx, by, bz;
-    const typename P::Target t = P::target(a, i, act, rowbase, cxa, bx, by, bz);
+    bool fi_own;
+    {
+        V4 t0, t1, t2;
+        P::target(a, it, act, rowbase, cxa, t0, t1, t2, bx, by, bz, fi_own);
+        if (w == 0) {
+            tgt[0][lane] = t0;
+            tgt[1][lane] = t1;
+            tgt[2][lane] = t2;
+        }
+    }
     const R big = (R)3.0e38f;
-    const R lox = wave_min(act ? bx : big), hix = wave_max(act ? bx : -big);
-    const R loy = wave_min(act ? by : big), hiy = wave_max(act ? by : -big);
-    const R loz = wave_min(act ? bz : big), hiz = wave_max(act ? bz : -big);
-    const uint64_t fmask_bits = __ballot(t.fi);
-    const bool any_fluid = fmask_bits != 0ull;
+    {
+        const R lx = group_min(act ? bx : big, kT), hx = group_max(act ? bx : -big, kT);
+        const R ly = group_min(act ? by : big, kT), hy = group_max(act ? by : -big, kT);
+        const R lz = group_min(act ? bz : big, kT), hz = group_max(act ? bz : -big, kT);
+        if (w == 0 && lane % kT == 0) {
+            const int g = lane / kT;
+            gbox[g][0] = lx;
+            gbox[g][1] = hx;
+            gbox[g][2] = ly;
+            gbox[g][3] = hy;
+            gbox[g][4] = lz;
+            gbox[g][5] = hz;
+        }
+    }
+    const R lox = group_min(act ? bx : big, kWave), hix = group_max(act ? bx : -big, kWave);
+    const R loy = group_min(act ? by : big, kWave), hiy = group_max(act ? by : -big, kWave);
+    const R loz = group_min(act ? bz : big, kWave), hiz = group_max(act ? bz : -big, kWave);
+    const uint64_t fluid_tgts = __ballot(fi_own);
+    const bool any_fluid = fluid_tgts != 0ull;
     const R cull2 = (R)(a.r2max * (1.0 + 1e-3));
     const uint64_t below = lanes_below();
 
@@ -496,16 +526,20 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
         }
         rows[w][lane] = make_int4(js, je, nbase, (dy + 1) | ((dz + 1) << 2));
     }
-    wave_sync();
+    __syncthreads();  // targets, group boxes and rows are in LDS
 
     auto next_row = [&](int q) {
         while (q < kRows && rows[w][q].x >= rows[w][q].y) ++q;
         return q;
     };
 
-    Acc<R> sum;
-    R mum = 0;
+    // lane -> (target t of a group, record slot s)
+    const int t_in_g = lane % kT;
+    const int slot_s = lane / kT;
+    Acc<R> acc[kG];
+    Stats sts[kG];
     Counters cn;
+
     int q = uni(next_row(0));
     int jb = q < kRows ? uni(rows[w][q].x) : 0;
     typename P::Cand cur, nxt;
@@ -538,24 +572,50 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
         }
         wave_sync();
         const int cnt = __popcll(m);
-        Acc<R> b;  // this batch's partial sums
         if (cnt > 0) {
-            V4 n0 = stg[w][0][0], n1 = stg[w][1][0], n2 = stg[w][2][0], n3 = stg[w][3][0];
-            for (int k = 0; k < cnt; ++k) {
-                const V4 r0 = n0, r1 = n1, r2 = n2, r3 = n3;
-                if (k + 1 < cnt) {
-                    n0 = stg[w][0][k + 1];
-                    n1 = stg[w][1][k + 1];
-                    n2 = stg[w][2][k + 1];
-                    n3 = stg[w][3][k + 1];
+            // per group: the staged records that can reach the group's box
+            R px = 0, py = 0, pz = 0;
+            bool rf = false;
+            if (lane < cnt) {
+                const V4 r0 = stg[w][0][lane];
+                const V4 r3 = stg[w][3][lane];
+                P::rec_pos(a, r0, cxa, px, py, pz);
+                rf = P::rec_fluid(r3);
+            }
+            int gcnt[kG];
+#pragma unroll
+            for (int g = 0; g < kG; ++g) {
+                const uint64_t gbits = kT == 64 ? ~0ull : (((1ull << kT) - 1) << (g * kT));
+                const bool gf = (fluid_tgts & gbits) != 0ull;
+                const R ex = fmax(fmax(gbox[g][0] - px, px - gbox[g][1]), (R)0);
+                const R ey = fmax(fmax(gbox[g][2] - py, py - gbox[g][3]), (R)0);
+                const R ez = fmax(fmax(gbox[g][4] - pz, pz - gbox[g][5]), (R)0);
+                const bool k = lane < cnt && (ex * ex + ey * ey + ez * ez) <= cull2 && (gf || rf);
+                const uint64_t gm = __ballot(k);
+                if (k) glist[w][g][__popcll(gm & below)] = (uint8_t)lane;
+                gcnt[g] = __popcll(gm);
+            }
+            wave_sync();
+#pragma unroll
+            for (int g = 0; g < kG; ++g) {
+                if (gcnt[g] == 0) continue;
+                const int tidx = g * kT + t_in_g;
+                typename P::T tg;
+                tg.a = tgt[0][tidx];
+                tg.b = tgt[1][tidx];
+                tg.c = tgt[2][tidx];
+                const int ti = cs0 + tidx;
+                for (int s0 = 0; s0 < gcnt[g]; s0 += kG) {
+                    const int sl = s0 + slot_s;
+                    const bool valid = sl < gcnt[g] && tidx < ntgt;
+                    const int k = sl < gcnt[g] ? (int)glist[w][g][sl] : 0;
+                    const V4 r0 = stg[w][0][k], r1 = stg[w][1][k];
+                    const V4 r2 = stg[w][2][k], r3 = stg[w][3][k];
+                    P::template pair<kStats>(a, tg, ti, valid, r0, r1, r2, r3, acc[g], cn,
+                                             sts[g]);
                 }
-                P::template pair<kStats>(a, t, r0, r1, r2, r3, fmask_bits, b, mum, cn);
             }
         }
-        sum.ax += b.ax;
-        sum.ay += b.ay;
-        sum.az += b.az;
-        sum.dr += b.dr;
         wave_sync();
         cur = nxt;
         q = q2;
@@ -568,66 +628,92 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
         if (cn.fb) atomicAdd(&a.pairs[1], (unsigned long long)cn.fb);
         if (cn.bf) atomicAdd(&a.pairs[2], (unsigned long long)cn.bf);
     }
-    if constexpr (kSplit > 1) {
-        auto red = [&](int wave, int f) -> R & {
-            return reinterpret_cast<R *>(&stg[wave][0][0])[f * kWave + lane];
-        };
-        auto redi = [&](int wave, int f) -> int32_t & {
-            return reinterpret_cast<int32_t *>(reinterpret_cast<R *>(&stg[wave][0][0]) +
-                                               5 * kWave)[f * kWave + lane];
-        };
-        red(w, 0) = sum.ax;
-        red(w, 1) = sum.ay;
-        red(w, 2) = sum.az;
-        red(w, 3) = sum.dr;
-        red(w, 4) = mum;
-        if constexpr (kStats) {
-            redi(w, 0) = cn.st_f;
-            redi(w, 1) = cn.st_b;
-            redi(w, 2) = (int32_t)cn.st_h;
-        }
-        __syncthreads();
-        if (w != 0) return;
-        // fixed summation order over the waves
-        sum.ax = red(0, 0);
-        sum.ay = red(0, 1);
-        sum.az = red(0, 2);
-        sum.dr = red(0, 3);
-        mum = red(0, 4);
-        for (int k = 1; k < kSplit; ++k) {
-            sum.ax += red(k, 0);
-            sum.ay += red(k, 1);
-            sum.az += red(k, 2);
-            sum.dr += red(k, 3);
-            mum = red(k, 4) > mum ? red(k, 4) : mum;
+    // sum the kG lanes that share a target (fixed shuffle tree); each wave's
+    // per-target sums go to LDS
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+        for (int off = kT; off < kWave; off <<= 1) {
+            acc[g].ax += __shfl_xor(acc[g].ax, off, kWave);
+            acc[g].ay += __shfl_xor(acc[g].ay, off, kWave);
+            acc[g].az += __shfl_xor(acc[g].az, off, kWave);
+            acc[g].dr += __shfl_xor(acc[g].dr, off, kWave);
+            const R om = __shfl_xor(acc[g].mu, off, kWave);
+            acc[g].mu = om > acc[g].mu ? om : acc[g].mu;
             if constexpr (kStats) {
-                cn.st_f += redi(k, 0);
-                cn.st_b += redi(k, 1);
-                cn.st_h += (uint32_t)redi(k, 2);
+                sts[g].f += __shfl_xor(sts[g].f, off, kWave);
+                sts[g].b += __shfl_xor(sts[g].b, off, kWave);
+                sts[g].h += (uint32_t)__shfl_xor((int)sts[g].h, off, kWave);
             }
+        }
+        if (slot_s == 0) {
+            const int tidx = g * kT + t_in_g;
+            red(w, 0, tidx) = acc[g].ax;
+            red(w, 1, tidx) = acc[g].ay;
+            red(w, 2, tidx) = acc[g].az;
+            red(w, 3, tidx) = acc[g].dr;
+            red(w, 4, tidx) = acc[g].mu;
+            if constexpr (kStats) {
+                redi(w, 0, tidx) = sts[g].f;
+                redi(w, 1, tidx) = sts[g].b;
+                redi(w, 2, tidx) = (int32_t)sts[g].h;
+            }
+        }
+    }
+    __syncthreads();
+    if (w != 0) return;
+    // fixed summation order over the waves; lane = target index again
+    R sx = red(0, 0, lane), sy = red(0, 1, lane), sz = red(0, 2, lane);
+    R sd = red(0, 3, lane), sm = red(0, 4, lane);
+    int32_t nf = 0, nbd = 0;
+    uint32_t hs = 0;
+    if constexpr (kStats) {
+        nf = redi(0, 0, lane);
+        nbd = redi(0, 1, lane);
+        hs = (uint32_t)redi(0, 2, lane);
+    }
+    for (int k = 1; k < kSplit; ++k) {
+        sx += red(k, 0, lane);
+        sy += red(k, 1, lane);
+        sz += red(k, 2, lane);
+        sd += red(k, 3, lane);
+        sm = red(k, 4, lane) > sm ? red(k, 4, lane) : sm;
+        if constexpr (kStats) {
+            nf += redi(k, 0, lane);
+            nbd += redi(k, 1, lane);
+            hs += (uint32_t)redi(k, 2, lane);
         }
     }
     double bound = __longlong_as_double(0x7ff0000000000000ll);
     if (act) {
-        P::store(a, i, t, sum.ax, sum.ay, sum.az, sum.dr, mum, bound);
+        P::store(a, it, fi_own, sx, sy, sz, sd, sm, bound);
         if constexpr (kStats) {
-            a.st_nf[i] = cn.st_f;
-            a.st_nb[i] = cn.st_b;
-            a.st_hash[i] = cn.st_h;
+            a.st_nf[it] = nf;
+            a.st_nb[it] = nbd;
+            a.st_hash[it] = hs;
         }
     }
-    bound = wave_min(bound);
+    bound = group_min(bound, kWave);
     if (lane == 0) atomicMin(a.dt_min_bits, (unsigned long long)__double_as_longlong(bound));
 }
 
 // ================================================================ launch
 
-static int g_split[2] = {0, 0};  // 0 = automatic, else 1, 3 or 9 (per precision)
+// interaction launch shape per precision: waves per chunk and targets per
+// group (0 = automatic)
+static int g_split[2] = {0, 0};
+static int g_group[2] = {0, 0};
 
 int set_split(int precision, int split) {
     if (precision != SPH_FP64 && precision != SPH_MIXED) return -1;
     if (split != 0 && split != 1 && split != 3 && split != 9) return -1;
     g_split[precision] = split;
+    return 0;
+}
+
+int set_group(int precision, int group) {
+    if (precision != SPH_FP64 && precision != SPH_MIXED) return -1;
+    if (group != 0 && group != 8 && group != 16 && group != 64) return -1;
+    g_group[precision] = group;
     return 0;
 }
 
@@ -640,17 +726,42 @@ int split_for(const sph_params &p, int64_t max_chunks) {
     return 1;
 }
 
-template <class P, bool kStats>
-static void launch_split(int split, uint32_t nb, const InteractArgs &a, hipStream_t st) {
-    switch (split) {
-    case 9:
-        hipLaunchKernelGGL((k_interact<P, 9, kStats>), dim3(nb), dim3(kWave * 9), 0, st, a);
+int group_for(const sph_params &p) {
+    const int pr = p.precision == SPH_MIXED ? SPH_MIXED : SPH_FP64;
+    if (g_group[pr]) return g_group[pr];
+    return pr == SPH_MIXED ? 8 : 16;
+}
+
+template <class P, int kSplit, bool kStats>
+static void launch_group(int group, uint32_t nb, const InteractArgs &a, hipStream_t st) {
+    switch (group) {
+    case 8:
+        hipLaunchKernelGGL((k_interact<P, kSplit, 8, kStats>), dim3(nb), dim3(kWave * kSplit), 0,
+                           st, a);
         break;
-    case 3:
-        hipLaunchKernelGGL((k_interact<P, 3, kStats>), dim3(nb), dim3(kWave * 3), 0, st, a);
+    case 16:
+        hipLaunchKernelGGL((k_interact<P, kSplit, 16, kStats>), dim3(nb), dim3(kWave * kSplit), 0,
+                           st, a);
         break;
     default:
-        hipLaunchKernelGGL((k_interact<P, 1, kStats>), dim3(nb), dim3(kWave), 0, st, a);
+        hipLaunchKernelGGL((k_interact<P, kSplit, 64, kStats>), dim3(nb), dim3(kWave * kSplit), 0,
+                           st, a);
+        break;
+    }
+}
+
+template <class P, bool kStats>
+static void launch_shape(int split, int group, uint32_t nb, const InteractArgs &a,
+                         hipStream_t st) {
+    switch (split) {
+    case 9:
+        launch_group<P, 9, kStats>(group, nb, a, st);
+        break;
+    case 3:
+        launch_group<P, 3, kStats>(group, nb, a, st);
+        break;
+    default:
+        launch_group<P, 1, kStats>(group, nb, a, st);
         break;
     }
 }
@@ -701,16 +812,17 @@ int launch_interact(const sph_params &p, const sph_state &s, const Ws &w, hipStr
     a.gz = p.g[2];
     a.delta_all = p.delta_pairs == SPH_DELTA_ALL;
     const int split = split_for(p, w.L.max_chunks);
+    const int group = group_for(p);
     if (p.precision == SPH_MIXED) {
         if (stats)
-            launch_split<Mixed, true>(split, nb, a, st);
+            launch_shape<Mixed, true>(split, group, nb, a, st);
         else
-            launch_split<Mixed, false>(split, nb, a, st);
+            launch_shape<Mixed, false>(split, group, nb, a, st);
     } else {
         if (stats)
-            launch_split<Fp64, true>(split, nb, a, st);
+            launch_shape<Fp64, true>(split, group, nb, a, st);
         else
-            launch_split<Fp64, false>(split, nb, a, st);
+            launch_shape<Fp64, false>(split, group, nb, a, st);
     }
     return launch_check("interact");
 }

@@ -47,7 +47,8 @@ _P = C.c_void_p
 
 class SphTuning(C.Structure):
     _fields_ = [("split_fp64", C.c_int32), ("split_mixed", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("group_fp64", C.c_int32), ("group_mixed", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class SphState(C.Structure):
@@ -100,7 +101,7 @@ def load(path: str = LIB_PATH):
     L.sph_last_error.restype = C.c_char_p
     L.sph_check_params.argtypes = [PP]
     L.sph_set_tuning.argtypes = [C.POINTER(SphTuning)]
-    L.sph_get_split.argtypes = [PP, C.c_int64, C.POINTER(C.c_int32)]
+    L.sph_get_split.argtypes = [PP, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.sph_workspace_bytes.argtypes = [PP, C.c_int64, C.POINTER(C.c_size_t)]
     L.sph_workspace_init.argtypes = [PP, C.c_int64, _P, C.c_size_t, _P]
     L.sph_set_density.argtypes = [PP, PS, _P, C.c_int32, _P]
@@ -123,18 +124,23 @@ def check(rc: int) -> None:
         raise SphError(rc, load().sph_last_error().decode())
 
 
-def set_tuning(split_fp64: int = 0, split_mixed: int = 0) -> None:
+def set_tuning(split_fp64: int = 0, split_mixed: int = 0, group_fp64: int = 0,
+               group_mixed: int = 0) -> None:
     """Process-wide interaction launch shape (0 = the library's choice)."""
     t = SphTuning()
     t.split_fp64 = int(split_fp64)
     t.split_mixed = int(split_mixed)
+    t.group_fp64 = int(group_fp64)
+    t.group_mixed = int(group_mixed)
     check(load().sph_set_tuning(C.byref(t)))
 
 
-def get_split(params: "SphParams", n: int) -> int:
+def get_split(params: "SphParams", n: int):
+    """(waves per chunk, targets per group) the library will launch."""
     v = C.c_int32(0)
-    check(load().sph_get_split(C.byref(params), int(n), C.byref(v)))
-    return int(v.value)
+    g = C.c_int32(0)
+    check(load().sph_get_split(C.byref(params), int(n), C.byref(v), C.byref(g)))
+    return int(v.value), int(g.value)
 
 
 def make_params(prm: Dict[str, object], precision: str = "mixed", *,

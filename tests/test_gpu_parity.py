@@ -278,9 +278,10 @@ def test_hydrostatic_column(gpu, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_every_split_matches(gpu, oracle_lib, developed, precision):
-    """The launch shapes the autotuner may pick (1, 3 or 9 waves per chunk)
-    give bit-identical neighbour sets and oracle-parity rates."""
+def test_every_launch_shape_matches(gpu, oracle_lib, developed, precision):
+    """Every launch shape the autotuner may pick (1, 3 or 9 waves per chunk
+    x 8, 16 or 64 targets per group) gives bit-identical neighbour sets and
+    oracle-parity rates."""
     params, st = developed
     sc, prev = scene_from_oracle(st, params)
     ref = _oracle_rates(oracle_lib, params, st)
@@ -288,18 +289,19 @@ def test_every_split_matches(gpu, oracle_lib, developed, precision):
     stats = []
     try:
         for split in (1, 3, 9):
-            if precision == "fp64":
-                gpu.set_tuning(split_fp64=split)
-            else:
-                gpu.set_tuning(split_mixed=split)
-            sim = _sim(gpu, sc, precision, prev)
-            assert gpu.get_split(sim.params, sim.n) == split
-            got = sim.rates_by_id()
-            for k in range(4):
-                assert rel_l2(got[k], ref[k]) < tol, (split, k)
-            stats.append(sim.neighbour_stats())
+            for group in (8, 16, 64):
+                if precision == "fp64":
+                    gpu.set_tuning(split_fp64=split, group_fp64=group)
+                else:
+                    gpu.set_tuning(split_mixed=split, group_mixed=group)
+                sim = _sim(gpu, sc, precision, prev)
+                assert gpu.get_split(sim.params, sim.n) == (split, group)
+                got = sim.rates_by_id()
+                for k in range(4):
+                    assert rel_l2(got[k], ref[k]) < tol, (split, group, k)
+                stats.append(sim.neighbour_stats())
     finally:
-        gpu.set_tuning(0, 0)
+        gpu.set_tuning()
     for s_ in stats[1:]:
         for a_, b_ in zip(s_, stats[0]):
             assert np.array_equal(a_, b_)
