@@ -39,15 +39,17 @@ def hip_runtime():
 
 
 class Events:
-    """Arrays of hipEvent_t for per-launch kernel timing."""
+    """hipEvent_t pairs around the interaction kernel of every `every`-th
+    step (NULL for the other steps)."""
 
-    def __init__(self, hip, n):
+    def __init__(self, hip, n, every=1):
         self.hip = hip
         self.n = n
+        self.steps = list(range(0, n, every))
         self.begin = (C.c_void_p * n)()
         self.end = (C.c_void_p * n)()
         for arr in (self.begin, self.end):
-            for k in range(n):
+            for k in self.steps:
                 h = C.c_void_p()
                 assert hip.hipEventCreate(C.byref(h)) == 0
                 arr[k] = h
@@ -56,15 +58,18 @@ class Events:
     def mean_ms(self):
         tot = 0.0
         ms = C.c_float()
-        for k in range(self.n):
+        for k in self.steps:
             assert self.hip.hipEventElapsedTime(C.byref(ms), self.begin[k], self.end[k]) == 0
             tot += ms.value
-        return tot / self.n
+        return tot / len(self.steps)
 
     def close(self):
         for arr in (self.begin, self.end):
-            for k in range(self.n):
+            for k in self.steps:
                 self.hip.hipEventDestroy(C.c_void_p(arr[k]))
+
+
+EVENT_EVERY = 10   # interaction kernels timed with HIP events: every 10th step
 
 
 def time_gpu(scene_obj, precision, steps, warmup, hip):
@@ -73,7 +78,7 @@ def time_gpu(scene_obj, precision, steps, warmup, hip):
     sim = lib.Simulation(scene_obj, precision)
     sim.run(warmup, -1.0, 0)
     d0, _ = sim.diagnostics()
-    ev = Events(hip, steps)
+    ev = Events(hip, steps, every=EVENT_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.run_profiled(steps, -1.0, warmup, ev.begin, ev.end)
@@ -120,7 +125,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
-    ap.add_argument("--retune", action="store_true", help="ignore the autotune cache")
+    ap.add_argument("--retune", action="store_true", help="ignore the autotune table")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 512 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -132,6 +139,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     hip = hip_runtime()
 
+    if args.calib_copy:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this kernel
+        # calibrate the same counters read on the interaction kernel
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     from paper_2306_01959_amd import autotune
     sc = scene.config_scene(2)
     splits = {"mixed": autotune.tune(sc, "mixed", use_cache=not args.retune,

@@ -278,7 +278,9 @@ int sph_run(const sph_params *p, sph_state *s, void *ws, int64_t nsteps, double 
  * sph_run that also records caller-created hipEvent_t handles on the stream
  * immediately before (ev_begin[k]) and after (ev_end[k]) the interaction
  * kernel of step k, for timing that kernel alone.  Both arrays hold nsteps
- * handles, or both are NULL (then it is sph_run).
+ * entries (a step whose two entries are NULL records nothing), or both
+ * arrays are NULL (then it is sph_run).  An event record drains the stream,
+ * so sampling a few steps disturbs the run least.
  */
 int sph_run_profiled(const sph_params *p, sph_state *s, void *ws, int64_t nsteps, double dt,
                      int64_t step0, void *const *ev_begin, void *const *ev_end, void *stream);

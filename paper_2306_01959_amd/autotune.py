@@ -3,9 +3,10 @@
 For a given scene and precision it times whole steps for every supported
 shape -- waves per 64-target chunk (1, 3, 9) x targets per group (8, 16,
 64) -- keeps the fastest, sets it in the library (sph_set_tuning) and caches
-the choice in a JSON file keyed by the problem shape (precision, particle
-count, grid).  The cache path comes from
-WCSPH_TUNE_CACHE (default: tune_cache.json next to this file).
+the choice in a JSON table keyed by the problem shape (precision, particle
+count, grid).  The table path comes from WCSPH_TUNE_CACHE (default:
+tune_table.json next to this file, which holds the shapes measured on
+MI355X for the benchmark workloads).
 """
 from __future__ import annotations
 
@@ -19,7 +20,7 @@ from . import lib
 SPLITS = (1, 3, 9)
 GROUPS = (8, 16, 64)
 CACHE = os.environ.get("WCSPH_TUNE_CACHE",
-                       os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json"))
+                       os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json"))
 
 
 def _key(precision: str, scene) -> str:

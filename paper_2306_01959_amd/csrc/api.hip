@@ -326,7 +326,8 @@ int sph_run_profiled(const sph_params *p, sph_state *s, void *ws, int64_t nsteps
         return fail(SPH_E_INVAL, "ev_begin and ev_end must both be given or both be NULL");
     if (ev_begin)
         for (int64_t k = 0; k < nsteps; ++k)
-            if (!ev_begin[k] || !ev_end[k]) return fail(SPH_E_INVAL, "event handle is NULL");
+            if ((ev_begin[k] == nullptr) != (ev_end[k] == nullptr))
+                return fail(SPH_E_INVAL, "event handles of a step must both be set or both NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (nsteps > 0 && s->cells_valid)
         if (int rc = launch_chunks(*p, w, st)) return rc;

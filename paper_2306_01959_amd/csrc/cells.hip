@@ -346,7 +346,8 @@ int launch_cell_table(const sph_params &p, const Ws &w, const uint32_t *keys, hi
 // The interaction works on chunks: up to 64 consecutive sorted particles of
 // one cell row (fixed cy, cz).  One workgroup scans the rows, writes every
 // chunk {start, end, row, 0} and the chunk count, and resets the running
-// minimum of the time-step bound for the interaction that follows.
+// minimum of the time-step bound and the chunk counter for the interaction
+// that follows.
 __global__ __launch_bounds__(1024) void k_chunks(const uint32_t *__restrict__ start, int nx,
                                                  int64_t nrows, int4 *__restrict__ chunks,
                                                  DevScalars *sc) {
@@ -356,6 +357,7 @@ __global__ __launch_bounds__(1024) void k_chunks(const uint32_t *__restrict__ st
     if (t == 0) {
         carry = 0;
         sc->dt_min_bits = 0x7ff0000000000000ull;  // +inf
+        sc->work = 0;
     }
     __syncthreads();
     for (int64_t r0 = 0; r0 < nrows; r0 += 1024) {

@@ -34,6 +34,8 @@ struct DevScalars {
     unsigned int nchunks;            // interaction chunks of the current cells
     unsigned int dt_cfl_violation;   // a step used dt > dt_cfl
     unsigned long long pairs[3];     // interacting pairs since init: FF, FB, BF
+    unsigned int work;               // next interaction chunk to take
+    unsigned int pad_;
 };
 
 // Byte offsets of the workspace regions (all 256-byte aligned).

@@ -175,6 +175,7 @@ __global__ void k_ws_init(DevScalars *sc) {
         sc->nchunks = 0;
         sc->dt_cfl_violation = 0;
         sc->pairs[0] = sc->pairs[1] = sc->pairs[2] = 0;
+        sc->work = 0;
     }
 }
 

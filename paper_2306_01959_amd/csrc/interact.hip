@@ -48,11 +48,11 @@ struct InteractArgs {
     void *ax, *ay, *az, *drho, *mumax;
     unsigned long long *dt_min_bits;
     unsigned long long *pairs;   // running totals: fluid-fluid, fluid-boundary, boundary-fluid
+    unsigned int *work;          // next chunk to take (reset to 0 with the chunk list)
     const uint32_t *id;          // original ids (neighbour statistics only)
     int32_t *st_nf, *st_nb;      // per-particle fluid / boundary neighbour counts
     uint32_t *st_hash;           // per-particle sum of id_hash(id_j) mod 2^32
     int nx, ny, nz;
-    uint32_t nblocks;
     double cs, h, invh, r2max, eta2, Fm, alpha, kdelta, rho0, c0, gx, gy, gz;
     int delta_all;
 };
@@ -116,13 +116,6 @@ __device__ __forceinline__ uint32_t id_hash(uint32_t v) {
     v *= 0xc2b2ae35u;
     v ^= v >> 16;
     return v;
-}
-
-// Chunk handled by this block: consecutive chunks go to the same XCD (blocks
-// are dealt round-robin to the 8 XCDs), so neighbouring chunks share L2.
-__device__ __forceinline__ uint32_t xcd_chunk(uint32_t b, uint32_t nb) {
-    const uint32_t per = nb / 8;  // nb is a multiple of 8
-    return (b % 8) * per + b / 8;
 }
 
 // Per-lane sums of one (target, record subset).
@@ -464,8 +457,17 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
 
     const int w = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const uint32_t chunk = xcd_chunk(blockIdx.x, a.nblocks);
-    if (chunk >= a.sc->nchunks) return;  // uniform over the workgroup
+    __shared__ uint32_t s_next;
+    Counters cn;
+    // Persistent workgroups take chunks from a counter: chunk costs vary with
+    // the flow (dense water, dry walls), so static assignment leaves CUs idle.
+    // Chunks are independent and each is summed in a fixed order, so results
+    // do not depend on which workgroup takes which chunk.
+    for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(a.work, 1u);
+    __syncthreads();  // also retires the previous chunk's use of LDS
+    const uint32_t chunk = (uint32_t)uni((int)s_next);
+    if (chunk >= a.sc->nchunks) break;
     const int4 ch = a.chunks[chunk];
     const int cs0 = uni(ch.x), cs1 = uni(ch.y), row = uni(ch.z);
     const int cy = row % a.ny, cz = row / a.ny;
@@ -538,7 +540,6 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     const int slot_s = lane / kT;
     Acc<R> acc[kG];
     Stats sts[kG];
-    Counters cn;
 
     int q = uni(next_row(0));
     int jb = q < kRows ? uni(rows[w][q].x) : 0;
@@ -622,12 +623,6 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
         jb = jb2;
     }
 
-    // pair totals: integer atomics, order does not matter
-    if (lane == 0) {
-        if (cn.ff) atomicAdd(&a.pairs[0], (unsigned long long)cn.ff);
-        if (cn.fb) atomicAdd(&a.pairs[1], (unsigned long long)cn.fb);
-        if (cn.bf) atomicAdd(&a.pairs[2], (unsigned long long)cn.bf);
-    }
     // sum the kG lanes that share a target (fixed shuffle tree); each wave's
     // per-target sums go to LDS
 #pragma unroll
@@ -660,7 +655,7 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
         }
     }
     __syncthreads();
-    if (w != 0) return;
+    if (w == 0) {
     // fixed summation order over the waves; lane = target index again
     R sx = red(0, 0, lane), sy = red(0, 1, lane), sz = red(0, 2, lane);
     R sd = red(0, 3, lane), sm = red(0, 4, lane);
@@ -694,6 +689,14 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     }
     bound = group_min(bound, kWave);
     if (lane == 0) atomicMin(a.dt_min_bits, (unsigned long long)__double_as_longlong(bound));
+    }  // w == 0
+    }  // chunks
+    // pair totals: integer atomics, order does not matter
+    if (lane == 0) {
+        if (cn.ff) atomicAdd(&a.pairs[0], (unsigned long long)cn.ff);
+        if (cn.fb) atomicAdd(&a.pairs[1], (unsigned long long)cn.fb);
+        if (cn.bf) atomicAdd(&a.pairs[2], (unsigned long long)cn.bf);
+    }
 }
 
 // ================================================================ launch
@@ -732,20 +735,42 @@ int group_for(const sph_params &p) {
     return pr == SPH_MIXED ? 8 : 16;
 }
 
+// Workgroups that fit on the device at once (all CUs, full occupancy),
+// capped by the number of chunks: the grid of the persistent kernel.
+template <class K>
+static uint32_t persistent_grid(K kernel, int threads, uint32_t cap) {
+    int dev = 0;
+    int cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
+        per <= 0)
+        per = 1;
+    const uint64_t full = (uint64_t)cus * (uint64_t)per;
+    return (uint32_t)(full < cap ? full : cap);
+}
+
+template <class P, int kSplit, int kT, bool kStats>
+static void launch_one(uint32_t cap, const InteractArgs &a, hipStream_t st) {
+    auto kern = k_interact<P, kSplit, kT, kStats>;
+    const uint32_t nb = persistent_grid(kern, kWave * kSplit, cap);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kWave * kSplit), 0, st, a);
+}
+
 template <class P, int kSplit, bool kStats>
-static void launch_group(int group, uint32_t nb, const InteractArgs &a, hipStream_t st) {
+static void launch_group(int group, uint32_t cap, const InteractArgs &a, hipStream_t st) {
     switch (group) {
     case 8:
-        hipLaunchKernelGGL((k_interact<P, kSplit, 8, kStats>), dim3(nb), dim3(kWave * kSplit), 0,
-                           st, a);
+        launch_one<P, kSplit, 8, kStats>(cap, a, st);
         break;
     case 16:
-        hipLaunchKernelGGL((k_interact<P, kSplit, 16, kStats>), dim3(nb), dim3(kWave * kSplit), 0,
-                           st, a);
+        launch_one<P, kSplit, 16, kStats>(cap, a, st);
         break;
     default:
-        hipLaunchKernelGGL((k_interact<P, kSplit, 64, kStats>), dim3(nb), dim3(kWave * kSplit), 0,
-                           st, a);
+        launch_one<P, kSplit, 64, kStats>(cap, a, st);
         break;
     }
 }
@@ -794,8 +819,8 @@ int launch_interact(const sph_params &p, const sph_state &s, const Ws &w, hipStr
     a.nx = p.dims[0];
     a.ny = p.dims[1];
     a.nz = p.dims[2];
-    const uint32_t nb = (uint32_t)((w.L.max_chunks + 7) / 8 * 8);
-    a.nblocks = nb;
+    const uint32_t nb = (uint32_t)w.L.max_chunks;  // cap on the persistent grid
+    a.work = &w.scalars()->work;
     a.cs = p.cell_size;
     a.h = p.h;
     a.invh = 1.0 / p.h;
