@@ -274,16 +274,25 @@ int sph_step(const sph_params *p, sph_state *s, void *ws, double dt, int64_t ste
 int sph_run(const sph_params *p, sph_state *s, void *ws, int64_t nsteps, double dt,
             int64_t step0, void *stream);
 
+/* Regions of a step that sph_run_profiled can bracket with events. */
+typedef enum {
+    SPH_REGION_INTERACT = 0, /* the interaction kernel */
+    SPH_REGION_SORT = 1,     /* all passes of the radix sort */
+    SPH_REGION_REORDER = 2,  /* the gather into cell order (+ interaction view) */
+    SPH_REGION_STEP = 3      /* the whole step */
+} sph_region;
+
 /*
  * sph_run that also records caller-created hipEvent_t handles on the stream
- * immediately before (ev_begin[k]) and after (ev_end[k]) the interaction
- * kernel of step k, for timing that kernel alone.  Both arrays hold nsteps
+ * immediately before (ev_begin[k]) and after (ev_end[k]) one region of step
+ * k (sph_region), for timing that region alone.  Both arrays hold nsteps
  * entries (a step whose two entries are NULL records nothing), or both
  * arrays are NULL (then it is sph_run).  An event record drains the stream,
  * so sampling a few steps disturbs the run least.
  */
 int sph_run_profiled(const sph_params *p, sph_state *s, void *ws, int64_t nsteps, double dt,
-                     int64_t step0, void *const *ev_begin, void *const *ev_end, void *stream);
+                     int64_t step0, int32_t region, void *const *ev_begin, void *const *ev_end,
+                     void *stream);
 
 /*
  * FP64 global diagnostics of the current state and Shepard-filtered probe
@@ -295,6 +304,92 @@ int sph_run_profiled(const sph_params *p, sph_state *s, void *ws, int64_t nsteps
  */
 int sph_diagnostics(const sph_params *p, const sph_state *s, void *ws, const double *probes_xyz,
                     int32_t np, sph_diag *out, double *probe_p, void *stream);
+
+/* ======================================================================
+ * Batches: an ensemble of independent systems advanced together, as in the
+ * paper's artificial-viscosity study (Section 4: several alpha values on one
+ * dam break) and its resolution study (several l0).  Every instance has its
+ * own sph_params (grid, dp, h, mass, alpha, c0, ...), its own time step and
+ * clock; particles of different instances never interact.  One cell hash,
+ * one sort, one reorder, one interaction launch and one update per step
+ * serve all instances: each instance's cells follow the previous instance's
+ * in one global numbering.
+ *
+ * Particles: one sph_state holds all of them.  Instance k owns the original
+ * ids [o_k, o_k + counts[k]) with o_k = counts[0] + ... + counts[k-1]; the
+ * particles may come in any order (id bits 0..30 name the instance, bit 31
+ * marks boundary particles as for a single system).
+ */
+#define SPH_MAX_INSTANCES 4096
+
+typedef struct sph_batch {
+    int32_t ninst;             /* 1 .. SPH_MAX_INSTANCES */
+    int32_t reserved;          /* must be 0 */
+    const sph_params *params;  /* host array of ninst; one precision for all */
+    const int64_t *counts;     /* host array of ninst particle counts (>= 1) */
+} sph_batch;
+
+/* Run modes (bit flags) of sph_batch_run. */
+#define SPH_RUN_LAGGED 1 /* step n > 0 takes dt = Cr x the bound of step n-1
+                            (eq. sphdt one step late; step 0 its own bound), so
+                            the interaction kernel advances each particle as
+                            soon as its sums are complete: one fused kernel
+                            instead of interaction + update */
+#define SPH_RUN_GRAPH 2  /* capture a period of steps (lcm of 4 and every
+                            N_s, at most 400) in a HIP graph and replay it;
+                            the stream must not be NULL; the call then
+                            synchronises the stream before it returns */
+
+/* Workspace bytes of a batch; SPH_E_RANGE if the sums of particles or cells
+ * reach 2^31. */
+int sph_batch_workspace_bytes(const sph_batch *b, size_t *bytes);
+
+/*
+ * Prepare a batch workspace: uploads the instance table (so the host arrays
+ * of b may be freed on return) and clears every instance's clock.  Every
+ * later sph_batch_* call on this workspace must pass the same batch
+ * description; it is re-validated host-side on every call.  Synchronises
+ * the stream.
+ */
+int sph_batch_workspace_init(const sph_batch *b, void *ws, size_t ws_bytes, void *stream);
+
+/* Density conversion of a batch (see sph_set_density): each particle uses
+ * its instance's rho0.  Requires an initialised workspace. */
+int sph_batch_set_density(const sph_batch *b, sph_state *s, void *ws, const double *rho,
+                          int32_t which, void *stream);
+int sph_batch_get_density(const sph_batch *b, const sph_state *s, void *ws, double *rho,
+                          int32_t which, void *stream);
+
+/* sph_build_cells / sph_interact for a whole batch (same outputs, all n). */
+int sph_batch_build_cells(const sph_batch *b, sph_state *s, void *ws, void *stream);
+int sph_batch_interact(const sph_batch *b, const sph_state *s, void *ws, double *ax, double *ay,
+                       double *az, double *drho, double *mumax, void *stream);
+
+/*
+ * nsteps steps of every instance (step indices step0 ..), dt > 0 for all
+ * instances or dt <= 0 for each instance's own bound (eq. sphdt).  mode = 0
+ * gives exactly sph_run on every instance; SPH_RUN_LAGGED and SPH_RUN_GRAPH
+ * as above.  With SPH_RUN_LAGGED a step n > 0 needs the bound of an earlier
+ * interaction on this workspace: without one that step takes dt = 0 and
+ * raises SPH_FLAG_DT_CFL.
+ */
+int sph_batch_run(const sph_batch *b, sph_state *s, void *ws, int64_t nsteps, double dt,
+                  int64_t step0, int32_t mode, void *stream);
+
+/* sph_batch_run (no SPH_RUN_GRAPH) with events around one region, as
+ * sph_run_profiled. */
+int sph_batch_run_profiled(const sph_batch *b, sph_state *s, void *ws, int64_t nsteps, double dt,
+                           int64_t step0, int32_t mode, int32_t region, void *const *ev_begin,
+                           void *const *ev_end, void *stream);
+
+/*
+ * Per-instance diagnostics (see sph_diagnostics, without probes): out holds
+ * ninst results.  Sums run over each instance's own particles; steps, the
+ * pair counters and the CFL flag are totals of the batch.  Requires current
+ * cells; synchronises the stream.
+ */
+int sph_batch_diagnostics(const sph_batch *b, const sph_state *s, void *ws, sph_diag *out,
+                          void *stream);
 
 #ifdef __cplusplus
 }

@@ -28,19 +28,21 @@ int launch_check(const char *what) { return hip_check(hipGetLastError(), what); 
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-WsLayout make_layout(const sph_params &p, int64_t n) {
+WsLayout make_layout(const Problem &P) {
     WsLayout L;
+    const int64_t n = P.n;
     L.n = n;
-    L.precision = p.precision;
-    L.ncells = (int64_t)p.dims[0] * p.dims[1] * p.dims[2];
-    L.nrows = (int64_t)p.dims[1] * p.dims[2];
+    L.precision = P.precision;
+    L.ninst = (int32_t)P.host.size();
+    L.ncells = P.ncells;
+    L.nrows = P.nrows;
     L.ntiles = (n + kSortTile - 1) / kSortTile;
     L.max_chunks = (n + kChunk - 1) / kChunk + L.nrows;
     int bits = 0;
     while (bits < 32 && ((int64_t)1 << bits) < L.ncells) ++bits;
     L.key_bits = bits;
     const int passes = bits <= 0 ? 1 : (bits + kRadixBits - 1) / kRadixBits;
-    const bool mixed = p.precision == SPH_MIXED;
+    const bool mixed = P.precision == SPH_MIXED;
     L.view_elem = mixed ? 16 : 32;
     L.rate_elem = mixed ? 4 : 8;
     size_t off = 0;
@@ -62,10 +64,70 @@ WsLayout make_layout(const sph_params &p, int64_t n) {
     L.view2 = take((mixed ? 8 : 16) * (size_t)n);
     L.rates = take(5 * L.rate_elem * (size_t)n);
     L.scalars = take(sizeof(DevScalars));
-    L.diag_part = take(sizeof(double) * ((size_t)kDiagBlocks * kDiagFields + kDiagFields +
-                                         4 * (size_t)kMaxProbes));
+    L.inst_tab = take(sizeof(Inst) * (size_t)L.ninst);
+    L.inst_state = take(sizeof(InstState) * (size_t)L.ninst);
+    L.diag_part = take(sizeof(double) * ((size_t)L.ninst * diag_blocks(L.ninst) * kDiagFields +
+                                         (size_t)L.ninst * kDiagFields + 4 * (size_t)kMaxProbes));
     L.total = off;
     return L;
+}
+
+Insts insts_of(const Problem &P, const Ws &w) {
+    Insts I;
+    I.n = (int)P.host.size();
+    I.one = P.host[0];
+    I.tab = P.batch ? w.inst_tab() : nullptr;
+    return I;
+}
+
+// Constants of one system occupying global cells from cell_base, rows from
+// row_base and original ids [pstart, pend).
+static Inst inst_from(const sph_params &p, uint32_t cell_base, uint32_t row_base,
+                      uint32_t pstart, uint32_t pend) {
+    Inst I{};
+    I.ox = p.origin[0];
+    I.oy = p.origin[1];
+    I.oz = p.origin[2];
+    I.cs = p.cell_size;
+    I.h = p.h;
+    I.invh = 1.0 / p.h;
+    I.r2max = 4.0 * p.h * p.h;
+    I.eta2 = p.eta2_coef * p.h * p.h;
+    I.wd = 21.0 / (16.0 * M_PI * p.h * p.h * p.h);
+    I.Fm = p.mass * 5.0 * I.wd / (p.h * p.h);
+    I.alpha = p.alpha;
+    I.kdelta = 2.0 * p.delta * p.h * p.c0;
+    I.rho0 = p.rho0;
+    I.c0 = p.c0;
+    I.B = p.rho0 * p.c0 * p.c0 / p.gamma;
+    I.gamma = p.gamma;
+    I.gx = p.g[0];
+    I.gy = p.g[1];
+    I.gz = p.g[2];
+    I.cfl = p.cfl;
+    I.mass = p.mass;
+    I.nx = p.dims[0];
+    I.ny = p.dims[1];
+    I.nz = p.dims[2];
+    I.c_const = p.c_mode == SPH_C_CONST;
+    I.delta_all = p.delta_pairs == SPH_DELTA_ALL;
+    I.verlet_ns = p.verlet_ns;
+    I.cell_base = cell_base;
+    I.row_base = row_base;
+    I.pstart = pstart;
+    I.pend = pend;
+    return I;
+}
+
+static Problem single_problem(const sph_params &p, int64_t n) {
+    Problem P;
+    P.precision = p.precision;
+    P.n = n;
+    P.ncells = (int64_t)p.dims[0] * p.dims[1] * p.dims[2];
+    P.nrows = (int64_t)p.dims[1] * p.dims[2];
+    P.host.push_back(inst_from(p, 0, 0, 0, (uint32_t)n));
+    P.batch = false;
+    return P;
 }
 
 static bool finite_all(std::initializer_list<double> v) {
@@ -113,7 +175,7 @@ static int check_n(int64_t n) {
 
 static bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
-static int check_state(const sph_params *p, const sph_state *s) {
+static int check_state(int precision, const sph_state *s) {
     if (!s) return fail(SPH_E_INVAL, "state is NULL");
     if (int rc = check_n(s->n)) return rc;
     const void *ptrs[] = {s->x,      s->y,      s->z,      s->ux,      s->uy,      s->uz,
@@ -122,15 +184,14 @@ static int check_state(const sph_params *p, const sph_state *s) {
                           s->uxm_alt, s->uym_alt, s->uzm_alt, s->rho_alt, s->rhom_alt, s->id_alt};
     for (const void *q : ptrs) {
         if (!q) return fail(SPH_E_INVAL, "state array pointer is NULL");
-        if (!aligned(q, 8) && !(p->precision == SPH_MIXED && aligned(q, 4)))
-            return fail(SPH_E_INVAL, "state array pointer is misaligned");
+        if (!aligned(q, 4)) return fail(SPH_E_INVAL, "state array pointer is misaligned");
     }
     const double *d8[] = {s->x, s->y, s->z, s->ux, s->uy, s->uz, s->uxm, s->uym, s->uzm,
                           s->x_alt, s->y_alt, s->z_alt, s->ux_alt, s->uy_alt, s->uz_alt,
                           s->uxm_alt, s->uym_alt, s->uzm_alt};
     for (const double *q : d8)
         if (!aligned(q, 8)) return fail(SPH_E_INVAL, "double array pointer is misaligned");
-    if (p->precision == SPH_FP64) {
+    if (precision == SPH_FP64) {
         const void *r8[] = {s->rho, s->rhom, s->rho_alt, s->rhom_alt};
         for (const void *q : r8)
             if (!aligned(q, 8)) return fail(SPH_E_INVAL, "density pointer is misaligned");
@@ -139,43 +200,263 @@ static int check_state(const sph_params *p, const sph_state *s) {
     return SPH_OK;
 }
 
-static int check_ws(const sph_params *p, const sph_state *s, void *ws, Ws *out) {
+static int check_ws_ptr(const void *ws) {
     if (!ws) return fail(SPH_E_INVAL, "workspace is NULL");
     if (!aligned(ws, 256)) return fail(SPH_E_INVAL, "workspace must be 256-byte aligned");
-    out->L = make_layout(*p, s->n);
-    out->base = static_cast<char *>(ws);
     return SPH_OK;
 }
 
-static int validate(const sph_params *p, const sph_state *s, void *ws, Ws *w) {
+// Single system: params + state + workspace -> problem and workspace view.
+static int validate(const sph_params *p, const sph_state *s, void *ws, Problem *P, Ws *w) {
     if (int rc = check_params(p)) return rc;
-    if (int rc = check_state(p, s)) return rc;
-    return check_ws(p, s, ws, w);
+    if (int rc = check_state(p->precision, s)) return rc;
+    if (int rc = check_ws_ptr(ws)) return rc;
+    *P = single_problem(*p, s->n);
+    w->L = make_layout(*P);
+    w->base = static_cast<char *>(ws);
+    return SPH_OK;
 }
 
-static int build_cells(const sph_params &p, sph_state &s, const Ws &w, hipStream_t st) {
-    if (int rc = launch_encode(p, s, w, st)) return rc;
+// Batch description -> problem (host table of instances).
+static int batch_problem(const sph_batch *b, Problem *P) {
+    if (!b) return fail(SPH_E_INVAL, "batch is NULL");
+    if (b->ninst < 1 || b->ninst > SPH_MAX_INSTANCES)
+        return fail(SPH_E_INVAL, "ninst must be in [1, SPH_MAX_INSTANCES]");
+    if (b->reserved != 0) return fail(SPH_E_INVAL, "batch reserved must be 0");
+    if (!b->params || !b->counts) return fail(SPH_E_INVAL, "batch arrays are NULL");
+    P->host.clear();
+    P->batch = true;
+    P->precision = b->params[0].precision;
+    int64_t n = 0, cells = 0, rows = 0;
+    for (int k = 0; k < b->ninst; ++k) {
+        const sph_params &p = b->params[k];
+        if (int rc = check_params(&p))
+            return fail(rc, "instance " + std::to_string(k) + ": " + g_err);
+        if (p.precision != P->precision)
+            return fail(SPH_E_INVAL, "all instances must have the same precision");
+        const int64_t c = b->counts[k];
+        if (c < 1) return fail(SPH_E_INVAL, "every instance needs >= 1 particle");
+        const int64_t nc = (int64_t)p.dims[0] * p.dims[1] * p.dims[2];
+        const int64_t nr = (int64_t)p.dims[1] * p.dims[2];
+        if (n + c >= ((int64_t)1 << 31)) return fail(SPH_E_RANGE, "total particles must be < 2^31");
+        if (cells + nc >= ((int64_t)1 << 31) - 1)
+            return fail(SPH_E_RANGE, "total cells must be < 2^31 - 1");
+        P->host.push_back(inst_from(p, (uint32_t)cells, (uint32_t)rows, (uint32_t)n,
+                                    (uint32_t)(n + c)));
+        n += c;
+        cells += nc;
+        rows += nr;
+    }
+    P->n = n;
+    P->ncells = cells;
+    P->nrows = rows;
+    return SPH_OK;
+}
+
+static int validate_batch(const sph_batch *b, const sph_state *s, void *ws, Problem *P, Ws *w) {
+    if (int rc = batch_problem(b, P)) return rc;
+    if (int rc = check_state(P->precision, s)) return rc;
+    if (s->n != P->n) return fail(SPH_E_INVAL, "state n must equal the sum of the counts");
+    if (int rc = check_ws_ptr(ws)) return rc;
+    w->L = make_layout(*P);
+    w->base = static_cast<char *>(ws);
+    return SPH_OK;
+}
+
+// Timing marks: events recorded around one region of a step.
+struct Marks {
+    int region = SPH_REGION_INTERACT;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int at(int r, bool begin, hipStream_t st) const {
+        if (!e0 || r != region) return SPH_OK;
+        return hip_check(hipEventRecord(begin ? e0 : e1, st), "event record");
+    }
+};
+
+static int build_cells(const Problem &P, sph_state &s, const Ws &w, hipStream_t st,
+                       bool lagged = false, double dt = 0.0, const Marks &m = Marks()) {
+    if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
+    if (int rc = launch_encode(P, s, w, st)) return rc;
     uint32_t *keys = nullptr, *perm = nullptr;
+    if (int rc = m.at(SPH_REGION_SORT, true, st)) return rc;
     if (int rc = launch_sort(w, st, &keys, &perm)) return rc;
-    if (int rc = launch_reorder(p, s, w, keys, perm, st)) return rc;
-    if (int rc = launch_cell_table(p, w, keys, st)) return rc;
-    if (int rc = launch_chunks(p, w, st)) return rc;
+    if (int rc = m.at(SPH_REGION_SORT, false, st)) return rc;
+    if (int rc = m.at(SPH_REGION_REORDER, true, st)) return rc;
+    if (int rc = launch_reorder(P, s, w, keys, perm, st)) return rc;
+    if (int rc = m.at(SPH_REGION_REORDER, false, st)) return rc;
+    if (int rc = launch_cell_table(w, keys, st)) return rc;
+    if (int rc = launch_chunks(P, w, lagged, dt, st)) return rc;
     s.cells_valid = 1;
     return SPH_OK;
 }
 
-static int one_step(const sph_params &p, sph_state &s, const Ws &w, double dt, int64_t step,
-                    hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
-    if (!s.cells_valid)
-        if (int rc = build_cells(p, s, w, st)) return rc;
-    if (ev0)
-        if (int rc = hip_check(hipEventRecord(ev0, st), "event record")) return rc;
-    if (int rc = launch_interact(p, s, w, st)) return rc;
-    if (ev1)
-        if (int rc = hip_check(hipEventRecord(ev1, st), "event record")) return rc;
-    if (int rc = launch_integrate(p, s, w, dt, step, st)) return rc;
+// One step.  fused: the lagged-dt form, where the interaction also advances
+// the state (one kernel instead of interaction + update).
+static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
+                    bool fused, hipStream_t st, const Marks &m = Marks()) {
+    if (!s.cells_valid) {
+        if (int rc = build_cells(P, s, w, st, fused, dt, m)) return rc;
+    } else {
+        if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
+        if (int rc = launch_chunks(P, w, fused, dt, st)) return rc;  // fresh dt bound
+    }
+    if (int rc = m.at(SPH_REGION_INTERACT, true, st)) return rc;
+    if (int rc = launch_interact(P, s, w, st, nullptr, nullptr, nullptr, fused, step)) return rc;
+    if (int rc = m.at(SPH_REGION_INTERACT, false, st)) return rc;
+    if (fused) {
+        after_fused_step(s);
+    } else {
+        if (int rc = launch_integrate(P, s, w, dt, step, st)) return rc;
+    }
+    if (int rc = m.at(SPH_REGION_STEP, false, st)) return rc;
     s.cells_valid = 0;
     return SPH_OK;
+}
+
+static int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Steps after which a captured sequence repeats itself: the state pointers
+// cycle with period 4 (the cell-order gather and the level rotation each
+// swap pairs of buffers), and each instance's Euler reset with its N_s.
+static int64_t graph_period(const Problem &P) {
+    int64_t L = 4;
+    for (const Inst &ip : P.host) {
+        if (ip.verlet_ns > 0) L = L / gcd64(L, ip.verlet_ns) * ip.verlet_ns;
+        if (L > kMaxGraphSteps) return 0;
+    }
+    return L;
+}
+
+static bool same_pointers(const sph_state &a, const sph_state &b) {
+    return a.x == b.x && a.y == b.y && a.z == b.z && a.ux == b.ux && a.uy == b.uy &&
+           a.uz == b.uz && a.uxm == b.uxm && a.uym == b.uym && a.uzm == b.uzm &&
+           a.rho == b.rho && a.rhom == b.rhom && a.id == b.id && a.x_alt == b.x_alt &&
+           a.y_alt == b.y_alt && a.z_alt == b.z_alt && a.ux_alt == b.ux_alt &&
+           a.uy_alt == b.uy_alt && a.uz_alt == b.uz_alt && a.uxm_alt == b.uxm_alt &&
+           a.uym_alt == b.uym_alt && a.uzm_alt == b.uzm_alt && a.rho_alt == b.rho_alt &&
+           a.rhom_alt == b.rhom_alt && a.id_alt == b.id_alt;
+}
+
+// Capture `len` steps from index step into a graph (nothing runs), then
+// replay it `reps` times.  The state pointers must come back to where they
+// started, which the period guarantees.
+static int graph_steps(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
+                       int64_t len, int64_t reps, bool lagged, hipStream_t st) {
+    const sph_state s0 = s;
+    if (int rc = hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed), "capture"))
+        return rc;
+    int rc = SPH_OK;
+    for (int64_t k = 0; k < len && rc == SPH_OK; ++k)
+        rc = one_step(P, s, w, dt, step + k, lagged && step + k > 0, st);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &g);
+    if (rc == SPH_OK) rc = hip_check(ec, "end capture");
+    if (rc == SPH_OK && !same_pointers(s, s0))
+        rc = fail(SPH_E_STATE, "captured steps did not return the state to its buffers");
+    hipGraphExec_t ex = nullptr;
+    if (rc == SPH_OK)
+        rc = hip_check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "graph instantiate");
+    for (int64_t r = 0; r < reps && rc == SPH_OK; ++r)
+        rc = hip_check(hipGraphLaunch(ex, st), "graph launch");
+    if (ex) {
+        // the replays must finish before the executable graph goes away
+        const int rs = hip_check(hipStreamSynchronize(st), "graph sync");
+        if (rc == SPH_OK) rc = rs;
+        (void)hipGraphExecDestroy(ex);
+    }
+    if (g) (void)hipGraphDestroy(g);
+    s = s0;
+    s.cells_valid = 0;
+    return rc;
+}
+
+static int run_steps(const Problem &P, sph_state &s, const Ws &w, int64_t nsteps, double dt,
+                     int64_t step0, int mode, hipStream_t st, int region = SPH_REGION_INTERACT,
+                     void *const *ev_begin = nullptr, void *const *ev_end = nullptr) {
+    const bool lagged = (mode & SPH_RUN_LAGGED) != 0;
+    const int64_t L = (mode & SPH_RUN_GRAPH) ? graph_period(P) : 0;
+    int64_t k = 0;
+    while (k < nsteps) {
+        const int64_t idx = step0 + k;
+        if (L > 0 && idx > 0 && idx % L == 0 && nsteps - k >= L && !ev_begin) {
+            const int64_t reps = (nsteps - k) / L;
+            s.cells_valid = 0;  // every captured step rebuilds its cells
+            if (int rc = graph_steps(P, s, w, dt, idx, L, reps, lagged, st)) return rc;
+            k += reps * L;
+            continue;
+        }
+        Marks m;
+        m.region = region;
+        if (ev_begin) {
+            m.e0 = static_cast<hipEvent_t>(ev_begin[k]);
+            m.e1 = static_cast<hipEvent_t>(ev_end[k]);
+        }
+        if (int rc = one_step(P, s, w, dt, idx, lagged && idx > 0, st, m)) return rc;
+        ++k;
+    }
+    return SPH_OK;
+}
+
+static int check_run_args(double dt, int64_t nsteps, int64_t step0, int mode) {
+    if (!std::isfinite(dt)) return fail(SPH_E_INVAL, "dt must be finite");
+    if (nsteps < 0 || step0 < 0) return fail(SPH_E_INVAL, "nsteps and step0 must be >= 0");
+    if (mode & ~(SPH_RUN_LAGGED | SPH_RUN_GRAPH)) return fail(SPH_E_INVAL, "unknown mode bits");
+    return SPH_OK;
+}
+
+static int check_events(int64_t nsteps, int32_t region, void *const *ev_begin,
+                        void *const *ev_end) {
+    if (region < SPH_REGION_INTERACT || region > SPH_REGION_STEP)
+        return fail(SPH_E_INVAL, "unknown region");
+    if ((ev_begin == nullptr) != (ev_end == nullptr))
+        return fail(SPH_E_INVAL, "ev_begin and ev_end must both be given or both be NULL");
+    if (ev_begin)
+        for (int64_t k = 0; k < nsteps; ++k)
+            if ((ev_begin[k] == nullptr) != (ev_end[k] == nullptr))
+                return fail(SPH_E_INVAL, "event handles of a step must both be set or both NULL");
+    return SPH_OK;
+}
+
+static int check_rates_out(const double *ax, const double *ay, const double *az,
+                           const double *drho, const double *mumax) {
+    if (!ax || !ay || !az || !drho) return fail(SPH_E_INVAL, "output pointer is NULL");
+    const double *outs[] = {ax, ay, az, drho};
+    for (const double *q : outs)
+        if (!aligned(q, 8)) return fail(SPH_E_INVAL, "output pointer is misaligned");
+    if (mumax && !aligned(mumax, 8)) return fail(SPH_E_INVAL, "mumax is misaligned");
+    return SPH_OK;
+}
+
+static int interact_rates(const Problem &P, const sph_state &s, const Ws &w, double *ax,
+                          double *ay, double *az, double *drho, double *mumax, hipStream_t st) {
+    if (!s.cells_valid) return fail(SPH_E_STATE, "rates need current cells (build_cells)");
+    if (int rc = launch_chunks(P, w, false, 0.0, st)) return rc;  // resets the dt bound
+    if (int rc = launch_interact(P, s, w, st)) return rc;
+    return launch_export_rates(P, w, ax, ay, az, drho, mumax, st);
+}
+
+static int ws_init(const Problem &P, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (int rc = check_ws_ptr(ws)) return rc;
+    Ws w;
+    w.L = make_layout(P);
+    w.base = static_cast<char *>(ws);
+    if (ws_bytes < w.L.total) return fail(SPH_E_SIZE, "workspace too small");
+    return launch_ws_init(P, w, st);
+}
+
+static int density_io(const Problem &P, sph_state *s, const Ws &w, double *rho, int32_t which,
+                      bool set, hipStream_t st) {
+    if (!rho || !aligned(rho, 8)) return fail(SPH_E_INVAL, "rho is NULL or misaligned");
+    if (which != 0 && which != 1) return fail(SPH_E_INVAL, "which must be 0 or 1");
+    return set ? launch_set_density(P, *s, w, rho, which, st)
+               : launch_get_density(P, *s, w, rho, which, st);
 }
 
 }  // namespace wcsph
@@ -211,8 +492,9 @@ int sph_get_split(const sph_params *p, int64_t n, int32_t *split, int32_t *group
     if (int rc = check_params(p)) return rc;
     if (int rc = check_n(n)) return rc;
     if (!split || !group) return fail(SPH_E_INVAL, "output is NULL");
-    *split = split_for(*p, make_layout(*p, n).max_chunks);
-    *group = group_for(*p);
+    const Problem P = single_problem(*p, n);
+    *split = split_for(P, make_layout(P).max_chunks);
+    *group = group_for(P);
     return SPH_OK;
 }
 
@@ -220,134 +502,191 @@ int sph_workspace_bytes(const sph_params *p, int64_t n, size_t *bytes) {
     if (int rc = check_params(p)) return rc;
     if (int rc = check_n(n)) return rc;
     if (!bytes) return fail(SPH_E_INVAL, "bytes is NULL");
-    *bytes = make_layout(*p, n).total;
+    *bytes = make_layout(single_problem(*p, n)).total;
     return SPH_OK;
 }
 
 int sph_workspace_init(const sph_params *p, int64_t n, void *ws, size_t ws_bytes, void *stream) {
     if (int rc = check_params(p)) return rc;
     if (int rc = check_n(n)) return rc;
-    if (!ws) return fail(SPH_E_INVAL, "workspace is NULL");
-    if (!aligned(ws, 256)) return fail(SPH_E_INVAL, "workspace must be 256-byte aligned");
-    Ws w;
-    w.L = make_layout(*p, n);
-    w.base = static_cast<char *>(ws);
-    if (ws_bytes < w.L.total) return fail(SPH_E_SIZE, "workspace too small");
-    return launch_ws_init(w, static_cast<hipStream_t>(stream));
+    return ws_init(single_problem(*p, n), ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 int sph_set_density(const sph_params *p, sph_state *s, const double *rho, int32_t which,
                     void *stream) {
     if (int rc = check_params(p)) return rc;
-    if (int rc = check_state(p, s)) return rc;
-    if (!rho || !aligned(rho, 8)) return fail(SPH_E_INVAL, "rho is NULL or misaligned");
-    if (which != 0 && which != 1) return fail(SPH_E_INVAL, "which must be 0 or 1");
-    return launch_set_density(*p, *s, rho, which, static_cast<hipStream_t>(stream));
+    if (int rc = check_state(p->precision, s)) return rc;
+    const Problem P = single_problem(*p, s->n);
+    Ws w;  // single systems need no workspace for the conversion
+    return density_io(P, s, w, const_cast<double *>(rho), which, true,
+                      static_cast<hipStream_t>(stream));
 }
 
 int sph_get_density(const sph_params *p, const sph_state *s, double *rho, int32_t which,
                     void *stream) {
     if (int rc = check_params(p)) return rc;
-    if (int rc = check_state(p, s)) return rc;
-    if (!rho || !aligned(rho, 8)) return fail(SPH_E_INVAL, "rho is NULL or misaligned");
-    if (which != 0 && which != 1) return fail(SPH_E_INVAL, "which must be 0 or 1");
-    return launch_get_density(*p, *s, rho, which, static_cast<hipStream_t>(stream));
+    if (int rc = check_state(p->precision, s)) return rc;
+    const Problem P = single_problem(*p, s->n);
+    Ws w;
+    return density_io(P, const_cast<sph_state *>(s), w, rho, which, false,
+                      static_cast<hipStream_t>(stream));
 }
 
 int sph_build_cells(const sph_params *p, sph_state *s, void *ws, void *stream) {
+    Problem P;
     Ws w;
-    if (int rc = validate(p, s, ws, &w)) return rc;
-    return build_cells(*p, *s, w, static_cast<hipStream_t>(stream));
+    if (int rc = validate(p, s, ws, &P, &w)) return rc;
+    return build_cells(P, *s, w, static_cast<hipStream_t>(stream));
 }
 
 int sph_interact(const sph_params *p, const sph_state *s, void *ws, double *ax, double *ay,
                  double *az, double *drho, double *mumax, void *stream) {
+    Problem P;
     Ws w;
-    if (int rc = validate(p, s, ws, &w)) return rc;
-    if (!ax || !ay || !az || !drho) return fail(SPH_E_INVAL, "output pointer is NULL");
-    const double *outs[] = {ax, ay, az, drho};
-    for (const double *q : outs)
-        if (!aligned(q, 8)) return fail(SPH_E_INVAL, "output pointer is misaligned");
-    if (mumax && !aligned(mumax, 8)) return fail(SPH_E_INVAL, "mumax is misaligned");
-    if (!s->cells_valid) return fail(SPH_E_STATE, "sph_interact needs current cells (sph_build_cells)");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (int rc = launch_chunks(*p, w, st)) return rc;  // resets the dt bound
-    if (int rc = launch_interact(*p, *s, w, st)) return rc;
-    return launch_export_rates(*p, w, s->n, ax, ay, az, drho, mumax, st);
+    if (int rc = validate(p, s, ws, &P, &w)) return rc;
+    if (int rc = check_rates_out(ax, ay, az, drho, mumax)) return rc;
+    return interact_rates(P, *s, w, ax, ay, az, drho, mumax, static_cast<hipStream_t>(stream));
 }
 
 int sph_neighbour_stats(const sph_params *p, const sph_state *s, void *ws, int32_t *n_fluid_nbrs,
                         int32_t *n_boundary_nbrs, uint32_t *id_hash, void *stream) {
+    Problem P;
     Ws w;
-    if (int rc = validate(p, s, ws, &w)) return rc;
+    if (int rc = validate(p, s, ws, &P, &w)) return rc;
     if (!n_fluid_nbrs || !n_boundary_nbrs || !id_hash)
         return fail(SPH_E_INVAL, "output pointer is NULL");
     if (!aligned(n_fluid_nbrs, 4) || !aligned(n_boundary_nbrs, 4) || !aligned(id_hash, 4))
         return fail(SPH_E_INVAL, "output pointer is misaligned");
     if (!s->cells_valid) return fail(SPH_E_STATE, "sph_neighbour_stats needs current cells");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (int rc = launch_chunks(*p, w, st)) return rc;
-    return launch_interact(*p, *s, w, st, n_fluid_nbrs, n_boundary_nbrs, id_hash);
+    if (int rc = launch_chunks(P, w, false, 0.0, st)) return rc;
+    return launch_interact(P, *s, w, st, n_fluid_nbrs, n_boundary_nbrs, id_hash);
 }
 
 int sph_step(const sph_params *p, sph_state *s, void *ws, double dt, int64_t step_index,
              void *stream) {
+    Problem P;
     Ws w;
-    if (int rc = validate(p, s, ws, &w)) return rc;
-    if (!std::isfinite(dt)) return fail(SPH_E_INVAL, "dt must be finite");
-    if (step_index < 0) return fail(SPH_E_INVAL, "step_index must be >= 0");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (s->cells_valid)
-        if (int rc = launch_chunks(*p, w, st)) return rc;  // fresh dt bound
-    return one_step(*p, *s, w, dt, step_index, st);
+    if (int rc = validate(p, s, ws, &P, &w)) return rc;
+    if (int rc = check_run_args(dt, 1, step_index, 0)) return rc;
+    return one_step(P, *s, w, dt, step_index, false, static_cast<hipStream_t>(stream));
 }
 
 int sph_run(const sph_params *p, sph_state *s, void *ws, int64_t nsteps, double dt, int64_t step0,
             void *stream) {
+    Problem P;
     Ws w;
-    if (int rc = validate(p, s, ws, &w)) return rc;
-    if (!std::isfinite(dt)) return fail(SPH_E_INVAL, "dt must be finite");
-    if (nsteps < 0 || step0 < 0) return fail(SPH_E_INVAL, "nsteps and step0 must be >= 0");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (nsteps > 0 && s->cells_valid)
-        if (int rc = launch_chunks(*p, w, st)) return rc;
-    for (int64_t k = 0; k < nsteps; ++k)
-        if (int rc = one_step(*p, *s, w, dt, step0 + k, st)) return rc;
-    return SPH_OK;
+    if (int rc = validate(p, s, ws, &P, &w)) return rc;
+    if (int rc = check_run_args(dt, nsteps, step0, 0)) return rc;
+    return run_steps(P, *s, w, nsteps, dt, step0, 0, static_cast<hipStream_t>(stream));
 }
 
 int sph_run_profiled(const sph_params *p, sph_state *s, void *ws, int64_t nsteps, double dt,
-                     int64_t step0, void *const *ev_begin, void *const *ev_end, void *stream) {
+                     int64_t step0, int32_t region, void *const *ev_begin, void *const *ev_end,
+                     void *stream) {
+    Problem P;
     Ws w;
-    if (int rc = validate(p, s, ws, &w)) return rc;
-    if (!std::isfinite(dt)) return fail(SPH_E_INVAL, "dt must be finite");
-    if (nsteps < 0 || step0 < 0) return fail(SPH_E_INVAL, "nsteps and step0 must be >= 0");
-    if ((ev_begin == nullptr) != (ev_end == nullptr))
-        return fail(SPH_E_INVAL, "ev_begin and ev_end must both be given or both be NULL");
-    if (ev_begin)
-        for (int64_t k = 0; k < nsteps; ++k)
-            if ((ev_begin[k] == nullptr) != (ev_end[k] == nullptr))
-                return fail(SPH_E_INVAL, "event handles of a step must both be set or both NULL");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (nsteps > 0 && s->cells_valid)
-        if (int rc = launch_chunks(*p, w, st)) return rc;
-    for (int64_t k = 0; k < nsteps; ++k) {
-        hipEvent_t e0 = ev_begin ? static_cast<hipEvent_t>(ev_begin[k]) : nullptr;
-        hipEvent_t e1 = ev_end ? static_cast<hipEvent_t>(ev_end[k]) : nullptr;
-        if (int rc = one_step(*p, *s, w, dt, step0 + k, st, e0, e1)) return rc;
-    }
-    return SPH_OK;
+    if (int rc = validate(p, s, ws, &P, &w)) return rc;
+    if (int rc = check_run_args(dt, nsteps, step0, 0)) return rc;
+    if (int rc = check_events(nsteps, region, ev_begin, ev_end)) return rc;
+    return run_steps(P, *s, w, nsteps, dt, step0, 0, static_cast<hipStream_t>(stream), region,
+                     ev_begin, ev_end);
 }
 
 int sph_diagnostics(const sph_params *p, const sph_state *s, void *ws, const double *probes_xyz,
                     int32_t np, sph_diag *out, double *probe_p, void *stream) {
+    Problem P;
     Ws w;
-    if (int rc = validate(p, s, ws, &w)) return rc;
+    if (int rc = validate(p, s, ws, &P, &w)) return rc;
     if (!out) return fail(SPH_E_INVAL, "out is NULL");
     if (np < 0 || np > kMaxProbes) return fail(SPH_E_INVAL, "np must be in [0, 1024]");
     if (np > 0 && (!probes_xyz || !probe_p)) return fail(SPH_E_INVAL, "probe arrays are NULL");
     if (!s->cells_valid) return fail(SPH_E_STATE, "sph_diagnostics needs current cells");
-    return launch_diag(*p, *s, w, probes_xyz, np, out, probe_p, static_cast<hipStream_t>(stream));
+    return launch_diag(P, *s, w, probes_xyz, np, out, probe_p, static_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------------------------ batch
+
+int sph_batch_workspace_bytes(const sph_batch *b, size_t *bytes) {
+    Problem P;
+    if (int rc = batch_problem(b, &P)) return rc;
+    if (!bytes) return fail(SPH_E_INVAL, "bytes is NULL");
+    *bytes = make_layout(P).total;
+    return SPH_OK;
+}
+
+int sph_batch_workspace_init(const sph_batch *b, void *ws, size_t ws_bytes, void *stream) {
+    Problem P;
+    if (int rc = batch_problem(b, &P)) return rc;
+    return ws_init(P, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int sph_batch_set_density(const sph_batch *b, sph_state *s, void *ws, const double *rho,
+                          int32_t which, void *stream) {
+    Problem P;
+    Ws w;
+    if (int rc = validate_batch(b, s, ws, &P, &w)) return rc;
+    return density_io(P, s, w, const_cast<double *>(rho), which, true,
+                      static_cast<hipStream_t>(stream));
+}
+
+int sph_batch_get_density(const sph_batch *b, const sph_state *s, void *ws, double *rho,
+                          int32_t which, void *stream) {
+    Problem P;
+    Ws w;
+    if (int rc = validate_batch(b, s, ws, &P, &w)) return rc;
+    return density_io(P, const_cast<sph_state *>(s), w, rho, which, false,
+                      static_cast<hipStream_t>(stream));
+}
+
+int sph_batch_build_cells(const sph_batch *b, sph_state *s, void *ws, void *stream) {
+    Problem P;
+    Ws w;
+    if (int rc = validate_batch(b, s, ws, &P, &w)) return rc;
+    return build_cells(P, *s, w, static_cast<hipStream_t>(stream));
+}
+
+int sph_batch_interact(const sph_batch *b, const sph_state *s, void *ws, double *ax, double *ay,
+                       double *az, double *drho, double *mumax, void *stream) {
+    Problem P;
+    Ws w;
+    if (int rc = validate_batch(b, s, ws, &P, &w)) return rc;
+    if (int rc = check_rates_out(ax, ay, az, drho, mumax)) return rc;
+    return interact_rates(P, *s, w, ax, ay, az, drho, mumax, static_cast<hipStream_t>(stream));
+}
+
+int sph_batch_run(const sph_batch *b, sph_state *s, void *ws, int64_t nsteps, double dt,
+                  int64_t step0, int32_t mode, void *stream) {
+    Problem P;
+    Ws w;
+    if (int rc = validate_batch(b, s, ws, &P, &w)) return rc;
+    if (int rc = check_run_args(dt, nsteps, step0, mode)) return rc;
+    if ((mode & SPH_RUN_GRAPH) && !stream)
+        return fail(SPH_E_INVAL, "SPH_RUN_GRAPH needs a stream other than NULL");
+    return run_steps(P, *s, w, nsteps, dt, step0, mode, static_cast<hipStream_t>(stream));
+}
+
+int sph_batch_run_profiled(const sph_batch *b, sph_state *s, void *ws, int64_t nsteps, double dt,
+                           int64_t step0, int32_t mode, int32_t region, void *const *ev_begin,
+                           void *const *ev_end, void *stream) {
+    Problem P;
+    Ws w;
+    if (int rc = validate_batch(b, s, ws, &P, &w)) return rc;
+    if (int rc = check_run_args(dt, nsteps, step0, mode & ~SPH_RUN_GRAPH)) return rc;
+    if (mode & SPH_RUN_GRAPH) return fail(SPH_E_INVAL, "profiled runs take no graph");
+    if (int rc = check_events(nsteps, region, ev_begin, ev_end)) return rc;
+    return run_steps(P, *s, w, nsteps, dt, step0, mode, static_cast<hipStream_t>(stream), region,
+                     ev_begin, ev_end);
+}
+
+int sph_batch_diagnostics(const sph_batch *b, const sph_state *s, void *ws, sph_diag *out,
+                          void *stream) {
+    Problem P;
+    Ws w;
+    if (int rc = validate_batch(b, s, ws, &P, &w)) return rc;
+    if (!out) return fail(SPH_E_INVAL, "out is NULL");
+    if (!s->cells_valid) return fail(SPH_E_STATE, "diagnostics need current cells");
+    return launch_diag(P, *s, w, nullptr, 0, out, nullptr, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

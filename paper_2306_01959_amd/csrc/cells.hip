@@ -26,22 +26,24 @@ __device__ __forceinline__ int axis_cell(double v, double o, double cs, int n) {
     return (int)f;
 }
 
+// key = the instance's first global cell + the particle's cell in its grid
 __global__ void k_encode(const double *__restrict__ x, const double *__restrict__ y,
-                         const double *__restrict__ z, int64_t n, Grid g,
-                         uint32_t *__restrict__ keys) {
+                         const double *__restrict__ z, const uint32_t *__restrict__ id,
+                         int64_t n, Insts I, uint32_t *__restrict__ keys) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int cx = axis_cell(x[i], g.ox, g.cs, g.nx);
-    int cy = axis_cell(y[i], g.oy, g.cs, g.ny);
-    int cz = axis_cell(z[i], g.oz, g.cs, g.nz);
-    keys[i] = (uint32_t)lin_cell(cx, cy, cz, g.nx, g.ny);
+    const Inst ip = I.get(I.of_id(id[i] & 0x7fffffffu));
+    const int cx = axis_cell(x[i], ip.ox, ip.cs, ip.nx);
+    const int cy = axis_cell(y[i], ip.oy, ip.cs, ip.ny);
+    const int cz = axis_cell(z[i], ip.oz, ip.cs, ip.nz);
+    keys[i] = ip.cell_base + (uint32_t)lin_cell(cx, cy, cz, ip.nx, ip.ny);
 }
 
-int launch_encode(const sph_params &p, const sph_state &s, const Ws &w, hipStream_t st) {
+int launch_encode(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st) {
     int64_t n = s.n;
     int blocks = (int)((n + 255) / 256);
-    hipLaunchKernelGGL(k_encode, dim3(blocks), dim3(256), 0, st, s.x, s.y, s.z, n, grid_of(p),
-                       w.keys());
+    hipLaunchKernelGGL(k_encode, dim3(blocks), dim3(256), 0, st, s.x, s.y, s.z, s.id, n,
+                       insts_of(P, w), w.keys());
     return launch_check("encode");
 }
 
@@ -206,9 +208,7 @@ struct ReorderArgs {
     uint32_t *id2;
     // view
     void *v0, *v1, *v2;
-    Grid g;
-    double rho0, B, gamma, c0;
-    int c_const;
+    Insts I;
 };
 
 // Offset of coordinate v from the centre of cell c, computed in FP64 with
@@ -220,6 +220,10 @@ __device__ __forceinline__ float cell_offset(double v, double o, int c, double c
     return (float)(t - ctr);
 }
 
+// Gathers the state into cell order and writes the interaction view:
+// mixed: {offset from the cell centre (FP32), rho - rho0}, {u (FP32), P},
+// {1/rho, +-c}; FP64: {r, rho}, {u, P}, {1/rho, +-c}; c < 0 marks a boundary
+// particle.  P from the Tait equation, c the Tait sound speed (or c0).
 template <bool kMixed>
 __global__ void k_reorder(ReorderArgs a) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -239,21 +243,23 @@ __global__ void k_reorder(ReorderArgs a) {
     a.uzm2[k] = a.uzm[src];
     a.id2[k] = id;
     const bool bnd = (id >> 31) != 0;
+    const uint32_t key = a.keys[k];
+    const Inst ip = a.I.get(a.I.of_cell(key));
     if constexpr (kMixed) {
         const float dr = static_cast<const float *>(a.rho)[src];
         static_cast<float *>(a.rho2)[k] = dr;
         static_cast<float *>(a.rhom2)[k] = static_cast<const float *>(a.rhom)[src];
-        const uint32_t c = a.keys[k];
-        const int cx = (int)(c % (uint32_t)a.g.nx);
-        const int cy = (int)((c / (uint32_t)a.g.nx) % (uint32_t)a.g.ny);
-        const int cz = (int)(c / ((uint32_t)a.g.nx * (uint32_t)a.g.ny));
-        const double xr = (double)dr / a.rho0;
+        const uint32_t c = key - ip.cell_base;
+        const int cx = (int)(c % (uint32_t)ip.nx);
+        const int cy = (int)((c / (uint32_t)ip.nx) % (uint32_t)ip.ny);
+        const int cz = (int)(c / ((uint32_t)ip.nx * (uint32_t)ip.ny));
+        const double xr = (double)dr / ip.rho0;
         const double l1p = log1p(xr);
-        const double P = a.B * expm1(a.gamma * l1p);
-        const double cs = a.c_const ? a.c0 : a.c0 * exp(0.5 * (a.gamma - 1.0) * l1p);
-        const double inv = 1.0 / (a.rho0 + (double)dr);
-        float4 v0 = make_float4(cell_offset(x, a.g.ox, cx, a.g.cs), cell_offset(y, a.g.oy, cy, a.g.cs),
-                                cell_offset(z, a.g.oz, cz, a.g.cs), dr);
+        const double P = ip.B * expm1(ip.gamma * l1p);
+        const double cs = ip.c_const ? ip.c0 : ip.c0 * exp(0.5 * (ip.gamma - 1.0) * l1p);
+        const double inv = 1.0 / (ip.rho0 + (double)dr);
+        float4 v0 = make_float4(cell_offset(x, ip.ox, cx, ip.cs), cell_offset(y, ip.oy, cy, ip.cs),
+                                cell_offset(z, ip.oz, cz, ip.cs), dr);
         float4 v1 = make_float4((float)ux, (float)uy, (float)uz, (float)P);
         float2 v2 = make_float2((float)inv, bnd ? -(float)cs : (float)cs);
         static_cast<float4 *>(a.v0)[k] = v0;
@@ -263,9 +269,9 @@ __global__ void k_reorder(ReorderArgs a) {
         const double rho = static_cast<const double *>(a.rho)[src];
         static_cast<double *>(a.rho2)[k] = rho;
         static_cast<double *>(a.rhom2)[k] = static_cast<const double *>(a.rhom)[src];
-        const double r = rho / a.rho0;
-        const double P = a.B * (pow(r, a.gamma) - 1.0);
-        const double cs = a.c_const ? a.c0 : a.c0 * pow(r, 0.5 * (a.gamma - 1.0));
+        const double r = rho / ip.rho0;
+        const double P = ip.B * (pow(r, ip.gamma) - 1.0);
+        const double cs = ip.c_const ? ip.c0 : ip.c0 * pow(r, 0.5 * (ip.gamma - 1.0));
         double4 v0 = make_double4(x, y, z, rho);
         double4 v1 = make_double4(ux, uy, uz, P);
         double2 v2 = make_double2(1.0 / rho, bnd ? -cs : cs);
@@ -275,7 +281,7 @@ __global__ void k_reorder(ReorderArgs a) {
     }
 }
 
-int launch_reorder(const sph_params &p, sph_state &s, const Ws &w, const uint32_t *keys,
+int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *keys,
                    const uint32_t *perm, hipStream_t st) {
     ReorderArgs a;
     a.perm = perm;
@@ -292,14 +298,9 @@ int launch_reorder(const sph_params &p, sph_state &s, const Ws &w, const uint32_
     a.v0 = w.base + w.L.view0;
     a.v1 = w.base + w.L.view1;
     a.v2 = w.base + w.L.view2;
-    a.g = grid_of(p);
-    a.rho0 = p.rho0;
-    a.B = p.rho0 * p.c0 * p.c0 / p.gamma;
-    a.gamma = p.gamma;
-    a.c0 = p.c0;
-    a.c_const = p.c_mode == SPH_C_CONST;
+    a.I = insts_of(P, w);
     int blocks = (int)((s.n + 255) / 256);
-    if (p.precision == SPH_MIXED)
+    if (P.precision == SPH_MIXED)
         hipLaunchKernelGGL(k_reorder<true>, dim3(blocks), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(k_reorder<false>, dim3(blocks), dim3(256), 0, st, a);
@@ -332,8 +333,7 @@ __global__ void k_cell_table(const uint32_t *__restrict__ keys, int64_t n, int64
     start[c] = (uint32_t)lo;
 }
 
-int launch_cell_table(const sph_params &p, const Ws &w, const uint32_t *keys, hipStream_t st) {
-    (void)p;
+int launch_cell_table(const Ws &w, const uint32_t *keys, hipStream_t st) {
     int64_t m = w.L.ncells + 1;
     int blocks = (int)((m + 255) / 256);
     hipLaunchKernelGGL(k_cell_table, dim3(blocks), dim3(256), 0, st, keys, w.L.n, w.L.ncells,
@@ -344,28 +344,58 @@ int launch_cell_table(const sph_params &p, const Ws &w, const uint32_t *keys, hi
 // ------------------------------------------------------------ chunk list
 //
 // The interaction works on chunks: up to 64 consecutive sorted particles of
-// one cell row (fixed cy, cz).  One workgroup scans the rows, writes every
-// chunk {start, end, row, 0} and the chunk count, and resets the running
-// minimum of the time-step bound and the chunk counter for the interaction
-// that follows.
-__global__ __launch_bounds__(1024) void k_chunks(const uint32_t *__restrict__ start, int nx,
+// one cell row (fixed cy, cz) of one instance.  One workgroup scans all rows
+// of all instances, writes every chunk {start, end, local row, instance} and
+// the chunk count, and prepares the per-instance time-step bound for the
+// interaction that follows: the bound of the last interaction (if there was
+// one) becomes the lagged bound, and the running minimum restarts at +inf.
+// With `lagged` it also sets this step's dt before the interaction runs:
+// the caller's dt, else Cr times the lagged bound (eq. sphdt one step late);
+// with no bound yet, dt = 0 and the CFL flag is raised.
+__global__ __launch_bounds__(1024) void k_chunks(const uint32_t *__restrict__ start, Insts I,
                                                  int64_t nrows, int4 *__restrict__ chunks,
-                                                 DevScalars *sc) {
+                                                 DevScalars *sc, InstState *ist, int lagged,
+                                                 double dt_arg) {
     __shared__ uint32_t sums[1024];
     __shared__ uint32_t carry;
     const int t = threadIdx.x;
     if (t == 0) {
         carry = 0;
-        sc->dt_min_bits = 0x7ff0000000000000ull;  // +inf
         sc->work = 0;
+        if (lagged) sc->steps += 1;
+    }
+    constexpr unsigned long long kInf = 0x7ff0000000000000ull;
+    for (int k = t; k < I.n; k += 1024) {
+        if (ist[k].dt_min_bits != kInf) ist[k].dt_lag_bits = ist[k].dt_min_bits;
+        ist[k].dt_min_bits = kInf;
+        if (lagged) {
+            const double cfl = I.get(k).cfl;
+            const unsigned long long lb = ist[k].dt_lag_bits;
+            const double bound = cfl * __longlong_as_double((long long)lb);
+            double dt = dt_arg > 0.0 ? dt_arg : bound;
+            if (lb == kInf) {
+                if (!(dt_arg > 0.0)) dt = 0.0;
+                sc->dt_cfl_violation = 1u;
+            } else if (dt > bound) {
+                sc->dt_cfl_violation = 1u;
+            }
+            ist[k].dt_cfl = bound;
+            ist[k].dt_last = dt;
+            ist[k].time += dt;
+        }
     }
     __syncthreads();
     for (int64_t r0 = 0; r0 < nrows; r0 += 1024) {
-        int64_t r = r0 + t;
+        const int64_t r = r0 + t;
         uint32_t b = 0, e = 0, nch = 0;
+        int inst = 0, lrow = 0;
         if (r < nrows) {
-            b = start[r * nx];
-            e = start[(r + 1) * nx];
+            inst = I.of_row((uint32_t)r);
+            const Inst ip = I.get(inst);
+            lrow = (int)(r - ip.row_base);
+            const uint32_t c0 = ip.cell_base + (uint32_t)lrow * (uint32_t)ip.nx;
+            b = start[c0];
+            e = start[c0 + ip.nx];
             nch = (e - b + kChunk - 1) / kChunk;
         }
         sums[t] = nch;
@@ -380,7 +410,7 @@ __global__ __launch_bounds__(1024) void k_chunks(const uint32_t *__restrict__ st
         for (uint32_t k = 0; k < nch; ++k) {
             uint32_t s0 = b + k * kChunk;
             uint32_t s1 = s0 + kChunk < e ? s0 + kChunk : e;
-            chunks[first + k] = make_int4((int)s0, (int)s1, (int)r, 0);
+            chunks[first + k] = make_int4((int)s0, (int)s1, lrow, inst);
         }
         __syncthreads();
         if (t == 1023) carry += sums[1023];
@@ -389,9 +419,9 @@ __global__ __launch_bounds__(1024) void k_chunks(const uint32_t *__restrict__ st
     if (t == 0) sc->nchunks = carry;
 }
 
-int launch_chunks(const sph_params &p, const Ws &w, hipStream_t st) {
-    hipLaunchKernelGGL(k_chunks, dim3(1), dim3(1024), 0, st, w.cell_start(), p.dims[0],
-                       w.L.nrows, w.chunks(), w.scalars());
+int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStream_t st) {
+    hipLaunchKernelGGL(k_chunks, dim3(1), dim3(1024), 0, st, w.cell_start(), insts_of(P, w),
+                       w.L.nrows, w.chunks(), w.scalars(), w.inst_state(), (int)lagged, dt);
     return launch_check("chunk list");
 }
 

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "wcsph.h"
 
@@ -19,23 +20,98 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kChunk = 64;           // targets per interaction chunk (one wave)
 constexpr int kDiagThreads = 256;
-constexpr int kDiagBlocks = 512;     // fixed partial count: deterministic sums
+constexpr int kDiagBlocks = 256;     // partial sums of a single system (fixed: deterministic)
+constexpr int kDiagBlocksBatch = 32; // partial sums per instance of a batch
 constexpr int kDiagFields = 16;
-constexpr int kMaxProbes = 1024;    // probe points per sph_diagnostics call
+constexpr int kMaxProbes = 1024;     // probe points per sph_diagnostics call
+constexpr int64_t kMaxGraphSteps = 400;  // longest captured step sequence
 
-// Device-resident scalars inside the workspace.
-struct DevScalars {
-    unsigned long long dt_min_bits;  // bits of the running min of the dt bound
-                                     // (positive doubles order like integers)
+// Constants of one particle system ("instance"): its grid, its slice of the
+// global cell and row numbering, its particles' original ids, and the
+// physical parameters.  A batch holds several; a single system is a batch of
+// one.
+struct Inst {
+    double ox, oy, oz, cs;  // grid origin and cell edge
+    double h, invh, r2max, eta2;
+    double Fm;              // m * 5 w_D / h^2 (radial gradient factor times mass)
+    double wd;              // kernel constant 21 / (16 pi h^3)
+    double alpha, kdelta;   // kdelta = 2 delta h c0
+    double rho0, c0, B, gamma;
+    double gx, gy, gz;
+    double cfl, mass;
+    int32_t nx, ny, nz;
+    int32_t c_const, delta_all, verlet_ns;
+    uint32_t cell_base;     // first global cell id
+    uint32_t row_base;      // first global row id (a row = fixed cy, cz)
+    uint32_t pstart, pend;  // original particle ids [pstart, pend)
+};
+
+// Per-instance device state (time step and clock).
+struct InstState {
+    unsigned long long dt_min_bits;  // running min of this step's bound (bits of
+                                     // a positive double order like integers)
+    unsigned long long dt_lag_bits;  // the previous step's bound (lagged dt)
     double dt_cfl;                   // Cr * bound of the last interaction
     double dt_last;                  // dt used by the last step
     double time;                     // accumulated simulated time
+    double pad;
+};
+
+// Device-wide scalars.
+struct DevScalars {
     long long steps;                 // steps taken
     unsigned int nchunks;            // interaction chunks of the current cells
-    unsigned int dt_cfl_violation;   // a step used dt > dt_cfl
-    unsigned long long pairs[3];     // interacting pairs since init: FF, FB, BF
     unsigned int work;               // next interaction chunk to take
+    unsigned int dt_cfl_violation;   // a step used dt > dt_cfl
     unsigned int pad_;
+    unsigned long long pairs[3];     // interacting pairs since init: FF, FB, BF
+};
+
+// Device-side access to the instances: a table in the workspace (batches) or
+// a single instance passed by value.
+struct Insts {
+    const Inst *tab;
+    Inst one;
+    int n;
+    __device__ __forceinline__ Inst get(int k) const { return tab ? tab[k] : one; }
+    // instance of an original particle id / global cell id / global row
+    __device__ __forceinline__ int of_id(uint32_t id) const {
+        if (n == 1) return 0;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[mid].pstart <= id) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    __device__ __forceinline__ int of_cell(uint32_t cell) const {
+        if (n == 1) return 0;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[mid].cell_base <= cell) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    __device__ __forceinline__ int of_row(uint32_t row) const {
+        if (n == 1) return 0;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[mid].row_base <= row) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+};
+
+// A problem: one or more instances sharing precision and particle arrays.
+struct Problem {
+    int precision = SPH_MIXED;
+    int64_t n = 0;          // particles in total
+    int64_t ncells = 0;     // cells in total
+    int64_t nrows = 0;      // rows in total
+    std::vector<Inst> host; // host copy of the instance constants
+    bool batch = false;     // table in the workspace (else single, by value)
 };
 
 // Byte offsets of the workspace regions (all 256-byte aligned).
@@ -45,6 +121,7 @@ struct WsLayout {
     int64_t nrows = 0;
     int64_t ntiles = 0;
     int64_t max_chunks = 0;
+    int32_t ninst = 0;
     int32_t key_bits = 0;
     int32_t precision = 0;
     size_t keys = 0, keys_alt = 0, vals = 0, vals_alt = 0;
@@ -53,15 +130,17 @@ struct WsLayout {
     size_t cell_start = 0;
     size_t chunks = 0;
     size_t view0 = 0, view1 = 0, view2 = 0;
-    size_t rates = 0;   // ax, ay, az, drho, mumax (each n values)
+    size_t rates = 0;        // ax, ay, az, drho, mumax (each n values)
     size_t scalars = 0;
+    size_t inst_tab = 0;     // Inst[ninst]
+    size_t inst_state = 0;   // InstState[ninst]
     size_t diag_part = 0;
     size_t total = 0;
-    size_t view_elem = 0;  // bytes of one view record (per array)
-    size_t rate_elem = 0;  // bytes of one rate value
+    size_t view_elem = 0;    // bytes of one view record (first two arrays)
+    size_t rate_elem = 0;    // bytes of one rate value
 };
 
-WsLayout make_layout(const sph_params &p, int64_t n);
+WsLayout make_layout(const Problem &P);
 
 // Typed views into a workspace.
 struct Ws {
@@ -77,60 +156,51 @@ struct Ws {
     uint32_t *cell_start() const { return at<uint32_t>(L.cell_start); }
     int4 *chunks() const { return at<int4>(L.chunks); }
     DevScalars *scalars() const { return at<DevScalars>(L.scalars); }
+    Inst *inst_tab() const { return at<Inst>(L.inst_tab); }
+    InstState *inst_state() const { return at<InstState>(L.inst_state); }
     double *diag_part() const { return at<double>(L.diag_part); }
 };
+
+// Accessor for the kernels of one call.
+Insts insts_of(const Problem &P, const Ws &w);
 
 // Thread-local error reporting.
 int fail(int code, const std::string &msg);
 int hip_check(hipError_t e, const char *what);
 int launch_check(const char *what);
 
-// Grid and kernel constants shared by the kernels of one call.
-struct Grid {
-    double ox, oy, oz, cs, inv_cs;
-    int nx, ny, nz;
-};
-
-inline Grid grid_of(const sph_params &p) {
-    Grid g;
-    g.ox = p.origin[0];
-    g.oy = p.origin[1];
-    g.oz = p.origin[2];
-    g.cs = p.cell_size;
-    g.inv_cs = 1.0 / p.cell_size;
-    g.nx = p.dims[0];
-    g.ny = p.dims[1];
-    g.nz = p.dims[2];
-    return g;
-}
-
 // Launchers implemented in the kernel translation units.
-int launch_encode(const sph_params &p, const sph_state &s, const Ws &w, hipStream_t st);
+int launch_encode(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st);
 int launch_sort(const Ws &w, hipStream_t st, uint32_t **sorted_keys, uint32_t **perm);
-int launch_reorder(const sph_params &p, sph_state &s, const Ws &w, const uint32_t *keys,
+int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *keys,
                    const uint32_t *perm, hipStream_t st);
-int launch_cell_table(const sph_params &p, const Ws &w, const uint32_t *keys, hipStream_t st);
-int launch_chunks(const sph_params &p, const Ws &w, hipStream_t st);
-int launch_interact(const sph_params &p, const sph_state &s, const Ws &w, hipStream_t st,
+int launch_cell_table(const Ws &w, const uint32_t *keys, hipStream_t st);
+// lagged: also fix this step's dt from the previous interaction's bound (or dt > 0)
+int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStream_t st);
+// fuse: the interaction also advances every target (time update of step
+// `step`) with the dt already stored per instance, instead of storing rates.
+int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st,
                     int32_t *st_nf = nullptr, int32_t *st_nb = nullptr,
-                    uint32_t *st_hash = nullptr);
-int launch_export_rates(const sph_params &p, const Ws &w, int64_t n, double *ax, double *ay,
-                        double *az, double *drho, double *mumax, hipStream_t st);
-int launch_integrate(const sph_params &p, sph_state &s, const Ws &w, double dt, int64_t step,
+                    uint32_t *st_hash = nullptr, bool fuse = false, int64_t step = 0);
+int launch_export_rates(const Problem &P, const Ws &w, double *ax, double *ay, double *az,
+                        double *drho, double *mumax, hipStream_t st);
+int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
                      hipStream_t st);
-int launch_diag(const sph_params &p, const sph_state &s, const Ws &w, const double *probes,
+int launch_diag(const Problem &P, const sph_state &s, const Ws &w, const double *probes,
                 int32_t np, sph_diag *out, double *probe_p, hipStream_t st);
-int launch_set_density(const sph_params &p, sph_state &s, const double *rho, int which,
-                       hipStream_t st);
-int launch_get_density(const sph_params &p, const sph_state &s, double *rho, int which,
-                       hipStream_t st);
-int launch_ws_init(const Ws &w, hipStream_t st);
+int launch_set_density(const Problem &P, sph_state &s, const Ws &w, const double *rho,
+                       int which, hipStream_t st);
+int launch_get_density(const Problem &P, const sph_state &s, const Ws &w, double *rho,
+                       int which, hipStream_t st);
+int launch_ws_init(const Problem &P, const Ws &w, hipStream_t st);
+void after_fused_step(sph_state &s);
+int diag_blocks(int ninst);
 int set_split(int precision, int split);
 int set_group(int precision, int group);
-int split_for(const sph_params &p, int64_t max_chunks);
-int group_for(const sph_params &p);
+int split_for(const Problem &P, int64_t max_chunks);
+int group_for(const Problem &P);
 
-// Cell id layout: linear = cx + nx * (cy + ny * cz).
+// Cell id layout inside an instance: local = cx + nx * (cy + ny * cz).
 __host__ __device__ inline int64_t lin_cell(int cx, int cy, int cz, int nx, int ny) {
     return cx + (int64_t)nx * (cy + (int64_t)ny * cz);
 }

@@ -9,38 +9,49 @@
 #include <cstdint>
 
 #include "common.h"
+#include "update.h"
 
 namespace wcsph {
 
 struct IntegrateArgs {
     int64_t n;
-    double *x, *y, *z;
-    const double *ux, *uy, *uz;
-    double *uxm, *uym, *uzm;  // in: u at t - dt; out: u at t + dt
-    const void *rho;
-    void *rhom;               // in: rho at t - dt; out: rho at t + dt
-    const uint32_t *id;
-    const void *rates;        // ax, ay, az, drho (n each)
+    StateArrays state;
+    const void *rates;  // ax, ay, az, drho (n each)
+    Insts I;
     DevScalars *sc;
-    double dt_arg, cfl;
-    int euler;
+    InstState *ist;
+    double dt_arg;
+    long long step;
 };
+
+// dt of the instance for this step: the caller's, or Cr times the bound
+// reduced by this step's interaction (eq. sphdt)
+__device__ __forceinline__ double step_dt(const IntegrateArgs &a, const Inst &ip, int k) {
+    const double b = __longlong_as_double((long long)a.ist[k].dt_min_bits);
+    return a.dt_arg > 0.0 ? a.dt_arg : ip.cfl * b;
+}
 
 template <bool kMixed>
 __global__ void k_integrate(IntegrateArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // dt: the caller's, or Cr times the bound reduced by the interaction
-    const double dt = a.dt_arg > 0.0 ? a.dt_arg
-                                     : a.cfl * __longlong_as_double((long long)a.sc->dt_min_bits);
-    if (i == 0) {
-        const double cflb = a.cfl * __longlong_as_double((long long)a.sc->dt_min_bits);
-        a.sc->dt_cfl = cflb;
-        a.sc->dt_last = dt;
-        a.sc->time += dt;
-        a.sc->steps += 1;
-        if (dt > cflb) a.sc->dt_cfl_violation = 1u;
+    if (blockIdx.x == 0) {
+        // per-instance clock
+        for (int k = threadIdx.x; k < a.I.n; k += blockDim.x) {
+            const Inst ip = a.I.get(k);
+            const double b = __longlong_as_double((long long)a.ist[k].dt_min_bits);
+            const double dt = step_dt(a, ip, k);
+            a.ist[k].dt_cfl = ip.cfl * b;
+            a.ist[k].dt_last = dt;
+            a.ist[k].time += dt;
+            if (dt > ip.cfl * b) a.sc->dt_cfl_violation = 1u;
+        }
+        if (threadIdx.x == 0) a.sc->steps += 1;
     }
     if (i >= a.n) return;
+    const int k = a.I.of_id(a.state.id[i] & 0x7fffffffu);
+    const Inst ip = a.I.get(k);
+    const double dt = step_dt(a, ip, k);
+    const bool euler = a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
     const int64_t n = a.n;
     double ax, ay, az, dr;
     if constexpr (kMixed) {
@@ -56,131 +67,122 @@ __global__ void k_integrate(IntegrateArgs a) {
         az = r[2 * n + i];
         dr = r[3 * n + i];
     }
-    const double w = a.euler ? dt : 2.0 * dt;
-    if constexpr (kMixed) {
-        const double cur = (double)static_cast<const float *>(a.rho)[i];
-        float *pm = static_cast<float *>(a.rhom);
-        const double base = a.euler ? cur : (double)pm[i];
-        pm[i] = (float)(base + w * dr);
-    } else {
-        const double cur = static_cast<const double *>(a.rho)[i];
-        double *pm = static_cast<double *>(a.rhom);
-        const double base = a.euler ? cur : pm[i];
-        pm[i] = base + w * dr;
-    }
-    const double ux = a.ux[i], uy = a.uy[i], uz = a.uz[i];
-    if ((a.id[i] >> 31) != 0) {  // boundary: does not move
-        a.uxm[i] = ux;
-        a.uym[i] = uy;
-        a.uzm[i] = uz;
-        return;
-    }
-    const double hdt2 = 0.5 * dt * dt;
-    const double bx = a.euler ? ux : a.uxm[i];
-    const double by = a.euler ? uy : a.uym[i];
-    const double bz = a.euler ? uz : a.uzm[i];
-    a.x[i] = a.x[i] + dt * ux + hdt2 * ax;
-    a.y[i] = a.y[i] + dt * uy + hdt2 * ay;
-    a.z[i] = a.z[i] + dt * uz + hdt2 * az;
-    a.uxm[i] = bx + w * ax;
-    a.uym[i] = by + w * ay;
-    a.uzm[i] = bz + w * az;
+    advance<kMixed>(a.state, i, dt, euler, ax, ay, az, dr);
 }
 
-int launch_integrate(const sph_params &p, sph_state &s, const Ws &w, double dt, int64_t step,
-                     hipStream_t st) {
-    IntegrateArgs a;
-    a.n = s.n;
-    a.x = s.x;
-    a.y = s.y;
-    a.z = s.z;
-    a.ux = s.ux;
-    a.uy = s.uy;
-    a.uz = s.uz;
-    a.uxm = s.uxm;
-    a.uym = s.uym;
-    a.uzm = s.uzm;
-    a.rho = s.rho;
-    a.rhom = s.rhom;
-    a.id = s.id;
-    a.rates = w.base + w.L.rates;
-    a.sc = w.scalars();
-    a.dt_arg = dt;
-    a.cfl = p.cfl;
-    a.euler = (step == 0) || (p.verlet_ns > 0 && step % p.verlet_ns == 0);
-    const int blocks = (int)((s.n + 255) / 256);
-    if (p.precision == SPH_MIXED)
-        hipLaunchKernelGGL(k_integrate<true>, dim3(blocks), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_integrate<false>, dim3(blocks), dim3(256), 0, st, a);
-    if (int rc = launch_check("integrate")) return rc;
-    // the new level was written over the previous one: rotate the pointers
+static void rotate_levels(sph_state &s) {
+    // the new level was written over the previous one
     auto swp = [](auto &u, auto &v) { auto t = u; u = v; v = t; };
     swp(s.ux, s.uxm);
     swp(s.uy, s.uym);
     swp(s.uz, s.uzm);
     swp(s.rho, s.rhom);
+}
+
+int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
+                     hipStream_t st) {
+    IntegrateArgs a;
+    a.n = s.n;
+    a.state = StateArrays{s.x,   s.y,   s.z,   s.ux,  s.uy,   s.uz,
+                          s.uxm, s.uym, s.uzm, s.rho, s.rhom, s.id};
+    a.rates = w.base + w.L.rates;
+    a.I = insts_of(P, w);
+    a.sc = w.scalars();
+    a.ist = w.inst_state();
+    a.dt_arg = dt;
+    a.step = step;
+    const int blocks = (int)((s.n + 255) / 256);
+    if (P.precision == SPH_MIXED)
+        hipLaunchKernelGGL(k_integrate<true>, dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_integrate<false>, dim3(blocks), dim3(256), 0, st, a);
+    if (int rc = launch_check("integrate")) return rc;
+    rotate_levels(s);
     return 0;
 }
 
+// The fused interaction advanced the state in place: rotate the levels.
+void after_fused_step(sph_state &s) { rotate_levels(s); }
+
 // --------------------------------------------------- density conversion
 
-__global__ void k_set_density(const double *__restrict__ src, void *dst, int64_t n, double rho0,
-                              int mixed) {
+__global__ void k_set_density(const double *__restrict__ src, void *dst, int64_t n, Insts I,
+                              const uint32_t *__restrict__ id, int mixed) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (mixed)
+    if (mixed) {
+        const double rho0 = I.get(I.of_id(id[i] & 0x7fffffffu)).rho0;
         static_cast<float *>(dst)[i] = (float)(src[i] - rho0);
-    else
+    } else {
         static_cast<double *>(dst)[i] = src[i];
+    }
 }
 
-__global__ void k_get_density(const void *src, double *__restrict__ dst, int64_t n, double rho0,
-                              int mixed) {
+__global__ void k_get_density(const void *src, double *__restrict__ dst, int64_t n, Insts I,
+                              const uint32_t *__restrict__ id, int mixed) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (mixed)
+    if (mixed) {
+        const double rho0 = I.get(I.of_id(id[i] & 0x7fffffffu)).rho0;
         dst[i] = rho0 + (double)static_cast<const float *>(src)[i];
-    else
+    } else {
         dst[i] = static_cast<const double *>(src)[i];
+    }
 }
 
-int launch_set_density(const sph_params &p, sph_state &s, const double *rho, int which,
+int launch_set_density(const Problem &P, sph_state &s, const Ws &w, const double *rho, int which,
                        hipStream_t st) {
     void *dst = which == 0 ? s.rho : s.rhom;
     const int blocks = (int)((s.n + 255) / 256);
-    hipLaunchKernelGGL(k_set_density, dim3(blocks), dim3(256), 0, st, rho, dst, s.n, p.rho0,
-                       (int)(p.precision == SPH_MIXED));
+    hipLaunchKernelGGL(k_set_density, dim3(blocks), dim3(256), 0, st, rho, dst, s.n,
+                       insts_of(P, w), s.id, (int)(P.precision == SPH_MIXED));
     return launch_check("set density");
 }
 
-int launch_get_density(const sph_params &p, const sph_state &s, double *rho, int which,
+int launch_get_density(const Problem &P, const sph_state &s, const Ws &w, double *rho, int which,
                        hipStream_t st) {
     const void *src = which == 0 ? s.rho : s.rhom;
     const int blocks = (int)((s.n + 255) / 256);
-    hipLaunchKernelGGL(k_get_density, dim3(blocks), dim3(256), 0, st, src, rho, s.n, p.rho0,
-                       (int)(p.precision == SPH_MIXED));
+    hipLaunchKernelGGL(k_get_density, dim3(blocks), dim3(256), 0, st, src, rho, s.n,
+                       insts_of(P, w), s.id, (int)(P.precision == SPH_MIXED));
     return launch_check("get density");
 }
 
 // ------------------------------------------------------ workspace scalars
 
-__global__ void k_ws_init(DevScalars *sc) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        sc->dt_min_bits = 0x7ff0000000000000ull;
-        sc->dt_cfl = 0.0;
-        sc->dt_last = 0.0;
-        sc->time = 0.0;
+__global__ void k_ws_init(DevScalars *sc, InstState *ist, int ninst) {
+    const int t = threadIdx.x;
+    if (t == 0) {
         sc->steps = 0;
         sc->nchunks = 0;
-        sc->dt_cfl_violation = 0;
-        sc->pairs[0] = sc->pairs[1] = sc->pairs[2] = 0;
         sc->work = 0;
+        sc->dt_cfl_violation = 0;
+        sc->pad_ = 0;
+        sc->pairs[0] = sc->pairs[1] = sc->pairs[2] = 0;
+    }
+    for (int k = t; k < ninst; k += blockDim.x) {
+        ist[k].dt_min_bits = 0x7ff0000000000000ull;  // +inf: no bound yet
+        ist[k].dt_lag_bits = 0x7ff0000000000000ull;
+        ist[k].dt_cfl = 0.0;
+        ist[k].dt_last = 0.0;
+        ist[k].time = 0.0;
+        ist[k].pad = 0.0;
     }
 }
 
-int launch_ws_init(const Ws &w, hipStream_t st) {
-    hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(64), 0, st, w.scalars());
+int launch_ws_init(const Problem &P, const Ws &w, hipStream_t st) {
+    if (P.batch) {
+        // the instance table lives in the workspace; the host copy is
+        // staged by the runtime, so the caller may free it on return
+        if (int rc = hip_check(hipMemcpyAsync(w.inst_tab(), P.host.data(),
+                                              sizeof(Inst) * P.host.size(),
+                                              hipMemcpyHostToDevice, st),
+                               "instance table upload"))
+            return rc;
+        if (int rc = hip_check(hipStreamSynchronize(st), "instance table upload")) return rc;
+    }
+    hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(256), 0, st, w.scalars(), w.inst_state(),
+                       (int)P.host.size());
     return launch_check("workspace init");
 }
 

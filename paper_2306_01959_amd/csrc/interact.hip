@@ -36,25 +36,26 @@
 #include <cstdint>
 
 #include "common.h"
+#include "update.h"
 
 namespace wcsph {
 
 struct InteractArgs {
     const int4 *chunks;
-    const DevScalars *sc;
-    const uint32_t *keys;        // sorted cell id of every particle
+    DevScalars *sc;
+    InstState *ist;
+    Insts I;
+    const uint32_t *keys;        // sorted global cell id of every particle
     const uint32_t *cell_start;  // ncells + 1
     const void *v0, *v1, *v2;    // interaction view
     void *ax, *ay, *az, *drho, *mumax;
-    unsigned long long *dt_min_bits;
     unsigned long long *pairs;   // running totals: fluid-fluid, fluid-boundary, boundary-fluid
     unsigned int *work;          // next chunk to take (reset to 0 with the chunk list)
     const uint32_t *id;          // original ids (neighbour statistics only)
     int32_t *st_nf, *st_nb;      // per-particle fluid / boundary neighbour counts
     uint32_t *st_hash;           // per-particle sum of id_hash(id_j) mod 2^32
-    int nx, ny, nz;
-    double cs, h, invh, r2max, eta2, Fm, alpha, kdelta, rho0, c0, gx, gy, gz;
-    int delta_all;
+    StateArrays state;           // fused update: the state to advance
+    long long step;              // fused update: step index (selects the Euler reset)
 };
 
 __device__ __forceinline__ float sq_sum_f32(float dx, float dy, float dz) {
@@ -142,6 +143,7 @@ struct Stats {
 struct Mixed {
     using R = float;
     using V4 = float4;
+    static constexpr bool kMixed = true;
     // target: {o_x, o_y, o_z, own cell x}, {u, P}, {1/rho (0 for boundary),
     // rho - rho0, |c|, -}
     struct T {
@@ -154,7 +156,7 @@ struct Mixed {
         int cx;
         bool ok;
     };
-    __device__ static void target(const InteractArgs &a, int i, bool act, int rowbase, int cxa,
+    __device__ static void target(const InteractArgs &a, const Inst &ip, int i, bool act, int rowbase, int cxa,
                                   V4 &t0, V4 &t1, V4 &t2, float &bx, float &by, float &bz,
                                   bool &fi) {
         float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
@@ -170,12 +172,12 @@ struct Mixed {
         t0 = make_float4(v0.x, v0.y, v0.z, (float)cix);
         t1 = v1;
         t2 = make_float4(fi ? v2.x : 0.f, v0.w, fabsf(v2.y), 0.f);
-        const float csf = (float)a.cs;
+        const float csf = (float)ip.cs;
         bx = v0.x + (float)(cix - cxa) * csf;
         by = v0.y;
         bz = v0.z;
     }
-    __device__ static void load(const InteractArgs &a, int j, int je, int nbase, Cand &c) {
+    __device__ static void load(const InteractArgs &a, const Inst &ip, int j, int je, int nbase, Cand &c) {
         c.ok = j < je;
         if (c.ok) {
             c.v0 = static_cast<const float4 *>(a.v0)[j];
@@ -191,16 +193,16 @@ struct Mixed {
     }
     // position of a candidate in the chunk frame (cell cxa of the chunk's
     // row), for culling only
-    __device__ static void cull_pos(const InteractArgs &a, const Cand &c, int cxa, int dy, int dz,
+    __device__ static void cull_pos(const InteractArgs &a, const Inst &ip, const Cand &c, int cxa, int dy, int dz,
                                     float &qx, float &qy, float &qz) {
-        const float csf = (float)a.cs;
+        const float csf = (float)ip.cs;
         qx = c.v0.x + (float)(c.cx - cxa) * csf;
         qy = c.v0.y + (float)dy * csf;
         qz = c.v0.z + (float)dz * csf;
     }
-    __device__ static void rec_pos(const InteractArgs &a, const float4 &r0, int cxa, float &qx,
+    __device__ static void rec_pos(const InteractArgs &a, const Inst &ip, const float4 &r0, int cxa, float &qx,
                                    float &qy, float &qz) {
-        qx = r0.x + (r0.y - (float)cxa) * (float)a.cs;
+        qx = r0.x + (r0.y - (float)cxa) * (float)ip.cs;
         qy = r0.z;
         qz = r0.w;
     }
@@ -209,12 +211,12 @@ struct Mixed {
     // record: {o_x, c_x, o_y + dy cs, o_z + dz cs}, {u, P/rho}, {index bits,
     // 1/rho, (rho - rho0) B, B} with B = 2 delta h c0 / rho (0 when the pair
     // carries no delta term), {rho - rho0, +-c (- = boundary), -, -}
-    __device__ static void stage(const InteractArgs &a, const Cand &c, int j, int dy, int dz,
+    __device__ static void stage(const InteractArgs &a, const Inst &ip, const Cand &c, int j, int dy, int dz,
                                  float4 *rec0, float4 *rec1, float4 *rec2, float4 *rec3) {
-        const float csf = (float)a.cs;
+        const float csf = (float)ip.cs;
         const float invr = c.v2.x;
         const bool fj = c.v2.y > 0.f;
-        const float kd = (fj || a.delta_all) ? (float)a.kdelta : 0.f;
+        const float kd = (fj || ip.delta_all) ? (float)ip.kdelta : 0.f;
         const float B = kd * invr;
         *rec0 = make_float4(c.v0.x, (float)c.cx, c.v0.y + (float)dy * csf,
                             c.v0.z + (float)dz * csf);
@@ -224,10 +226,10 @@ struct Mixed {
     }
     // one (target, record) pair; `valid` is false for idle lanes
     template <bool kStats>
-    __device__ static void pair(const InteractArgs &a, const T &t, int ti, bool valid,
+    __device__ static void pair(const InteractArgs &a, const Inst &ip, const T &t, int ti, bool valid,
                                 const float4 &r0, const float4 &r1, const float4 &r2,
                                 const float4 &r3, Acc<float> &acc, Counters &cn, Stats &st) {
-        const float csf = (float)a.cs;
+        const float csf = (float)ip.cs;
         const bool fi = t.fluid();
         const bool fj = r3.y > 0.f;
         const float sx = fmaf(r0.y - t.a.w, csf, r0.x);
@@ -236,7 +238,7 @@ struct Mixed {
         const float dz = r0.w - t.a.z;
         const float rr = sq_sum_f32(dx, dy, dz);
         const int j = __float_as_int(r2.x);
-        const bool in = valid && rr < (float)a.r2max && j != ti && (fi || fj);
+        const bool in = valid && rr < (float)ip.r2max && j != ti && (fi || fj);
         const uint64_t inm = __ballot(in);
         if (inm == 0) return;
         const uint64_t fim = __ballot(fi);
@@ -252,41 +254,49 @@ struct Mixed {
             st.h += id_hash(a.id[j] & 0x7fffffffu);
         }
         const float r = __builtin_amdgcn_sqrtf(rr);
-        const float q2 = fmaf(r, -0.5f * (float)a.invh, 1.f);  // 1 - q/2
-        const float F = in ? (float)a.Fm * q2 * q2 * q2 : 0.f;   // m 5 w_D/h^2 (1-q/2)^3
+        const float q2 = fmaf(r, -0.5f * (float)ip.invh, 1.f);  // 1 - q/2
+        const float F = in ? (float)ip.Fm * q2 * q2 * q2 : 0.f;   // m 5 w_D/h^2 (1-q/2)^3
         const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const float vr = vx * dx + vy * dy + vz * dz;               // u_ij . r_ij
-        const float mu = (float)a.h * vr * __builtin_amdgcn_rcpf(rr + (float)a.eta2);
+        const float mu = (float)ip.h * vr * __builtin_amdgcn_rcpf(rr + (float)ip.eta2);
         acc.mu = in ? fmaxf(acc.mu, fabsf(mu)) : acc.mu;
         acc.dr -= F * vr;                                    // m (u_i - u_j) . grad_i W_ij
         const float Fd = fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;             // delta term
         const float visc =
-            vr < 0.f ? -(float)a.alpha * (t.c.z + fabsf(r3.y)) * mu *
-                           __builtin_amdgcn_rcpf((float)(2.0 * a.rho0) + t.c.y + r3.x)
+            vr < 0.f ? -(float)ip.alpha * (t.c.z + fabsf(r3.y)) * mu *
+                           __builtin_amdgcn_rcpf((float)(2.0 * ip.rho0) + t.c.y + r3.x)
                      : 0.f;
         const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
         acc.az -= s * dz;
     }
-    __device__ static void store(const InteractArgs &a, int i, bool fi, float ax, float ay,
-                                 float az, float dr, float mum, double &bound) {
+    // final sums of target i: + g for fluid; optional store of the rates;
+    // the particle's time-step bound (eq. sphdt); FP64 accelerations out
+    __device__ static void store(const InteractArgs &a, const Inst &ip, int i, bool fi, float ax,
+                                 float ay, float az, float dr, float mum, bool write,
+                                 double &bound, double &oax, double &oay, double &oaz) {
         float fax = 0.f, fay = 0.f, faz = 0.f;
         if (fi) {
-            fax = ax + (float)a.gx;
-            fay = ay + (float)a.gy;
-            faz = az + (float)a.gz;
+            fax = ax + (float)ip.gx;
+            fay = ay + (float)ip.gy;
+            faz = az + (float)ip.gz;
         }
-        static_cast<float *>(a.ax)[i] = fax;
-        static_cast<float *>(a.ay)[i] = fay;
-        static_cast<float *>(a.az)[i] = faz;
-        static_cast<float *>(a.drho)[i] = dr;
-        static_cast<float *>(a.mumax)[i] = mum;
-        bound = a.h / (a.c0 + (double)mum);
+        if (write) {
+            static_cast<float *>(a.ax)[i] = fax;
+            static_cast<float *>(a.ay)[i] = fay;
+            static_cast<float *>(a.az)[i] = faz;
+            static_cast<float *>(a.drho)[i] = dr;
+            static_cast<float *>(a.mumax)[i] = mum;
+        }
+        oax = fax;
+        oay = fay;
+        oaz = faz;
+        bound = ip.h / (ip.c0 + (double)mum);
         if (fi) {
             const double am = sqrt((double)fax * fax + (double)fay * fay + (double)faz * faz);
-            if (am > 0.0) bound = fmin(bound, sqrt(a.h / am));
+            if (am > 0.0) bound = fmin(bound, sqrt(ip.h / am));
         }
     }
 };
@@ -294,6 +304,7 @@ struct Mixed {
 struct Fp64 {
     using R = double;
     using V4 = double4;
+    static constexpr bool kMixed = false;
     // target: {x, y, z, -}, {u, P}, {1/rho (0 for boundary), rho, |c|, -}
     struct T {
         double4 a, b, c;
@@ -304,7 +315,7 @@ struct Fp64 {
         double2 v2;
         bool ok;
     };
-    __device__ static void target(const InteractArgs &a, int i, bool act, int rowbase, int cxa,
+    __device__ static void target(const InteractArgs &a, const Inst &ip, int i, bool act, int rowbase, int cxa,
                                   V4 &t0, V4 &t1, V4 &t2, double &bx, double &by, double &bz,
                                   bool &fi) {
         (void)rowbase;
@@ -324,7 +335,7 @@ struct Fp64 {
         by = v0.y;
         bz = v0.z;
     }
-    __device__ static void load(const InteractArgs &a, int j, int je, int nbase, Cand &c) {
+    __device__ static void load(const InteractArgs &a, const Inst &ip, int j, int je, int nbase, Cand &c) {
         (void)nbase;
         c.ok = j < je;
         if (c.ok) {
@@ -337,7 +348,7 @@ struct Fp64 {
             c.v2 = make_double2(1, 1);
         }
     }
-    __device__ static void cull_pos(const InteractArgs &a, const Cand &c, int cxa, int dy, int dz,
+    __device__ static void cull_pos(const InteractArgs &a, const Inst &ip, const Cand &c, int cxa, int dy, int dz,
                                     double &qx, double &qy, double &qz) {
         (void)a;
         (void)cxa;
@@ -347,7 +358,7 @@ struct Fp64 {
         qy = c.v0.y;
         qz = c.v0.z;
     }
-    __device__ static void rec_pos(const InteractArgs &a, const double4 &r0, int cxa, double &qx,
+    __device__ static void rec_pos(const InteractArgs &a, const Inst &ip, const double4 &r0, int cxa, double &qx,
                                    double &qy, double &qz) {
         (void)a;
         (void)cxa;
@@ -358,20 +369,20 @@ struct Fp64 {
     __device__ static bool cand_fluid(const Cand &c) { return c.v2.y > 0.0; }
     __device__ static bool rec_fluid(const double4 &r3) { return r3.y > 0.0; }
     // record: {x, y, z, index}, {u, P/rho}, {1/rho, B, rho, -}, {-, +-c, -, -}
-    __device__ static void stage(const InteractArgs &a, const Cand &c, int j, int dy, int dz,
+    __device__ static void stage(const InteractArgs &a, const Inst &ip, const Cand &c, int j, int dy, int dz,
                                  double4 *rec0, double4 *rec1, double4 *rec2, double4 *rec3) {
         (void)dy;
         (void)dz;
         const double invr = c.v2.x;
         const bool fj = c.v2.y > 0.0;
-        const double B = (fj || a.delta_all) ? a.kdelta * invr : 0.0;
+        const double B = (fj || ip.delta_all) ? ip.kdelta * invr : 0.0;
         *rec0 = make_double4(c.v0.x, c.v0.y, c.v0.z, (double)j);
         *rec1 = make_double4(c.v1.x, c.v1.y, c.v1.z, c.v1.w * invr);
         *rec2 = make_double4(invr, B, c.v0.w, 0.0);
         *rec3 = make_double4(0.0, c.v2.y, 0.0, 0.0);
     }
     template <bool kStats>
-    __device__ static void pair(const InteractArgs &a, const T &t, int ti, bool valid,
+    __device__ static void pair(const InteractArgs &a, const Inst &ip, const T &t, int ti, bool valid,
                                 const double4 &r0, const double4 &r1, const double4 &r2,
                                 const double4 &r3, Acc<double> &acc, Counters &cn, Stats &st) {
         const bool fi = t.fluid();
@@ -379,7 +390,7 @@ struct Fp64 {
         const double dx = r0.x - t.a.x, dy = r0.y - t.a.y, dz = r0.z - t.a.z;
         const double rr = sq_sum_f64(dx, dy, dz);
         const int j = (int)r0.w;
-        const bool in = valid && rr < a.r2max && j != ti && (fi || fj);
+        const bool in = valid && rr < ip.r2max && j != ti && (fi || fj);
         const uint64_t inm = __ballot(in);
         if (inm == 0) return;
         const uint64_t fim = __ballot(fi);
@@ -394,46 +405,53 @@ struct Fp64 {
                 ++st.b;
             st.h += id_hash(a.id[j] & 0x7fffffffu);
         }
-        const double q2 = 1.0 - 0.5 * (sqrt(rr) * a.invh);
-        const double F = in ? a.Fm * q2 * q2 * q2 : 0.0;
+        const double q2 = 1.0 - 0.5 * (sqrt(rr) * ip.invh);
+        const double F = in ? ip.Fm * q2 * q2 * q2 : 0.0;
         const double vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const double vr = vx * dx + vy * dy + vz * dz;
-        const double mu = a.h * vr / (rr + a.eta2);
+        const double mu = ip.h * vr / (rr + ip.eta2);
         acc.mu = in ? fmax(acc.mu, fabs(mu)) : acc.mu;
         acc.dr -= F * vr;
         const double Fd = fi ? F : 0.0;
         acc.dr += (r2.z - t.c.y) * r2.y * Fd;
         const double visc =
-            vr < 0.0 ? -a.alpha * (t.c.z + fabs(r3.y)) * mu / (t.c.y + r2.z) : 0.0;
+            vr < 0.0 ? -ip.alpha * (t.c.z + fabs(r3.y)) * mu / (t.c.y + r2.z) : 0.0;
         const double s = (fma(t.b.w, r2.x, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
         acc.az -= s * dz;
     }
-    __device__ static void store(const InteractArgs &a, int i, bool fi, double ax, double ay,
-                                 double az, double dr, double mum, double &bound) {
+    __device__ static void store(const InteractArgs &a, const Inst &ip, int i, bool fi,
+                                 double ax, double ay, double az, double dr, double mum,
+                                 bool write, double &bound, double &oax, double &oay,
+                                 double &oaz) {
         double fax = 0, fay = 0, faz = 0;
         if (fi) {
-            fax = ax + a.gx;
-            fay = ay + a.gy;
-            faz = az + a.gz;
+            fax = ax + ip.gx;
+            fay = ay + ip.gy;
+            faz = az + ip.gz;
         }
-        static_cast<double *>(a.ax)[i] = fax;
-        static_cast<double *>(a.ay)[i] = fay;
-        static_cast<double *>(a.az)[i] = faz;
-        static_cast<double *>(a.drho)[i] = dr;
-        static_cast<double *>(a.mumax)[i] = mum;
-        bound = a.h / (a.c0 + mum);
+        if (write) {
+            static_cast<double *>(a.ax)[i] = fax;
+            static_cast<double *>(a.ay)[i] = fay;
+            static_cast<double *>(a.az)[i] = faz;
+            static_cast<double *>(a.drho)[i] = dr;
+            static_cast<double *>(a.mumax)[i] = mum;
+        }
+        oax = fax;
+        oay = fay;
+        oaz = faz;
+        bound = ip.h / (ip.c0 + mum);
         if (fi) {
             const double am = sqrt(fax * fax + fay * fay + faz * faz);
-            if (am > 0.0) bound = fmin(bound, sqrt(a.h / am));
+            if (am > 0.0) bound = fmin(bound, sqrt(ip.h / am));
         }
     }
 };
 
 // ================================================================ skeleton
 
-template <class P, int kSplit, int kT, bool kStats>
+template <class P, int kSplit, int kT, bool kStats, bool kFuse>
 __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     using R = typename P::R;
     using V4 = typename P::V4;
@@ -469,10 +487,11 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     const uint32_t chunk = (uint32_t)uni((int)s_next);
     if (chunk >= a.sc->nchunks) break;
     const int4 ch = a.chunks[chunk];
-    const int cs0 = uni(ch.x), cs1 = uni(ch.y), row = uni(ch.z);
-    const int cy = row % a.ny, cz = row / a.ny;
+    const int cs0 = uni(ch.x), cs1 = uni(ch.y), row = uni(ch.z), inst = uni(ch.w);
+    const Inst ip = a.I.get(inst);
+    const int cy = row % ip.ny, cz = row / ip.ny;
     const int ntgt = cs1 - cs0;
-    const int rowbase = row * a.nx;
+    const int rowbase = (int)ip.cell_base + row * ip.nx;
     const int cxa = uni((int)a.keys[cs0] - rowbase);
     const int cxb = uni((int)a.keys[cs1 - 1] - rowbase);
 
@@ -483,7 +502,7 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     bool fi_own;
     {
         V4 t0, t1, t2;
-        P::target(a, it, act, rowbase, cxa, t0, t1, t2, bx, by, bz, fi_own);
+        P::target(a, ip, it, act, rowbase, cxa, t0, t1, t2, bx, by, bz, fi_own);
         if (w == 0) {
             tgt[0][lane] = t0;
             tgt[1][lane] = t1;
@@ -510,7 +529,7 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     const R loz = group_min(act ? bz : big, kWave), hiz = group_max(act ? bz : -big, kWave);
     const uint64_t fluid_tgts = __ballot(fi_own);
     const bool any_fluid = fluid_tgts != 0ull;
-    const R cull2 = (R)(a.r2max * (1.0 + 1e-3));
+    const R cull2 = (R)(ip.r2max * (1.0 + 1e-3));
     const uint64_t below = lanes_below();
 
     // this wave's stencil rows: {first, end, row base cell, (dy+1) | (dz+1) << 2}
@@ -519,10 +538,10 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
         const int dz = rr / 3 - 1, dy = rr % 3 - 1;
         const int czn = cz + dz, cyn = cy + dy;
         int js = 0, je = 0, nbase = 0;
-        if (czn >= 0 && czn < a.nz && cyn >= 0 && cyn < a.ny) {
-            nbase = (czn * a.ny + cyn) * a.nx;
+        if (czn >= 0 && czn < ip.nz && cyn >= 0 && cyn < ip.ny) {
+            nbase = (int)ip.cell_base + (czn * ip.ny + cyn) * ip.nx;
             const int xlo = cxa - 1 < 0 ? 0 : cxa - 1;
-            const int xhi = cxb + 1 >= a.nx ? a.nx - 1 : cxb + 1;
+            const int xhi = cxb + 1 >= ip.nx ? ip.nx - 1 : cxb + 1;
             js = (int)a.cell_start[nbase + xlo];
             je = (int)a.cell_start[nbase + xhi + 1];
         }
@@ -544,7 +563,7 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     int q = uni(next_row(0));
     int jb = q < kRows ? uni(rows[w][q].x) : 0;
     typename P::Cand cur, nxt;
-    if (q < kRows) P::load(a, jb + lane, rows[w][q].y, rows[w][q].z, cur);
+    if (q < kRows) P::load(a, ip, jb + lane, rows[w][q].y, rows[w][q].z, cur);
     while (q < kRows) {
         const int4 rq = rows[w][q];
         const int dy = (rq.w & 3) - 1, dz = (rq.w >> 2) - 1;
@@ -553,13 +572,13 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
             q2 = uni(next_row(q + 1));
             jb2 = q2 < kRows ? uni(rows[w][q2].x) : 0;
         }
-        if (q2 < kRows) P::load(a, jb2 + lane, rows[w][q2].y, rows[w][q2].z, nxt);
+        if (q2 < kRows) P::load(a, ip, jb2 + lane, rows[w][q2].y, rows[w][q2].z, nxt);
 
         // cull against the chunk box, compact the survivors into LDS
         bool keep = false;
         if (cur.ok) {
             R qx, qy, qz;
-            P::cull_pos(a, cur, cxa, dy, dz, qx, qy, qz);
+            P::cull_pos(a, ip, cur, cxa, dy, dz, qx, qy, qz);
             const R ex = fmax(fmax(lox - qx, qx - hix), (R)0);
             const R ey = fmax(fmax(loy - qy, qy - hiy), (R)0);
             const R ez = fmax(fmax(loz - qz, qz - hiz), (R)0);
@@ -568,7 +587,7 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
         const uint64_t m = __ballot(keep);
         if (keep) {
             const int slot = __popcll(m & below);
-            P::stage(a, cur, jb + lane, dy, dz, &stg[w][0][slot], &stg[w][1][slot],
+            P::stage(a, ip, cur, jb + lane, dy, dz, &stg[w][0][slot], &stg[w][1][slot],
                      &stg[w][2][slot], &stg[w][3][slot]);
         }
         wave_sync();
@@ -580,7 +599,7 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
             if (lane < cnt) {
                 const V4 r0 = stg[w][0][lane];
                 const V4 r3 = stg[w][3][lane];
-                P::rec_pos(a, r0, cxa, px, py, pz);
+                P::rec_pos(a, ip, r0, cxa, px, py, pz);
                 rf = P::rec_fluid(r3);
             }
             int gcnt[kG];
@@ -612,7 +631,7 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
                     const int k = sl < gcnt[g] ? (int)glist[w][g][sl] : 0;
                     const V4 r0 = stg[w][0][k], r1 = stg[w][1][k];
                     const V4 r2 = stg[w][2][k], r3 = stg[w][3][k];
-                    P::template pair<kStats>(a, tg, ti, valid, r0, r1, r2, r3, acc[g], cn,
+                    P::template pair<kStats>(a, ip, tg, ti, valid, r0, r1, r2, r3, acc[g], cn,
                                              sts[g]);
                 }
             }
@@ -680,15 +699,26 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     }
     double bound = __longlong_as_double(0x7ff0000000000000ll);
     if (act) {
-        P::store(a, it, fi_own, sx, sy, sz, sd, sm, bound);
+        double fax, fay, faz;
+        P::store(a, ip, it, fi_own, sx, sy, sz, sd, sm, !kFuse, bound, fax, fay, faz);
         if constexpr (kStats) {
             a.st_nf[it] = nf;
             a.st_nb[it] = nbd;
             a.st_hash[it] = hs;
         }
+        if constexpr (kFuse) {
+            // every chunk reads the view, a separate copy of the state, so a
+            // target can be advanced as soon as its own sums are complete; dt
+            // was fixed before the launch (the lagged bound or the caller's)
+            const double dt = a.ist[inst].dt_last;
+            const bool euler =
+                a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
+            advance<P::kMixed>(a.state, it, dt, euler, fax, fay, faz, (double)sd);
+        }
     }
     bound = group_min(bound, kWave);
-    if (lane == 0) atomicMin(a.dt_min_bits, (unsigned long long)__double_as_longlong(bound));
+    if (lane == 0)
+        atomicMin(&a.ist[inst].dt_min_bits, (unsigned long long)__double_as_longlong(bound));
     }  // w == 0
     }  // chunks
     // pair totals: integer atomics, order does not matter
@@ -720,8 +750,8 @@ int set_group(int precision, int group) {
     return 0;
 }
 
-int split_for(const sph_params &p, int64_t max_chunks) {
-    const int s = g_split[p.precision == SPH_MIXED ? SPH_MIXED : SPH_FP64];
+int split_for(const Problem &P, int64_t max_chunks) {
+    const int s = g_split[P.precision == SPH_MIXED ? SPH_MIXED : SPH_FP64];
     if (s) return s;
     // enough waves to fill 256 CUs x 4 SIMDs several times over
     if (max_chunks < 2048) return 9;
@@ -729,8 +759,8 @@ int split_for(const sph_params &p, int64_t max_chunks) {
     return 1;
 }
 
-int group_for(const sph_params &p) {
-    const int pr = p.precision == SPH_MIXED ? SPH_MIXED : SPH_FP64;
+int group_for(const Problem &P) {
+    const int pr = P.precision == SPH_MIXED ? SPH_MIXED : SPH_FP64;
     if (g_group[pr]) return g_group[pr];
     return pr == SPH_MIXED ? 8 : 16;
 }
@@ -753,49 +783,72 @@ static uint32_t persistent_grid(K kernel, int threads, uint32_t cap) {
     return (uint32_t)(full < cap ? full : cap);
 }
 
-template <class P, int kSplit, int kT, bool kStats>
+template <class P, int kSplit, int kT, bool kStats, bool kFuse>
 static void launch_one(uint32_t cap, const InteractArgs &a, hipStream_t st) {
-    auto kern = k_interact<P, kSplit, kT, kStats>;
-    const uint32_t nb = persistent_grid(kern, kWave * kSplit, cap);
+    auto kern = k_interact<P, kSplit, kT, kStats, kFuse>;
+    // the grid depends only on the kernel and the device: computed once
+    static thread_local int dev_seen = -1;
+    static thread_local uint32_t full = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (dev != dev_seen) {
+        full = persistent_grid(kern, kWave * kSplit, 0xffffffffu);
+        dev_seen = dev;
+    }
+    const uint32_t nb = full < cap ? full : cap;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kWave * kSplit), 0, st, a);
 }
 
-template <class P, int kSplit, bool kStats>
+template <class P, int kSplit, bool kStats, bool kFuse>
 static void launch_group(int group, uint32_t cap, const InteractArgs &a, hipStream_t st) {
     switch (group) {
     case 8:
-        launch_one<P, kSplit, 8, kStats>(cap, a, st);
+        launch_one<P, kSplit, 8, kStats, kFuse>(cap, a, st);
         break;
     case 16:
-        launch_one<P, kSplit, 16, kStats>(cap, a, st);
+        launch_one<P, kSplit, 16, kStats, kFuse>(cap, a, st);
         break;
     default:
-        launch_one<P, kSplit, 64, kStats>(cap, a, st);
+        launch_one<P, kSplit, 64, kStats, kFuse>(cap, a, st);
         break;
     }
 }
 
-template <class P, bool kStats>
+template <class P, bool kStats, bool kFuse>
 static void launch_shape(int split, int group, uint32_t nb, const InteractArgs &a,
                          hipStream_t st) {
     switch (split) {
     case 9:
-        launch_group<P, 9, kStats>(group, nb, a, st);
+        launch_group<P, 9, kStats, kFuse>(group, nb, a, st);
         break;
     case 3:
-        launch_group<P, 3, kStats>(group, nb, a, st);
+        launch_group<P, 3, kStats, kFuse>(group, nb, a, st);
         break;
     default:
-        launch_group<P, 1, kStats>(group, nb, a, st);
+        launch_group<P, 1, kStats, kFuse>(group, nb, a, st);
         break;
     }
 }
 
-int launch_interact(const sph_params &p, const sph_state &s, const Ws &w, hipStream_t st,
-                    int32_t *st_nf, int32_t *st_nb, uint32_t *st_hash) {
+template <class P>
+static void launch_prec(int split, int group, uint32_t nb, bool stats, bool fuse,
+                        const InteractArgs &a, hipStream_t st) {
+    if (stats)
+        launch_shape<P, true, false>(split, group, nb, a, st);
+    else if (fuse)
+        launch_shape<P, false, true>(split, group, nb, a, st);
+    else
+        launch_shape<P, false, false>(split, group, nb, a, st);
+}
+
+int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st,
+                    int32_t *st_nf, int32_t *st_nb, uint32_t *st_hash, bool fuse,
+                    int64_t step) {
     InteractArgs a;
     a.chunks = w.chunks();
     a.sc = w.scalars();
+    a.ist = w.inst_state();
+    a.I = insts_of(P, w);
     a.keys = w.at<uint32_t>(w.L.sorted_keys);
     a.cell_start = w.cell_start();
     a.v0 = w.base + w.L.view0;
@@ -809,46 +862,23 @@ int launch_interact(const sph_params &p, const sph_state &s, const Ws &w, hipStr
     a.az = r + 2 * e * n;
     a.drho = r + 3 * e * n;
     a.mumax = r + 4 * e * n;
-    a.dt_min_bits = &w.scalars()->dt_min_bits;
     a.pairs = w.scalars()->pairs;
+    a.work = &w.scalars()->work;
     a.id = s.id;
     a.st_nf = st_nf;
     a.st_nb = st_nb;
     a.st_hash = st_hash;
+    a.state = StateArrays{s.x,   s.y,   s.z,   s.ux,   s.uy,  s.uz,
+                          s.uxm, s.uym, s.uzm, s.rho,  s.rhom, s.id};
+    a.step = step;
     const bool stats = st_nf != nullptr;
-    a.nx = p.dims[0];
-    a.ny = p.dims[1];
-    a.nz = p.dims[2];
     const uint32_t nb = (uint32_t)w.L.max_chunks;  // cap on the persistent grid
-    a.work = &w.scalars()->work;
-    a.cs = p.cell_size;
-    a.h = p.h;
-    a.invh = 1.0 / p.h;
-    a.r2max = 4.0 * p.h * p.h;
-    a.eta2 = p.eta2_coef * p.h * p.h;
-    const double wd = 21.0 / (16.0 * M_PI * p.h * p.h * p.h);
-    a.Fm = p.mass * 5.0 * wd / (p.h * p.h);
-    a.alpha = p.alpha;
-    a.kdelta = 2.0 * p.delta * p.h * p.c0;
-    a.rho0 = p.rho0;
-    a.c0 = p.c0;
-    a.gx = p.g[0];
-    a.gy = p.g[1];
-    a.gz = p.g[2];
-    a.delta_all = p.delta_pairs == SPH_DELTA_ALL;
-    const int split = split_for(p, w.L.max_chunks);
-    const int group = group_for(p);
-    if (p.precision == SPH_MIXED) {
-        if (stats)
-            launch_shape<Mixed, true>(split, group, nb, a, st);
-        else
-            launch_shape<Mixed, false>(split, group, nb, a, st);
-    } else {
-        if (stats)
-            launch_shape<Fp64, true>(split, group, nb, a, st);
-        else
-            launch_shape<Fp64, false>(split, group, nb, a, st);
-    }
+    const int split = split_for(P, w.L.max_chunks);
+    const int group = group_for(P);
+    if (P.precision == SPH_MIXED)
+        launch_prec<Mixed>(split, group, nb, stats, fuse && !stats, a, st);
+    else
+        launch_prec<Fp64>(split, group, nb, stats, fuse && !stats, a, st);
     return launch_check("interact");
 }
 
@@ -865,10 +895,11 @@ __global__ void k_export(const T *__restrict__ r, int64_t n, double *ax, double 
     if (mm) mm[i] = (double)r[4 * n + i];
 }
 
-int launch_export_rates(const sph_params &p, const Ws &w, int64_t n, double *ax, double *ay,
-                        double *az, double *drho, double *mumax, hipStream_t st) {
+int launch_export_rates(const Problem &P, const Ws &w, double *ax, double *ay, double *az,
+                        double *drho, double *mumax, hipStream_t st) {
+    const int64_t n = P.n;
     int blocks = (int)((n + 255) / 256);
-    if (p.precision == SPH_MIXED)
+    if (P.precision == SPH_MIXED)
         hipLaunchKernelGGL(k_export<float>, dim3(blocks), dim3(256), 0, st,
                            w.at<const float>(w.L.rates), n, ax, ay, az, drho, mumax);
     else

@@ -1,0 +1,58 @@
+// Time update of one particle (Section 2.2): Verlet scheme, eqs. sphu1,
+// sphr1, sphrho1, and the Euler reset of eqs. sphu2, sphr2, sphrho2.  Fluid
+// particles update r, u, rho; dynamic boundary particles rho only.  The new
+// level is written over the previous one (um, rhom); the caller then swaps the
+// (u, um) and (rho, rhom) pointers.  FP64 accumulators for r and u; the mixed
+// path keeps rho - rho0 in FP32, updated in FP64 and rounded once.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace wcsph {
+
+struct StateArrays {
+    double *x, *y, *z;
+    const double *ux, *uy, *uz;
+    double *uxm, *uym, *uzm;
+    const void *rho;
+    void *rhom;
+    const uint32_t *id;
+};
+
+template <bool kMixed>
+__device__ __forceinline__ void advance(const StateArrays &s, int64_t i, double dt, bool euler,
+                                        double ax, double ay, double az, double dr) {
+    const double w = euler ? dt : 2.0 * dt;
+    if constexpr (kMixed) {
+        const double cur = (double)static_cast<const float *>(s.rho)[i];
+        float *pm = static_cast<float *>(s.rhom);
+        const double base = euler ? cur : (double)pm[i];
+        pm[i] = (float)(base + w * dr);
+    } else {
+        const double cur = static_cast<const double *>(s.rho)[i];
+        double *pm = static_cast<double *>(s.rhom);
+        const double base = euler ? cur : pm[i];
+        pm[i] = base + w * dr;
+    }
+    const double ux = s.ux[i], uy = s.uy[i], uz = s.uz[i];
+    if ((s.id[i] >> 31) != 0) {  // boundary: does not move
+        s.uxm[i] = ux;
+        s.uym[i] = uy;
+        s.uzm[i] = uz;
+        return;
+    }
+    const double hdt2 = 0.5 * dt * dt;
+    const double bx = euler ? ux : s.uxm[i];
+    const double by = euler ? uy : s.uym[i];
+    const double bz = euler ? uz : s.uzm[i];
+    s.x[i] = s.x[i] + dt * ux + hdt2 * ax;
+    s.y[i] = s.y[i] + dt * uy + hdt2 * ay;
+    s.z[i] = s.z[i] + dt * uz + hdt2 * az;
+    s.uxm[i] = bx + w * ax;
+    s.uym[i] = by + w * ay;
+    s.uzm[i] = bz + w * az;
+}
+
+}  // namespace wcsph

@@ -23,12 +23,19 @@ SPH_DELTA_FLUID, SPH_DELTA_ALL = 0, 1
 FLAG_NONFINITE, FLAG_OUTSIDE, FLAG_DENSITY, FLAG_DT_CFL = 1, 2, 4, 8
 BOUNDARY_BIT = np.uint32(1 << 31)
 
+REGION_INTERACT, REGION_SORT, REGION_REORDER, REGION_STEP = 0, 1, 2, 3
+RUN_LAGGED, RUN_GRAPH = 1, 2
+MAX_INSTANCES = 4096
+
 #: every symbol include/wcsph.h declares
 EXPORTS = ("sph_version", "sph_last_error", "sph_check_params", "sph_set_tuning",
            "sph_get_split", "sph_workspace_bytes",
            "sph_workspace_init", "sph_set_density", "sph_get_density", "sph_build_cells",
            "sph_interact", "sph_neighbour_stats", "sph_step", "sph_run", "sph_run_profiled",
-           "sph_diagnostics")
+           "sph_diagnostics", "sph_batch_workspace_bytes", "sph_batch_workspace_init",
+           "sph_batch_set_density", "sph_batch_get_density", "sph_batch_build_cells",
+           "sph_batch_interact", "sph_batch_run", "sph_batch_run_profiled",
+           "sph_batch_diagnostics")
 
 
 class SphParams(C.Structure):
@@ -76,6 +83,11 @@ class SphDiag(C.Structure):
         return d
 
 
+class SphBatch(C.Structure):
+    _fields_ = [("ninst", C.c_int32), ("reserved", C.c_int32),
+                ("params", C.POINTER(SphParams)), ("counts", C.POINTER(C.c_int64))]
+
+
 class SphError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libwcsph error {code}: {msg}")
@@ -111,8 +123,20 @@ def load(path: str = LIB_PATH):
     L.sph_neighbour_stats.argtypes = [PP, PS, _P, _P, _P, _P, _P]
     L.sph_step.argtypes = [PP, PS, _P, C.c_double, C.c_int64, _P]
     L.sph_run.argtypes = [PP, PS, _P, C.c_int64, C.c_double, C.c_int64, _P]
-    L.sph_run_profiled.argtypes = [PP, PS, _P, C.c_int64, C.c_double, C.c_int64, _P, _P, _P]
+    L.sph_run_profiled.argtypes = [PP, PS, _P, C.c_int64, C.c_double, C.c_int64, C.c_int32,
+                                   _P, _P, _P]
     L.sph_diagnostics.argtypes = [PP, PS, _P, _P, C.c_int32, PD, _P, _P]
+    PB = C.POINTER(SphBatch)
+    L.sph_batch_workspace_bytes.argtypes = [PB, C.POINTER(C.c_size_t)]
+    L.sph_batch_workspace_init.argtypes = [PB, _P, C.c_size_t, _P]
+    L.sph_batch_set_density.argtypes = [PB, PS, _P, _P, C.c_int32, _P]
+    L.sph_batch_get_density.argtypes = [PB, PS, _P, _P, C.c_int32, _P]
+    L.sph_batch_build_cells.argtypes = [PB, PS, _P, _P]
+    L.sph_batch_interact.argtypes = [PB, PS, _P, _P, _P, _P, _P, _P, _P]
+    L.sph_batch_run.argtypes = [PB, PS, _P, C.c_int64, C.c_double, C.c_int64, C.c_int32, _P]
+    L.sph_batch_run_profiled.argtypes = [PB, PS, _P, C.c_int64, C.c_double, C.c_int64,
+                                         C.c_int32, C.c_int32, _P, _P, _P]
+    L.sph_batch_diagnostics.argtypes = [PB, PS, _P, PD, _P]
     for name in EXPORTS[2:]:
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -166,25 +190,15 @@ def _stream_ptr(stream) -> Optional[int]:
     return s.cuda_stream
 
 
-class Simulation:
-    """Device state, workspace and stream for one particle system.
+class _System:
+    """Device state (two copies of every array: the library ping-pongs
+    between them), workspace and stream of one system or one batch."""
 
-    Owns two copies of every state array (the library ping-pongs between
-    them) and one workspace tensor.  Arrays come back in original particle
-    order via :meth:`fetch`.
-    """
-
-    def __init__(self, scene, precision: str = "mixed", device: str = "cuda:0",
-                 stream=None, c_mode: int = SPH_C_TAIT, delta_pairs: int = SPH_DELTA_FLUID):
+    def _alloc(self, n: int, precision: str, device: str, stream, ws_bytes: int) -> None:
         import torch
         self.torch = torch
-        self.lib = load()
         self.dev = torch.device(device)
         self.precision = precision
-        self.params = make_params(scene.params, precision, c_mode=c_mode,
-                                  delta_pairs=delta_pairs)
-        check(self.lib.sph_check_params(C.byref(self.params)))
-        n = scene.n
         self.n = n
         self.stream = stream
         f64 = dict(dtype=torch.float64, device=self.dev)
@@ -198,9 +212,7 @@ class Simulation:
                 self._buf[k + suffix] = torch.zeros(n, dtype=rdt, device=self.dev)
         for suffix in ("", "_alt"):
             self._buf["id" + suffix] = torch.zeros(n, dtype=torch.int32, device=self.dev)
-        nbytes = C.c_size_t(0)
-        check(self.lib.sph_workspace_bytes(C.byref(self.params), n, C.byref(nbytes)))
-        self.ws_bytes = int(nbytes.value)
+        self.ws_bytes = int(ws_bytes)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
         base = self.ws.data_ptr()
         self.ws_ptr = (base + 255) // 256 * 256
@@ -211,9 +223,6 @@ class Simulation:
         st.cells_valid = 0
         st.reserved = 0
         self.state = st
-        check(self.lib.sph_workspace_init(C.byref(self.params), n, self.ws_ptr,
-                                          self.ws_bytes, self._s()))
-        self.upload(scene)
 
     # -- plumbing ---------------------------------------------------------
     def _s(self):
@@ -227,34 +236,47 @@ class Simulation:
                 return t
         raise KeyError(name)
 
-    def upload(self, scene, prev=None) -> None:
-        """Load a scene (original order).  `prev` optionally gives the
-        previous Verlet level as a dict with ux, uy, uz, rho; by default it
-        equals the current level."""
+    def _upload_arrays(self, vals, ids, rho, rhom) -> None:
         torch = self.torch
-        ids = np.arange(scene.n, dtype=np.uint32)
-        ids[scene.is_boundary] |= BOUNDARY_BIT
-        pv = prev if prev is not None else dict(ux=scene.ux, uy=scene.uy, uz=scene.uz,
-                                                rho=scene.rho)
-        vals = dict(x=scene.x, y=scene.y, z=scene.z, ux=scene.ux, uy=scene.uy, uz=scene.uz,
-                    uxm=pv["ux"], uym=pv["uy"], uzm=pv["uz"])
         for k, v in vals.items():
             self._cur(k).copy_(torch.from_numpy(np.ascontiguousarray(v, np.float64)))
         self._cur("id").copy_(torch.from_numpy(ids.view(np.int32)))
-        for which, r in ((0, scene.rho), (1, pv["rho"])):
-            rho = torch.from_numpy(np.ascontiguousarray(r, np.float64)).to(self.dev)
-            check(self.lib.sph_set_density(C.byref(self.params), C.byref(self.state),
-                                           rho.data_ptr(), which, self._s()))
-            self.sync()
+        dens = [torch.from_numpy(np.ascontiguousarray(r, np.float64)).to(self.dev)
+                for r in (rho, rhom)]
+        self.sync()  # the copies ran on torch's stream, the library may use another
+        for which, t in enumerate(dens):
+            self._set_density(t.data_ptr(), which)
+        self.sync()
         self.state.cells_valid = 0
 
     def sync(self) -> None:
         self.torch.cuda.synchronize(self.dev)
 
-    # -- the four verbs ---------------------------------------------------
-    def build_cells(self) -> None:
-        check(self.lib.sph_build_cells(C.byref(self.params), C.byref(self.state), self.ws_ptr,
-                                       self._s()))
+    # -- read-back ----------------------------------------------------------
+    def ids(self) -> np.ndarray:
+        raw = self._cur("id").cpu().numpy().view(np.uint32)
+        return (raw & np.uint32(0x7FFFFFFF)).astype(np.int64)
+
+    def density(self, which: int = 0):
+        """FP64 densities (current order); synchronises the device, since the
+        library may run on another stream than torch's."""
+        out = self.torch.empty(self.n, dtype=self.torch.float64, device=self.dev)
+        self._get_density(out.data_ptr(), which)
+        self.sync()
+        return out
+
+    def fetch(self) -> Dict[str, np.ndarray]:
+        """All state arrays in original particle order (numpy, FP64)."""
+        self.sync()
+        ids = self.ids()
+        inv = np.empty_like(ids)
+        inv[ids] = np.arange(ids.size)
+        out = {}
+        for k in ("x", "y", "z", "ux", "uy", "uz", "uxm", "uym", "uzm"):
+            out[k] = self._cur(k).cpu().numpy()[inv]
+        out["rho"] = self.density(0).cpu().numpy()[inv]
+        out["rhom"] = self.density(1).cpu().numpy()[inv]
+        return out
 
     def interact(self, want_mumax: bool = True):
         """Rates at the current state, FP64 tensors in current (cell) order."""
@@ -262,10 +284,72 @@ class Simulation:
         if not self.state.cells_valid:
             self.build_cells()
         outs = [torch.empty(self.n, dtype=torch.float64, device=self.dev) for _ in range(5)]
-        check(self.lib.sph_interact(C.byref(self.params), C.byref(self.state), self.ws_ptr,
-                                    *[o.data_ptr() for o in outs[:4]],
-                                    outs[4].data_ptr() if want_mumax else None, self._s()))
+        self._interact([o.data_ptr() for o in outs[:4]],
+                       outs[4].data_ptr() if want_mumax else None)
         return outs
+
+    def rates_by_id(self):
+        """(ax, ay, az, drho, mumax) in original particle order."""
+        outs = self.interact()
+        self.sync()
+        ids = self.ids()
+        res = []
+        for o in outs:
+            a = np.empty(self.n)
+            a[ids] = o.cpu().numpy()
+            res.append(a)
+        return tuple(res)
+
+
+def _ids_of(scene, offset: int = 0) -> np.ndarray:
+    ids = np.arange(offset, offset + scene.n, dtype=np.uint32)
+    ids[scene.is_boundary] |= BOUNDARY_BIT
+    return ids
+
+
+class Simulation(_System):
+    """One particle system.  Arrays come back in original particle order via
+    :meth:`fetch`."""
+
+    def __init__(self, scene, precision: str = "mixed", device: str = "cuda:0",
+                 stream=None, c_mode: int = SPH_C_TAIT, delta_pairs: int = SPH_DELTA_FLUID):
+        self.lib = load()
+        self.params = make_params(scene.params, precision, c_mode=c_mode,
+                                  delta_pairs=delta_pairs)
+        check(self.lib.sph_check_params(C.byref(self.params)))
+        nbytes = C.c_size_t(0)
+        check(self.lib.sph_workspace_bytes(C.byref(self.params), scene.n, C.byref(nbytes)))
+        self._alloc(scene.n, precision, device, stream, nbytes.value)
+        check(self.lib.sph_workspace_init(C.byref(self.params), self.n, self.ws_ptr,
+                                          self.ws_bytes, self._s()))
+        self.upload(scene)
+
+    def _set_density(self, ptr, which):
+        check(self.lib.sph_set_density(C.byref(self.params), C.byref(self.state), ptr, which,
+                                       self._s()))
+
+    def _get_density(self, ptr, which):
+        check(self.lib.sph_get_density(C.byref(self.params), C.byref(self.state), ptr, which,
+                                       self._s()))
+
+    def _interact(self, outs, mumax):
+        check(self.lib.sph_interact(C.byref(self.params), C.byref(self.state), self.ws_ptr,
+                                    *outs, mumax, self._s()))
+
+    def upload(self, scene, prev=None) -> None:
+        """Load a scene (original order).  `prev` optionally gives the
+        previous Verlet level as a dict with ux, uy, uz, rho; by default it
+        equals the current level."""
+        pv = prev if prev is not None else dict(ux=scene.ux, uy=scene.uy, uz=scene.uz,
+                                                rho=scene.rho)
+        vals = dict(x=scene.x, y=scene.y, z=scene.z, ux=scene.ux, uy=scene.uy, uz=scene.uz,
+                    uxm=pv["ux"], uym=pv["uy"], uzm=pv["uz"])
+        self._upload_arrays(vals, _ids_of(scene), scene.rho, pv["rho"])
+
+    # -- the four verbs ---------------------------------------------------
+    def build_cells(self) -> None:
+        check(self.lib.sph_build_cells(C.byref(self.params), C.byref(self.state), self.ws_ptr,
+                                       self._s()))
 
     def neighbour_stats(self):
         """(fluid-neighbour count, boundary-neighbour count, id-set hash) per
@@ -297,12 +381,13 @@ class Simulation:
         check(self.lib.sph_run(C.byref(self.params), C.byref(self.state), self.ws_ptr,
                                int(nsteps), float(dt), int(step0), self._s()))
 
-    def run_profiled(self, nsteps: int, dt: float, step0: int, ev_begin, ev_end) -> None:
+    def run_profiled(self, nsteps: int, dt: float, step0: int, ev_begin, ev_end,
+                     region: int = REGION_INTERACT) -> None:
         """run() recording hipEvent_t handles (ctypes arrays of c_void_p)
-        around every interaction kernel."""
+        around one region of every step."""
         check(self.lib.sph_run_profiled(C.byref(self.params), C.byref(self.state), self.ws_ptr,
-                                        int(nsteps), float(dt), int(step0), ev_begin, ev_end,
-                                        self._s()))
+                                        int(nsteps), float(dt), int(step0), int(region),
+                                        ev_begin, ev_end, self._s()))
 
     def diagnostics(self, probes: Optional[Sequence[Sequence[float]]] = None):
         if not self.state.cells_valid:
@@ -318,38 +403,75 @@ class Simulation:
             pp.ctypes.data if npts else None, self._s()))
         return out.as_dict(), pp[:npts]
 
-    # -- read-back ----------------------------------------------------------
-    def ids(self) -> np.ndarray:
-        raw = self._cur("id").cpu().numpy().view(np.uint32)
-        return (raw & np.uint32(0x7FFFFFFF)).astype(np.int64)
 
-    def density(self, which: int = 0):
-        out = self.torch.empty(self.n, dtype=self.torch.float64, device=self.dev)
-        check(self.lib.sph_get_density(C.byref(self.params), C.byref(self.state),
-                                       out.data_ptr(), which, self._s()))
-        return out
+class Ensemble(_System):
+    """A batch of independent systems in one state (sph_batch_*).  Instance k
+    owns original ids [offsets[k], offsets[k] + counts[k])."""
 
-    def fetch(self) -> Dict[str, np.ndarray]:
-        """All state arrays in original particle order (numpy, FP64)."""
-        self.sync()
-        ids = self.ids()
-        inv = np.empty_like(ids)
-        inv[ids] = np.arange(ids.size)
-        out = {}
-        for k in ("x", "y", "z", "ux", "uy", "uz", "uxm", "uym", "uzm"):
-            out[k] = self._cur(k).cpu().numpy()[inv]
-        out["rho"] = self.density(0).cpu().numpy()[inv]
-        out["rhom"] = self.density(1).cpu().numpy()[inv]
-        return out
+    def __init__(self, scenes, precision: str = "mixed", device: str = "cuda:0", stream=None,
+                 c_mode: int = SPH_C_TAIT, delta_pairs: int = SPH_DELTA_FLUID):
+        self.lib = load()
+        k = len(scenes)
+        self.ninst = k
+        self._params = (SphParams * k)()
+        for i, sc in enumerate(scenes):
+            self._params[i] = make_params(sc.params, precision, c_mode=c_mode,
+                                          delta_pairs=delta_pairs)
+        self.counts = np.array([sc.n for sc in scenes], dtype=np.int64)
+        self.offsets = np.concatenate([[0], np.cumsum(self.counts)[:-1]]).astype(np.int64)
+        self._counts = (C.c_int64 * k)(*[int(c) for c in self.counts])
+        self.batch = SphBatch(k, 0, self._params, self._counts)
+        nbytes = C.c_size_t(0)
+        check(self.lib.sph_batch_workspace_bytes(C.byref(self.batch), C.byref(nbytes)))
+        self._alloc(int(self.counts.sum()), precision, device, stream, nbytes.value)
+        check(self.lib.sph_batch_workspace_init(C.byref(self.batch), self.ws_ptr,
+                                                self.ws_bytes, self._s()))
+        self.upload(scenes)
 
-    def rates_by_id(self):
-        """(ax, ay, az, drho, mumax) in original particle order."""
-        outs = self.interact()
-        self.sync()
-        ids = self.ids()
-        res = []
-        for o in outs:
-            a = np.empty(self.n)
-            a[ids] = o.cpu().numpy()
-            res.append(a)
-        return tuple(res)
+    def _set_density(self, ptr, which):
+        check(self.lib.sph_batch_set_density(C.byref(self.batch), C.byref(self.state),
+                                             self.ws_ptr, ptr, which, self._s()))
+
+    def _get_density(self, ptr, which):
+        check(self.lib.sph_batch_get_density(C.byref(self.batch), C.byref(self.state),
+                                             self.ws_ptr, ptr, which, self._s()))
+
+    def _interact(self, outs, mumax):
+        check(self.lib.sph_batch_interact(C.byref(self.batch), C.byref(self.state),
+                                          self.ws_ptr, *outs, mumax, self._s()))
+
+    def upload(self, scenes) -> None:
+        cat = lambda f: np.concatenate([np.asarray(getattr(sc, f), np.float64) for sc in scenes])
+        vals = {k: cat(k) for k in ("x", "y", "z", "ux", "uy", "uz")}
+        vals.update(uxm=vals["ux"], uym=vals["uy"], uzm=vals["uz"])
+        ids = np.concatenate([_ids_of(sc, int(o)) for sc, o in zip(scenes, self.offsets)])
+        rho = cat("rho")
+        self._upload_arrays(vals, ids, rho, rho)
+
+    def build_cells(self) -> None:
+        check(self.lib.sph_batch_build_cells(C.byref(self.batch), C.byref(self.state),
+                                             self.ws_ptr, self._s()))
+
+    def run(self, nsteps: int, dt: float, step0: int, mode: int = 0) -> None:
+        check(self.lib.sph_batch_run(C.byref(self.batch), C.byref(self.state), self.ws_ptr,
+                                     int(nsteps), float(dt), int(step0), int(mode), self._s()))
+
+    def run_profiled(self, nsteps: int, dt: float, step0: int, ev_begin, ev_end,
+                     region: int = REGION_INTERACT, mode: int = 0) -> None:
+        check(self.lib.sph_batch_run_profiled(C.byref(self.batch), C.byref(self.state),
+                                              self.ws_ptr, int(nsteps), float(dt), int(step0),
+                                              int(mode), int(region), ev_begin, ev_end,
+                                              self._s()))
+
+    def diagnostics(self):
+        """One dict per instance."""
+        if not self.state.cells_valid:
+            self.build_cells()
+        out = (SphDiag * self.ninst)()
+        check(self.lib.sph_batch_diagnostics(C.byref(self.batch), C.byref(self.state),
+                                             self.ws_ptr, out, self._s()))
+        return [o.as_dict() for o in out]
+
+    def split_by_instance(self, arr: np.ndarray):
+        """Split an array in original-id order into per-instance pieces."""
+        return [arr[o:o + c] for o, c in zip(self.offsets, self.counts)]

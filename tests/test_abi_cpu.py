@@ -44,13 +44,16 @@ def test_version(L):
     assert L.sph_version() == 1
 
 
+STRUCTS = (("sph_params", lib.SphParams), ("sph_state", lib.SphState),
+           ("sph_diag", lib.SphDiag), ("sph_tuning", lib.SphTuning), ("sph_batch", lib.SphBatch))
+
+
 def test_struct_layout_matches_header(tmp_path):
-    """sizeof/offsetof of the three structs, compiled from the header with
+    """sizeof/offsetof of the ABI structs, compiled from the header with
     gcc, equal the binding's ctypes mirrors."""
     prog = tmp_path / "layout.c"
     checks = []
-    for cname, py in (("sph_params", lib.SphParams), ("sph_state", lib.SphState),
-                      ("sph_diag", lib.SphDiag)):
+    for cname, py in STRUCTS:
         checks.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             checks.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
@@ -61,8 +64,7 @@ def test_struct_layout_matches_header(tmp_path):
                    check=True)
     got = dict(ln.split() for ln in subprocess.run([str(exe)], capture_output=True, text=True,
                                                   check=True).stdout.splitlines())
-    for cname, py in (("sph_params", lib.SphParams), ("sph_state", lib.SphState),
-                      ("sph_diag", lib.SphDiag)):
+    for cname, py in STRUCTS:
         assert int(got[cname]) == C.sizeof(py)
         for f, _ in py._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
@@ -146,3 +148,79 @@ def test_calls_rejected_before_launch(L):
 def test_workspace_init_size_check(L):
     p = params()
     assert L.sph_workspace_init(C.byref(p), 100, 1 << 30, 64, None) == lib.SPH_E_SIZE
+
+
+# ------------------------------------------------------------------ batch
+
+def batch_of(plist, counts):
+    arr = (lib.SphParams * len(plist))(*plist)
+    cnt = (C.c_int64 * len(counts))(*counts)
+    b = lib.SphBatch(len(plist), 0, arr, cnt)
+    b._keep = (arr, cnt)
+    return b
+
+
+def test_batch_workspace_bytes(L):
+    p1 = params()
+    p2 = lib.make_params(scene.make_params(0.03, alpha=0.05), "mixed")
+    b = batch_of([p1, p2], [5000, 3000])
+    nb = C.c_size_t(0)
+    assert L.sph_batch_workspace_bytes(C.byref(b), C.byref(nb)) == 0
+    assert nb.value > 8000 * 70 and nb.value % 256 == 0
+    # one more instance of the same grid adds at least its cell table
+    b3 = batch_of([p1, p2, p1], [5000, 3000, 1])
+    nb3 = C.c_size_t(0)
+    assert L.sph_batch_workspace_bytes(C.byref(b3), C.byref(nb3)) == 0
+    ncell = p1.dims[0] * p1.dims[1] * p1.dims[2]
+    assert nb3.value >= nb.value + 4 * ncell
+
+
+def test_batch_rejected_before_launch(L):
+    p1 = params()
+    p64 = lib.make_params(scene.make_params(0.02), "fp64")
+    nb = C.c_size_t(0)
+    assert L.sph_batch_workspace_bytes(None, C.byref(nb)) == lib.SPH_E_INVAL
+    b = batch_of([p1, p64], [10, 10])
+    assert L.sph_batch_workspace_bytes(C.byref(b), C.byref(nb)) == lib.SPH_E_INVAL
+    assert "precision" in L.sph_last_error().decode()
+    b = batch_of([p1, p1], [10, 0])
+    assert L.sph_batch_workspace_bytes(C.byref(b), C.byref(nb)) == lib.SPH_E_INVAL
+    b = batch_of([p1], [10])
+    b.ninst = 0
+    assert L.sph_batch_workspace_bytes(C.byref(b), C.byref(nb)) == lib.SPH_E_INVAL
+    b.ninst = lib.MAX_INSTANCES + 1
+    assert L.sph_batch_workspace_bytes(C.byref(b), C.byref(nb)) == lib.SPH_E_INVAL
+    bad = params(h=-1.0)
+    b = batch_of([p1, bad], [10, 10])
+    assert L.sph_batch_workspace_bytes(C.byref(b), C.byref(nb)) == lib.SPH_E_INVAL
+    assert "instance 1" in L.sph_last_error().decode()
+    b = batch_of([p1, p1], [1 << 30, 1 << 30])
+    assert L.sph_batch_workspace_bytes(C.byref(b), C.byref(nb)) == lib.SPH_E_RANGE
+    # state checks: n must equal the sum of the counts; run mode bits
+    b = batch_of([p1, p1], [60, 40])
+    st = lib.SphState()
+    fake = 1 << 20
+    for k, _ in lib.SphState._fields_:
+        if k not in ("n", "cells_valid", "reserved"):
+            setattr(st, k, fake)
+            fake += 1 << 20
+    st.n = 99
+    assert L.sph_batch_build_cells(C.byref(b), C.byref(st), 1 << 30, None) == lib.SPH_E_INVAL
+    st.n = 100
+    assert L.sph_batch_run(C.byref(b), C.byref(st), 1 << 30, 1, 1e-4, 0, 4,
+                           None) == lib.SPH_E_INVAL
+    assert L.sph_batch_run(C.byref(b), C.byref(st), 1 << 30, 1, 1e-4, 0, lib.RUN_GRAPH,
+                           None) == lib.SPH_E_INVAL
+    assert "stream" in L.sph_last_error().decode()
+    assert L.sph_batch_run_profiled(C.byref(b), C.byref(st), 1 << 30, 1, 1e-4, 0,
+                                    lib.RUN_GRAPH, 0, None, None, 1 << 12) == lib.SPH_E_INVAL
+    assert L.sph_batch_run_profiled(C.byref(b), C.byref(st), 1 << 30, 1, 1e-4, 0, 0, 9,
+                                    None, None, None) == lib.SPH_E_INVAL
+    st.cells_valid = 0
+    d = (lib.SphDiag * 2)()
+    assert L.sph_batch_diagnostics(C.byref(b), C.byref(st), 1 << 30, d,
+                                   None) == lib.SPH_E_STATE
+    outs = [1 << 33] * 4
+    assert L.sph_batch_interact(C.byref(b), C.byref(st), 1 << 30, *outs, None,
+                                None) == lib.SPH_E_STATE
+    assert L.sph_batch_workspace_init(C.byref(b), 1 << 30, 64, None) == lib.SPH_E_SIZE
