@@ -9,8 +9,9 @@ FP64 integration).  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: particle-steps/s of the mixed step, the FP64 step on the
 same workload for the ratio, the interaction kernel's roofline (achieved
-algorithmic FP32 FLOP/s over HIP-event kernel time) and the FP64 CPU oracle
-timed on this host.
+algorithmic FP32 FLOP/s over HIP-event kernel time), the batched ensemble of
+64 dam breaks (throughput, sort/reorder HBM bandwidth against peak) and the
+FP64 CPU oracle timed on this host.
 """
 import argparse
 import ctypes as C
@@ -39,13 +40,13 @@ def hip_runtime():
 
 
 class Events:
-    """hipEvent_t pairs around the interaction kernel of every `every`-th
-    step (NULL for the other steps)."""
+    """hipEvent_t pairs around one region (by default the interaction kernel)
+    of every `every`-th step (NULL for the other steps)."""
 
-    def __init__(self, hip, n, every=1):
+    def __init__(self, hip, n, every=1, start=0):
         self.hip = hip
         self.n = n
-        self.steps = list(range(0, n, every))
+        self.steps = list(range(start, n, every))
         self.begin = (C.c_void_p * n)()
         self.end = (C.c_void_p * n)()
         for arr in (self.begin, self.end):
@@ -59,7 +60,8 @@ class Events:
         tot = 0.0
         ms = C.c_float()
         for k in self.steps:
-            assert self.hip.hipEventElapsedTime(C.byref(ms), self.begin[k], self.end[k]) == 0
+            rc = self.hip.hipEventElapsedTime(C.byref(ms), self.begin[k], self.end[k])
+            assert rc == 0, f"hipEventElapsedTime of step {k}: error {rc}"
             tot += ms.value
         return tot / len(self.steps)
 
@@ -95,6 +97,81 @@ def time_gpu(scene_obj, precision, steps, warmup, hip):
                 umax=d1["umax"], x_front=d1["x_front"])
 
 
+# algorithmic HBM bytes per particle of the cell-list kernels (mixed state)
+SORT_BYTES_FIRST = 16   # pass 0: histogram reads the key; scatter reads it, writes key + index
+SORT_BYTES_PASS = 20    # later passes: + the index read
+REORDER_BYTES = 4 + 4 + 84 + 84 + 40  # perm + key in, state gathered (84 B) and written,
+                                      # interaction view written (40 B)
+
+
+def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True):
+    """The batched ensemble: n_inst dam breaks with dp drawn from {0.02,
+    0.015, 0.01} m and alpha from U[0, 0.1], mixed precision, lagged-dt fused
+    interaction + update, replayed 40-step HIP graphs."""
+    import torch
+    from paper_2306_01959_amd import lib, scene
+    scenes = scene.ensemble(n_inst, master_seed=seed)
+    ens = lib.Ensemble(scenes, "mixed", stream=torch.cuda.Stream())
+    period = 40
+    steps = max(period, (steps + period - 1) // period * period)
+    mode = lib.RUN_LAGGED
+    ens.run(period, -1.0, 0, mode)                      # eager warm-up, steps 0..39
+    d0 = ens.diagnostics()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.run(steps, -1.0, period, mode | (lib.RUN_GRAPH if graph else 0))  # graph replays
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d1 = ens.diagnostics()
+    step = period + steps
+    # kernel times of the same steps, eager with events (sampled)
+    kern = {}
+    for name, region in (("sort", lib.REGION_SORT), ("reorder", lib.REGION_REORDER),
+                         ("interact", lib.REGION_INTERACT), ("step", lib.REGION_STEP)):
+        # from the second step on: the first one reuses the cells the
+        # diagnostics built and has no sort or reorder of its own
+        ev = Events(hip, 21, every=2, start=1)
+        ens.run_profiled(21, -1.0, step, ev.begin, ev.end, region=region, mode=mode)
+        torch.cuda.synchronize()
+        kern[name] = ev.mean_ms()
+        ev.close()
+        step += 21
+    assert all(d["n_nonfinite"] == 0 for d in d1), "non-finite state"
+    n = ens.n
+    key_bits = int(np.ceil(np.log2(sum(int(np.prod(s.params["dims"])) for s in scenes))))
+    passes = max(1, (key_bits + 7) // 8)
+    sort_bytes = n * (SORT_BYTES_FIRST + SORT_BYTES_PASS * (passes - 1))
+    reorder_bytes = n * REORDER_BYTES
+    pairs = [(d1[0][k] - d0[0][k]) / steps for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
+    flop = FLOP_FF * pairs[0] + FLOP_FB * pairs[1] + FLOP_BF * pairs[2]
+
+    def bw(nbytes, ms):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"achieved": gbs, "peak": HBM_TBS * 1e3, "unit": "GB/s",
+                "frac": gbs / (HBM_TBS * 1e3), "kernel_ms": ms, "bytes_per_launch": nbytes}
+
+    counts = [s.n for s in scenes]
+    return {
+        "value": n * steps / (t1 - t0),
+        "unit": "particle-steps/s",
+        "ms_per_step": (t1 - t0) / steps * 1e3,
+        "steps": steps,
+        "workload": f"{n_inst} dam-break instances (same tank), dp from {{0.02, 0.015, 0.01}} m, "
+                    "alpha ~ U[0, 0.1], mixed FP32, lagged CFL dt per instance, fused "
+                    "interaction + update, "
+                    + ("40-step HIP graph replays" if graph else "eager launches"),
+        "instances": n_inst,
+        "particles": n,
+        "particles_per_instance": {"min": min(counts), "max": max(counts)},
+        "sort": dict(bw(sort_bytes, kern["sort"]), passes=passes, key_bits=key_bits),
+        "reorder": bw(reorder_bytes, kern["reorder"]),
+        "interact": {"kernel_ms": kern["interact"], "achieved": flop / (kern["interact"] * 1e-3)
+                     / 1e12, "unit": "TFLOP/s", "peak": PEAK_FP32_TFLOPS,
+                     "flop_per_launch": flop},
+        "eager_step_ms": kern["step"],
+    }
+
+
 def cpu_baseline(scene_obj, seconds=10.0):
     """The FP64 oracle on this host's cores: 2 warm-up steps, then steps of
     the same workload until `seconds` elapse (at least 3)."""
@@ -126,6 +203,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
     ap.add_argument("--retune", action="store_true", help="ignore the autotune table")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="only the batched ensemble (profiling its kernels alone)")
+    ap.add_argument("--ensemble-eager", action="store_true",
+                    help="ensemble without HIP graphs (for counter collection)")
+    ap.add_argument("--ensemble-steps", type=int, default=200,
+                    help="timed ensemble steps (rounded up to whole 40-step graphs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -147,6 +231,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.ensemble_only:
+        print(json.dumps({"ensemble": time_ensemble(args.ensemble_steps, hip,
+                                                    graph=not args.ensemble_eager)}), flush=True)
+        return
     from paper_2306_01959_amd import autotune
     sc = scene.config_scene(2)
     splits = {"mixed": autotune.tune(sc, "mixed", use_cache=not args.retune,
@@ -202,6 +290,8 @@ def main():
         out["fp64"] = {"value": v64, "ms_per_step": fp64["ms_per_step"],
                        "interact_ms": fp64["interact_ms"]}
         out["mixed_over_fp64"] = value / v64
+    if not args.no_ensemble:
+        out["ensemble"] = time_ensemble(args.ensemble_steps, hip)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(out), flush=True)

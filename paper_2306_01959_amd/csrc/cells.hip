@@ -91,30 +91,103 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t *__re
     for (int d = tid; d < kRadix; d += kSortThreads) hist[(int64_t)d * ntiles + blockIdx.x] = h[d];
 }
 
-// Exclusive scan of m values in place, one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t *__restrict__ a, int64_t m) {
-    __shared__ uint32_t sums[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (m + 1023) / 1024;
-    const int64_t b = t * per;
-    const int64_t e = b + per < m ? b + per : m;
-    uint32_t s = 0;
-    for (int64_t k = b; k < e; ++k) s += a[k];
-    sums[t] = s;
+// Exclusive scan of the (digit, tile) counts.  A block of 1024 threads
+// scans a span of kScanSpan values (4 consecutive values per thread, wave
+// prefix sums by shuffles, one LDS exchange of the 16 wave totals).  Small
+// arrays: one block walks all spans with a carry.  Large arrays: span
+// totals -> scan of the totals (one block) -> spans scanned with their
+// offsets, all spans in parallel.
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t o = __shfl_up(v, off, kWave);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// Exclusive prefix of v over the block (1024 threads); total = block sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, uint32_t &total) {
+    const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[w] = inc;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = t >= off ? sums[t - off] : 0u;
-        __syncthreads();
-        sums[t] += v;
-        __syncthreads();
+    if (w == 0) {
+        const uint32_t x = lane < kScanThreads / kWave ? wsum[lane] : 0u;
+        const uint32_t xi = wave_incl_scan(x);
+        if (lane < kScanThreads / kWave) wsum[lane] = xi - x;  // exclusive wave offsets
+        if (lane == kScanThreads / kWave - 1) wsum[kScanThreads / kWave] = xi;
     }
-    uint32_t run = t > 0 ? sums[t - 1] : 0u;
-    for (int64_t k = b; k < e; ++k) {
-        uint32_t v = a[k];
-        a[k] = run;
-        run += v;
+    __syncthreads();
+    const uint32_t r = wsum[w] + inc - v;
+    total = wsum[kScanThreads / kWave];
+    __syncthreads();  // wsum may be reused by the next call
+    return r;
+}
+
+// Loads this thread's 4 values of span `base` (zeros past m).
+__device__ __forceinline__ void span_load(const uint32_t *a, int64_t m, int64_t base, uint32_t v[4]) {
+    const int64_t i0 = base + 4 * (int64_t)threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = i0 + q < m ? a[i0 + q] : 0u;
+}
+
+// Scans span `base` in place with a starting offset; returns the span total.
+__device__ __forceinline__ uint32_t span_scan(uint32_t *a, int64_t m, int64_t base, uint32_t carry,
+                                              uint32_t *wsum) {
+    uint32_t v[4];
+    span_load(a, m, base, v);
+    const uint32_t tsum = (v[0] + v[1]) + (v[2] + v[3]);
+    uint32_t total;
+    uint32_t run = carry + block_excl_scan(tsum, wsum, total);
+    const int64_t i0 = base + 4 * (int64_t)threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (i0 + q < m) a[i0 + q] = run;
+        run += v[q];
     }
+    return total;
+}
+
+// One block: all spans in order.
+__global__ __launch_bounds__(kScanThreads) void k_scan_serial(uint32_t *__restrict__ a, int64_t m) {
+    __shared__ uint32_t wsum[kScanThreads / kWave + 1];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < m; base += kScanSpan) carry += span_scan(a, m, base, carry, wsum);
+}
+
+// Block b: the total of span b.
+__global__ __launch_bounds__(kScanThreads) void k_scan_totals(const uint32_t *__restrict__ a,
+                                                              int64_t m, uint32_t *__restrict__ tot) {
+    __shared__ uint32_t wsum[kScanThreads / kWave + 1];
+    uint32_t v[4];
+    span_load(a, m, (int64_t)blockIdx.x * kScanSpan, v);
+    uint32_t total;
+    block_excl_scan((v[0] + v[1]) + (v[2] + v[3]), wsum, total);
+    if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
+// Block b: span b scanned from its offset (the scanned totals).
+__global__ __launch_bounds__(kScanThreads) void k_scan_spans(uint32_t *__restrict__ a, int64_t m,
+                                                             const uint32_t *__restrict__ off) {
+    __shared__ uint32_t wsum[kScanThreads / kWave + 1];
+    span_scan(a, m, (int64_t)blockIdx.x * kScanSpan, off[blockIdx.x], wsum);
+}
+
+int launch_scan(uint32_t *a, int64_t m, uint32_t *tot, hipStream_t st) {
+    const int64_t spans = (m + kScanSpan - 1) / kScanSpan;
+    if (spans <= kScanSerialSpans) {
+        hipLaunchKernelGGL(k_scan_serial, dim3(1), dim3(kScanThreads), 0, st, a, m);
+    } else {
+        hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)spans), dim3(kScanThreads), 0, st, a, m,
+                           tot);
+        hipLaunchKernelGGL(k_scan_serial, dim3(1), dim3(kScanThreads), 0, st, tot, spans);
+        hipLaunchKernelGGL(k_scan_spans, dim3((unsigned)spans), dim3(kScanThreads), 0, st, a, m,
+                           tot);
+    }
+    return launch_check("scan");
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
@@ -177,8 +250,7 @@ int launch_sort(const Ws &w, hipStream_t st, uint32_t **sorted_keys, uint32_t **
         uint32_t *vout = vbuf[pass & 1];
         hipLaunchKernelGGL(k_sort_hist, dim3(ntiles), dim3(kSortThreads), 0, st, kin, n, shift,
                            w.hist(), ntiles);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, w.hist(),
-                           (int64_t)kRadix * ntiles);
+        if (int rc = launch_scan(w.hist(), (int64_t)kRadix * ntiles, w.scan_tot(), st)) return rc;
         hipLaunchKernelGGL(k_sort_scatter, dim3(ntiles), dim3(kSortThreads), 0, st, kin, vin,
                            kout, vout, n, shift, w.hist(), ntiles);
         if (int rc = launch_check("radix sort")) return rc;
@@ -344,28 +416,40 @@ int launch_cell_table(const Ws &w, const uint32_t *keys, hipStream_t st) {
 // ------------------------------------------------------------ chunk list
 //
 // The interaction works on chunks: up to 64 consecutive sorted particles of
-// one cell row (fixed cy, cz) of one instance.  One workgroup scans all rows
-// of all instances, writes every chunk {start, end, local row, instance} and
-// the chunk count, and prepares the per-instance time-step bound for the
+// one cell row (fixed cy, cz) of one instance.  Per row: the number of its
+// chunks (k_row_counts), an exclusive scan of those numbers (the first chunk
+// of every row), then the chunks {start, end, local row, instance} and the
+// chunk count (k_row_chunks).
+//
+// k_row_counts also prepares the per-instance time-step bound for the
 // interaction that follows: the bound of the last interaction (if there was
 // one) becomes the lagged bound, and the running minimum restarts at +inf.
 // With `lagged` it also sets this step's dt before the interaction runs:
 // the caller's dt, else Cr times the lagged bound (eq. sphdt one step late);
 // with no bound yet, dt = 0 and the CFL flag is raised.
-__global__ __launch_bounds__(1024) void k_chunks(const uint32_t *__restrict__ start, Insts I,
-                                                 int64_t nrows, int4 *__restrict__ chunks,
-                                                 DevScalars *sc, InstState *ist, int lagged,
-                                                 double dt_arg) {
-    __shared__ uint32_t sums[1024];
-    __shared__ uint32_t carry;
-    const int t = threadIdx.x;
-    if (t == 0) {
-        carry = 0;
+
+// sorted range [b, e) of global row r, and its instance / local row
+__device__ __forceinline__ void row_range(const uint32_t *start, const Insts &I, int64_t r,
+                                          uint32_t &b, uint32_t &e, int &inst, int &lrow) {
+    inst = I.of_row((uint32_t)r);
+    const Inst ip = I.get(inst);
+    lrow = (int)(r - ip.row_base);
+    const uint32_t c0 = ip.cell_base + (uint32_t)lrow * (uint32_t)ip.nx;
+    b = start[c0];
+    e = start[c0 + ip.nx];
+}
+
+__global__ void k_row_counts(const uint32_t *__restrict__ start, Insts I, int64_t nrows,
+                             uint32_t *__restrict__ cnt, DevScalars *sc, InstState *ist,
+                             int lagged, double dt_arg) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0) {
         sc->work = 0;
         if (lagged) sc->steps += 1;
     }
     constexpr unsigned long long kInf = 0x7ff0000000000000ull;
-    for (int k = t; k < I.n; k += 1024) {
+    if (g < I.n) {
+        const int k = (int)g;
         if (ist[k].dt_min_bits != kInf) ist[k].dt_lag_bits = ist[k].dt_min_bits;
         ist[k].dt_min_bits = kInf;
         if (lagged) {
@@ -384,44 +468,42 @@ __global__ __launch_bounds__(1024) void k_chunks(const uint32_t *__restrict__ st
             ist[k].time += dt;
         }
     }
-    __syncthreads();
-    for (int64_t r0 = 0; r0 < nrows; r0 += 1024) {
-        const int64_t r = r0 + t;
-        uint32_t b = 0, e = 0, nch = 0;
-        int inst = 0, lrow = 0;
-        if (r < nrows) {
-            inst = I.of_row((uint32_t)r);
-            const Inst ip = I.get(inst);
-            lrow = (int)(r - ip.row_base);
-            const uint32_t c0 = ip.cell_base + (uint32_t)lrow * (uint32_t)ip.nx;
-            b = start[c0];
-            e = start[c0 + ip.nx];
-            nch = (e - b + kChunk - 1) / kChunk;
-        }
-        sums[t] = nch;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            uint32_t v = t >= off ? sums[t - off] : 0u;
-            __syncthreads();
-            sums[t] += v;
-            __syncthreads();
-        }
-        uint32_t first = carry + sums[t] - nch;
-        for (uint32_t k = 0; k < nch; ++k) {
-            uint32_t s0 = b + k * kChunk;
-            uint32_t s1 = s0 + kChunk < e ? s0 + kChunk : e;
-            chunks[first + k] = make_int4((int)s0, (int)s1, lrow, inst);
-        }
-        __syncthreads();
-        if (t == 1023) carry += sums[1023];
-        __syncthreads();
+    if (g >= nrows) return;
+    uint32_t b, e;
+    int inst, lrow;
+    row_range(start, I, g, b, e, inst, lrow);
+    cnt[g] = (e - b + kChunk - 1) / kChunk;
+}
+
+__global__ void k_row_chunks(const uint32_t *__restrict__ start, Insts I, int64_t nrows,
+                             const uint32_t *__restrict__ first, int4 *__restrict__ chunks,
+                             DevScalars *sc) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    uint32_t b, e;
+    int inst, lrow;
+    row_range(start, I, r, b, e, inst, lrow);
+    const uint32_t nch = (e - b + kChunk - 1) / kChunk;
+    const uint32_t f = first[r];
+    for (uint32_t k = 0; k < nch; ++k) {
+        const uint32_t s0 = b + k * kChunk;
+        const uint32_t s1 = s0 + kChunk < e ? s0 + kChunk : e;
+        chunks[f + k] = make_int4((int)s0, (int)s1, lrow, inst);
     }
-    if (t == 0) sc->nchunks = carry;
+    if (r == nrows - 1) sc->nchunks = f + nch;
 }
 
 int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStream_t st) {
-    hipLaunchKernelGGL(k_chunks, dim3(1), dim3(1024), 0, st, w.cell_start(), insts_of(P, w),
-                       w.L.nrows, w.chunks(), w.scalars(), w.inst_state(), (int)lagged, dt);
+    const int64_t nrows = w.L.nrows;
+    const int64_t m = nrows > (int64_t)P.host.size() ? nrows : (int64_t)P.host.size();
+    const int blocks = (int)((m + 255) / 256);
+    const Insts I = insts_of(P, w);
+    hipLaunchKernelGGL(k_row_counts, dim3(blocks), dim3(256), 0, st, w.cell_start(), I, nrows,
+                       w.row_first(), w.scalars(), w.inst_state(), (int)lagged, dt);
+    if (int rc = launch_check("chunk counts")) return rc;
+    if (int rc = launch_scan(w.row_first(), nrows, w.scan_tot(), st)) return rc;
+    hipLaunchKernelGGL(k_row_chunks, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st,
+                       w.cell_start(), I, nrows, w.row_first(), w.chunks(), w.scalars());
     return launch_check("chunk list");
 }
 

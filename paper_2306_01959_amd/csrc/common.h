@@ -18,6 +18,9 @@ constexpr int kSortItems = 16;       // keys per thread per tile
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+constexpr int kScanThreads = 1024;   // scan workgroup
+constexpr int kScanSpan = 4 * kScanThreads;  // values per scanned span
+constexpr int kScanSerialSpans = 4;  // up to this many spans: one block scans them in turn
 constexpr int kChunk = 64;           // targets per interaction chunk (one wave)
 constexpr int kDiagThreads = 256;
 constexpr int kDiagBlocks = 256;     // partial sums of a single system (fixed: deterministic)
@@ -127,6 +130,8 @@ struct WsLayout {
     size_t keys = 0, keys_alt = 0, vals = 0, vals_alt = 0;
     size_t sorted_keys = 0;  // keys or keys_alt, whichever holds the sort output
     size_t hist = 0;
+    size_t scan_tot = 0;     // span totals of a scan (counts of the sort, chunks per row)
+    size_t row_first = 0;    // chunks per row, then the first chunk of each row
     size_t cell_start = 0;
     size_t chunks = 0;
     size_t view0 = 0, view1 = 0, view2 = 0;
@@ -153,6 +158,8 @@ struct Ws {
     uint32_t *vals() const { return at<uint32_t>(L.vals); }
     uint32_t *vals_alt() const { return at<uint32_t>(L.vals_alt); }
     uint32_t *hist() const { return at<uint32_t>(L.hist); }
+    uint32_t *scan_tot() const { return at<uint32_t>(L.scan_tot); }
+    uint32_t *row_first() const { return at<uint32_t>(L.row_first); }
     uint32_t *cell_start() const { return at<uint32_t>(L.cell_start); }
     int4 *chunks() const { return at<int4>(L.chunks); }
     DevScalars *scalars() const { return at<DevScalars>(L.scalars); }
@@ -172,6 +179,8 @@ int launch_check(const char *what);
 // Launchers implemented in the kernel translation units.
 int launch_encode(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st);
 int launch_sort(const Ws &w, hipStream_t st, uint32_t **sorted_keys, uint32_t **perm);
+// in-place exclusive scan of m values; tot: ceil(m / kScanSpan) values of scratch
+int launch_scan(uint32_t *a, int64_t m, uint32_t *tot, hipStream_t st);
 int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *keys,
                    const uint32_t *perm, hipStream_t st);
 int launch_cell_table(const Ws &w, const uint32_t *keys, hipStream_t st);

@@ -72,6 +72,22 @@ def test_build_cells_invariants(gpu, precision):
     assert np.array_equal(x, s.x[ids]) and np.array_equal(z, s.z[ids])
 
 
+def test_build_cells_large_sort(gpu):
+    """700k particles: the counts scan of the radix sort runs on many spans
+    in parallel (not one block); the order must still be the stable sort."""
+    sc = scene.random_cloud(700_000, 3, dp=0.002, box=0.2)
+    sim = _sim(gpu, sc, "mixed")
+    sim.build_cells()
+    sim.sync()
+    ids = sim.ids()
+    prm = sc.params
+    (cx, cy, cz), _ = bruteforce.cells_and_offsets(sc.x, sc.y, sc.z, prm["origin"],
+                                                   prm["cell_size"], prm["dims"])
+    nx, ny = prm["dims"][0], prm["dims"][1]
+    key = cx + nx * (cy + ny * cz)
+    assert np.array_equal(ids, np.argsort(key, kind="stable"))
+
+
 # ----------------------------------------------------------- neighbours
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
