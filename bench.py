@@ -34,6 +34,34 @@ PEAK_FP32_SCALAR_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 HBM_TBS = 8.0
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_interact_mixed_dambreak_dp0.01.txt")
+KERNEL_SOURCES = ("paper_2306_01959_amd/csrc/interact.hip", "paper_2306_01959_amd/csrc/update.h",
+                  "paper_2306_01959_amd/csrc/common.h")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's), or None when the
+    summary is for another kernel or the kernel's sources changed since."""
+    import hashlib
+    try:
+        kv = {}
+        with open(PROFILE) as f:
+            for ln in f:
+                if " = " in ln:
+                    k, v = ln.split(" = ", 1)
+                    kv[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for src in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+    except OSError:
+        return None
+    if kv.get("source_sha256") != h.hexdigest() or kv.get("kernel") != kernel:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def hip_runtime():
     import torch  # noqa: F401  (loads the HIP runtime the library binds to)
     return C.CDLL("libamdhip64.so.7")
@@ -270,13 +298,14 @@ def main():
             "waves_per_chunk": splits,
         },
         "roofline": {
-            "kernel": "k_interact<Mixed, %d, %d, false>" % tuple(splits["mixed"]),
+            "kernel": "k_interact<Mixed, %d, %d, false, false>" % tuple(splits["mixed"]),
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic("k_interact<Mixed, %d, %d, false, false>"
+                                        % tuple(splits["mixed"])),
             "kernel_ms": mixed["interact_ms"],
             "flop_per_launch": mixed["flop_per_launch"],
             "pairs_per_launch": {"ff": mixed["pairs_per_step"][0],
