@@ -39,6 +39,17 @@ KERNEL_SOURCES = ("paper_2306_01959_amd/csrc/interact.hip", "paper_2306_01959_am
                   "paper_2306_01959_amd/csrc/common.h")
 
 
+def kernel_name(shape, precision="Mixed"):
+    """Name of the interaction kernel launched for an autotuner shape
+    ((kernel, split, group), or (split, group) for the row-split kernel)."""
+    shape = tuple(shape)
+    if len(shape) == 2:
+        shape = (1,) + shape
+    if shape[0] == 2:
+        return "k_interact_g<%s, %d, false, false>" % (precision, shape[2])
+    return "k_interact<%s, %d, %d, false, false>" % (precision, shape[1], shape[2])
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's), or None when the
@@ -295,17 +306,16 @@ def main():
                         "interaction + FP64 integration",
             "particles": sc.n, "fluid": sc.n_fluid, "boundary": sc.n_boundary,
             "precision": "mixed", "parallelism": "single GPU",
-            "waves_per_chunk": splits,
+            "interaction_shape": splits,
         },
         "roofline": {
-            "kernel": "k_interact<Mixed, %d, %d, false, false>" % tuple(splits["mixed"]),
+            "kernel": kernel_name(splits["mixed"]),
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": measured_traffic("k_interact<Mixed, %d, %d, false, false>"
-                                        % tuple(splits["mixed"])),
+            "traffic": measured_traffic(kernel_name(splits["mixed"])),
             "kernel_ms": mixed["interact_ms"],
             "flop_per_launch": mixed["flop_per_launch"],
             "pairs_per_launch": {"ff": mixed["pairs_per_step"][0],

@@ -171,28 +171,41 @@ const char *sph_last_error(void);
 /* Validate params (see sph_params) without touching the device. */
 int sph_check_params(const sph_params *p);
 
+/* Decomposition of the interaction kernel. */
+typedef enum {
+    SPH_KERNEL_AUTO = 0,
+    SPH_KERNEL_ROWS = 1,   /* chunks of up to 64 targets of one cell row; `split`
+                              waves (1, 3 or 9) divide the 9 stencil rows; inside
+                              a wave the targets form groups of `group` (8, 16
+                              or 64), each culled on its own */
+    SPH_KERNEL_GROUPS = 2  /* one independent wave per group of up to `group`
+                              targets of one cell row (8, 16 or 64), streaming
+                              and culling its own candidates; `split` unused */
+} sph_kernel;
+
 /*
- * Launch shape of the interaction kernel (an autotuner sets it).  A chunk of
- * up to 64 targets is owned by `split` waves (1, 3 or 9), which divide the 9
- * stencil rows between them; inside a wave the targets form groups of
- * `group` particles (8, 16 or 64), each culled on its own, and a wave step
- * evaluates `group` targets against 64/`group` candidates.  0 = the
- * library's choice.  Per precision, process-wide, host-side; it changes
- * launch shapes only, never results beyond summation order.  Not to be
- * changed while another thread is launching.
+ * Launch shape of the interaction (an autotuner sets it): the kernel, the
+ * waves per chunk and the targets per group; a wave step evaluates `group`
+ * targets against 64/`group` candidates.  0 = the library's choice.  Per
+ * precision, process-wide, host-side; it changes launch shapes only, never
+ * results beyond summation order.  Not to be changed while another thread is
+ * launching.
  */
 typedef struct sph_tuning {
     int32_t split_fp64;
     int32_t split_mixed;
     int32_t group_fp64;
     int32_t group_mixed;
-    int32_t reserved[4]; /* must be 0 */
+    int32_t kernel_fp64;  /* sph_kernel */
+    int32_t kernel_mixed;
+    int32_t reserved[2];  /* must be 0 */
 } sph_tuning;
 
 int sph_set_tuning(const sph_tuning *t);
 
 /* The launch shape the library uses for (p, n), after sph_set_tuning. */
-int sph_get_split(const sph_params *p, int64_t n, int32_t *split, int32_t *group);
+int sph_get_split(const sph_params *p, int64_t n, int32_t *split, int32_t *group,
+                  int32_t *kernel);
 
 /* Bytes of workspace needed for (p, n particles); 0 < n < 2^31. */
 int sph_workspace_bytes(const sph_params *p, int64_t n, size_t *bytes);

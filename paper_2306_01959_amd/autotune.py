@@ -1,8 +1,9 @@
 """Autotuner for the interaction launch shape.
 
 For a given scene and precision it times whole steps for every supported
-shape -- waves per 64-target chunk (1, 3, 9) x targets per group (8, 16,
-64) -- keeps the fastest, sets it in the library (sph_set_tuning) and caches
+shape -- the row-split kernel with 1, 3 or 9 waves per 64-target chunk x 8,
+16 or 64 targets per group, and the group-per-wave kernel with 8, 16 or 64
+targets per wave -- keeps the fastest, sets it in the library (sph_set_tuning) and caches
 the choice in a JSON table keyed by the problem shape (precision, particle
 count, grid).  The table path comes from WCSPH_TUNE_CACHE (default:
 tune_table.json next to this file, which holds the shapes measured on
@@ -19,6 +20,10 @@ from . import lib
 
 SPLITS = (1, 3, 9)
 GROUPS = (8, 16, 64)
+KERNEL_ROWS, KERNEL_GROUPS = 1, 2
+#: (kernel, waves per chunk, targets per group)
+SHAPES = tuple((KERNEL_ROWS, s, g) for s in SPLITS for g in GROUPS) + tuple(
+    (KERNEL_GROUPS, 1, g) for g in GROUPS)
 CACHE = os.environ.get("WCSPH_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json"))
 
@@ -43,13 +48,19 @@ def _save(tab: Dict[str, dict]) -> None:
     os.replace(tmp, CACHE)
 
 
-_state = {"fp64": (0, 0), "mixed": (0, 0)}
+_state = {"fp64": (0, 0, 0), "mixed": (0, 0, 0)}
 
 
 def apply(precision: str, shape) -> None:
-    _state[precision] = (int(shape[0]), int(shape[1]))
-    lib.set_tuning(split_fp64=_state["fp64"][0], split_mixed=_state["mixed"][0],
-                   group_fp64=_state["fp64"][1], group_mixed=_state["mixed"][1])
+    """shape = (kernel, split, group); older two-entry (split, group) table
+    entries mean the row-split kernel."""
+    shape = tuple(int(v) for v in shape)
+    if len(shape) == 2:
+        shape = (KERNEL_ROWS,) + shape
+    _state[precision] = shape
+    f, m = _state["fp64"], _state["mixed"]
+    lib.set_tuning(split_fp64=f[1], split_mixed=m[1], group_fp64=f[2], group_mixed=m[2],
+                   kernel_fp64=f[0], kernel_mixed=m[0])
 
 
 def tune(scene, precision: str = "mixed", steps: int = 30, warmup: int = 5,
@@ -62,25 +73,24 @@ def tune(scene, precision: str = "mixed", steps: int = 30, warmup: int = 5,
         apply(precision, tab[key]["shape"])
         return tuple(tab[key]["shape"])
     times = {}
-    for split in SPLITS:
-        for group in GROUPS:
-            apply(precision, (split, group))
-            sim = lib.Simulation(scene, precision)
-            sim.run(warmup, -1.0, 0)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            sim.run(steps, -1.0, warmup)
-            torch.cuda.synchronize()
-            times[(split, group)] = (time.perf_counter() - t0) / steps
-            del sim
-            if verbose:
-                print(f"autotune {key} split={split} group={group}: "
-                      f"{times[(split, group)] * 1e3:.3f} ms/step", flush=True)
+    for shape in SHAPES:
+        apply(precision, shape)
+        sim = lib.Simulation(scene, precision)
+        sim.run(warmup, -1.0, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(steps, -1.0, warmup)
+        torch.cuda.synchronize()
+        times[shape] = (time.perf_counter() - t0) / steps
+        del sim
+        if verbose:
+            print(f"autotune {key} kernel={shape[0]} split={shape[1]} group={shape[2]}: "
+                  f"{times[shape] * 1e3:.3f} ms/step", flush=True)
     best = min(times, key=times.get)
     apply(precision, best)
     tab = _load()
     tab[key] = {"shape": list(best),
-                "ms_per_step": {f"{k[0]}x{k[1]}": v * 1e3 for k, v in times.items()}}
+                "ms_per_step": {"%dx%dx%d" % k: v * 1e3 for k, v in times.items()}}
     try:
         _save(tab)
     except OSError:

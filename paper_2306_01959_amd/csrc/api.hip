@@ -38,7 +38,8 @@ WsLayout make_layout(const Problem &P) {
     L.ncells = P.ncells;
     L.nrows = P.nrows;
     L.ntiles = (n + kSortTile - 1) / kSortTile;
-    L.max_chunks = (n + kChunk - 1) / kChunk + L.nrows;
+    // chunks hold >= kMinChunk targets except the last of each row
+    L.max_chunks = (n + kMinChunk - 1) / kMinChunk + L.nrows;
     int bits = 0;
     while (bits < 32 && ((int64_t)1 << bits) < L.ncells) ++bits;
     L.key_bits = bits;
@@ -477,28 +478,37 @@ int sph_check_params(const sph_params *p) { return check_params(p); }
 
 int sph_set_tuning(const sph_tuning *t) {
     if (!t) return fail(SPH_E_INVAL, "tuning is NULL");
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 2; ++k)
         if (t->reserved[k] != 0) return fail(SPH_E_INVAL, "tuning reserved must be 0");
     auto split_ok = [](int v) { return v == 0 || v == 1 || v == 3 || v == 9; };
     auto group_ok = [](int v) { return v == 0 || v == 8 || v == 16 || v == 64; };
+    auto kernel_ok = [](int v) {
+        return v == SPH_KERNEL_AUTO || v == SPH_KERNEL_ROWS || v == SPH_KERNEL_GROUPS;
+    };
     if (!split_ok(t->split_fp64) || !split_ok(t->split_mixed))
         return fail(SPH_E_INVAL, "split must be 0, 1, 3 or 9");
     if (!group_ok(t->group_fp64) || !group_ok(t->group_mixed))
         return fail(SPH_E_INVAL, "group must be 0, 8, 16 or 64");
+    if (!kernel_ok(t->kernel_fp64) || !kernel_ok(t->kernel_mixed))
+        return fail(SPH_E_INVAL, "kernel must be an sph_kernel value");
     set_split(SPH_FP64, t->split_fp64);
     set_split(SPH_MIXED, t->split_mixed);
     set_group(SPH_FP64, t->group_fp64);
     set_group(SPH_MIXED, t->group_mixed);
+    set_kernel(SPH_FP64, t->kernel_fp64);
+    set_kernel(SPH_MIXED, t->kernel_mixed);
     return SPH_OK;
 }
 
-int sph_get_split(const sph_params *p, int64_t n, int32_t *split, int32_t *group) {
+int sph_get_split(const sph_params *p, int64_t n, int32_t *split, int32_t *group,
+                  int32_t *kernel) {
     if (int rc = check_params(p)) return rc;
     if (int rc = check_n(n)) return rc;
-    if (!split || !group) return fail(SPH_E_INVAL, "output is NULL");
+    if (!split || !group || !kernel) return fail(SPH_E_INVAL, "output is NULL");
     const Problem P = single_problem(*p, n);
-    *split = split_for(P, make_layout(P).max_chunks);
+    *split = split_for(P);
     *group = group_for(P);
+    *kernel = kernel_for(P);
     return SPH_OK;
 }
 

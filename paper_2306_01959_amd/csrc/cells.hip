@@ -415,8 +415,9 @@ int launch_cell_table(const Ws &w, const uint32_t *keys, hipStream_t st) {
 
 // ------------------------------------------------------------ chunk list
 //
-// The interaction works on chunks: up to 64 consecutive sorted particles of
-// one cell row (fixed cy, cz) of one instance.  Per row: the number of its
+// The interaction works on chunks: up to csz (64, or the group size of the
+// group-per-wave kernel) consecutive sorted particles of one cell row (fixed
+// cy, cz) of one instance.  Per row: the number of its
 // chunks (k_row_counts), an exclusive scan of those numbers (the first chunk
 // of every row), then the chunks {start, end, local row, instance} and the
 // chunk count (k_row_chunks).
@@ -440,13 +441,10 @@ __device__ __forceinline__ void row_range(const uint32_t *start, const Insts &I,
 }
 
 __global__ void k_row_counts(const uint32_t *__restrict__ start, Insts I, int64_t nrows,
-                             uint32_t *__restrict__ cnt, DevScalars *sc, InstState *ist,
-                             int lagged, double dt_arg) {
+                             uint32_t csz, uint32_t *__restrict__ cnt, DevScalars *sc,
+                             InstState *ist, int lagged, double dt_arg) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g == 0) {
-        sc->work = 0;
-        if (lagged) sc->steps += 1;
-    }
+    if (g == 0 && lagged) sc->steps += 1;
     constexpr unsigned long long kInf = 0x7ff0000000000000ull;
     if (g < I.n) {
         const int k = (int)g;
@@ -472,22 +470,22 @@ __global__ void k_row_counts(const uint32_t *__restrict__ start, Insts I, int64_
     uint32_t b, e;
     int inst, lrow;
     row_range(start, I, g, b, e, inst, lrow);
-    cnt[g] = (e - b + kChunk - 1) / kChunk;
+    cnt[g] = (e - b + csz - 1) / csz;
 }
 
 __global__ void k_row_chunks(const uint32_t *__restrict__ start, Insts I, int64_t nrows,
-                             const uint32_t *__restrict__ first, int4 *__restrict__ chunks,
-                             DevScalars *sc) {
+                             uint32_t csz, const uint32_t *__restrict__ first,
+                             int4 *__restrict__ chunks, DevScalars *sc) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrows) return;
     uint32_t b, e;
     int inst, lrow;
     row_range(start, I, r, b, e, inst, lrow);
-    const uint32_t nch = (e - b + kChunk - 1) / kChunk;
+    const uint32_t nch = (e - b + csz - 1) / csz;
     const uint32_t f = first[r];
     for (uint32_t k = 0; k < nch; ++k) {
-        const uint32_t s0 = b + k * kChunk;
-        const uint32_t s1 = s0 + kChunk < e ? s0 + kChunk : e;
+        const uint32_t s0 = b + k * csz;
+        const uint32_t s1 = s0 + csz < e ? s0 + csz : e;
         chunks[f + k] = make_int4((int)s0, (int)s1, lrow, inst);
     }
     if (r == nrows - 1) sc->nchunks = f + nch;
@@ -498,12 +496,13 @@ int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStre
     const int64_t m = nrows > (int64_t)P.host.size() ? nrows : (int64_t)P.host.size();
     const int blocks = (int)((m + 255) / 256);
     const Insts I = insts_of(P, w);
+    const uint32_t csz = (uint32_t)chunk_for(P);
     hipLaunchKernelGGL(k_row_counts, dim3(blocks), dim3(256), 0, st, w.cell_start(), I, nrows,
-                       w.row_first(), w.scalars(), w.inst_state(), (int)lagged, dt);
+                       csz, w.row_first(), w.scalars(), w.inst_state(), (int)lagged, dt);
     if (int rc = launch_check("chunk counts")) return rc;
     if (int rc = launch_scan(w.row_first(), nrows, w.scan_tot(), st)) return rc;
     hipLaunchKernelGGL(k_row_chunks, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st,
-                       w.cell_start(), I, nrows, w.row_first(), w.chunks(), w.scalars());
+                       w.cell_start(), I, nrows, csz, w.row_first(), w.chunks(), w.scalars());
     return launch_check("chunk list");
 }
 

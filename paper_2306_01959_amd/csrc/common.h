@@ -21,12 +21,14 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kScanThreads = 1024;   // scan workgroup
 constexpr int kScanSpan = 4 * kScanThreads;  // values per scanned span
 constexpr int kScanSerialSpans = 4;  // up to this many spans: one block scans them in turn
-constexpr int kChunk = 64;           // targets per interaction chunk (one wave)
+constexpr int kChunk = 64;           // targets per chunk of the row-split interaction
+constexpr int kMinChunk = 8;         // smallest chunk (group-per-wave interaction)
 constexpr int kDiagThreads = 256;
 constexpr int kDiagBlocks = 256;     // partial sums of a single system (fixed: deterministic)
 constexpr int kDiagBlocksBatch = 32; // partial sums per instance of a batch
 constexpr int kDiagFields = 16;
 constexpr int kMaxProbes = 1024;     // probe points per sph_diagnostics call
+constexpr int kPairSlots = 8;        // copies of the pair counters
 constexpr int64_t kMaxGraphSteps = 400;  // longest captured step sequence
 
 // Constants of one particle system ("instance"): its grid, its slice of the
@@ -64,10 +66,10 @@ struct InstState {
 struct DevScalars {
     long long steps;                 // steps taken
     unsigned int nchunks;            // interaction chunks of the current cells
-    unsigned int work;               // next interaction chunk to take
     unsigned int dt_cfl_violation;   // a step used dt > dt_cfl
-    unsigned int pad_;
-    unsigned long long pairs[3];     // interacting pairs since init: FF, FB, BF
+    // interacting pairs since init, [slot][FF, FB, BF]; the total is the sum
+    // over slots (spread to keep atomics of many workgroups apart)
+    unsigned long long pairs[3 * kPairSlots];
 };
 
 // Device-side access to the instances: a table in the workspace (batches) or
@@ -206,8 +208,11 @@ void after_fused_step(sph_state &s);
 int diag_blocks(int ninst);
 int set_split(int precision, int split);
 int set_group(int precision, int group);
-int split_for(const Problem &P, int64_t max_chunks);
+int set_kernel(int precision, int kernel);
+int split_for(const Problem &P);
 int group_for(const Problem &P);
+int kernel_for(const Problem &P);
+int chunk_for(const Problem &P);  // targets per chunk of the interaction launched for P
 
 // Cell id layout inside an instance: local = cx + nx * (cy + ny * cz).
 __host__ __device__ inline int64_t lin_cell(int cx, int cy, int cz, int nx, int ny) {

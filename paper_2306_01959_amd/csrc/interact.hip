@@ -49,8 +49,7 @@ struct InteractArgs {
     const uint32_t *cell_start;  // ncells + 1
     const void *v0, *v1, *v2;    // interaction view
     void *ax, *ay, *az, *drho, *mumax;
-    unsigned long long *pairs;   // running totals: fluid-fluid, fluid-boundary, boundary-fluid
-    unsigned int *work;          // next chunk to take (reset to 0 with the chunk list)
+    unsigned long long *pairs;   // running totals: [slot][fluid-fluid, fluid-boundary, boundary-fluid]
     const uint32_t *id;          // original ids (neighbour statistics only)
     int32_t *st_nf, *st_nb;      // per-particle fluid / boundary neighbour counts
     uint32_t *st_hash;           // per-particle sum of id_hash(id_j) mod 2^32
@@ -134,6 +133,25 @@ struct Stats {
     uint32_t h = 0;
 };
 
+// Running minimum of positive doubles by their bit patterns (which order like
+// the values).  The bound rarely improves on the current minimum, so most
+// calls skip the atomic after a relaxed read: contended atomics on one
+// address are slow, and a stale read can only be larger, never wrong.
+__device__ __forceinline__ void min_bits(unsigned long long *p, double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (b < cur) atomicMin(p, b);
+}
+
+// Pair totals, spread over kPairSlots copies (by workgroup) so that the
+// integer atomics of many workgroups do not all meet on one address.
+__device__ __forceinline__ void add_pairs(unsigned long long *pairs, const Counters &cn) {
+    unsigned long long *p = pairs + 3 * (blockIdx.x % kPairSlots);
+    if (cn.ff) atomicAdd(&p[0], (unsigned long long)cn.ff);
+    if (cn.fb) atomicAdd(&p[1], (unsigned long long)cn.fb);
+    if (cn.bf) atomicAdd(&p[2], (unsigned long long)cn.bf);
+}
+
 // ================================================================ policies
 //
 // A policy supplies the target record (three vectors of 4 in LDS), the raw
@@ -153,7 +171,9 @@ struct Mixed {
     struct Cand {
         float4 v0, v1;
         float2 v2;
-        int cx;
+        uint32_t key;  // global cell (raw: nothing is computed from a load
+                       // before it is needed, so the next batch's loads stay
+                       // in flight while the current batch is processed)
         bool ok;
     };
     __device__ static void target(const InteractArgs &a, const Inst &ip, int i, bool act, int rowbase, int cxa,
@@ -177,26 +197,23 @@ struct Mixed {
         by = v0.y;
         bz = v0.z;
     }
-    __device__ static void load(const InteractArgs &a, const Inst &ip, int j, int je, int nbase, Cand &c) {
+    // Loads candidate j (< je), or for j >= je particle 0 with ok = false:
+    // no branch around the loads, so the compiler can count them exactly
+    // and wait for the current batch only.
+    __device__ static void load(const InteractArgs &a, const Inst &ip, int j, int je, Cand &c) {
         c.ok = j < je;
-        if (c.ok) {
-            c.v0 = static_cast<const float4 *>(a.v0)[j];
-            c.v1 = static_cast<const float4 *>(a.v1)[j];
-            c.v2 = static_cast<const float2 *>(a.v2)[j];
-            c.cx = (int)a.keys[j] - nbase;
-        } else {
-            c.v0 = make_float4(0.f, 0.f, 0.f, 0.f);
-            c.v1 = c.v0;
-            c.v2 = make_float2(1.f, 1.f);
-            c.cx = 0;
-        }
+        const int jj = c.ok ? j : 0;
+        c.v0 = static_cast<const float4 *>(a.v0)[jj];
+        c.v1 = static_cast<const float4 *>(a.v1)[jj];
+        c.v2 = static_cast<const float2 *>(a.v2)[jj];
+        c.key = a.keys[jj];
     }
     // position of a candidate in the chunk frame (cell cxa of the chunk's
-    // row), for culling only
-    __device__ static void cull_pos(const InteractArgs &a, const Inst &ip, const Cand &c, int cxa, int dy, int dz,
-                                    float &qx, float &qy, float &qz) {
+    // row), for culling only; nbase = first global cell of its row
+    __device__ static void cull_pos(const InteractArgs &a, const Inst &ip, const Cand &c, int nbase,
+                                    int cxa, int dy, int dz, float &qx, float &qy, float &qz) {
         const float csf = (float)ip.cs;
-        qx = c.v0.x + (float)(c.cx - cxa) * csf;
+        qx = c.v0.x + (float)((int)c.key - nbase - cxa) * csf;
         qy = c.v0.y + (float)dy * csf;
         qz = c.v0.z + (float)dz * csf;
     }
@@ -211,14 +228,15 @@ struct Mixed {
     // record: {o_x, c_x, o_y + dy cs, o_z + dz cs}, {u, P/rho}, {index bits,
     // 1/rho, (rho - rho0) B, B} with B = 2 delta h c0 / rho (0 when the pair
     // carries no delta term), {rho - rho0, +-c (- = boundary), -, -}
-    __device__ static void stage(const InteractArgs &a, const Inst &ip, const Cand &c, int j, int dy, int dz,
-                                 float4 *rec0, float4 *rec1, float4 *rec2, float4 *rec3) {
+    __device__ static void stage(const InteractArgs &a, const Inst &ip, const Cand &c, int nbase,
+                                 int j, int dy, int dz, float4 *rec0, float4 *rec1, float4 *rec2,
+                                 float4 *rec3) {
         const float csf = (float)ip.cs;
         const float invr = c.v2.x;
         const bool fj = c.v2.y > 0.f;
         const float kd = (fj || ip.delta_all) ? (float)ip.kdelta : 0.f;
         const float B = kd * invr;
-        *rec0 = make_float4(c.v0.x, (float)c.cx, c.v0.y + (float)dy * csf,
+        *rec0 = make_float4(c.v0.x, (float)((int)c.key - nbase), c.v0.y + (float)dy * csf,
                             c.v0.z + (float)dz * csf);
         *rec1 = make_float4(c.v1.x, c.v1.y, c.v1.z, c.v1.w * invr);
         *rec2 = make_float4(__int_as_float(j), invr, c.v0.w * B, B);
@@ -335,22 +353,17 @@ struct Fp64 {
         by = v0.y;
         bz = v0.z;
     }
-    __device__ static void load(const InteractArgs &a, const Inst &ip, int j, int je, int nbase, Cand &c) {
-        (void)nbase;
+    __device__ static void load(const InteractArgs &a, const Inst &ip, int j, int je, Cand &c) {
         c.ok = j < je;
-        if (c.ok) {
-            c.v0 = static_cast<const double4 *>(a.v0)[j];
-            c.v1 = static_cast<const double4 *>(a.v1)[j];
-            c.v2 = static_cast<const double2 *>(a.v2)[j];
-        } else {
-            c.v0 = make_double4(0, 0, 0, 1);
-            c.v1 = make_double4(0, 0, 0, 0);
-            c.v2 = make_double2(1, 1);
-        }
+        const int jj = c.ok ? j : 0;
+        c.v0 = static_cast<const double4 *>(a.v0)[jj];
+        c.v1 = static_cast<const double4 *>(a.v1)[jj];
+        c.v2 = static_cast<const double2 *>(a.v2)[jj];
     }
-    __device__ static void cull_pos(const InteractArgs &a, const Inst &ip, const Cand &c, int cxa, int dy, int dz,
-                                    double &qx, double &qy, double &qz) {
+    __device__ static void cull_pos(const InteractArgs &a, const Inst &ip, const Cand &c, int nbase,
+                                    int cxa, int dy, int dz, double &qx, double &qy, double &qz) {
         (void)a;
+        (void)nbase;
         (void)cxa;
         (void)dy;
         (void)dz;
@@ -369,8 +382,10 @@ struct Fp64 {
     __device__ static bool cand_fluid(const Cand &c) { return c.v2.y > 0.0; }
     __device__ static bool rec_fluid(const double4 &r3) { return r3.y > 0.0; }
     // record: {x, y, z, index}, {u, P/rho}, {1/rho, B, rho, -}, {-, +-c, -, -}
-    __device__ static void stage(const InteractArgs &a, const Inst &ip, const Cand &c, int j, int dy, int dz,
-                                 double4 *rec0, double4 *rec1, double4 *rec2, double4 *rec3) {
+    __device__ static void stage(const InteractArgs &a, const Inst &ip, const Cand &c, int nbase,
+                                 int j, int dy, int dz, double4 *rec0, double4 *rec1, double4 *rec2,
+                                 double4 *rec3) {
+        (void)nbase;
         (void)dy;
         (void)dz;
         const double invr = c.v2.x;
@@ -475,17 +490,14 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
 
     const int w = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    __shared__ uint32_t s_next;
     Counters cn;
-    // Persistent workgroups take chunks from a counter: chunk costs vary with
-    // the flow (dense water, dry walls), so static assignment leaves CUs idle.
-    // Chunks are independent and each is summed in a fixed order, so results
-    // do not depend on which workgroup takes which chunk.
-    for (;;) {
-    if (threadIdx.x == 0) s_next = atomicAdd(a.work, 1u);
-    __syncthreads();  // also retires the previous chunk's use of LDS
-    const uint32_t chunk = (uint32_t)uni((int)s_next);
-    if (chunk >= a.sc->nchunks) break;
+    // One workgroup per chunk; the grid covers the most chunks the cells can
+    // produce and the workgroups past the current count exit at once.  The
+    // hardware dispatcher balances the uneven chunk costs (dense water, dry
+    // walls) with no shared counter to contend for.
+    {
+    const uint32_t chunk = blockIdx.x;
+    if (chunk >= a.sc->nchunks) return;
     const int4 ch = a.chunks[chunk];
     const int cs0 = uni(ch.x), cs1 = uni(ch.y), row = uni(ch.z), inst = uni(ch.w);
     const Inst ip = a.I.get(inst);
@@ -560,25 +572,17 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     Acc<R> acc[kG];
     Stats sts[kG];
 
-    int q = uni(next_row(0));
-    int jb = q < kRows ? uni(rows[w][q].x) : 0;
-    typename P::Cand cur, nxt;
-    if (q < kRows) P::load(a, ip, jb + lane, rows[w][q].y, rows[w][q].z, cur);
-    while (q < kRows) {
+    // One batch of 64 candidates (row q, first index jb): cull against the
+    // chunk box, compact into LDS, per group the records that reach it, then
+    // the pairs.
+    auto process = [&](const typename P::Cand &cur, int q, int jb) __attribute__((always_inline)) {
         const int4 rq = rows[w][q];
         const int dy = (rq.w & 3) - 1, dz = (rq.w >> 2) - 1;
-        int q2 = q, jb2 = jb + kWave;
-        if (jb2 >= rq.y) {
-            q2 = uni(next_row(q + 1));
-            jb2 = q2 < kRows ? uni(rows[w][q2].x) : 0;
-        }
-        if (q2 < kRows) P::load(a, ip, jb2 + lane, rows[w][q2].y, rows[w][q2].z, nxt);
-
         // cull against the chunk box, compact the survivors into LDS
         bool keep = false;
         if (cur.ok) {
             R qx, qy, qz;
-            P::cull_pos(a, ip, cur, cxa, dy, dz, qx, qy, qz);
+            P::cull_pos(a, ip, cur, rq.z, cxa, dy, dz, qx, qy, qz);
             const R ex = fmax(fmax(lox - qx, qx - hix), (R)0);
             const R ey = fmax(fmax(loy - qy, qy - hiy), (R)0);
             const R ez = fmax(fmax(loz - qz, qz - hiz), (R)0);
@@ -587,7 +591,7 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
         const uint64_t m = __ballot(keep);
         if (keep) {
             const int slot = __popcll(m & below);
-            P::stage(a, ip, cur, jb + lane, dy, dz, &stg[w][0][slot], &stg[w][1][slot],
+            P::stage(a, ip, cur, rq.z, jb + lane, dy, dz, &stg[w][0][slot], &stg[w][1][slot],
                      &stg[w][2][slot], &stg[w][3][slot]);
         }
         wave_sync();
@@ -637,9 +641,37 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
             }
         }
         wave_sync();
-        cur = nxt;
-        q = q2;
-        jb = jb2;
+    };
+    // the batch after (q, jb): the next 64 of the row, else the next non-empty row
+    auto next_batch = [&](int q, int jb, int &q2, int &jb2) __attribute__((always_inline)) {
+        q2 = q;
+        jb2 = jb + kWave;
+        if (jb2 >= rows[w][q].y) {
+            q2 = uni(next_row(q + 1));
+            jb2 = q2 < kRows ? uni(rows[w][q2].x) : 0;
+        }
+    };
+    // (a batch past the last row loads nothing useful: every lane not ok)
+    auto load_batch = [&](int q, int jb, typename P::Cand &c) __attribute__((always_inline)) {
+        const bool has = q < kRows;
+        const int je = has ? rows[w][has ? q : 0].y : 0;
+        P::load(a, ip, has ? jb + lane : 0, je, c);
+    };
+    // two candidate register sets in alternation: the loads of the next
+    // batch are in flight while the current one is processed
+    typename P::Cand ca, cb;
+    int qa = uni(next_row(0));
+    int ja = qa < kRows ? uni(rows[w][qa].x) : 0;
+    load_batch(qa, ja, ca);
+    while (qa < kRows) {
+        int qb, jbb;
+        next_batch(qa, ja, qb, jbb);
+        load_batch(qb, jbb, cb);
+        process(ca, qa, ja);
+        if (qb >= kRows) break;
+        next_batch(qb, jbb, qa, ja);
+        load_batch(qa, ja, ca);
+        process(cb, qb, jbb);
     }
 
     // sum the kG lanes that share a target (fixed shuffle tree); each wave's
@@ -713,20 +745,188 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
             const double dt = a.ist[inst].dt_last;
             const bool euler =
                 a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
-            advance<P::kMixed>(a.state, it, dt, euler, fax, fay, faz, (double)sd);
+            wcsph::advance<P::kMixed>(a.state, it, dt, euler, fax, fay, faz, (double)sd);
         }
     }
     bound = group_min(bound, kWave);
-    if (lane == 0)
-        atomicMin(&a.ist[inst].dt_min_bits, (unsigned long long)__double_as_longlong(bound));
+    if (lane == 0) min_bits(&a.ist[inst].dt_min_bits, bound);
     }  // w == 0
-    }  // chunks
-    // pair totals: integer atomics, order does not matter
-    if (lane == 0) {
-        if (cn.ff) atomicAdd(&a.pairs[0], (unsigned long long)cn.ff);
-        if (cn.fb) atomicAdd(&a.pairs[1], (unsigned long long)cn.fb);
-        if (cn.bf) atomicAdd(&a.pairs[2], (unsigned long long)cn.bf);
+    }  // chunk
+    if (lane == 0) add_pairs(a.pairs, cn);
+}
+
+// ======================================================= wave-per-group
+//
+// Second decomposition: a work item is a group of up to kT consecutive sorted
+// particles of one cell row, owned by one wave that streams the item's own
+// candidates (the nine stencil rows over [cx_first - 1, cx_last + 1]) and
+// culls them against the group's box directly.  Waves never wait for each
+// other (no workgroup barriers, no cross-wave sums) and hold one set of
+// accumulators, so they need far fewer registers than the chunk kernel and
+// more of them fit on a SIMD.  Lane (t, s) works on target t and on every
+// (64 / kT)-th staged record; the per-target sums are combined by the same
+// fixed shuffle tree, so results are deterministic.
+
+constexpr int kWavesPerGroupWG = 4;  // independent waves per workgroup
+
+template <class P, int kT, bool kStats, bool kFuse>
+__global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(InteractArgs a) {
+    using R = typename P::R;
+    using V4 = typename P::V4;
+    constexpr int kG = kWave / kT;
+    static_assert(kT == 8 || kT == 16 || kT == 64, "group size");
+    __shared__ V4 stg_all[kWavesPerGroupWG][4][kWave];
+    const int w = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    V4(*stg)[kWave] = stg_all[w];
+    const int t_in = lane % kT;
+    const int slot_s = lane / kT;
+    const uint64_t below = lanes_below();
+    Counters cn;
+    {
+        const uint32_t item = blockIdx.x * kWavesPerGroupWG + w;
+        if (item >= a.sc->nchunks) return;  // waves of a workgroup are independent
+        const int4 ch = a.chunks[item];
+        const int cs0 = uni(ch.x), cs1 = uni(ch.y), row = uni(ch.z), inst = uni(ch.w);
+        const Inst ip = a.I.get(inst);
+        const int cy = row % ip.ny, cz = row / ip.ny;
+        const int ntgt = cs1 - cs0;
+        const int rowbase = (int)ip.cell_base + row * ip.nx;
+        const int cxa = uni((int)a.keys[cs0] - rowbase);
+        const int cxb = uni((int)a.keys[cs1 - 1] - rowbase);
+
+        // the target of this lane (every slot lane of target t loads it)
+        const int it = cs0 + t_in;
+        const bool act = t_in < ntgt;
+        typename P::T tg;
+        R bx, by, bz;
+        bool fi_own;
+        P::target(a, ip, it, act, rowbase, cxa, tg.a, tg.b, tg.c, bx, by, bz, fi_own);
+        const R big = (R)3.0e38f;
+        const R lox = group_min(act ? bx : big, kWave), hix = group_max(act ? bx : -big, kWave);
+        const R loy = group_min(act ? by : big, kWave), hiy = group_max(act ? by : -big, kWave);
+        const R loz = group_min(act ? bz : big, kWave), hiz = group_max(act ? bz : -big, kWave);
+        const bool any_fluid = __ballot(fi_own) != 0ull;
+        const R cull2 = (R)(ip.r2max * (1.0 + 1e-3));
+
+        // stencil rows: lane q < 9 holds row q's {first, end, base cell, dy/dz code}
+        int r_js = 0, r_je = 0, r_nb = 0, r_code = 0;
+        if (lane < 9) {
+            const int dz = lane / 3 - 1, dy = lane % 3 - 1;
+            const int czn = cz + dz, cyn = cy + dy;
+            r_code = (dy + 1) | ((dz + 1) << 2);
+            if (czn >= 0 && czn < ip.nz && cyn >= 0 && cyn < ip.ny) {
+                r_nb = (int)ip.cell_base + (czn * ip.ny + cyn) * ip.nx;
+                const int xlo = cxa - 1 < 0 ? 0 : cxa - 1;
+                const int xhi = cxb + 1 >= ip.nx ? ip.nx - 1 : cxb + 1;
+                r_js = (int)a.cell_start[r_nb + xlo];
+                r_je = (int)a.cell_start[r_nb + xhi + 1];
+            }
+        }
+        auto row_js = [&](int q) { return __builtin_amdgcn_readlane(r_js, q); };
+        auto row_je = [&](int q) { return __builtin_amdgcn_readlane(r_je, q); };
+        auto next_row = [&](int q) {
+            while (q < 9 && row_js(q) >= row_je(q)) ++q;
+            return q;
+        };
+        auto next_batch = [&](int q, int jb, int &q2, int &jb2) __attribute__((always_inline)) {
+            q2 = q;
+            jb2 = jb + kWave;
+            if (jb2 >= row_je(q)) {
+                q2 = next_row(q + 1);
+                jb2 = q2 < 9 ? row_js(q2) : 0;
+            }
+        };
+        auto load_batch = [&](int q, int jb, typename P::Cand &c) __attribute__((always_inline)) {
+            const bool has = q < 9;
+            P::load(a, ip, has ? jb + lane : 0, has ? row_je(q) : 0, c);
+        };
+
+        Acc<R> acc;
+        Stats sts;
+        auto process = [&](const typename P::Cand &cur, int q, int jb) __attribute__((always_inline)) {
+            const int code = __builtin_amdgcn_readlane(r_code, q);
+            const int nbase = __builtin_amdgcn_readlane(r_nb, q);
+            const int dy = (code & 3) - 1, dz = (code >> 2) - 1;
+            bool keep = false;
+            if (cur.ok) {
+                R qx, qy, qz;
+                P::cull_pos(a, ip, cur, nbase, cxa, dy, dz, qx, qy, qz);
+                const R ex = fmax(fmax(lox - qx, qx - hix), (R)0);
+                const R ey = fmax(fmax(loy - qy, qy - hiy), (R)0);
+                const R ez = fmax(fmax(loz - qz, qz - hiz), (R)0);
+                keep = (ex * ex + ey * ey + ez * ez) <= cull2 && (any_fluid || P::cand_fluid(cur));
+            }
+            const uint64_t m = __ballot(keep);
+            if (keep) {
+                const int slot = __popcll(m & below);
+                P::stage(a, ip, cur, nbase, jb + lane, dy, dz, &stg[0][slot], &stg[1][slot],
+                         &stg[2][slot], &stg[3][slot]);
+            }
+            wave_sync();
+            const int cnt = __popcll(m);
+            for (int s0 = 0; s0 < cnt; s0 += kG) {
+                const int sl = s0 + slot_s;
+                const bool valid = sl < cnt && act;
+                const int k = sl < cnt ? sl : 0;
+                const V4 r0 = stg[0][k], r1 = stg[1][k];
+                const V4 r2 = stg[2][k], r3 = stg[3][k];
+                P::template pair<kStats>(a, ip, tg, it, valid, r0, r1, r2, r3, acc, cn, sts);
+            }
+            wave_sync();
+        };
+
+        // two candidate register sets in alternation (see the chunk kernel)
+        typename P::Cand ca, cb;
+        int qa = next_row(0);
+        int ja = qa < 9 ? row_js(qa) : 0;
+        load_batch(qa, ja, ca);
+        while (qa < 9) {
+            int qb, jbb;
+            next_batch(qa, ja, qb, jbb);
+            load_batch(qb, jbb, cb);
+            process(ca, qa, ja);
+            if (qb >= 9) break;
+            next_batch(qb, jbb, qa, ja);
+            load_batch(qa, ja, ca);
+            process(cb, qb, jbb);
+        }
+
+        // sum the slot lanes of each target (fixed shuffle tree)
+        for (int off = kT; off < kWave; off <<= 1) {
+            acc.ax += __shfl_xor(acc.ax, off, kWave);
+            acc.ay += __shfl_xor(acc.ay, off, kWave);
+            acc.az += __shfl_xor(acc.az, off, kWave);
+            acc.dr += __shfl_xor(acc.dr, off, kWave);
+            const R om = __shfl_xor(acc.mu, off, kWave);
+            acc.mu = om > acc.mu ? om : acc.mu;
+            if constexpr (kStats) {
+                sts.f += __shfl_xor(sts.f, off, kWave);
+                sts.b += __shfl_xor(sts.b, off, kWave);
+                sts.h += (uint32_t)__shfl_xor((int)sts.h, off, kWave);
+            }
+        }
+        double bound = __longlong_as_double(0x7ff0000000000000ll);
+        if (act && slot_s == 0) {
+            double fax, fay, faz;
+            P::store(a, ip, it, fi_own, acc.ax, acc.ay, acc.az, acc.dr, acc.mu, !kFuse, bound,
+                     fax, fay, faz);
+            if constexpr (kStats) {
+                a.st_nf[it] = sts.f;
+                a.st_nb[it] = sts.b;
+                a.st_hash[it] = sts.h;
+            }
+            if constexpr (kFuse) {
+                const double dt = a.ist[inst].dt_last;
+                const bool euler =
+                    a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
+                wcsph::advance<P::kMixed>(a.state, it, dt, euler, fax, fay, faz, (double)acc.dr);
+            }
+        }
+        bound = group_min(bound, kWave);
+        if (lane == 0) min_bits(&a.ist[inst].dt_min_bits, bound);
     }
+    if (lane == 0) add_pairs(a.pairs, cn);
 }
 
 // ================================================================ launch
@@ -735,6 +935,24 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
 // group (0 = automatic)
 static int g_split[2] = {0, 0};
 static int g_group[2] = {0, 0};
+static int g_kernel[2] = {0, 0};
+
+int set_kernel(int precision, int kernel) {
+    if (precision != SPH_FP64 && precision != SPH_MIXED) return -1;
+    if (kernel != SPH_KERNEL_AUTO && kernel != SPH_KERNEL_ROWS && kernel != SPH_KERNEL_GROUPS)
+        return -1;
+    g_kernel[precision] = kernel;
+    return 0;
+}
+
+int kernel_for(const Problem &P) {
+    const int pr = P.precision == SPH_MIXED ? SPH_MIXED : SPH_FP64;
+    return g_kernel[pr] ? g_kernel[pr] : SPH_KERNEL_ROWS;
+}
+
+int chunk_for(const Problem &P) {
+    return kernel_for(P) == SPH_KERNEL_GROUPS ? group_for(P) : kChunk;
+}
 
 int set_split(int precision, int split) {
     if (precision != SPH_FP64 && precision != SPH_MIXED) return -1;
@@ -750,9 +968,10 @@ int set_group(int precision, int group) {
     return 0;
 }
 
-int split_for(const Problem &P, int64_t max_chunks) {
+int split_for(const Problem &P) {
     const int s = g_split[P.precision == SPH_MIXED ? SPH_MIXED : SPH_FP64];
     if (s) return s;
+    const int64_t max_chunks = (P.n + kChunk - 1) / kChunk + P.nrows;
     // enough waves to fill 256 CUs x 4 SIMDs several times over
     if (max_chunks < 2048) return 9;
     if (max_chunks < 16384) return 3;
@@ -765,38 +984,11 @@ int group_for(const Problem &P) {
     return pr == SPH_MIXED ? 8 : 16;
 }
 
-// Workgroups that fit on the device at once (all CUs, full occupancy),
-// capped by the number of chunks: the grid of the persistent kernel.
-template <class K>
-static uint32_t persistent_grid(K kernel, int threads, uint32_t cap) {
-    int dev = 0;
-    int cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-        cus = 256;
-    int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
-        per <= 0)
-        per = 1;
-    const uint64_t full = (uint64_t)cus * (uint64_t)per;
-    return (uint32_t)(full < cap ? full : cap);
-}
-
+// nb: the most chunks the cells can produce (one workgroup each)
 template <class P, int kSplit, int kT, bool kStats, bool kFuse>
-static void launch_one(uint32_t cap, const InteractArgs &a, hipStream_t st) {
-    auto kern = k_interact<P, kSplit, kT, kStats, kFuse>;
-    // the grid depends only on the kernel and the device: computed once
-    static thread_local int dev_seen = -1;
-    static thread_local uint32_t full = 0;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    if (dev != dev_seen) {
-        full = persistent_grid(kern, kWave * kSplit, 0xffffffffu);
-        dev_seen = dev;
-    }
-    const uint32_t nb = full < cap ? full : cap;
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(kWave * kSplit), 0, st, a);
+static void launch_one(uint32_t nb, const InteractArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL((k_interact<P, kSplit, kT, kStats, kFuse>), dim3(nb), dim3(kWave * kSplit),
+                       0, st, a);
 }
 
 template <class P, int kSplit, bool kStats, bool kFuse>
@@ -830,9 +1022,41 @@ static void launch_shape(int split, int group, uint32_t nb, const InteractArgs &
     }
 }
 
+// nb: workgroups of kWavesPerGroupWG waves covering the most chunks
+template <class P, int kT, bool kStats, bool kFuse>
+static void launch_g(uint32_t nb, const InteractArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL((k_interact_g<P, kT, kStats, kFuse>), dim3(nb),
+                       dim3(kWave * kWavesPerGroupWG), 0, st, a);
+}
+
+template <class P, bool kStats, bool kFuse>
+static void launch_g_group(int group, uint32_t cap, const InteractArgs &a, hipStream_t st) {
+    switch (group) {
+    case 8:
+        launch_g<P, 8, kStats, kFuse>(cap, a, st);
+        break;
+    case 16:
+        launch_g<P, 16, kStats, kFuse>(cap, a, st);
+        break;
+    default:
+        launch_g<P, 64, kStats, kFuse>(cap, a, st);
+        break;
+    }
+}
+
 template <class P>
-static void launch_prec(int split, int group, uint32_t nb, bool stats, bool fuse,
+static void launch_prec(int kernel, int split, int group, uint32_t nb, bool stats, bool fuse,
                         const InteractArgs &a, hipStream_t st) {
+    if (kernel == SPH_KERNEL_GROUPS) {
+        const uint32_t cap = (nb + kWavesPerGroupWG - 1) / kWavesPerGroupWG;
+        if (stats)
+            launch_g_group<P, true, false>(group, cap, a, st);
+        else if (fuse)
+            launch_g_group<P, false, true>(group, cap, a, st);
+        else
+            launch_g_group<P, false, false>(group, cap, a, st);
+        return;
+    }
     if (stats)
         launch_shape<P, true, false>(split, group, nb, a, st);
     else if (fuse)
@@ -863,7 +1087,6 @@ int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream
     a.drho = r + 3 * e * n;
     a.mumax = r + 4 * e * n;
     a.pairs = w.scalars()->pairs;
-    a.work = &w.scalars()->work;
     a.id = s.id;
     a.st_nf = st_nf;
     a.st_nb = st_nb;
@@ -872,13 +1095,16 @@ int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream
                           s.uxm, s.uym, s.uzm, s.rho,  s.rhom, s.id};
     a.step = step;
     const bool stats = st_nf != nullptr;
-    const uint32_t nb = (uint32_t)w.L.max_chunks;  // cap on the persistent grid
-    const int split = split_for(P, w.L.max_chunks);
+    // chunks of <= csz targets: at most ceil(n / csz) + one short chunk per row
+    const int64_t csz = chunk_for(P);
+    const uint32_t nb = (uint32_t)((P.n + csz - 1) / csz + P.nrows);
+    const int split = split_for(P);
     const int group = group_for(P);
+    const int kernel = kernel_for(P);
     if (P.precision == SPH_MIXED)
-        launch_prec<Mixed>(split, group, nb, stats, fuse && !stats, a, st);
+        launch_prec<Mixed>(kernel, split, group, nb, stats, fuse && !stats, a, st);
     else
-        launch_prec<Fp64>(split, group, nb, stats, fuse && !stats, a, st);
+        launch_prec<Fp64>(kernel, split, group, nb, stats, fuse && !stats, a, st);
     return launch_check("interact");
 }
 

@@ -52,10 +52,14 @@ class SphParams(C.Structure):
 _P = C.c_void_p
 
 
+SPH_KERNEL_AUTO, SPH_KERNEL_ROWS, SPH_KERNEL_GROUPS = 0, 1, 2
+
+
 class SphTuning(C.Structure):
     _fields_ = [("split_fp64", C.c_int32), ("split_mixed", C.c_int32),
                 ("group_fp64", C.c_int32), ("group_mixed", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("kernel_fp64", C.c_int32), ("kernel_mixed", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class SphState(C.Structure):
@@ -113,7 +117,8 @@ def load(path: str = LIB_PATH):
     L.sph_last_error.restype = C.c_char_p
     L.sph_check_params.argtypes = [PP]
     L.sph_set_tuning.argtypes = [C.POINTER(SphTuning)]
-    L.sph_get_split.argtypes = [PP, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.sph_get_split.argtypes = [PP, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_int32)]
     L.sph_workspace_bytes.argtypes = [PP, C.c_int64, C.POINTER(C.c_size_t)]
     L.sph_workspace_init.argtypes = [PP, C.c_int64, _P, C.c_size_t, _P]
     L.sph_set_density.argtypes = [PP, PS, _P, C.c_int32, _P]
@@ -149,22 +154,25 @@ def check(rc: int) -> None:
 
 
 def set_tuning(split_fp64: int = 0, split_mixed: int = 0, group_fp64: int = 0,
-               group_mixed: int = 0) -> None:
+               group_mixed: int = 0, kernel_fp64: int = 0, kernel_mixed: int = 0) -> None:
     """Process-wide interaction launch shape (0 = the library's choice)."""
     t = SphTuning()
     t.split_fp64 = int(split_fp64)
     t.split_mixed = int(split_mixed)
     t.group_fp64 = int(group_fp64)
     t.group_mixed = int(group_mixed)
+    t.kernel_fp64 = int(kernel_fp64)
+    t.kernel_mixed = int(kernel_mixed)
     check(load().sph_set_tuning(C.byref(t)))
 
 
 def get_split(params: "SphParams", n: int):
-    """(waves per chunk, targets per group) the library will launch."""
+    """(waves per chunk, targets per group, kernel) the library will launch."""
     v = C.c_int32(0)
     g = C.c_int32(0)
-    check(load().sph_get_split(C.byref(params), int(n), C.byref(v), C.byref(g)))
-    return int(v.value), int(g.value)
+    k = C.c_int32(0)
+    check(load().sph_get_split(C.byref(params), int(n), C.byref(v), C.byref(g), C.byref(k)))
+    return int(v.value), int(g.value), int(k.value)
 
 
 def make_params(prm: Dict[str, object], precision: str = "mixed", *,

@@ -295,27 +295,30 @@ def test_hydrostatic_column(gpu, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_every_launch_shape_matches(gpu, oracle_lib, developed, precision):
-    """Every launch shape the autotuner may pick (1, 3 or 9 waves per chunk
-    x 8, 16 or 64 targets per group) gives bit-identical neighbour sets and
-    oracle-parity rates."""
+    """Every launch shape the autotuner may pick -- the row-split kernel with
+    1, 3 or 9 waves per chunk x 8, 16 or 64 targets per group, and the
+    group-per-wave kernel with 8, 16 or 64 -- gives bit-identical neighbour
+    sets and oracle-parity rates."""
     params, st = developed
     sc, prev = scene_from_oracle(st, params)
     ref = _oracle_rates(oracle_lib, params, st)
     tol = 1e-12 if precision == "fp64" else 1e-5
+    shapes = [(gpu.SPH_KERNEL_ROWS, split, group) for split in (1, 3, 9)
+              for group in (8, 16, 64)]
+    shapes += [(gpu.SPH_KERNEL_GROUPS, 1, group) for group in (8, 16, 64)]
     stats = []
     try:
-        for split in (1, 3, 9):
-            for group in (8, 16, 64):
-                if precision == "fp64":
-                    gpu.set_tuning(split_fp64=split, group_fp64=group)
-                else:
-                    gpu.set_tuning(split_mixed=split, group_mixed=group)
-                sim = _sim(gpu, sc, precision, prev)
-                assert gpu.get_split(sim.params, sim.n) == (split, group)
-                got = sim.rates_by_id()
-                for k in range(4):
-                    assert rel_l2(got[k], ref[k]) < tol, (split, group, k)
-                stats.append(sim.neighbour_stats())
+        for kernel, split, group in shapes:
+            if precision == "fp64":
+                gpu.set_tuning(split_fp64=split, group_fp64=group, kernel_fp64=kernel)
+            else:
+                gpu.set_tuning(split_mixed=split, group_mixed=group, kernel_mixed=kernel)
+            sim = _sim(gpu, sc, precision, prev)
+            assert gpu.get_split(sim.params, sim.n) == (split, group, kernel)
+            got = sim.rates_by_id()
+            for k in range(4):
+                assert rel_l2(got[k], ref[k]) < tol, (kernel, split, group, k)
+            stats.append(sim.neighbour_stats())
     finally:
         gpu.set_tuning()
     for s_ in stats[1:]:
