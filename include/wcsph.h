@@ -178,9 +178,12 @@ typedef enum {
                               waves (1, 3 or 9) divide the 9 stencil rows; inside
                               a wave the targets form groups of `group` (8, 16
                               or 64), each culled on its own */
-    SPH_KERNEL_GROUPS = 2  /* one independent wave per group of up to `group`
+    SPH_KERNEL_GROUPS = 2, /* one independent wave per group of up to `group`
                               targets of one cell row (8, 16 or 64), streaming
                               and culling its own candidates; `split` unused */
+    SPH_KERNEL_COOP = 3    /* four groups of `group` targets (8 or 16; 64 acts
+                              as 16) per workgroup, which loads and culls their
+                              candidates once for all four; `split` unused */
 } sph_kernel;
 
 /*

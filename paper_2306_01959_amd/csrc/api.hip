@@ -64,6 +64,7 @@ WsLayout make_layout(const Problem &P) {
     L.row_first = take(4 * (size_t)L.nrows);
     L.cell_start = take(4 * (size_t)(L.ncells + 1));
     L.chunks = take(sizeof(int4) * (size_t)L.max_chunks);
+    L.chunk_out = take(sizeof(ChunkOut) * (size_t)L.max_chunks);
     L.view0 = take(L.view_elem * (size_t)n);
     L.view1 = take(L.view_elem * (size_t)n);
     L.view2 = take((mixed ? 8 : 16) * (size_t)n);
@@ -483,7 +484,8 @@ int sph_set_tuning(const sph_tuning *t) {
     auto split_ok = [](int v) { return v == 0 || v == 1 || v == 3 || v == 9; };
     auto group_ok = [](int v) { return v == 0 || v == 8 || v == 16 || v == 64; };
     auto kernel_ok = [](int v) {
-        return v == SPH_KERNEL_AUTO || v == SPH_KERNEL_ROWS || v == SPH_KERNEL_GROUPS;
+        return v == SPH_KERNEL_AUTO || v == SPH_KERNEL_ROWS || v == SPH_KERNEL_GROUPS ||
+               v == SPH_KERNEL_COOP;
     };
     if (!split_ok(t->split_fp64) || !split_ok(t->split_mixed))
         return fail(SPH_E_INVAL, "split must be 0, 1, 3 or 9");

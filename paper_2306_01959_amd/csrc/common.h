@@ -28,7 +28,6 @@ constexpr int kDiagBlocks = 256;     // partial sums of a single system (fixed: 
 constexpr int kDiagBlocksBatch = 32; // partial sums per instance of a batch
 constexpr int kDiagFields = 16;
 constexpr int kMaxProbes = 1024;     // probe points per sph_diagnostics call
-constexpr int kPairSlots = 8;        // copies of the pair counters
 constexpr int64_t kMaxGraphSteps = 400;  // longest captured step sequence
 
 // Constants of one particle system ("instance"): its grid, its slice of the
@@ -62,14 +61,20 @@ struct InstState {
     double pad;
 };
 
+// What the interaction leaves per chunk: the chunk's time-step bound
+// (eq. sphdt, before the Courant factor) and its pair counts FF, FB, BF.
+struct ChunkOut {
+    double bound;
+    uint32_t pairs[3];
+    uint32_t pad;
+};
+
 // Device-wide scalars.
 struct DevScalars {
     long long steps;                 // steps taken
     unsigned int nchunks;            // interaction chunks of the current cells
     unsigned int dt_cfl_violation;   // a step used dt > dt_cfl
-    // interacting pairs since init, [slot][FF, FB, BF]; the total is the sum
-    // over slots (spread to keep atomics of many workgroups apart)
-    unsigned long long pairs[3 * kPairSlots];
+    unsigned long long pairs[3];     // interacting pairs since init: FF, FB, BF
 };
 
 // Device-side access to the instances: a table in the workspace (batches) or
@@ -136,6 +141,7 @@ struct WsLayout {
     size_t row_first = 0;    // chunks per row, then the first chunk of each row
     size_t cell_start = 0;
     size_t chunks = 0;
+    size_t chunk_out = 0;    // ChunkOut per chunk
     size_t view0 = 0, view1 = 0, view2 = 0;
     size_t rates = 0;        // ax, ay, az, drho, mumax (each n values)
     size_t scalars = 0;
@@ -164,6 +170,7 @@ struct Ws {
     uint32_t *row_first() const { return at<uint32_t>(L.row_first); }
     uint32_t *cell_start() const { return at<uint32_t>(L.cell_start); }
     int4 *chunks() const { return at<int4>(L.chunks); }
+    ChunkOut *chunk_out() const { return at<ChunkOut>(L.chunk_out); }
     DevScalars *scalars() const { return at<DevScalars>(L.scalars); }
     Inst *inst_tab() const { return at<Inst>(L.inst_tab); }
     InstState *inst_state() const { return at<InstState>(L.inst_state); }

@@ -288,12 +288,9 @@ int launch_diag(const Problem &P, const sph_state &s, const Ws &w, const double 
         o->n_outside = (int64_t)hv[F_OUTSIDE];
         o->n_nonfinite = (int64_t)hv[F_NONFIN];
         o->steps = sc.steps;
-        uint64_t pr[3] = {0, 0, 0};
-        for (int q = 0; q < kPairSlots; ++q)
-            for (int c = 0; c < 3; ++c) pr[c] += sc.pairs[3 * q + c];
-        o->pairs_ff = (int64_t)pr[0];
-        o->pairs_fb = (int64_t)pr[1];
-        o->pairs_bf = (int64_t)pr[2];
+        o->pairs_ff = (int64_t)sc.pairs[0];
+        o->pairs_fb = (int64_t)sc.pairs[1];
+        o->pairs_bf = (int64_t)sc.pairs[2];
         uint32_t flags = 0;
         if (o->n_nonfinite > 0) flags |= SPH_FLAG_NONFINITE;
         if (o->n_outside > 0) flags |= SPH_FLAG_OUTSIDE;

@@ -156,7 +156,7 @@ __global__ void k_ws_init(DevScalars *sc, InstState *ist, int ninst) {
         sc->steps = 0;
         sc->nchunks = 0;
         sc->dt_cfl_violation = 0;
-        for (int q = 0; q < 3 * kPairSlots; ++q) sc->pairs[q] = 0;
+        sc->pairs[0] = sc->pairs[1] = sc->pairs[2] = 0;
     }
     for (int k = t; k < ninst; k += blockDim.x) {
         ist[k].dt_min_bits = 0x7ff0000000000000ull;  // +inf: no bound yet

@@ -49,7 +49,7 @@ struct InteractArgs {
     const uint32_t *cell_start;  // ncells + 1
     const void *v0, *v1, *v2;    // interaction view
     void *ax, *ay, *az, *drho, *mumax;
-    unsigned long long *pairs;   // running totals: [slot][fluid-fluid, fluid-boundary, boundary-fluid]
+    ChunkOut *cout;              // per chunk: time-step bound and pair counts
     const uint32_t *id;          // original ids (neighbour statistics only)
     int32_t *st_nf, *st_nb;      // per-particle fluid / boundary neighbour counts
     uint32_t *st_hash;           // per-particle sum of id_hash(id_j) mod 2^32
@@ -132,25 +132,6 @@ struct Stats {
     int32_t f = 0, b = 0;
     uint32_t h = 0;
 };
-
-// Running minimum of positive doubles by their bit patterns (which order like
-// the values).  The bound rarely improves on the current minimum, so most
-// calls skip the atomic after a relaxed read: contended atomics on one
-// address are slow, and a stale read can only be larger, never wrong.
-__device__ __forceinline__ void min_bits(unsigned long long *p, double v) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned long long cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (b < cur) atomicMin(p, b);
-}
-
-// Pair totals, spread over kPairSlots copies (by workgroup) so that the
-// integer atomics of many workgroups do not all meet on one address.
-__device__ __forceinline__ void add_pairs(unsigned long long *pairs, const Counters &cn) {
-    unsigned long long *p = pairs + 3 * (blockIdx.x % kPairSlots);
-    if (cn.ff) atomicAdd(&p[0], (unsigned long long)cn.ff);
-    if (cn.fb) atomicAdd(&p[1], (unsigned long long)cn.fb);
-    if (cn.bf) atomicAdd(&p[2], (unsigned long long)cn.bf);
-}
 
 // ================================================================ policies
 //
@@ -491,6 +472,8 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     const int w = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     Counters cn;
+    __shared__ uint32_t wg_pairs[3];
+    if (threadIdx.x < 3) wg_pairs[threadIdx.x] = 0u;  // ordered by the barrier below
     // One workgroup per chunk; the grid covers the most chunks the cells can
     // produce and the workgroups past the current count exit at once.  The
     // hardware dispatcher balances the uneven chunk costs (dense water, dry
@@ -609,7 +592,7 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
             int gcnt[kG];
 #pragma unroll
             for (int g = 0; g < kG; ++g) {
-                const uint64_t gbits = kT == 64 ? ~0ull : (((1ull << kT) - 1) << (g * kT));
+                const uint64_t gbits = kT == 64 ? ~0ull : (((1ull << (kT % 64)) - 1) << (g * kT % 64));
                 const bool gf = (fluid_tgts & gbits) != 0ull;
                 const R ex = fmax(fmax(gbox[g][0] - px, px - gbox[g][1]), (R)0);
                 const R ey = fmax(fmax(gbox[g][2] - py, py - gbox[g][3]), (R)0);
@@ -705,6 +688,12 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
             }
         }
     }
+    // the waves' pair counts (integer, order-free) for the chunk's record
+    if (lane == 0) {
+        atomicAdd(&wg_pairs[0], cn.ff);
+        atomicAdd(&wg_pairs[1], cn.fb);
+        atomicAdd(&wg_pairs[2], cn.bf);
+    }
     __syncthreads();
     if (w == 0) {
     // fixed summation order over the waves; lane = target index again
@@ -749,10 +738,10 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
         }
     }
     bound = group_min(bound, kWave);
-    if (lane == 0) min_bits(&a.ist[inst].dt_min_bits, bound);
+    if (lane == 0)
+        a.cout[chunk] = ChunkOut{bound, {wg_pairs[0], wg_pairs[1], wg_pairs[2]}, 0u};
     }  // w == 0
     }  // chunk
-    if (lane == 0) add_pairs(a.pairs, cn);
 }
 
 // ======================================================= wave-per-group
@@ -924,9 +913,280 @@ __global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(Interact
             }
         }
         bound = group_min(bound, kWave);
-        if (lane == 0) min_bits(&a.ist[inst].dt_min_bits, bound);
+        if (lane == 0) a.cout[item] = ChunkOut{bound, {cn.ff, cn.fb, cn.bf}, 0u};
     }
-    if (lane == 0) add_pairs(a.pairs, cn);
+}
+
+// ======================================================= cooperative groups
+//
+// Third decomposition: a chunk of kCW groups of kT targets (one cell row) per
+// workgroup of kCW waves.  The waves load the chunk's candidates together,
+// kCW x 64 per batch (each wave 64), cull them against the chunk's box and
+// compact them into a shared pool in LDS (double buffered: one barrier per
+// batch).  Each wave then culls the pool against its own group's box and
+// evaluates its pairs as in the group-per-wave kernel.  The candidate stream
+// is read once per chunk instead of once per group, and each wave still
+// holds one set of accumulators.
+
+constexpr int kCW = 4;  // waves (groups) per cooperative chunk
+
+template <class P, int kT, bool kStats, bool kFuse>
+__global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
+    using R = typename P::R;
+    using V4 = typename P::V4;
+    constexpr int kG = kWave / kT;
+    static_assert(kT == 8 || kT == 16, "group size");
+    __shared__ V4 pool[2][4][kCW * kWave];     // staged records, two buffers
+    __shared__ int pcnt[2][kCW];               // records each wave staged per buffer
+    __shared__ R gbox[kCW][6];                 // the groups' boxes
+    __shared__ uint8_t glist[kCW][kCW * kWave];  // per wave: pool records reaching its group
+    __shared__ int anyf;
+    const int w = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const uint64_t below = lanes_below();
+    const uint32_t chunk = blockIdx.x;
+    if (chunk >= a.sc->nchunks) return;
+    const int4 ch = a.chunks[chunk];
+    const int cs0 = uni(ch.x), cs1 = uni(ch.y), row = uni(ch.z), inst = uni(ch.w);
+    const Inst ip = a.I.get(inst);
+    const int cy = row % ip.ny, cz = row / ip.ny;
+    const int rowbase = (int)ip.cell_base + row * ip.nx;
+    const int cxa = uni((int)a.keys[cs0] - rowbase);
+    const int cxb = uni((int)a.keys[cs1 - 1] - rowbase);
+    const int g0 = cs0 + w * kT;                    // this wave's first target
+    const int ntgt = uni(cs1 - g0 < 0 ? 0 : (cs1 - g0 > kT ? kT : cs1 - g0));
+    const int t_in = lane % kT;
+    const int slot_s = lane / kT;
+    const int it = g0 + t_in;
+    const bool act = t_in < ntgt;
+
+    typename P::T tg;
+    R bx, by, bz;
+    bool fi_own;
+    P::target(a, ip, it, act, rowbase, cxa, tg.a, tg.b, tg.c, bx, by, bz, fi_own);
+    const R big = (R)3.0e38f;
+    {
+        const R lx = group_min(act ? bx : big, kWave), hx = group_max(act ? bx : -big, kWave);
+        const R ly = group_min(act ? by : big, kWave), hy = group_max(act ? by : -big, kWave);
+        const R lz = group_min(act ? bz : big, kWave), hz = group_max(act ? bz : -big, kWave);
+        if (lane == 0) {
+            gbox[w][0] = lx;
+            gbox[w][1] = hx;
+            gbox[w][2] = ly;
+            gbox[w][3] = hy;
+            gbox[w][4] = lz;
+            gbox[w][5] = hz;
+        }
+    }
+    if (threadIdx.x == 0) anyf = 0;
+    __syncthreads();
+    const bool my_fluid = __ballot(fi_own) != 0ull;  // (every lane takes part)
+    if (lane == 0 && my_fluid) atomicOr(&anyf, 1);
+    // my group's box (pair culling) and the chunk's box (shared culling)
+    const R mlx = gbox[w][0], mhx = gbox[w][1], mly = gbox[w][2], mhy = gbox[w][3];
+    const R mlz = gbox[w][4], mhz = gbox[w][5];
+    R clx = big, chx = -big, cly = big, chy = -big, clz = big, chz = -big;
+#pragma unroll
+    for (int k = 0; k < kCW; ++k) {
+        clx = fmin(clx, gbox[k][0]);
+        chx = fmax(chx, gbox[k][1]);
+        cly = fmin(cly, gbox[k][2]);
+        chy = fmax(chy, gbox[k][3]);
+        clz = fmin(clz, gbox[k][4]);
+        chz = fmax(chz, gbox[k][5]);
+    }
+    const R cull2 = (R)(ip.r2max * (1.0 + 1e-3));
+
+    // stencil rows: lane q < 9 holds row q's {first, end, base cell, dy/dz code}
+    int r_js = 0, r_je = 0, r_nb = 0, r_code = 0;
+    if (lane < 9) {
+        const int dz = lane / 3 - 1, dy = lane % 3 - 1;
+        const int czn = cz + dz, cyn = cy + dy;
+        r_code = (dy + 1) | ((dz + 1) << 2);
+        if (czn >= 0 && czn < ip.nz && cyn >= 0 && cyn < ip.ny) {
+            r_nb = (int)ip.cell_base + (czn * ip.ny + cyn) * ip.nx;
+            const int xlo = cxa - 1 < 0 ? 0 : cxa - 1;
+            const int xhi = cxb + 1 >= ip.nx ? ip.nx - 1 : cxb + 1;
+            r_js = (int)a.cell_start[r_nb + xlo];
+            r_je = (int)a.cell_start[r_nb + xhi + 1];
+        }
+    }
+    __syncthreads();  // anyf is final
+    const bool any_fluid = anyf != 0;
+    auto row_js = [&](int q) { return __builtin_amdgcn_readlane(r_js, q); };
+    auto row_je = [&](int q) { return __builtin_amdgcn_readlane(r_je, q); };
+    auto next_row = [&](int q) {
+        while (q < 9 && row_js(q) >= row_je(q)) ++q;
+        return q;
+    };
+    constexpr int kB = kCW * kWave;  // candidates per shared batch
+    auto next_batch = [&](int q, int jb, int &q2, int &jb2) __attribute__((always_inline)) {
+        q2 = q;
+        jb2 = jb + kB;
+        if (jb2 >= row_je(q)) {
+            q2 = next_row(q + 1);
+            jb2 = q2 < 9 ? row_js(q2) : 0;
+        }
+    };
+    auto load_batch = [&](int q, int jb, typename P::Cand &c) __attribute__((always_inline)) {
+        const bool has = q < 9;
+        P::load(a, ip, has ? jb + w * kWave + lane : 0, has ? row_je(q) : 0, c);
+    };
+
+    Acc<R> acc;
+    Stats sts;
+    Counters cn;
+    typename P::Cand cur;
+    int q = next_row(0);
+    int jb = q < 9 ? row_js(q) : 0;
+    load_batch(q, jb, cur);
+    int buf = 0;
+    while (q < 9) {
+        const int code = __builtin_amdgcn_readlane(r_code, q);
+        const int nbase = __builtin_amdgcn_readlane(r_nb, q);
+        const int dy = (code & 3) - 1, dz = (code >> 2) - 1;
+        // A: cull my 64 candidates against the chunk box, stage into the pool
+        bool keep = false;
+        if (cur.ok) {
+            R qx, qy, qz;
+            P::cull_pos(a, ip, cur, nbase, cxa, dy, dz, qx, qy, qz);
+            const R ex = fmax(fmax(clx - qx, qx - chx), (R)0);
+            const R ey = fmax(fmax(cly - qy, qy - chy), (R)0);
+            const R ez = fmax(fmax(clz - qz, qz - chz), (R)0);
+            keep = (ex * ex + ey * ey + ez * ez) <= cull2 && (any_fluid || P::cand_fluid(cur));
+        }
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int slot = w * kWave + __popcll(m & below);
+            P::stage(a, ip, cur, nbase, jb + w * kWave + lane, dy, dz, &pool[buf][0][slot],
+                     &pool[buf][1][slot], &pool[buf][2][slot], &pool[buf][3][slot]);
+        }
+        if (lane == 0) pcnt[buf][w] = __popcll(m);
+        // the next batch's loads are in flight during the barrier and B
+        int q2, jb2;
+        next_batch(q, jb, q2, jb2);
+        load_batch(q2, jb2, cur);
+        __syncthreads();
+        // B: the pool records that reach my group, then my pairs
+        if (ntgt > 0) {
+            int n = 0;
+#pragma unroll
+            for (int k = 0; k < kCW; ++k) {
+                const int cnt = pcnt[buf][k];
+                bool kk = false;
+                if (lane < cnt) {
+                    const V4 r0 = pool[buf][0][k * kWave + lane];
+                    const V4 r3 = pool[buf][3][k * kWave + lane];
+                    R px, py, pz;
+                    P::rec_pos(a, ip, r0, cxa, px, py, pz);
+                    const R ex = fmax(fmax(mlx - px, px - mhx), (R)0);
+                    const R ey = fmax(fmax(mly - py, py - mhy), (R)0);
+                    const R ez = fmax(fmax(mlz - pz, pz - mhz), (R)0);
+                    kk = (ex * ex + ey * ey + ez * ez) <= cull2 && (my_fluid || P::rec_fluid(r3));
+                }
+                const uint64_t gm = __ballot(kk);
+                if (kk) glist[w][n + __popcll(gm & below)] = (uint8_t)(k * kWave + lane);
+                n += __popcll(gm);
+            }
+            wave_sync();
+            for (int s0 = 0; s0 < n; s0 += kG) {
+                const int sl = s0 + slot_s;
+                const bool valid = sl < n && act;
+                // idle lanes read a record staged in this batch (entry 0):
+                // their terms are multiplied by zero and must stay finite
+                const int k = (int)glist[w][sl < n ? sl : 0];
+                const V4 r0 = pool[buf][0][k], r1 = pool[buf][1][k];
+                const V4 r2 = pool[buf][2][k], r3 = pool[buf][3][k];
+                P::template pair<kStats>(a, ip, tg, it, valid, r0, r1, r2, r3, acc, cn, sts);
+            }
+            wave_sync();
+        }
+        buf ^= 1;
+        q = q2;
+        jb = jb2;
+    }
+
+    // sum the slot lanes of each target (fixed shuffle tree)
+    for (int off = kT; off < kWave; off <<= 1) {
+        acc.ax += __shfl_xor(acc.ax, off, kWave);
+        acc.ay += __shfl_xor(acc.ay, off, kWave);
+        acc.az += __shfl_xor(acc.az, off, kWave);
+        acc.dr += __shfl_xor(acc.dr, off, kWave);
+        const R om = __shfl_xor(acc.mu, off, kWave);
+        acc.mu = om > acc.mu ? om : acc.mu;
+        if constexpr (kStats) {
+            sts.f += __shfl_xor(sts.f, off, kWave);
+            sts.b += __shfl_xor(sts.b, off, kWave);
+            sts.h += (uint32_t)__shfl_xor((int)sts.h, off, kWave);
+        }
+    }
+    double bound = __longlong_as_double(0x7ff0000000000000ll);
+    if (act && slot_s == 0) {
+        double fax, fay, faz;
+        P::store(a, ip, it, fi_own, acc.ax, acc.ay, acc.az, acc.dr, acc.mu, !kFuse, bound, fax,
+                 fay, faz);
+        if constexpr (kStats) {
+            a.st_nf[it] = sts.f;
+            a.st_nb[it] = sts.b;
+            a.st_hash[it] = sts.h;
+        }
+        if constexpr (kFuse) {
+            const double dt = a.ist[inst].dt_last;
+            const bool euler = a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
+            wcsph::advance<P::kMixed>(a.state, it, dt, euler, fax, fay, faz, (double)acc.dr);
+        }
+    }
+    // the workgroup's bound and pair counts for the chunk's record
+    __shared__ unsigned long long wb;
+    __shared__ uint32_t wp[3];
+    if (threadIdx.x == 0) {
+        wb = 0x7ff0000000000000ull;
+        wp[0] = wp[1] = wp[2] = 0u;
+    }
+    __syncthreads();
+    bound = group_min(bound, kWave);
+    if (lane == 0) {
+        atomicMin(&wb, (unsigned long long)__double_as_longlong(bound));
+        atomicAdd(&wp[0], cn.ff);
+        atomicAdd(&wp[1], cn.fb);
+        atomicAdd(&wp[2], cn.bf);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        a.cout[chunk] = ChunkOut{__longlong_as_double((long long)wb), {wp[0], wp[1], wp[2]}, 0u};
+}
+
+// Per-instance minimum of the chunks' time-step bounds and the pair totals.
+// Block b reduces chunks [1024 b, 1024 b + 1024): chunks are ordered by
+// instance, so the block's instances are inst0 .. inst0 + 1023 at most; a
+// minimum per instance in LDS, then one global atomic per instance and
+// block (a handful in all: no contention).
+__global__ __launch_bounds__(1024) void k_chunk_reduce(const int4 *__restrict__ chunks,
+                                                       const ChunkOut *__restrict__ cout,
+                                                       DevScalars *sc, InstState *ist) {
+    __shared__ unsigned long long smin[1024];
+    __shared__ unsigned long long spairs[3];
+    __shared__ int inst0;
+    const uint32_t nch = sc->nchunks;
+    const uint32_t c0 = blockIdx.x * 1024u;
+    if (c0 >= nch) return;
+    const int t = threadIdx.x;
+    smin[t] = 0x7ff0000000000000ull;
+    if (t < 3) spairs[t] = 0ull;
+    if (t == 0) inst0 = chunks[c0].w;
+    __syncthreads();
+    const uint32_t c = c0 + (uint32_t)t;
+    if (c < nch) {
+        const ChunkOut o = cout[c];
+        const int slot = chunks[c].w - inst0;
+        atomicMin(&smin[slot], (unsigned long long)__double_as_longlong(o.bound));
+        if (o.pairs[0]) atomicAdd(&spairs[0], (unsigned long long)o.pairs[0]);
+        if (o.pairs[1]) atomicAdd(&spairs[1], (unsigned long long)o.pairs[1]);
+        if (o.pairs[2]) atomicAdd(&spairs[2], (unsigned long long)o.pairs[2]);
+    }
+    __syncthreads();
+    if (smin[t] != 0x7ff0000000000000ull) atomicMin(&ist[inst0 + t].dt_min_bits, smin[t]);
+    if (t < 3 && spairs[t]) atomicAdd(&sc->pairs[t], spairs[t]);
 }
 
 // ================================================================ launch
@@ -939,7 +1199,8 @@ static int g_kernel[2] = {0, 0};
 
 int set_kernel(int precision, int kernel) {
     if (precision != SPH_FP64 && precision != SPH_MIXED) return -1;
-    if (kernel != SPH_KERNEL_AUTO && kernel != SPH_KERNEL_ROWS && kernel != SPH_KERNEL_GROUPS)
+    if (kernel != SPH_KERNEL_AUTO && kernel != SPH_KERNEL_ROWS && kernel != SPH_KERNEL_GROUPS &&
+        kernel != SPH_KERNEL_COOP)
         return -1;
     g_kernel[precision] = kernel;
     return 0;
@@ -951,7 +1212,10 @@ int kernel_for(const Problem &P) {
 }
 
 int chunk_for(const Problem &P) {
-    return kernel_for(P) == SPH_KERNEL_GROUPS ? group_for(P) : kChunk;
+    const int k = kernel_for(P);
+    if (k == SPH_KERNEL_GROUPS) return group_for(P);
+    if (k == SPH_KERNEL_COOP) return kCW * (group_for(P) == 8 ? 8 : 16);
+    return kChunk;
 }
 
 int set_split(int precision, int split) {
@@ -1044,9 +1308,28 @@ static void launch_g_group(int group, uint32_t cap, const InteractArgs &a, hipSt
     }
 }
 
+template <class P, bool kStats, bool kFuse>
+static void launch_c(int group, uint32_t nb, const InteractArgs &a, hipStream_t st) {
+    if (group == 8)
+        hipLaunchKernelGGL((k_interact_c<P, 8, kStats, kFuse>), dim3(nb), dim3(kWave * kCW), 0, st,
+                           a);
+    else
+        hipLaunchKernelGGL((k_interact_c<P, 16, kStats, kFuse>), dim3(nb), dim3(kWave * kCW), 0,
+                           st, a);
+}
+
 template <class P>
 static void launch_prec(int kernel, int split, int group, uint32_t nb, bool stats, bool fuse,
                         const InteractArgs &a, hipStream_t st) {
+    if (kernel == SPH_KERNEL_COOP) {
+        if (stats)
+            launch_c<P, true, false>(group, nb, a, st);
+        else if (fuse)
+            launch_c<P, false, true>(group, nb, a, st);
+        else
+            launch_c<P, false, false>(group, nb, a, st);
+        return;
+    }
     if (kernel == SPH_KERNEL_GROUPS) {
         const uint32_t cap = (nb + kWavesPerGroupWG - 1) / kWavesPerGroupWG;
         if (stats)
@@ -1086,7 +1369,7 @@ int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream
     a.az = r + 2 * e * n;
     a.drho = r + 3 * e * n;
     a.mumax = r + 4 * e * n;
-    a.pairs = w.scalars()->pairs;
+    a.cout = w.chunk_out();
     a.id = s.id;
     a.st_nf = st_nf;
     a.st_nb = st_nb;
@@ -1105,7 +1388,10 @@ int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream
         launch_prec<Mixed>(kernel, split, group, nb, stats, fuse && !stats, a, st);
     else
         launch_prec<Fp64>(kernel, split, group, nb, stats, fuse && !stats, a, st);
-    return launch_check("interact");
+    if (int rc = launch_check("interact")) return rc;
+    hipLaunchKernelGGL(k_chunk_reduce, dim3((nb + 1023) / 1024), dim3(1024), 0, st, w.chunks(),
+                       w.chunk_out(), w.scalars(), w.inst_state());
+    return launch_check("chunk reduce");
 }
 
 // Copy the internal rates (FP32 or FP64, current order) to FP64 outputs.

@@ -52,7 +52,7 @@ class SphParams(C.Structure):
 _P = C.c_void_p
 
 
-SPH_KERNEL_AUTO, SPH_KERNEL_ROWS, SPH_KERNEL_GROUPS = 0, 1, 2
+SPH_KERNEL_AUTO, SPH_KERNEL_ROWS, SPH_KERNEL_GROUPS, SPH_KERNEL_COOP = 0, 1, 2, 3
 
 
 class SphTuning(C.Structure):

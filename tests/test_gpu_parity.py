@@ -296,9 +296,9 @@ def test_hydrostatic_column(gpu, precision):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_every_launch_shape_matches(gpu, oracle_lib, developed, precision):
     """Every launch shape the autotuner may pick -- the row-split kernel with
-    1, 3 or 9 waves per chunk x 8, 16 or 64 targets per group, and the
-    group-per-wave kernel with 8, 16 or 64 -- gives bit-identical neighbour
-    sets and oracle-parity rates."""
+    1, 3 or 9 waves per chunk x 8, 16 or 64 targets per group, the
+    group-per-wave kernel with 8, 16 or 64, the cooperative kernel with 8 or
+    16 -- gives bit-identical neighbour sets and oracle-parity rates."""
     params, st = developed
     sc, prev = scene_from_oracle(st, params)
     ref = _oracle_rates(oracle_lib, params, st)
@@ -306,6 +306,7 @@ def test_every_launch_shape_matches(gpu, oracle_lib, developed, precision):
     shapes = [(gpu.SPH_KERNEL_ROWS, split, group) for split in (1, 3, 9)
               for group in (8, 16, 64)]
     shapes += [(gpu.SPH_KERNEL_GROUPS, 1, group) for group in (8, 16, 64)]
+    shapes += [(gpu.SPH_KERNEL_COOP, 1, group) for group in (8, 16)]
     stats = []
     try:
         for kernel, split, group in shapes:
