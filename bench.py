@@ -47,8 +47,9 @@ def kernel_name(shape, precision="Mixed"):
         shape = (1,) + shape
     if shape[0] == 2:
         return "k_interact_g<%s, %d, false, false>" % (precision, shape[2])
-    if shape[0] == 3:
-        return "k_interact_c<%s, %d, false, false>" % (precision, 8 if shape[2] == 8 else 16)
+    if shape[0] in (3, 4):
+        return "k_interact_c<%s, %d, false, false, %s>" % (
+            precision, 8 if shape[2] == 8 else 16, "true" if shape[0] == 4 else "false")
     return "k_interact<%s, %d, %d, false, false>" % (precision, shape[1], shape[2])
 
 

@@ -181,9 +181,12 @@ typedef enum {
     SPH_KERNEL_GROUPS = 2, /* one independent wave per group of up to `group`
                               targets of one cell row (8, 16 or 64), streaming
                               and culling its own candidates; `split` unused */
-    SPH_KERNEL_COOP = 3    /* four groups of `group` targets (8 or 16; 64 acts
+    SPH_KERNEL_COOP = 3,   /* four groups of `group` targets (8 or 16; 64 acts
                               as 16) per workgroup, which loads and culls their
                               candidates once for all four; `split` unused */
+    SPH_KERNEL_COOP2 = 4   /* SPH_KERNEL_COOP with the pairs in two phases: the
+                              neighbour test first, then the pair terms over
+                              each target's neighbours only */
 } sph_kernel;
 
 /*

@@ -20,10 +20,11 @@ from . import lib
 
 SPLITS = (1, 3, 9)
 GROUPS = (8, 16, 64)
-KERNEL_ROWS, KERNEL_GROUPS, KERNEL_COOP = 1, 2, 3
+KERNEL_ROWS, KERNEL_GROUPS, KERNEL_COOP, KERNEL_COOP2 = 1, 2, 3, 4
 #: (kernel, waves per chunk, targets per group)
 SHAPES = tuple((KERNEL_ROWS, s, g) for s in SPLITS for g in GROUPS) + tuple(
-    (KERNEL_GROUPS, 1, g) for g in GROUPS) + tuple((KERNEL_COOP, 1, g) for g in (8, 16))
+    (KERNEL_GROUPS, 1, g) for g in GROUPS) + tuple(
+    (k, 1, g) for k in (KERNEL_COOP, KERNEL_COOP2) for g in (8, 16))
 CACHE = os.environ.get("WCSPH_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json"))
 

@@ -37,7 +37,7 @@ WsLayout make_layout(const Problem &P) {
     L.ninst = (int32_t)P.host.size();
     L.ncells = P.ncells;
     L.nrows = P.nrows;
-    L.ntiles = (n + kSortTile - 1) / kSortTile;
+    L.ntiles = (n + sort_tile(n) - 1) / sort_tile(n);
     // chunks hold >= kMinChunk targets except the last of each row
     L.max_chunks = (n + kMinChunk - 1) / kMinChunk + L.nrows;
     int bits = 0;
@@ -485,7 +485,7 @@ int sph_set_tuning(const sph_tuning *t) {
     auto group_ok = [](int v) { return v == 0 || v == 8 || v == 16 || v == 64; };
     auto kernel_ok = [](int v) {
         return v == SPH_KERNEL_AUTO || v == SPH_KERNEL_ROWS || v == SPH_KERNEL_GROUPS ||
-               v == SPH_KERNEL_COOP;
+               v == SPH_KERNEL_COOP || v == SPH_KERNEL_COOP2;
     };
     if (!split_ok(t->split_fp64) || !split_ok(t->split_mixed))
         return fail(SPH_E_INVAL, "split must be 0, 1, 3 or 9");

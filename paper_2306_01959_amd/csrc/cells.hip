@@ -71,6 +71,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
     return peers;
 }
 
+template <int kItems>
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t *__restrict__ keys,
                                                             int64_t n, int shift,
                                                             uint32_t *__restrict__ hist,
@@ -79,8 +80,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t *__re
     const int tid = threadIdx.x;
     for (int d = tid; d < kRadix; d += kSortThreads) h[d] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int it = 0; it < kSortItems; ++it) {
+    const int64_t base = (int64_t)blockIdx.x * kSortThreads * kItems;
+    for (int it = 0; it < kItems; ++it) {
         int64_t idx = base + (int64_t)it * kSortThreads + tid;
         bool ok = idx < n;
         uint32_t d = ok ? (keys[idx] >> shift) & (kRadix - 1) : 0u;
@@ -190,6 +191,7 @@ int launch_scan(uint32_t *a, int64_t m, uint32_t *tot, hipStream_t st) {
     return launch_check("scan");
 }
 
+template <int kItems>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ hist,
@@ -204,9 +206,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
         for (int k = 0; k < kWaves; ++k) wpos[k][d] = 0;
     }
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = (int64_t)blockIdx.x * kSortThreads * kItems;
     const uint64_t lt = lanemask_lt();
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < kItems; ++it) {
         int64_t idx = base + (int64_t)it * kSortThreads + tid;
         bool ok = idx < n;
         uint32_t key = ok ? kin[idx] : 0u;
@@ -242,17 +244,26 @@ int launch_sort(const Ws &w, hipStream_t st, uint32_t **sorted_keys, uint32_t **
     const int64_t n = w.L.n;
     const int ntiles = (int)w.L.ntiles;
     const int passes = w.L.key_bits <= 0 ? 1 : (w.L.key_bits + kRadixBits - 1) / kRadixBits;
+    const bool small = sort_tile(n) == (int64_t)kSortThreads * kSortItemsSmall;
     uint32_t *kin = w.keys(), *kout = w.keys_alt();
     uint32_t *vbuf[2] = {w.vals(), w.vals_alt()};
     uint32_t *vin = nullptr;  // first pass ranks the identity permutation
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = pass * kRadixBits;
         uint32_t *vout = vbuf[pass & 1];
-        hipLaunchKernelGGL(k_sort_hist, dim3(ntiles), dim3(kSortThreads), 0, st, kin, n, shift,
-                           w.hist(), ntiles);
+        if (small)
+            hipLaunchKernelGGL(k_sort_hist<kSortItemsSmall>, dim3(ntiles), dim3(kSortThreads), 0,
+                               st, kin, n, shift, w.hist(), ntiles);
+        else
+            hipLaunchKernelGGL(k_sort_hist<kSortItemsLarge>, dim3(ntiles), dim3(kSortThreads), 0,
+                               st, kin, n, shift, w.hist(), ntiles);
         if (int rc = launch_scan(w.hist(), (int64_t)kRadix * ntiles, w.scan_tot(), st)) return rc;
-        hipLaunchKernelGGL(k_sort_scatter, dim3(ntiles), dim3(kSortThreads), 0, st, kin, vin,
-                           kout, vout, n, shift, w.hist(), ntiles);
+        if (small)
+            hipLaunchKernelGGL(k_sort_scatter<kSortItemsSmall>, dim3(ntiles), dim3(kSortThreads),
+                               0, st, kin, vin, kout, vout, n, shift, w.hist(), ntiles);
+        else
+            hipLaunchKernelGGL(k_sort_scatter<kSortItemsLarge>, dim3(ntiles), dim3(kSortThreads),
+                               0, st, kin, vin, kout, vout, n, shift, w.hist(), ntiles);
         if (int rc = launch_check("radix sort")) return rc;
         uint32_t *t = kin;
         kin = kout;

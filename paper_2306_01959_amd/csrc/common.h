@@ -14,13 +14,18 @@ namespace wcsph {
 
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kSortThreads = 256;    // radix sort workgroup
-constexpr int kSortItems = 16;       // keys per thread per tile
-constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kSortItemsLarge = 16;  // keys per thread per tile (large arrays)
+constexpr int kSortItemsSmall = 4;   // (up to kSortSmallN keys: more, smaller tiles)
+constexpr int64_t kSortSmallN = 1 << 21;
+// keys per sort tile for n keys: enough tiles to occupy the whole chip
+inline int64_t sort_tile(int64_t n) {
+    return (int64_t)kSortThreads * (n <= kSortSmallN ? kSortItemsSmall : kSortItemsLarge);
+}
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kScanThreads = 1024;   // scan workgroup
 constexpr int kScanSpan = 4 * kScanThreads;  // values per scanned span
-constexpr int kScanSerialSpans = 4;  // up to this many spans: one block scans them in turn
+constexpr int kScanSerialSpans = 12; // up to this many spans: one block scans them in turn
 constexpr int kChunk = 64;           // targets per chunk of the row-split interaction
 constexpr int kMinChunk = 8;         // smallest chunk (group-per-wave interaction)
 constexpr int kDiagThreads = 256;

@@ -206,9 +206,9 @@ struct Mixed {
     }
     __device__ static bool cand_fluid(const Cand &c) { return c.v2.y > 0.f; }
     __device__ static bool rec_fluid(const float4 &r3) { return r3.y > 0.f; }
-    // record: {o_x, c_x, o_y + dy cs, o_z + dz cs}, {u, P/rho}, {index bits,
-    // 1/rho, (rho - rho0) B, B} with B = 2 delta h c0 / rho (0 when the pair
-    // carries no delta term), {rho - rho0, +-c (- = boundary), -, -}
+    // record: {o_x, c_x, o_y + dy cs, o_z + dz cs}, {u, P/rho}, {-, 1/rho,
+    // (rho - rho0) B, B} with B = 2 delta h c0 / rho (0 when the pair carries
+    // no delta term), {rho - rho0, +-c (- = boundary), index bits, -}
     __device__ static void stage(const InteractArgs &a, const Inst &ip, const Cand &c, int nbase,
                                  int j, int dy, int dz, float4 *rec0, float4 *rec1, float4 *rec2,
                                  float4 *rec3) {
@@ -220,8 +220,8 @@ struct Mixed {
         *rec0 = make_float4(c.v0.x, (float)((int)c.key - nbase), c.v0.y + (float)dy * csf,
                             c.v0.z + (float)dz * csf);
         *rec1 = make_float4(c.v1.x, c.v1.y, c.v1.z, c.v1.w * invr);
-        *rec2 = make_float4(__int_as_float(j), invr, c.v0.w * B, B);
-        *rec3 = make_float4(c.v0.w, c.v2.y, 0.f, 0.f);
+        *rec2 = make_float4(0.f, invr, c.v0.w * B, B);
+        *rec3 = make_float4(c.v0.w, c.v2.y, __int_as_float(j), 0.f);
     }
     // one (target, record) pair; `valid` is false for idle lanes
     template <bool kStats>
@@ -236,7 +236,7 @@ struct Mixed {
         const float dy = r0.z - t.a.y;
         const float dz = r0.w - t.a.z;
         const float rr = sq_sum_f32(dx, dy, dz);
-        const int j = __float_as_int(r2.x);
+        const int j = __float_as_int(r3.z);
         const bool in = valid && rr < (float)ip.r2max && j != ti && (fi || fj);
         const uint64_t inm = __ballot(in);
         if (inm == 0) return;
@@ -262,6 +262,57 @@ struct Mixed {
         acc.dr -= F * vr;                                    // m (u_i - u_j) . grad_i W_ij
         const float Fd = fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;             // delta term
+        const float visc =
+            vr < 0.f ? -(float)ip.alpha * (t.c.z + fabsf(r3.y)) * mu *
+                           __builtin_amdgcn_rcpf((float)(2.0 * ip.rho0) + t.c.y + r3.x)
+                     : 0.f;
+        const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
+        acc.ax -= s * dx;
+        acc.ay -= s * dy;
+        acc.az -= s * dz;
+    }
+    // Two-phase form of pair(): the neighbour test alone, then the terms of
+    // a known neighbour.  disp() is the displacement and r^2 in the
+    // predicate's operation order.
+    __device__ static float disp(const Inst &ip, const T &t, const float4 &r0, float &dx, float &dy,
+                                 float &dz) {
+        const float sx = fmaf(r0.y - t.a.w, (float)ip.cs, r0.x);
+        dx = sx - t.a.x;
+        dy = r0.z - t.a.y;
+        dz = r0.w - t.a.z;
+        return sq_sum_f32(dx, dy, dz);
+    }
+    __device__ static bool filter(const Inst &ip, const T &t, int ti, const float4 &r0,
+                                  const float4 &r3, bool &fj) {
+        fj = r3.y > 0.f;
+        float dx, dy, dz;
+        const float rr = disp(ip, t, r0, dx, dy, dz);
+        return rr < (float)ip.r2max && __float_as_int(r3.z) != ti && (t.fluid() || fj);
+    }
+    template <bool kStats>
+    __device__ static void body(const InteractArgs &a, const Inst &ip, const T &t, bool valid,
+                                const float4 &r0, const float4 &r1, const float4 &r2,
+                                const float4 &r3, Acc<float> &acc, Stats &st) {
+        const bool fi = t.fluid();
+        float dx, dy, dz;
+        const float rr = disp(ip, t, r0, dx, dy, dz);
+        if (kStats && valid) {
+            if (r3.y > 0.f)
+                ++st.f;
+            else
+                ++st.b;
+            st.h += id_hash(a.id[__float_as_int(r3.z)] & 0x7fffffffu);
+        }
+        const float r = __builtin_amdgcn_sqrtf(rr);
+        const float q2 = fmaf(r, -0.5f * (float)ip.invh, 1.f);
+        const float F = valid ? (float)ip.Fm * q2 * q2 * q2 : 0.f;
+        const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
+        const float vr = vx * dx + vy * dy + vz * dz;
+        const float mu = (float)ip.h * vr * __builtin_amdgcn_rcpf(rr + (float)ip.eta2);
+        acc.mu = valid ? fmaxf(acc.mu, fabsf(mu)) : acc.mu;
+        acc.dr -= F * vr;
+        const float Fd = fi ? F : 0.f;
+        acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;
         const float visc =
             vr < 0.f ? -(float)ip.alpha * (t.c.z + fabsf(r3.y)) * mu *
                            __builtin_amdgcn_rcpf((float)(2.0 * ip.rho0) + t.c.y + r3.x)
@@ -407,6 +458,43 @@ struct Fp64 {
         const double vr = vx * dx + vy * dy + vz * dz;
         const double mu = ip.h * vr / (rr + ip.eta2);
         acc.mu = in ? fmax(acc.mu, fabs(mu)) : acc.mu;
+        acc.dr -= F * vr;
+        const double Fd = fi ? F : 0.0;
+        acc.dr += (r2.z - t.c.y) * r2.y * Fd;
+        const double visc =
+            vr < 0.0 ? -ip.alpha * (t.c.z + fabs(r3.y)) * mu / (t.c.y + r2.z) : 0.0;
+        const double s = (fma(t.b.w, r2.x, r1.w) * t.c.x + visc) * Fd;
+        acc.ax -= s * dx;
+        acc.ay -= s * dy;
+        acc.az -= s * dz;
+    }
+    __device__ static bool filter(const Inst &ip, const T &t, int ti, const double4 &r0,
+                                  const double4 &r3, bool &fj) {
+        fj = r3.y > 0.0;
+        const double dx = r0.x - t.a.x, dy = r0.y - t.a.y, dz = r0.z - t.a.z;
+        const double rr = sq_sum_f64(dx, dy, dz);
+        return rr < ip.r2max && (int)r0.w != ti && (t.fluid() || fj);
+    }
+    template <bool kStats>
+    __device__ static void body(const InteractArgs &a, const Inst &ip, const T &t, bool valid,
+                                const double4 &r0, const double4 &r1, const double4 &r2,
+                                const double4 &r3, Acc<double> &acc, Stats &st) {
+        const bool fi = t.fluid();
+        const double dx = r0.x - t.a.x, dy = r0.y - t.a.y, dz = r0.z - t.a.z;
+        const double rr = sq_sum_f64(dx, dy, dz);
+        if (kStats && valid) {
+            if (r3.y > 0.0)
+                ++st.f;
+            else
+                ++st.b;
+            st.h += id_hash(a.id[(int)r0.w] & 0x7fffffffu);
+        }
+        const double q2 = 1.0 - 0.5 * (sqrt(rr) * ip.invh);
+        const double F = valid ? ip.Fm * q2 * q2 * q2 : 0.0;
+        const double vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
+        const double vr = vx * dx + vy * dy + vz * dz;
+        const double mu = ip.h * vr / (rr + ip.eta2);
+        acc.mu = valid ? fmax(acc.mu, fabs(mu)) : acc.mu;
         acc.dr -= F * vr;
         const double Fd = fi ? F : 0.0;
         acc.dr += (r2.z - t.c.y) * r2.y * Fd;
@@ -930,14 +1018,22 @@ __global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(Interact
 
 constexpr int kCW = 4;  // waves (groups) per cooperative chunk
 
-template <class P, int kT, bool kStats, bool kFuse>
+// kTwo: the pairs of a batch in two phases -- first the neighbour test of
+// every (target, record) pair, appending each target's neighbours to its own
+// list, then the pair terms over the lists (lane (t, s): every kG-th entry of
+// target t's list), so that the costly terms run on neighbours only.  The
+// lists need LDS, so this form uses one pool buffer and two barriers per
+// batch.
+template <class P, int kT, bool kStats, bool kFuse, bool kTwo>
 __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
     using R = typename P::R;
     using V4 = typename P::V4;
     constexpr int kG = kWave / kT;
+    constexpr int kBufs = kTwo ? 1 : 2;
     static_assert(kT == 8 || kT == 16, "group size");
-    __shared__ V4 pool[2][4][kCW * kWave];     // staged records, two buffers
-    __shared__ int pcnt[2][kCW];               // records each wave staged per buffer
+    __shared__ V4 pool[kBufs][4][kCW * kWave];  // staged records
+    __shared__ int pcnt[kBufs][kCW];            // records each wave staged per buffer
+    __shared__ uint8_t tlist[kTwo ? kCW : 1][kTwo ? kT : 1][kCW * kWave];  // per target
     __shared__ R gbox[kCW][6];                 // the groups' boxes
     __shared__ uint8_t glist[kCW][kCW * kWave];  // per wave: pool records reaching its group
     __shared__ int anyf;
@@ -980,8 +1076,11 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
     }
     if (threadIdx.x == 0) anyf = 0;
     __syncthreads();
+    const uint64_t fim = __ballot(tg.fluid());      // lanes whose target is fluid
     const bool my_fluid = __ballot(fi_own) != 0ull;  // (every lane takes part)
     if (lane == 0 && my_fluid) atomicOr(&anyf, 1);
+    // lanes that work on the same target as this one: t_in + m kT
+    const uint64_t same_t = (kT == 16 ? 0x0001000100010001ull : 0x0101010101010101ull) << t_in;
     // my group's box (pair culling) and the chunk's box (shared culling)
     const R mlx = gbox[w][0], mhx = gbox[w][1], mly = gbox[w][2], mhy = gbox[w][3];
     const R mlz = gbox[w][4], mhz = gbox[w][5];
@@ -1089,19 +1188,55 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
                 n += __popcll(gm);
             }
             wave_sync();
-            for (int s0 = 0; s0 < n; s0 += kG) {
-                const int sl = s0 + slot_s;
-                const bool valid = sl < n && act;
-                // idle lanes read a record staged in this batch (entry 0):
-                // their terms are multiplied by zero and must stay finite
-                const int k = (int)glist[w][sl < n ? sl : 0];
-                const V4 r0 = pool[buf][0][k], r1 = pool[buf][1][k];
-                const V4 r2 = pool[buf][2][k], r3 = pool[buf][3][k];
-                P::template pair<kStats>(a, ip, tg, it, valid, r0, r1, r2, r3, acc, cn, sts);
+            if constexpr (kTwo) {
+                // phase 1: the neighbour test; target t's neighbours go to its list
+                uint8_t *tl = tlist[w][t_in];
+                int nn = 0;
+                for (int s0 = 0; s0 < n; s0 += kG) {
+                    const int sl = s0 + slot_s;
+                    const int k = (int)glist[w][sl < n ? sl : 0];
+                    const V4 r0 = pool[buf][0][k], r3 = pool[buf][3][k];
+                    bool fj;
+                    const bool in = P::filter(ip, tg, it, r0, r3, fj) && sl < n && act;
+                    const uint64_t inm = __ballot(in);
+                    const uint64_t fjm = __ballot(fj);
+                    cn.ff += (uint32_t)__popcll(inm & fim & fjm);
+                    cn.fb += (uint32_t)__popcll(inm & fim & ~fjm);
+                    cn.bf += (uint32_t)__popcll(inm & ~fim & fjm);
+                    const uint64_t mine = inm & same_t;
+                    if (in) tl[nn + __popcll(mine & below)] = (uint8_t)k;
+                    nn += __popcll(mine);
+                }
+                wave_sync();
+                // phase 2: the pair terms; idle lanes read a record of this
+                // batch (their terms are multiplied by zero and stay finite)
+                const int nmax = uni(group_max(nn, kWave));
+                const int k0 = (int)glist[w][0];
+                for (int s0 = 0; s0 < nmax; s0 += kG) {
+                    const int sl = s0 + slot_s;
+                    const bool valid = sl < nn;
+                    const int k = valid ? (int)tl[sl] : k0;
+                    const V4 r0 = pool[buf][0][k], r1 = pool[buf][1][k];
+                    const V4 r2 = pool[buf][2][k], r3 = pool[buf][3][k];
+                    P::template body<kStats>(a, ip, tg, valid, r0, r1, r2, r3, acc, sts);
+                }
+            } else {
+                for (int s0 = 0; s0 < n; s0 += kG) {
+                    const int sl = s0 + slot_s;
+                    const bool valid = sl < n && act;
+                    // idle lanes read a record staged in this batch (entry 0):
+                    // their terms are multiplied by zero and must stay finite
+                    const int k = (int)glist[w][sl < n ? sl : 0];
+                    const V4 r0 = pool[buf][0][k], r1 = pool[buf][1][k];
+                    const V4 r2 = pool[buf][2][k], r3 = pool[buf][3][k];
+                    P::template pair<kStats>(a, ip, tg, it, valid, r0, r1, r2, r3, acc, cn,
+                                             sts);
+                }
             }
             wave_sync();
         }
-        buf ^= 1;
+        if constexpr (kTwo) __syncthreads();  // the single pool is rewritten next
+        buf = (buf + 1) % kBufs;
         q = q2;
         jb = jb2;
     }
@@ -1200,7 +1335,7 @@ static int g_kernel[2] = {0, 0};
 int set_kernel(int precision, int kernel) {
     if (precision != SPH_FP64 && precision != SPH_MIXED) return -1;
     if (kernel != SPH_KERNEL_AUTO && kernel != SPH_KERNEL_ROWS && kernel != SPH_KERNEL_GROUPS &&
-        kernel != SPH_KERNEL_COOP)
+        kernel != SPH_KERNEL_COOP && kernel != SPH_KERNEL_COOP2)
         return -1;
     g_kernel[precision] = kernel;
     return 0;
@@ -1214,7 +1349,7 @@ int kernel_for(const Problem &P) {
 int chunk_for(const Problem &P) {
     const int k = kernel_for(P);
     if (k == SPH_KERNEL_GROUPS) return group_for(P);
-    if (k == SPH_KERNEL_COOP) return kCW * (group_for(P) == 8 ? 8 : 16);
+    if (k == SPH_KERNEL_COOP || k == SPH_KERNEL_COOP2) return kCW * (group_for(P) == 8 ? 8 : 16);
     return kChunk;
 }
 
@@ -1308,26 +1443,36 @@ static void launch_g_group(int group, uint32_t cap, const InteractArgs &a, hipSt
     }
 }
 
-template <class P, bool kStats, bool kFuse>
+template <class P, bool kStats, bool kFuse, bool kTwo>
 static void launch_c(int group, uint32_t nb, const InteractArgs &a, hipStream_t st) {
     if (group == 8)
-        hipLaunchKernelGGL((k_interact_c<P, 8, kStats, kFuse>), dim3(nb), dim3(kWave * kCW), 0, st,
-                           a);
+        hipLaunchKernelGGL((k_interact_c<P, 8, kStats, kFuse, kTwo>), dim3(nb), dim3(kWave * kCW),
+                           0, st, a);
     else
-        hipLaunchKernelGGL((k_interact_c<P, 16, kStats, kFuse>), dim3(nb), dim3(kWave * kCW), 0,
-                           st, a);
+        hipLaunchKernelGGL((k_interact_c<P, 16, kStats, kFuse, kTwo>), dim3(nb),
+                           dim3(kWave * kCW), 0, st, a);
+}
+
+template <class P, bool kTwo>
+static void launch_c_mode(int group, uint32_t nb, bool stats, bool fuse, const InteractArgs &a,
+                          hipStream_t st) {
+    if (stats)
+        launch_c<P, true, false, kTwo>(group, nb, a, st);
+    else if (fuse)
+        launch_c<P, false, true, kTwo>(group, nb, a, st);
+    else
+        launch_c<P, false, false, kTwo>(group, nb, a, st);
 }
 
 template <class P>
 static void launch_prec(int kernel, int split, int group, uint32_t nb, bool stats, bool fuse,
                         const InteractArgs &a, hipStream_t st) {
     if (kernel == SPH_KERNEL_COOP) {
-        if (stats)
-            launch_c<P, true, false>(group, nb, a, st);
-        else if (fuse)
-            launch_c<P, false, true>(group, nb, a, st);
-        else
-            launch_c<P, false, false>(group, nb, a, st);
+        launch_c_mode<P, false>(group, nb, stats, fuse, a, st);
+        return;
+    }
+    if (kernel == SPH_KERNEL_COOP2) {
+        launch_c_mode<P, true>(group, nb, stats, fuse, a, st);
         return;
     }
     if (kernel == SPH_KERNEL_GROUPS) {

@@ -52,7 +52,8 @@ class SphParams(C.Structure):
 _P = C.c_void_p
 
 
-SPH_KERNEL_AUTO, SPH_KERNEL_ROWS, SPH_KERNEL_GROUPS, SPH_KERNEL_COOP = 0, 1, 2, 3
+SPH_KERNEL_AUTO, SPH_KERNEL_ROWS, SPH_KERNEL_GROUPS, SPH_KERNEL_COOP, SPH_KERNEL_COOP2 = (
+    0, 1, 2, 3, 4)
 
 
 class SphTuning(C.Structure):

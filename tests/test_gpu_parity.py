@@ -306,7 +306,8 @@ def test_every_launch_shape_matches(gpu, oracle_lib, developed, precision):
     shapes = [(gpu.SPH_KERNEL_ROWS, split, group) for split in (1, 3, 9)
               for group in (8, 16, 64)]
     shapes += [(gpu.SPH_KERNEL_GROUPS, 1, group) for group in (8, 16, 64)]
-    shapes += [(gpu.SPH_KERNEL_COOP, 1, group) for group in (8, 16)]
+    shapes += [(k, 1, group) for k in (gpu.SPH_KERNEL_COOP, gpu.SPH_KERNEL_COOP2)
+               for group in (8, 16)]
     stats = []
     try:
         for kernel, split, group in shapes:
