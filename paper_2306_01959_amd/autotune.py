@@ -97,3 +97,41 @@ def tune(scene, precision: str = "mixed", steps: int = 30, warmup: int = 5,
     except OSError:
         pass
     return best
+
+
+def tune_ensemble(ens, precision: str = "mixed", steps: int = 20, step0: int = 40,
+                  use_cache: bool = True, verbose: bool = False):
+    """(kernel, split, group) for a batch (lib.Ensemble), timed on the batch
+    itself with the lagged fused step; cached like tune()."""
+    import torch
+    key = f"ensemble:{precision}:n={ens.n}:inst={ens.ninst}"
+    tab = _load() if use_cache else {}
+    if key in tab and "shape" in tab[key]:
+        apply(precision, tab[key]["shape"])
+        return tuple(tab[key]["shape"])
+    times = {}
+    step = step0
+    for shape in SHAPES:
+        if shape[0] == KERNEL_ROWS and shape[1] == 9:
+            continue  # nine waves per chunk never pays on batches this large
+        apply(precision, shape)
+        ens.run(2, -1.0, step, lib.RUN_LAGGED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ens.run(steps, -1.0, step + 2, lib.RUN_LAGGED)
+        torch.cuda.synchronize()
+        times[shape] = (time.perf_counter() - t0) / steps
+        step += steps + 2
+        if verbose:
+            print(f"autotune {key} kernel={shape[0]} split={shape[1]} group={shape[2]}: "
+                  f"{times[shape] * 1e3:.3f} ms/step", flush=True)
+    best = min(times, key=times.get)
+    apply(precision, best)
+    tab = _load()
+    tab[key] = {"shape": list(best),
+                "ms_per_step": {"%dx%dx%d" % k: v * 1e3 for k, v in times.items()}}
+    try:
+        _save(tab)
+    except OSError:
+        pass
+    return best
