@@ -1,0 +1,152 @@
+"""Parity at the workloads' full sizes, in the launch shapes the benchmark
+uses (the autotuner's table), through the C ABI.
+
+* Obstacle dam break at dp = 0.005 (875,904 particles) and dp = 0.0025
+  (5,798,336 particles): rates of every particle at a state the oracle
+  produced (a few oracle steps from the initial set), against the oracle's
+  rates at that state: mixed <= 1e-5 relative L2 (plus the interaction-only
+  norm), FP64 <= 1e-12; interacting pair counts equal to the oracle's in
+  FP64.
+* The 64-instance ensemble (4,526,960 particles): every instance's rates
+  against the oracle at its own oracle-advanced state; the lagged, fused,
+  graph-replayed run equal bit for bit to eager launches of the same steps.
+"""
+import numpy as np
+import pytest
+
+from paper_2306_01959_amd import autotune, scene
+from tests.gpu_helpers import rel_l2, scene_from_oracle
+
+pytestmark = pytest.mark.gpu
+
+BENCH_KEY = "n=146752:dims=40x16x30"  # the single-system benchmark workload
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_01959_amd import lib
+    lib.load()
+    return lib
+
+
+def bench_shape(gpu, precision):
+    """Apply the interaction shape the benchmark uses for `precision`."""
+    tab = autotune._load()
+    ent = tab.get(f"{precision}:{BENCH_KEY}")
+    if ent is not None:
+        autotune.apply(precision, ent["shape"])
+    return ent
+
+
+def oracle_state(orc, sc, nsteps):
+    p = orc.par(sc.params)
+    st = orc.State(sc)
+    orc.run(p, st, nsteps, dt_mode=1)
+    return p, st
+
+
+def check_rates(gpu, orc, sc, p, st, precision):
+    cur, prev = scene_from_oracle(st, sc.params)
+    ref_r, ref_cnt = orc.rates(p, st.x, st.y, st.z, st.ux, st.uy, st.uz, st.rho, st.is_bnd,
+                               want_counts=True)
+    sim = gpu.Simulation(cur, precision)
+    sim.upload(cur, prev)
+    d0, _ = sim.diagnostics()
+    got = sim.rates_by_id()
+    d1, _ = sim.diagnostics()
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for k in range(4):
+        err = rel_l2(got[k], ref_r[k])
+        assert err < tol, (precision, k, err)
+    # interaction-only norm: gravity removed from the fluid accelerations
+    f = ~cur.is_boundary
+    g = np.asarray(sc.params["g"])
+    a_got = np.concatenate([got[k][f] - g[k] for k in range(3)])
+    a_ref = np.concatenate([ref_r[k][f] - g[k] for k in range(3)])
+    assert rel_l2(a_got, a_ref) < (1e-11 if precision == "fp64" else 1e-4)
+    if precision == "fp64":
+        pairs = [d1[k] - d0[k] for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
+        assert pairs == [int(c) for c in ref_cnt], (pairs, ref_cnt)
+    del sim
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_obstacle_dp0005_rates(gpu, oracle_lib, precision):
+    sc = scene.config_scene(3)
+    assert sc.n == 875904
+    p, st = oracle_state(oracle_lib, sc, 8)
+    try:
+        bench_shape(gpu, precision)
+        check_rates(gpu, oracle_lib, sc, p, st, precision)
+    finally:
+        gpu.set_tuning()
+
+
+def test_obstacle_dp00025_rates_mixed(gpu, oracle_lib):
+    sc = scene.config_scene(5)
+    assert sc.n == 5798336
+    p, st = oracle_state(oracle_lib, sc, 2)
+    try:
+        bench_shape(gpu, "mixed")
+        check_rates(gpu, oracle_lib, sc, p, st, "mixed")
+    finally:
+        gpu.set_tuning()
+
+
+@pytest.fixture(scope="module")
+def ensemble_scenes():
+    scs = scene.ensemble(64)
+    assert sum(s.n for s in scs) == 4526960
+    return scs
+
+
+def test_ensemble_fullsize_rates(gpu, oracle_lib, ensemble_scenes):
+    """Every instance of the 64-instance batch, two oracle steps in, in the
+    batch's tuned launch shape."""
+    orc = oracle_lib
+    cur, states = [], []
+    for sc in ensemble_scenes:
+        p, st = oracle_state(orc, sc, 2)
+        c, _ = scene_from_oracle(st, sc.params)
+        cur.append(c)
+        states.append((p, st))
+    ens = gpu.Ensemble(cur, "mixed")
+    try:
+        tab = autotune._load()
+        ent = tab.get(f"ensemble:mixed:n={ens.n}:inst={ens.ninst}")
+        if ent is not None:
+            autotune.apply("mixed", ent["shape"])
+        got = ens.rates_by_id()
+    finally:
+        gpu.set_tuning()
+    worst = 0.0
+    for k, (p, st) in enumerate(states):
+        ref = orc.rates(p, st.x, st.y, st.z, st.ux, st.uy, st.uz, st.rho, st.is_bnd)
+        o, c = ens.offsets[k], ens.counts[k]
+        for q in range(4):
+            worst = max(worst, rel_l2(got[q][o:o + c], ref[q]))
+    assert worst < 1e-5, worst
+
+
+def test_ensemble_fullsize_graph_equals_eager(gpu, ensemble_scenes):
+    """80 steps of the benchmark's ensemble form (lagged dt, fused update):
+    40 eager, then one 40-step graph replayed once, against 80 eager steps."""
+    import torch
+    a = gpu.Ensemble(ensemble_scenes, "mixed")
+    a.run(80, -1.0, 0, mode=gpu.RUN_LAGGED)
+    ra = a.fetch()
+    da = a.diagnostics()
+    del a
+    b = gpu.Ensemble(ensemble_scenes, "mixed", stream=torch.cuda.Stream())
+    b.run(80, -1.0, 0, mode=gpu.RUN_LAGGED | gpu.RUN_GRAPH)
+    rb = b.fetch()
+    db = b.diagnostics()
+    for key in ("x", "y", "z", "ux", "uz", "rho"):
+        assert np.array_equal(ra[key], rb[key]), key
+    for k in range(len(ensemble_scenes)):
+        assert da[k]["time"] == db[k]["time"]
+        assert da[k]["n_nonfinite"] == 0
+        assert da[k]["flags"] & gpu.FLAG_DT_CFL == 0
