@@ -59,8 +59,10 @@ WsLayout make_layout(const Problem &P) {
     L.vals_alt = take(4 * (size_t)n);
     L.sorted_keys = (passes & 1) ? L.keys_alt : L.keys;
     L.hist = take(4 * (size_t)kRadix * (size_t)L.ntiles);
+    L.hist_off = take(4 * (size_t)kRadix * (size_t)L.ntiles);
     const size_t scanned = std::max((size_t)kRadix * (size_t)L.ntiles, (size_t)L.nrows);
     L.scan_tot = take(4 * ((scanned + kScanSpan - 1) / kScanSpan));
+    L.row_cnt = take(4 * (size_t)L.nrows);
     L.row_first = take(4 * (size_t)L.nrows);
     L.cell_start = take(4 * (size_t)(L.ncells + 1));
     L.chunks = take(sizeof(int4) * (size_t)L.max_chunks);

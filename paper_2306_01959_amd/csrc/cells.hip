@@ -135,28 +135,57 @@ __device__ __forceinline__ void span_load(const uint32_t *a, int64_t m, int64_t 
     for (int q = 0; q < 4; ++q) v[q] = i0 + q < m ? a[i0 + q] : 0u;
 }
 
-// Scans span `base` in place with a starting offset; returns the span total.
-__device__ __forceinline__ uint32_t span_scan(uint32_t *a, int64_t m, int64_t base, uint32_t carry,
-                                              uint32_t *wsum) {
+// Scans span `base` of `in` into `out` (may be the same array) from a
+// starting offset; returns the span total.
+__device__ __forceinline__ uint32_t span_scan(const uint32_t *in, uint32_t *out, int64_t m,
+                                              int64_t base, uint32_t carry, uint32_t *wsum) {
     uint32_t v[4];
-    span_load(a, m, base, v);
+    span_load(in, m, base, v);
     const uint32_t tsum = (v[0] + v[1]) + (v[2] + v[3]);
     uint32_t total;
     uint32_t run = carry + block_excl_scan(tsum, wsum, total);
     const int64_t i0 = base + 4 * (int64_t)threadIdx.x;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (i0 + q < m) a[i0 + q] = run;
+        if (i0 + q < m) out[i0 + q] = run;
         run += v[q];
     }
     return total;
 }
 
-// One block: all spans in order.
+// One block: all spans in order, in place.
 __global__ __launch_bounds__(kScanThreads) void k_scan_serial(uint32_t *__restrict__ a, int64_t m) {
     __shared__ uint32_t wsum[kScanThreads / kWave + 1];
     uint32_t carry = 0;
-    for (int64_t base = 0; base < m; base += kScanSpan) carry += span_scan(a, m, base, carry, wsum);
+    for (int64_t base = 0; base < m; base += kScanSpan) carry += span_scan(a, a, m, base, carry, wsum);
+}
+
+// Block b: the input of spans 0..b-1 summed, then span b scanned from there.
+__global__ __launch_bounds__(kScanThreads) void k_scan_redundant(const uint32_t *__restrict__ in,
+                                                                 uint32_t *__restrict__ out,
+                                                                 int64_t m) {
+    __shared__ uint32_t wsum[kScanThreads / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanSpan;  // a multiple of 4096
+    const uint4 *in4 = reinterpret_cast<const uint4 *>(in);    // (256-byte aligned arrays)
+    const int64_t n4 = base / 4;
+    uint32_t p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+    int64_t i = threadIdx.x;
+    for (; i + 3 * kScanThreads < n4; i += 4 * kScanThreads) {  // four loads in flight
+        const uint4 a = in4[i], b = in4[i + kScanThreads];
+        const uint4 c = in4[i + 2 * kScanThreads], d = in4[i + 3 * kScanThreads];
+        p0 += (a.x + a.y) + (a.z + a.w);
+        p1 += (b.x + b.y) + (b.z + b.w);
+        p2 += (c.x + c.y) + (c.z + c.w);
+        p3 += (d.x + d.y) + (d.z + d.w);
+    }
+    for (; i < n4; i += kScanThreads) {
+        const uint4 a = in4[i];
+        p0 += (a.x + a.y) + (a.z + a.w);
+    }
+    const uint32_t part = (p0 + p1) + (p2 + p3);
+    uint32_t offset;
+    block_excl_scan(part, wsum, offset);
+    span_scan(in, out, m, base, offset, wsum);
 }
 
 // Block b: the total of span b.
@@ -171,22 +200,24 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_totals(const uint32_t *__
 }
 
 // Block b: span b scanned from its offset (the scanned totals).
-__global__ __launch_bounds__(kScanThreads) void k_scan_spans(uint32_t *__restrict__ a, int64_t m,
+__global__ __launch_bounds__(kScanThreads) void k_scan_spans(const uint32_t *__restrict__ in,
+                                                             uint32_t *__restrict__ out, int64_t m,
                                                              const uint32_t *__restrict__ off) {
     __shared__ uint32_t wsum[kScanThreads / kWave + 1];
-    span_scan(a, m, (int64_t)blockIdx.x * kScanSpan, off[blockIdx.x], wsum);
+    span_scan(in, out, m, (int64_t)blockIdx.x * kScanSpan, off[blockIdx.x], wsum);
 }
 
-int launch_scan(uint32_t *a, int64_t m, uint32_t *tot, hipStream_t st) {
+int launch_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tot, hipStream_t st) {
     const int64_t spans = (m + kScanSpan - 1) / kScanSpan;
-    if (spans <= kScanSerialSpans) {
-        hipLaunchKernelGGL(k_scan_serial, dim3(1), dim3(kScanThreads), 0, st, a, m);
+    if (spans <= kScanRedundantSpans) {
+        hipLaunchKernelGGL(k_scan_redundant, dim3((unsigned)spans), dim3(kScanThreads), 0, st, in,
+                           out, m);
     } else {
-        hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)spans), dim3(kScanThreads), 0, st, a, m,
+        hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)spans), dim3(kScanThreads), 0, st, in, m,
                            tot);
         hipLaunchKernelGGL(k_scan_serial, dim3(1), dim3(kScanThreads), 0, st, tot, spans);
-        hipLaunchKernelGGL(k_scan_spans, dim3((unsigned)spans), dim3(kScanThreads), 0, st, a, m,
-                           tot);
+        hipLaunchKernelGGL(k_scan_spans, dim3((unsigned)spans), dim3(kScanThreads), 0, st, in, out,
+                           m, tot);
     }
     return launch_check("scan");
 }
@@ -257,13 +288,14 @@ int launch_sort(const Ws &w, hipStream_t st, uint32_t **sorted_keys, uint32_t **
         else
             hipLaunchKernelGGL(k_sort_hist<kSortItemsLarge>, dim3(ntiles), dim3(kSortThreads), 0,
                                st, kin, n, shift, w.hist(), ntiles);
-        if (int rc = launch_scan(w.hist(), (int64_t)kRadix * ntiles, w.scan_tot(), st)) return rc;
+        if (int rc = launch_scan(w.hist(), w.hist_off(), (int64_t)kRadix * ntiles, w.scan_tot(), st))
+            return rc;
         if (small)
             hipLaunchKernelGGL(k_sort_scatter<kSortItemsSmall>, dim3(ntiles), dim3(kSortThreads),
-                               0, st, kin, vin, kout, vout, n, shift, w.hist(), ntiles);
+                               0, st, kin, vin, kout, vout, n, shift, w.hist_off(), ntiles);
         else
             hipLaunchKernelGGL(k_sort_scatter<kSortItemsLarge>, dim3(ntiles), dim3(kSortThreads),
-                               0, st, kin, vin, kout, vout, n, shift, w.hist(), ntiles);
+                               0, st, kin, vin, kout, vout, n, shift, w.hist_off(), ntiles);
         if (int rc = launch_check("radix sort")) return rc;
         uint32_t *t = kin;
         kin = kout;
@@ -509,9 +541,9 @@ int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStre
     const Insts I = insts_of(P, w);
     const uint32_t csz = (uint32_t)chunk_for(P);
     hipLaunchKernelGGL(k_row_counts, dim3(blocks), dim3(256), 0, st, w.cell_start(), I, nrows,
-                       csz, w.row_first(), w.scalars(), w.inst_state(), (int)lagged, dt);
+                       csz, w.row_cnt(), w.scalars(), w.inst_state(), (int)lagged, dt);
     if (int rc = launch_check("chunk counts")) return rc;
-    if (int rc = launch_scan(w.row_first(), nrows, w.scan_tot(), st)) return rc;
+    if (int rc = launch_scan(w.row_cnt(), w.row_first(), nrows, w.scan_tot(), st)) return rc;
     hipLaunchKernelGGL(k_row_chunks, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st,
                        w.cell_start(), I, nrows, csz, w.row_first(), w.chunks(), w.scalars());
     return launch_check("chunk list");

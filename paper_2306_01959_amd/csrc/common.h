@@ -25,7 +25,7 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kScanThreads = 1024;   // scan workgroup
 constexpr int kScanSpan = 4 * kScanThreads;  // values per scanned span
-constexpr int kScanSerialSpans = 12; // up to this many spans: one block scans them in turn
+constexpr int kScanRedundantSpans = 16;  // up to this many spans: one launch
 constexpr int kChunk = 64;           // targets per chunk of the row-split interaction
 constexpr int kMinChunk = 8;         // smallest chunk (group-per-wave interaction)
 constexpr int kDiagThreads = 256;
@@ -141,9 +141,11 @@ struct WsLayout {
     int32_t precision = 0;
     size_t keys = 0, keys_alt = 0, vals = 0, vals_alt = 0;
     size_t sorted_keys = 0;  // keys or keys_alt, whichever holds the sort output
-    size_t hist = 0;
+    size_t hist = 0;         // (digit, tile) counts of a sort pass
+    size_t hist_off = 0;     // their exclusive scan: first output slot per (digit, tile)
     size_t scan_tot = 0;     // span totals of a scan (counts of the sort, chunks per row)
-    size_t row_first = 0;    // chunks per row, then the first chunk of each row
+    size_t row_cnt = 0;      // chunks per row
+    size_t row_first = 0;    // first chunk of each row
     size_t cell_start = 0;
     size_t chunks = 0;
     size_t chunk_out = 0;    // ChunkOut per chunk
@@ -173,6 +175,8 @@ struct Ws {
     uint32_t *hist() const { return at<uint32_t>(L.hist); }
     uint32_t *scan_tot() const { return at<uint32_t>(L.scan_tot); }
     uint32_t *row_first() const { return at<uint32_t>(L.row_first); }
+    uint32_t *row_cnt() const { return at<uint32_t>(L.row_cnt); }
+    uint32_t *hist_off() const { return at<uint32_t>(L.hist_off); }
     uint32_t *cell_start() const { return at<uint32_t>(L.cell_start); }
     int4 *chunks() const { return at<int4>(L.chunks); }
     ChunkOut *chunk_out() const { return at<ChunkOut>(L.chunk_out); }
@@ -193,8 +197,9 @@ int launch_check(const char *what);
 // Launchers implemented in the kernel translation units.
 int launch_encode(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st);
 int launch_sort(const Ws &w, hipStream_t st, uint32_t **sorted_keys, uint32_t **perm);
-// in-place exclusive scan of m values; tot: ceil(m / kScanSpan) values of scratch
-int launch_scan(uint32_t *a, int64_t m, uint32_t *tot, hipStream_t st);
+// exclusive scan of m values from `in` (left intact) to `out`; tot:
+// ceil(m / kScanSpan) values of scratch
+int launch_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tot, hipStream_t st);
 int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *keys,
                    const uint32_t *perm, hipStream_t st);
 int launch_cell_table(const Ws &w, const uint32_t *keys, hipStream_t st);
