@@ -252,13 +252,17 @@ struct Mixed {
                 ++st.b;
             st.h += id_hash(a.id[j] & 0x7fffffffu);
         }
+        // evaluated on every lane (no branch); lanes outside the support
+        // are zeroed through F and the |mu| select
         const float r = __builtin_amdgcn_sqrtf(rr);
         const float q2 = fmaf(r, -0.5f * (float)ip.invh, 1.f);  // 1 - q/2
-        const float F = in ? (float)ip.Fm * q2 * q2 * q2 : 0.f;   // m 5 w_D/h^2 (1-q/2)^3
+        const float Fr = (float)ip.Fm * q2 * q2 * q2;              // m 5 w_D/h^2 (1-q/2)^3
+        const float F = in ? Fr : 0.f;
         const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const float vr = vx * dx + vy * dy + vz * dz;               // u_ij . r_ij
         const float mu = (float)ip.h * vr * __builtin_amdgcn_rcpf(rr + (float)ip.eta2);
-        acc.mu = in ? fmaxf(acc.mu, fabsf(mu)) : acc.mu;
+        const float amu = in ? fabsf(mu) : 0.f;
+        acc.mu = amu > acc.mu ? amu : acc.mu;
         acc.dr -= F * vr;                                    // m (u_i - u_j) . grad_i W_ij
         const float Fd = fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;             // delta term
@@ -452,12 +456,16 @@ struct Fp64 {
                 ++st.b;
             st.h += id_hash(a.id[j] & 0x7fffffffu);
         }
+        // evaluated on every lane (no branch); lanes outside the support
+        // are zeroed through F and the |mu| select
         const double q2 = 1.0 - 0.5 * (sqrt(rr) * ip.invh);
-        const double F = in ? ip.Fm * q2 * q2 * q2 : 0.0;
+        const double Fr = ip.Fm * q2 * q2 * q2;
+        const double F = in ? Fr : 0.0;
         const double vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const double vr = vx * dx + vy * dy + vz * dz;
         const double mu = ip.h * vr / (rr + ip.eta2);
-        acc.mu = in ? fmax(acc.mu, fabs(mu)) : acc.mu;
+        const double amu = in ? fabs(mu) : 0.0;
+        acc.mu = amu > acc.mu ? amu : acc.mu;
         acc.dr -= F * vr;
         const double Fd = fi ? F : 0.0;
         acc.dr += (r2.z - t.c.y) * r2.y * Fd;
