@@ -38,10 +38,10 @@ WsLayout make_layout(const Problem &P) {
     L.ncells = P.ncells;
     L.nrows = P.nrows;
     L.ntiles = (n + sort_tile(n) - 1) / sort_tile(n);
-    // chunks hold >= kMinChunk targets except the last of each row
-    L.max_chunks = (n + kMinChunk - 1) / kMinChunk + L.nrows;
+    // at most ceil(particles / csz) + 1 chunks per half-row, csz >= kMinChunk
+    L.max_chunks = (n + kMinChunk - 1) / kMinChunk + 4 * L.nrows;
     int bits = 0;
-    while (bits < 32 && ((int64_t)1 << bits) < L.ncells) ++bits;
+    while (bits < 32 && ((int64_t)1 << bits) < 2 * L.ncells) ++bits;
     L.key_bits = bits;
     const int passes = bits <= 0 ? 1 : (bits + kRadixBits - 1) / kRadixBits;
     const bool mixed = P.precision == SPH_MIXED;
@@ -60,11 +60,11 @@ WsLayout make_layout(const Problem &P) {
     L.sorted_keys = (passes & 1) ? L.keys_alt : L.keys;
     L.hist = take(4 * (size_t)kRadix * (size_t)L.ntiles);
     L.hist_off = take(4 * (size_t)kRadix * (size_t)L.ntiles);
-    const size_t scanned = std::max((size_t)kRadix * (size_t)L.ntiles, (size_t)L.nrows);
+    const size_t scanned = std::max((size_t)kRadix * (size_t)L.ntiles, (size_t)(2 * L.nrows));
     L.scan_tot = take(4 * ((scanned + kScanSpan - 1) / kScanSpan));
-    L.row_cnt = take(4 * (size_t)L.nrows);
-    L.row_first = take(4 * (size_t)L.nrows);
-    L.cell_start = take(4 * (size_t)(L.ncells + 1));
+    L.row_cnt = take(4 * (size_t)(2 * L.nrows));  // per half-row
+    L.row_first = take(4 * (size_t)(2 * L.nrows));
+    L.cell_start = take(4 * (size_t)(2 * L.ncells + 1));
     L.chunks = take(sizeof(int4) * (size_t)L.max_chunks);
     L.chunk_out = take(sizeof(ChunkOut) * (size_t)L.max_chunks);
     L.view0 = take(L.view_elem * (size_t)n);
@@ -164,7 +164,7 @@ static int check_params(const sph_params *p) {
     for (int k = 0; k < 3; ++k)
         if (p->dims[k] < 1) return fail(SPH_E_INVAL, "dims must be >= 1");
     const int64_t nc = (int64_t)p->dims[0] * p->dims[1] * p->dims[2];
-    if (nc >= ((int64_t)1 << 31) - 1) return fail(SPH_E_RANGE, "too many cells (>= 2^31)");
+    if (nc >= ((int64_t)1 << 30)) return fail(SPH_E_RANGE, "too many cells (>= 2^30)");
     if (p->precision != SPH_FP64 && p->precision != SPH_MIXED)
         return fail(SPH_E_INVAL, "unknown precision");
     if (p->c_mode != SPH_C_TAIT && p->c_mode != SPH_C_CONST)
@@ -247,8 +247,8 @@ static int batch_problem(const sph_batch *b, Problem *P) {
         const int64_t nc = (int64_t)p.dims[0] * p.dims[1] * p.dims[2];
         const int64_t nr = (int64_t)p.dims[1] * p.dims[2];
         if (n + c >= ((int64_t)1 << 31)) return fail(SPH_E_RANGE, "total particles must be < 2^31");
-        if (cells + nc >= ((int64_t)1 << 31) - 1)
-            return fail(SPH_E_RANGE, "total cells must be < 2^31 - 1");
+        if (cells + nc >= ((int64_t)1 << 30))
+            return fail(SPH_E_RANGE, "total cells must be < 2^30");
         P->host.push_back(inst_from(p, (uint32_t)cells, (uint32_t)rows, (uint32_t)n,
                                     (uint32_t)(n + c)));
         n += c;

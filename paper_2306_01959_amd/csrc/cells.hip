@@ -26,7 +26,9 @@ __device__ __forceinline__ int axis_cell(double v, double o, double cs, int n) {
     return (int)f;
 }
 
-// key = the instance's first global cell + the particle's cell in its grid
+// key of the particle's cell in its half-row (fluid or boundary) of the
+// instance's grid: sorted, each cell row holds its fluid particles, x-cell by
+// x-cell, then its boundary particles
 __global__ void k_encode(const double *__restrict__ x, const double *__restrict__ y,
                          const double *__restrict__ z, const uint32_t *__restrict__ id,
                          int64_t n, Insts I, uint32_t *__restrict__ keys) {
@@ -36,7 +38,8 @@ __global__ void k_encode(const double *__restrict__ x, const double *__restrict_
     const int cx = axis_cell(x[i], ip.ox, ip.cs, ip.nx);
     const int cy = axis_cell(y[i], ip.oy, ip.cs, ip.ny);
     const int cz = axis_cell(z[i], ip.oz, ip.cs, ip.nz);
-    keys[i] = ip.cell_base + (uint32_t)lin_cell(cx, cy, cz, ip.nx, ip.ny);
+    const uint32_t lrow = (uint32_t)cz * (uint32_t)ip.ny + (uint32_t)cy;
+    keys[i] = half_row_key(ip.cell_base, ip.nx, lrow, id[i] >> 31) + (uint32_t)cx;
 }
 
 int launch_encode(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st) {
@@ -359,15 +362,16 @@ __global__ void k_reorder(ReorderArgs a) {
     a.id2[k] = id;
     const bool bnd = (id >> 31) != 0;
     const uint32_t key = a.keys[k];
-    const Inst ip = a.I.get(a.I.of_cell(key));
+    const Inst ip = a.I.get(a.I.of_cell(key_row_cell(key)));
     if constexpr (kMixed) {
         const float dr = static_cast<const float *>(a.rho)[src];
         static_cast<float *>(a.rho2)[k] = dr;
         static_cast<float *>(a.rhom2)[k] = static_cast<const float *>(a.rhom)[src];
-        const uint32_t c = key - ip.cell_base;
-        const int cx = (int)(c % (uint32_t)ip.nx);
-        const int cy = (int)((c / (uint32_t)ip.nx) % (uint32_t)ip.ny);
-        const int cz = (int)(c / ((uint32_t)ip.nx * (uint32_t)ip.ny));
+        const uint32_t off = key - 2u * ip.cell_base;  // (2 lrow + half) nx + cx
+        const uint32_t lrow = off / (2u * (uint32_t)ip.nx);
+        const int cx = (int)(off % (uint32_t)ip.nx);
+        const int cy = (int)(lrow % (uint32_t)ip.ny);
+        const int cz = (int)(lrow / (uint32_t)ip.ny);
         const double xr = (double)dr / ip.rho0;
         const double l1p = log1p(xr);
         const double P = ip.B * expm1(ip.gamma * l1p);
@@ -431,8 +435,10 @@ int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *
 
 // ------------------------------------------------------------ cell table
 
-// cell_start[c] = first sorted position whose key >= c, for c in [0, ncells]
-// (lower bound by binary search; empty cells get the start of the next one).
+// start[k] = first sorted position whose key >= k, for k in [0, 2 ncells]
+// (lower bound by binary search; an empty cell gets the start of the next
+// one).  Cells x0..x1 of a half-row with key k0 at x = 0 hold the sorted
+// range [start[k0 + x0], start[k0 + x1 + 1]).
 __global__ void k_cell_table(const uint32_t *__restrict__ keys, int64_t n, int64_t ncells,
                              uint32_t *__restrict__ start) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -449,21 +455,22 @@ __global__ void k_cell_table(const uint32_t *__restrict__ keys, int64_t n, int64
 }
 
 int launch_cell_table(const Ws &w, const uint32_t *keys, hipStream_t st) {
-    int64_t m = w.L.ncells + 1;
+    int64_t m = 2 * w.L.ncells + 1;
     int blocks = (int)((m + 255) / 256);
-    hipLaunchKernelGGL(k_cell_table, dim3(blocks), dim3(256), 0, st, keys, w.L.n, w.L.ncells,
-                       w.cell_start());
+    hipLaunchKernelGGL(k_cell_table, dim3(blocks), dim3(256), 0, st, keys, w.L.n,
+                       2 * w.L.ncells, w.cell_start());
     return launch_check("cell table");
 }
 
 // ------------------------------------------------------------ chunk list
 //
 // The interaction works on chunks: up to csz (64, or the group size of the
-// group-per-wave kernel) consecutive sorted particles of one cell row (fixed
-// cy, cz) of one instance.  Per row: the number of its
-// chunks (k_row_counts), an exclusive scan of those numbers (the first chunk
-// of every row), then the chunks {start, end, local row, instance} and the
-// chunk count (k_row_chunks).
+// group-per-wave kernels) consecutive sorted particles of one half-row (the
+// fluid or the boundary particles of a cell row, fixed cy and cz) of one
+// instance, so a chunk is all fluid or all boundary.  Per half-row: the
+// number of its chunks (k_row_counts), an exclusive scan of those numbers
+// (the first chunk of every half-row), then the chunks {start, end, local
+// half-row 2 lrow + half, instance} and the chunk count (k_row_chunks).
 //
 // k_row_counts also prepares the per-instance time-step bound for the
 // interaction that follows: the bound of the last interaction (if there was
@@ -472,20 +479,73 @@ int launch_cell_table(const Ws &w, const uint32_t *keys, hipStream_t st) {
 // the caller's dt, else Cr times the lagged bound (eq. sphdt one step late);
 // with no bound yet, dt = 0 and the CFL flag is raised.
 
-// sorted range [b, e) of global row r, and its instance / local row
-__device__ __forceinline__ void row_range(const uint32_t *start, const Insts &I, int64_t r,
-                                          uint32_t &b, uint32_t &e, int &inst, int &lrow) {
-    inst = I.of_row((uint32_t)r);
+// Global half-row r (row r / 2, half r % 2): its instance, local half-row
+// and the key of its cell x = 0.
+__device__ __forceinline__ void half_row(const Insts &I, int64_t r, int &inst, int &lhalf,
+                                         uint32_t &k0, int &nx) {
+    inst = I.of_row((uint32_t)(r >> 1));
     const Inst ip = I.get(inst);
-    lrow = (int)(r - ip.row_base);
-    const uint32_t c0 = ip.cell_base + (uint32_t)lrow * (uint32_t)ip.nx;
-    b = start[c0];
-    e = start[c0 + ip.nx];
+    lhalf = (int)(r - 2 * (int64_t)ip.row_base);
+    k0 = half_row_key(ip.cell_base, ip.nx, (uint32_t)lhalf >> 1, (uint32_t)lhalf & 1u);
+    nx = ip.nx;
 }
 
-__global__ void k_row_counts(const uint32_t *__restrict__ start, Insts I, int64_t nrows,
-                             uint32_t csz, uint32_t *__restrict__ cnt, DevScalars *sc,
-                             InstState *ist, int lagged, double dt_arg) {
+// The chunks of a half-row (cells k0 .. k0 + nx - 1): its runs of
+// consecutive non-empty cells, each cut into pieces of csz particles, so that
+// no chunk spans empty cells (a chunk with a gap inside streams every
+// candidate across the gap).  A run ends at an empty cell only while the
+// half-row keeps within ceil(particles / csz) + 1 chunks; past that budget a
+// chunk spans the gap, and the total stays below a fixed bound.  The rule is
+// sequential in x (the budget left depends on the runs before), so the 64
+// lanes of a wave load 64 cells at a time and one scalar loop visits the
+// gaps in order (a run can only end at an empty cell after a non-empty one;
+// later cells of the same gap would give the same answer).  Calls
+// emit(k, r0, r1) (all lanes, uniform arguments) for every run [r0, r1)
+// whose first chunk is chunk k; returns the chunk count.
+__device__ __forceinline__ uint32_t pieces(uint32_t len, uint32_t csz) {
+    return (len + csz - 1) / csz;
+}
+
+template <class F>
+__device__ __forceinline__ uint32_t half_row_chunks(const uint32_t *__restrict__ start,
+                                                    uint32_t k0, int nx, uint32_t csz, F emit) {
+    const int lane = threadIdx.x % kWave;
+    const uint32_t b = start[k0], e = start[k0 + nx];
+    const uint32_t budget = pieces(e - b, csz) + 1;
+    uint32_t used = 0, run0 = b;
+    for (int x0 = 0; x0 < nx; x0 += kWave) {
+        const int x = x0 + lane;
+        bool ev = false;
+        uint32_t p0 = 0;
+        if (x >= 1 && x < nx) {
+            const uint32_t pm = start[k0 + x - 1];
+            p0 = start[k0 + x];
+            const uint32_t p1 = start[k0 + x + 1];
+            ev = p1 == p0 && p0 > pm;  // cell x empty, cell x - 1 not
+        }
+        uint64_t m = __ballot(ev);
+        while (m) {
+            const int l = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const uint32_t prev = (uint32_t)__shfl((int)p0, l, kWave);
+            const uint32_t k = pieces(prev - run0, csz);
+            if (prev > run0 && used + k + pieces(e - prev, csz) <= budget) {
+                emit(used, run0, prev);
+                used += k;
+                run0 = prev;
+            }
+        }
+    }
+    emit(used, run0, e);
+    return used + pieces(e - run0, csz);
+}
+
+// One wave per half-row (wave index = half-row); the first threads also
+// advance the instances' clocks.
+__global__ __launch_bounds__(256) void k_row_counts(const uint32_t *__restrict__ start, Insts I,
+                                                    int64_t nhalf, uint32_t csz,
+                                                    uint32_t *__restrict__ cnt, DevScalars *sc,
+                                                    InstState *ist, int lagged, double dt_arg) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g == 0 && lagged) sc->steps += 1;
     constexpr unsigned long long kInf = 0x7ff0000000000000ull;
@@ -509,43 +569,50 @@ __global__ void k_row_counts(const uint32_t *__restrict__ start, Insts I, int64_
             ist[k].time += dt;
         }
     }
-    if (g >= nrows) return;
-    uint32_t b, e;
-    int inst, lrow;
-    row_range(start, I, g, b, e, inst, lrow);
-    cnt[g] = (e - b + csz - 1) / csz;
+    const int64_t r = g / kWave;
+    if (r >= nhalf) return;  // whole waves
+    int inst, lhalf, nx;
+    uint32_t k0;
+    half_row(I, r, inst, lhalf, k0, nx);
+    const uint32_t nch = half_row_chunks(start, k0, nx, csz, [](uint32_t, uint32_t, uint32_t) {});
+    if (g % kWave == 0) cnt[r] = nch;
 }
 
-__global__ void k_row_chunks(const uint32_t *__restrict__ start, Insts I, int64_t nrows,
-                             uint32_t csz, const uint32_t *__restrict__ first,
-                             int4 *__restrict__ chunks, DevScalars *sc) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrows) return;
-    uint32_t b, e;
-    int inst, lrow;
-    row_range(start, I, r, b, e, inst, lrow);
-    const uint32_t nch = (e - b + csz - 1) / csz;
+__global__ __launch_bounds__(256) void k_row_chunks(const uint32_t *__restrict__ start, Insts I,
+                                                    int64_t nhalf, uint32_t csz,
+                                                    const uint32_t *__restrict__ first,
+                                                    int4 *__restrict__ chunks, DevScalars *sc) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = g / kWave;
+    if (r >= nhalf) return;  // whole waves
+    const int lane = (int)(g % kWave);
+    int inst, lhalf, nx;
+    uint32_t k0;
+    half_row(I, r, inst, lhalf, k0, nx);
     const uint32_t f = first[r];
-    for (uint32_t k = 0; k < nch; ++k) {
-        const uint32_t s0 = b + k * csz;
-        const uint32_t s1 = s0 + csz < e ? s0 + csz : e;
-        chunks[f + k] = make_int4((int)s0, (int)s1, lrow, inst);
-    }
-    if (r == nrows - 1) sc->nchunks = f + nch;
+    const uint32_t nch =
+        half_row_chunks(start, k0, nx, csz, [&](uint32_t k, uint32_t r0, uint32_t r1) {
+            const uint32_t np = pieces(r1 - r0, csz);
+            for (uint32_t q = (uint32_t)lane; q < np; q += kWave) {
+                const uint32_t s0 = r0 + q * csz;
+                chunks[f + k + q] = make_int4((int)s0, (int)(s0 + csz < r1 ? s0 + csz : r1), lhalf, inst);
+            }
+        });
+    if (r == nhalf - 1 && lane == 0) sc->nchunks = f + nch;
 }
 
 int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStream_t st) {
-    const int64_t nrows = w.L.nrows;
-    const int64_t m = nrows > (int64_t)P.host.size() ? nrows : (int64_t)P.host.size();
-    const int blocks = (int)((m + 255) / 256);
+    const int64_t nhalf = 2 * w.L.nrows;
+    const int64_t threads = std::max<int64_t>(nhalf * kWave, (int64_t)P.host.size());
+    const int blocks = (int)((threads + 255) / 256);
     const Insts I = insts_of(P, w);
     const uint32_t csz = (uint32_t)chunk_for(P);
-    hipLaunchKernelGGL(k_row_counts, dim3(blocks), dim3(256), 0, st, w.cell_start(), I, nrows,
+    hipLaunchKernelGGL(k_row_counts, dim3(blocks), dim3(256), 0, st, w.cell_start(), I, nhalf,
                        csz, w.row_cnt(), w.scalars(), w.inst_state(), (int)lagged, dt);
     if (int rc = launch_check("chunk counts")) return rc;
-    if (int rc = launch_scan(w.row_cnt(), w.row_first(), nrows, w.scan_tot(), st)) return rc;
-    hipLaunchKernelGGL(k_row_chunks, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, st,
-                       w.cell_start(), I, nrows, csz, w.row_first(), w.chunks(), w.scalars());
+    if (int rc = launch_scan(w.row_cnt(), w.row_first(), nhalf, w.scan_tot(), st)) return rc;
+    hipLaunchKernelGGL(k_row_chunks, dim3((unsigned)((nhalf * kWave + 255) / 256)), dim3(256), 0,
+                       st, w.cell_start(), I, nhalf, csz, w.row_first(), w.chunks(), w.scalars());
     return launch_check("chunk list");
 }
 

@@ -82,6 +82,19 @@ struct DevScalars {
     unsigned long long pairs[3];     // interacting pairs since init: FF, FB, BF
 };
 
+// Sort keys.  Every cell row (fixed cy, cz) of an instance is split into a
+// fluid half-row and a boundary half-row, cells x-fastest within each, so a
+// run of cells of one row holds its fluid particles contiguously and its
+// boundary particles contiguously.  The key of cell x of half-row `half`
+// (0 fluid, 1 boundary) of local row `lrow` is half_row_key(...) + x; an
+// instance's keys fill [2 cell_base, 2 (cell_base + its cells)).
+__host__ __device__ __forceinline__ uint32_t half_row_key(uint32_t cell_base, uint32_t nx,
+                                                          uint32_t lrow, uint32_t half) {
+    return 2u * cell_base + (2u * lrow + half) * nx;
+}
+// a global cell of the key's row (enough to find the key's instance)
+__host__ __device__ __forceinline__ uint32_t key_row_cell(uint32_t key) { return key >> 1; }
+
 // Device-side access to the instances: a table in the workspace (batches) or
 // a single instance passed by value.
 struct Insts {

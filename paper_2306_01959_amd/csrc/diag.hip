@@ -51,16 +51,16 @@ __device__ __forceinline__ double density_at(const DiagArgs &a, const Inst &ip, 
                    : static_cast<const double *>(a.rho)[i];
 }
 
-// Instance blockIdx.y, its particles [cell_start[first cell],
-// cell_start[first cell + cells]) of the current (cell) order, split over
+// Instance blockIdx.y, its particles [start of its first cell,
+// end of its last cell) of the current (cell) order, split over
 // bpi blocks with a fixed stride: fixed summation order.
 __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(DiagArgs a) {
     __shared__ double red[kDiagThreads];
     const int k = blockIdx.y;
     const Inst ip = a.I.get(k);
     const int64_t ncell = (int64_t)ip.nx * ip.ny * ip.nz;
-    const int64_t lo = a.cell_start[ip.cell_base];
-    const int64_t hi = a.cell_start[ip.cell_base + ncell];
+    const int64_t lo = a.cell_start[2 * ip.cell_base];
+    const int64_t hi = a.cell_start[2 * (ip.cell_base + ncell)];
     const double B = ip.B, rho0 = ip.rho0, gamma = ip.gamma, mass = ip.mass;
     double acc[F_COUNT];
     for (int f = 0; f < F_COUNT; ++f) acc[f] = 0.0;
@@ -100,9 +100,10 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(DiagArgs a) {
             for (int dy = -1; dy <= 1 && !found; ++dy) {
                 const int czn = cz + dz, cyn = cy + dy;
                 if (czn < 0 || czn >= ip.nz || cyn < 0 || cyn >= ip.ny) continue;
-                const int64_t rb = ip.cell_base + lin_cell(0, cyn, czn, ip.nx, ip.ny);
+                // the fluid half of the stencil row
+                const uint32_t hb = half_row_key(ip.cell_base, ip.nx, czn * ip.ny + cyn, 0);
                 const int xl = cx > 0 ? cx - 1 : 0, xh = cx + 1 < ip.nx ? cx + 1 : ip.nx - 1;
-                const uint32_t js = a.cell_start[rb + xl], je = a.cell_start[rb + xh + 1];
+                const uint32_t js = a.cell_start[hb + xl], je = a.cell_start[hb + xh + 1];
                 for (uint32_t j = js; j < je; ++j) {
                     if ((int64_t)j == i || (a.id[j] >> 31) != 0) continue;
                     const double dx = a.x[j] - x, dy_ = a.y[j] - y, dz_ = a.z[j] - z;
@@ -183,9 +184,10 @@ __global__ __launch_bounds__(kDiagThreads) void k_probes(DiagArgs a, const doubl
         for (int dy = -1; dy <= 1; ++dy) {
             const int czn = cz + dz, cyn = cy + dy;
             if (czn < 0 || czn >= ip.nz || cyn < 0 || cyn >= ip.ny) continue;
-            const int64_t rb = ip.cell_base + lin_cell(0, cyn, czn, ip.nx, ip.ny);
+            // the fluid half of the stencil row
+            const uint32_t hb = half_row_key(ip.cell_base, ip.nx, czn * ip.ny + cyn, 0);
             const int xl = cx > 0 ? cx - 1 : 0, xh = cx + 1 < ip.nx ? cx + 1 : ip.nx - 1;
-            const uint32_t js = a.cell_start[rb + xl], je = a.cell_start[rb + xh + 1];
+            const uint32_t js = a.cell_start[hb + xl], je = a.cell_start[hb + xh + 1];
             for (uint32_t j = js + threadIdx.x; j < je; j += kDiagThreads) {
                 if ((a.id[j] >> 31) != 0) continue;
                 const double dx = a.x[j] - px, dy_ = a.y[j] - py, dz_ = a.z[j] - pz;

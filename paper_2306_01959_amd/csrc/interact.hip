@@ -1,12 +1,16 @@
 // Pairwise WCSPH interaction (Section 2.2, eqs. sphu, pi, cpmu, sphw,
 // sphrho, tait) and the per-particle time-step bound (eq. sphdt).
 //
-// Work decomposition.  A chunk is up to 64 consecutive sorted particles of
-// one cell row (fixed cy, cz; cells are numbered x-fastest).  Its candidates
-// are the nine stencil rows (cy+dy, cz+dz) over cells [cx_first - 1,
-// cx_last + 1], each a contiguous range of the sorted arrays.  A workgroup of
-// kSplit waves (1, 3 or 9) owns a chunk; each wave takes 9 / kSplit of the
-// rows, and the waves' partial sums are added in a fixed order at the end.
+// Work decomposition.  Particles are sorted by cell row (fixed cy, cz), then
+// fluid before boundary, then cell x.  A chunk is up to 64 consecutive sorted
+// particles of one half-row (the fluid or the boundary particles of a row),
+// so it is all fluid or all boundary.  Its candidates are the nine stencil
+// rows (cy+dy, cz+dz) over cells [cx_first - 1, cx_last + 1], each split
+// into its fluid and its boundary half: eighteen contiguous ranges of the
+// sorted arrays, of which a boundary chunk takes the nine fluid ones only.  A
+// workgroup of kSplit waves (1, 3 or 9) owns a chunk; each wave takes
+// 9 / kSplit of the stencil rows, and the waves' partial sums are added in a
+// fixed order at the end.
 //
 // Per wave, candidates stream through in batches of 64: the next batch is
 // loaded into registers while the current one is processed; a batch is
@@ -45,8 +49,8 @@ struct InteractArgs {
     DevScalars *sc;
     InstState *ist;
     Insts I;
-    const uint32_t *keys;        // sorted global cell id of every particle
-    const uint32_t *cell_start;  // ncells + 1
+    const uint32_t *keys;        // sorted half-row cell keys
+    const uint32_t *cell_start;  // first sorted position of every key, 2 ncells + 1
     const void *v0, *v1, *v2;    // interaction view
     void *ax, *ay, *az, *drho, *mumax;
     ChunkOut *cout;              // per chunk: time-step bound and pair counts
@@ -190,7 +194,7 @@ struct Mixed {
         c.key = a.keys[jj];
     }
     // position of a candidate in the chunk frame (cell cxa of the chunk's
-    // row), for culling only; nbase = first global cell of its row
+    // row), for culling only; nbase = key of cell x = 0 of its half-row
     __device__ static void cull_pos(const InteractArgs &a, const Inst &ip, const Cand &c, int nbase,
                                     int cxa, int dy, int dz, float &qx, float &qy, float &qz) {
         const float csf = (float)ip.cs;
@@ -541,13 +545,43 @@ struct Fp64 {
     }
 };
 
+// The candidate ranges of a chunk of cells cxa..cxb of local half-row `lh`
+// (2 row + half).  Range q in [0, 18): stencil row q / 2 (dz, dy in -1..1,
+// y fastest), half q % 2 (0 fluid, 1 boundary), cells [cxa - 1, cxb + 1]
+// clamped to the grid: one contiguous sorted range [js, je).  A boundary
+// chunk skips the boundary halves (boundary-boundary pairs do not interact),
+// so its candidates are the fluid particles near it only.  hb is the key of
+// cell x = 0 of the half-row (a candidate's cell x is its key - hb); code
+// packs (dy + 1) | (dz + 1) << 2.
+constexpr int kRanges = 18;
+
+__device__ __forceinline__ void stencil_range(const InteractArgs &a, const Inst &ip, int q, int lh,
+                                              int cxa, int cxb, int &js, int &je, int &hb,
+                                              int &code) {
+    const int rr = q >> 1, half = q & 1;
+    const int dz = rr / 3 - 1, dy = rr % 3 - 1;
+    const int row = lh >> 1;
+    const int czn = row / ip.ny + dz, cyn = row % ip.ny + dy;
+    code = (dy + 1) | ((dz + 1) << 2);
+    js = 0;
+    je = 0;
+    hb = 0;
+    if (czn >= 0 && czn < ip.nz && cyn >= 0 && cyn < ip.ny && !((lh & 1) && half)) {
+        hb = (int)half_row_key(ip.cell_base, ip.nx, (uint32_t)(czn * ip.ny + cyn), (uint32_t)half);
+        const int xlo = cxa - 1 < 0 ? 0 : cxa - 1;
+        const int xhi = cxb + 1 >= ip.nx ? ip.nx - 1 : cxb + 1;
+        js = (int)a.cell_start[hb + xlo];
+        je = (int)a.cell_start[hb + xhi + 1];
+    }
+}
+
 // ================================================================ skeleton
 
 template <class P, int kSplit, int kT, bool kStats, bool kFuse>
 __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     using R = typename P::R;
     using V4 = typename P::V4;
-    constexpr int kRows = 9 / kSplit;
+    constexpr int kRows = 2 * (9 / kSplit);  // candidate ranges per wave
     constexpr int kG = kWave / kT;  // target groups per chunk = records per step
     __shared__ V4 stg[kSplit][4][kWave];          // staged candidate records (per wave)
     __shared__ V4 tgt[3][kWave];                  // the chunk's targets
@@ -578,11 +612,10 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     const uint32_t chunk = blockIdx.x;
     if (chunk >= a.sc->nchunks) return;
     const int4 ch = a.chunks[chunk];
-    const int cs0 = uni(ch.x), cs1 = uni(ch.y), row = uni(ch.z), inst = uni(ch.w);
+    const int cs0 = uni(ch.x), cs1 = uni(ch.y), lh = uni(ch.z), inst = uni(ch.w);
     const Inst ip = a.I.get(inst);
-    const int cy = row % ip.ny, cz = row / ip.ny;
     const int ntgt = cs1 - cs0;
-    const int rowbase = (int)ip.cell_base + row * ip.nx;
+    const int rowbase = (int)half_row_key(ip.cell_base, ip.nx, lh >> 1, lh & 1);
     const int cxa = uni((int)a.keys[cs0] - rowbase);
     const int cxb = uni((int)a.keys[cs1 - 1] - rowbase);
 
@@ -623,20 +656,11 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     const R cull2 = (R)(ip.r2max * (1.0 + 1e-3));
     const uint64_t below = lanes_below();
 
-    // this wave's stencil rows: {first, end, row base cell, (dy+1) | (dz+1) << 2}
+    // this wave's candidate ranges: {first, end, half-row key base, code}
     if (lane < kRows) {
-        const int rr = w * kRows + lane;
-        const int dz = rr / 3 - 1, dy = rr % 3 - 1;
-        const int czn = cz + dz, cyn = cy + dy;
-        int js = 0, je = 0, nbase = 0;
-        if (czn >= 0 && czn < ip.nz && cyn >= 0 && cyn < ip.ny) {
-            nbase = (int)ip.cell_base + (czn * ip.ny + cyn) * ip.nx;
-            const int xlo = cxa - 1 < 0 ? 0 : cxa - 1;
-            const int xhi = cxb + 1 >= ip.nx ? ip.nx - 1 : cxb + 1;
-            js = (int)a.cell_start[nbase + xlo];
-            je = (int)a.cell_start[nbase + xhi + 1];
-        }
-        rows[w][lane] = make_int4(js, je, nbase, (dy + 1) | ((dz + 1) << 2));
+        int js, je, hb, code;
+        stencil_range(a, ip, w * kRows + lane, lh, cxa, cxb, js, je, hb, code);
+        rows[w][lane] = make_int4(js, je, hb, code);
     }
     __syncthreads();  // targets, group boxes and rows are in LDS
 
@@ -872,11 +896,10 @@ __global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(Interact
         const uint32_t item = blockIdx.x * kWavesPerGroupWG + w;
         if (item >= a.sc->nchunks) return;  // waves of a workgroup are independent
         const int4 ch = a.chunks[item];
-        const int cs0 = uni(ch.x), cs1 = uni(ch.y), row = uni(ch.z), inst = uni(ch.w);
+        const int cs0 = uni(ch.x), cs1 = uni(ch.y), lh = uni(ch.z), inst = uni(ch.w);
         const Inst ip = a.I.get(inst);
-        const int cy = row % ip.ny, cz = row / ip.ny;
         const int ntgt = cs1 - cs0;
-        const int rowbase = (int)ip.cell_base + row * ip.nx;
+        const int rowbase = (int)half_row_key(ip.cell_base, ip.nx, lh >> 1, lh & 1);
         const int cxa = uni((int)a.keys[cs0] - rowbase);
         const int cxb = uni((int)a.keys[cs1 - 1] - rowbase);
 
@@ -894,24 +917,14 @@ __global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(Interact
         const bool any_fluid = __ballot(fi_own) != 0ull;
         const R cull2 = (R)(ip.r2max * (1.0 + 1e-3));
 
-        // stencil rows: lane q < 9 holds row q's {first, end, base cell, dy/dz code}
+        // candidate ranges: lane q < kRanges holds range q's {first, end,
+        // half-row key base, dy/dz code}
         int r_js = 0, r_je = 0, r_nb = 0, r_code = 0;
-        if (lane < 9) {
-            const int dz = lane / 3 - 1, dy = lane % 3 - 1;
-            const int czn = cz + dz, cyn = cy + dy;
-            r_code = (dy + 1) | ((dz + 1) << 2);
-            if (czn >= 0 && czn < ip.nz && cyn >= 0 && cyn < ip.ny) {
-                r_nb = (int)ip.cell_base + (czn * ip.ny + cyn) * ip.nx;
-                const int xlo = cxa - 1 < 0 ? 0 : cxa - 1;
-                const int xhi = cxb + 1 >= ip.nx ? ip.nx - 1 : cxb + 1;
-                r_js = (int)a.cell_start[r_nb + xlo];
-                r_je = (int)a.cell_start[r_nb + xhi + 1];
-            }
-        }
+        if (lane < kRanges) stencil_range(a, ip, lane, lh, cxa, cxb, r_js, r_je, r_nb, r_code);
         auto row_js = [&](int q) { return __builtin_amdgcn_readlane(r_js, q); };
         auto row_je = [&](int q) { return __builtin_amdgcn_readlane(r_je, q); };
         auto next_row = [&](int q) {
-            while (q < 9 && row_js(q) >= row_je(q)) ++q;
+            while (q < kRanges && row_js(q) >= row_je(q)) ++q;
             return q;
         };
         auto next_batch = [&](int q, int jb, int &q2, int &jb2) __attribute__((always_inline)) {
@@ -919,11 +932,11 @@ __global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(Interact
             jb2 = jb + kWave;
             if (jb2 >= row_je(q)) {
                 q2 = next_row(q + 1);
-                jb2 = q2 < 9 ? row_js(q2) : 0;
+                jb2 = q2 < kRanges ? row_js(q2) : 0;
             }
         };
         auto load_batch = [&](int q, int jb, typename P::Cand &c) __attribute__((always_inline)) {
-            const bool has = q < 9;
+            const bool has = q < kRanges;
             P::load(a, ip, has ? jb + lane : 0, has ? row_je(q) : 0, c);
         };
 
@@ -964,14 +977,14 @@ __global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(Interact
         // two candidate register sets in alternation (see the chunk kernel)
         typename P::Cand ca, cb;
         int qa = next_row(0);
-        int ja = qa < 9 ? row_js(qa) : 0;
+        int ja = qa < kRanges ? row_js(qa) : 0;
         load_batch(qa, ja, ca);
-        while (qa < 9) {
+        while (qa < kRanges) {
             int qb, jbb;
             next_batch(qa, ja, qb, jbb);
             load_batch(qb, jbb, cb);
             process(ca, qa, ja);
-            if (qb >= 9) break;
+            if (qb >= kRanges) break;
             next_batch(qb, jbb, qa, ja);
             load_batch(qa, ja, ca);
             process(cb, qb, jbb);
@@ -1051,10 +1064,9 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
     const uint32_t chunk = blockIdx.x;
     if (chunk >= a.sc->nchunks) return;
     const int4 ch = a.chunks[chunk];
-    const int cs0 = uni(ch.x), cs1 = uni(ch.y), row = uni(ch.z), inst = uni(ch.w);
+    const int cs0 = uni(ch.x), cs1 = uni(ch.y), lh = uni(ch.z), inst = uni(ch.w);
     const Inst ip = a.I.get(inst);
-    const int cy = row % ip.ny, cz = row / ip.ny;
-    const int rowbase = (int)ip.cell_base + row * ip.nx;
+    const int rowbase = (int)half_row_key(ip.cell_base, ip.nx, lh >> 1, lh & 1);
     const int cxa = uni((int)a.keys[cs0] - rowbase);
     const int cxb = uni((int)a.keys[cs1 - 1] - rowbase);
     const int g0 = cs0 + w * kT;                    // this wave's first target
@@ -1104,26 +1116,16 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
     }
     const R cull2 = (R)(ip.r2max * (1.0 + 1e-3));
 
-    // stencil rows: lane q < 9 holds row q's {first, end, base cell, dy/dz code}
+    // candidate ranges: lane q < kRanges holds range q's {first, end,
+    // half-row key base, dy/dz code}
     int r_js = 0, r_je = 0, r_nb = 0, r_code = 0;
-    if (lane < 9) {
-        const int dz = lane / 3 - 1, dy = lane % 3 - 1;
-        const int czn = cz + dz, cyn = cy + dy;
-        r_code = (dy + 1) | ((dz + 1) << 2);
-        if (czn >= 0 && czn < ip.nz && cyn >= 0 && cyn < ip.ny) {
-            r_nb = (int)ip.cell_base + (czn * ip.ny + cyn) * ip.nx;
-            const int xlo = cxa - 1 < 0 ? 0 : cxa - 1;
-            const int xhi = cxb + 1 >= ip.nx ? ip.nx - 1 : cxb + 1;
-            r_js = (int)a.cell_start[r_nb + xlo];
-            r_je = (int)a.cell_start[r_nb + xhi + 1];
-        }
-    }
+    if (lane < kRanges) stencil_range(a, ip, lane, lh, cxa, cxb, r_js, r_je, r_nb, r_code);
     __syncthreads();  // anyf is final
     const bool any_fluid = anyf != 0;
     auto row_js = [&](int q) { return __builtin_amdgcn_readlane(r_js, q); };
     auto row_je = [&](int q) { return __builtin_amdgcn_readlane(r_je, q); };
     auto next_row = [&](int q) {
-        while (q < 9 && row_js(q) >= row_je(q)) ++q;
+        while (q < kRanges && row_js(q) >= row_je(q)) ++q;
         return q;
     };
     constexpr int kB = kCW * kWave;  // candidates per shared batch
@@ -1132,11 +1134,11 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
         jb2 = jb + kB;
         if (jb2 >= row_je(q)) {
             q2 = next_row(q + 1);
-            jb2 = q2 < 9 ? row_js(q2) : 0;
+            jb2 = q2 < kRanges ? row_js(q2) : 0;
         }
     };
     auto load_batch = [&](int q, int jb, typename P::Cand &c) __attribute__((always_inline)) {
-        const bool has = q < 9;
+        const bool has = q < kRanges;
         P::load(a, ip, has ? jb + w * kWave + lane : 0, has ? row_je(q) : 0, c);
     };
 
@@ -1145,10 +1147,10 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
     Counters cn;
     typename P::Cand cur;
     int q = next_row(0);
-    int jb = q < 9 ? row_js(q) : 0;
+    int jb = q < kRanges ? row_js(q) : 0;
     load_batch(q, jb, cur);
     int buf = 0;
-    while (q < 9) {
+    while (q < kRanges) {
         const int code = __builtin_amdgcn_readlane(r_code, q);
         const int nbase = __builtin_amdgcn_readlane(r_nb, q);
         const int dy = (code & 3) - 1, dz = (code >> 2) - 1;
@@ -1531,9 +1533,9 @@ int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream
                           s.uxm, s.uym, s.uzm, s.rho,  s.rhom, s.id};
     a.step = step;
     const bool stats = st_nf != nullptr;
-    // chunks of <= csz targets: at most ceil(n / csz) + one short chunk per row
+    // chunks of <= csz targets: at most ceil(particles / csz) + 1 per half-row
     const int64_t csz = chunk_for(P);
-    const uint32_t nb = (uint32_t)((P.n + csz - 1) / csz + P.nrows);
+    const uint32_t nb = (uint32_t)((P.n + csz - 1) / csz + 4 * P.nrows);
     const int split = split_for(P);
     const int group = group_for(P);
     const int kernel = kernel_for(P);

@@ -63,9 +63,10 @@ def test_build_cells_invariants(gpu, precision):
     (cx, cy, cz), _ = bruteforce.cells_and_offsets(x, y, z, prm["origin"], prm["cell_size"],
                                                    prm["dims"])
     nx, ny = prm["dims"][0], prm["dims"][1]
-    key = cx + nx * (cy + ny * cz)
+    # cell row, then fluid before boundary, then cell x
+    key = (2 * (cy + ny * cz) + s.is_boundary[ids]) * nx + cx
     assert np.all(np.diff(key) >= 0)
-    # stable: inside a cell the original order is kept
+    # stable: inside a cell's fluid or boundary particles the original order is kept
     same = np.diff(key) == 0
     assert np.all(np.diff(ids)[same] > 0)
     # positions travelled with their ids
@@ -74,7 +75,8 @@ def test_build_cells_invariants(gpu, precision):
 
 def test_build_cells_large_sort(gpu):
     """700k particles: the counts scan of the radix sort runs on many spans
-    in parallel (not one block); the order must still be the stable sort."""
+    in parallel (not one block); the order must still be the stable sort by
+    (cell row, boundary flag, cell x)."""
     sc = scene.random_cloud(700_000, 3, dp=0.002, box=0.2)
     sim = _sim(gpu, sc, "mixed")
     sim.build_cells()
@@ -84,7 +86,7 @@ def test_build_cells_large_sort(gpu):
     (cx, cy, cz), _ = bruteforce.cells_and_offsets(sc.x, sc.y, sc.z, prm["origin"],
                                                    prm["cell_size"], prm["dims"])
     nx, ny = prm["dims"][0], prm["dims"][1]
-    key = cx + nx * (cy + ny * cz)
+    key = (2 * (cy + ny * cz) + sc.is_boundary) * nx + cx
     assert np.array_equal(ids, np.argsort(key, kind="stable"))
 
 
