@@ -99,13 +99,18 @@ class Events:
         hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
 
     def mean_ms(self):
+        return self.mean_ms_upto(self.n)
+
+    def mean_ms_upto(self, m):
+        """Mean over the sampled steps below m (the steps a shorter run used)."""
         tot = 0.0
         ms = C.c_float()
-        for k in self.steps:
+        steps = [k for k in self.steps if k < m]
+        for k in steps:
             rc = self.hip.hipEventElapsedTime(C.byref(ms), self.begin[k], self.end[k])
             assert rc == 0, f"hipEventElapsedTime of step {k}: error {rc}"
             tot += ms.value
-        return tot / len(self.steps)
+        return tot / len(steps)
 
     def close(self):
         for arr in (self.begin, self.end):
@@ -116,31 +121,75 @@ class Events:
 EVENT_EVERY = 10   # interaction kernels timed with HIP events: every 10th step
 
 
-def time_gpu(scene_obj, precision, steps, warmup, hip):
+REPEATS = 5  # timed segments; the step time reported is their median
+
+
+def time_gpu(scene_obj, precision, steps, warmup, hip, repeats=REPEATS):
+    """`warmup` untimed steps, then `steps` steps in `repeats` consecutive
+    segments, each bracketed by events on the library's stream (device
+    time); the interaction kernel is timed by events inside the library every
+    EVENT_EVERY-th step."""
     import torch
     from paper_2306_01959_amd import lib
     sim = lib.Simulation(scene_obj, precision)
     sim.run(warmup, -1.0, 0)
     d0, _ = sim.diagnostics()
-    ev = Events(hip, steps, every=EVENT_EVERY)
+    repeats = max(1, min(repeats, steps))
+    lens = [steps // repeats + (1 if r < steps % repeats else 0) for r in range(repeats)]
+    ev = Events(hip, max(lens), every=EVENT_EVERY)
+    seg_ms, kern = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.run_profiled(steps, -1.0, warmup, ev.begin, ev.end)
-    torch.cuda.synchronize()
+    step = warmup
+    for seg in lens:  # exactly `steps` steps in all
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        sim.run_profiled(seg, -1.0, step, ev.begin, ev.end)
+        b.record()
+        b.synchronize()
+        seg_ms.append(a.elapsed_time(b) / seg)
+        kern.append(ev.mean_ms_upto(seg))
+        step += seg
     t1 = time.perf_counter()
     d1, _ = sim.diagnostics()
-    kern_ms = ev.mean_ms()
     ev.close()
     pairs = [(d1[k] - d0[k]) / steps for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
     flop = FLOP_FF * pairs[0] + FLOP_FB * pairs[1] + FLOP_BF * pairs[2]
     assert d1["n_nonfinite"] == 0, "non-finite state"
-    return dict(wall_s=t1 - t0, ms_per_step=(t1 - t0) / steps * 1e3, interact_ms=kern_ms,
-                pairs_per_step=pairs, flop_per_launch=flop, sim_time=d1["time"] - d0["time"],
-                umax=d1["umax"], x_front=d1["x_front"])
+    return dict(wall_s=t1 - t0, steps=steps, ms_per_step=float(np.median(seg_ms)),
+                segment_ms=seg_ms, interact_ms=float(np.median(kern)), pairs_per_step=pairs,
+                flop_per_launch=flop, sim_time=d1["time"] - d0["time"], umax=d1["umax"],
+                x_front=d1["x_front"])
+
+
+def config_table(hip, steps_scale=1.0):
+    """Both precisions on configurations 1, 2, 3 and 5 (the dam break at dp
+    0.02, 0.01, and with the obstacle at 0.005 and 0.0025 m), each in its
+    autotuned launch shape."""
+    from paper_2306_01959_amd import autotune, scene
+    rows = []
+    for cfg, steps in ((1, 400), (2, 400), (3, 200), (5, 50)):
+        sc = scene.config_scene(cfg)
+        for prec in ("mixed", "fp64"):
+            shape = autotune.tune(sc, prec)
+            r = time_gpu(sc, prec, max(REPEATS, int(steps * steps_scale)), 20, hip)
+            pps = sc.n / (r["ms_per_step"] * 1e-3)
+            rows.append({
+                "config": cfg, "precision": prec, "particles": sc.n, "fluid": sc.n_fluid,
+                "shape": list(shape), "ms_per_step": r["ms_per_step"],
+                "particle_steps_per_s": pps,
+                "fluid_particle_steps_per_s": sc.n_fluid / (r["ms_per_step"] * 1e-3),
+                "pairs_per_s": sum(r["pairs_per_step"]) / (r["ms_per_step"] * 1e-3),
+                "interact_ms": r["interact_ms"],
+                "interact_tflops": r["flop_per_launch"] / (r["interact_ms"] * 1e-3) / 1e12,
+            })
+            print(json.dumps(rows[-1]), flush=True)
+    return rows
 
 
 # algorithmic HBM bytes per particle of the cell-list kernels (mixed state)
-SORT_BYTES_FIRST = 16   # pass 0: histogram reads the key; scatter reads it, writes key + index
+SORT_BYTES_FIRST = 44   # pass 0: histogram reads x, y, z, id and writes the key; scatter
+                        # reads the key, writes key + index
 SORT_BYTES_PASS = 20    # later passes: + the index read
 REORDER_BYTES = 4 + 4 + 84 + 84 + 40  # perm + key in, state gathered (84 B) and written,
                                       # interaction view written (40 B)
@@ -260,6 +309,8 @@ def main():
                     help="timed ensemble steps (rounded up to whole 40-step graphs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--configs", action="store_true",
+                    help="only the per-configuration table (configs 1, 2, 3, 5; both precisions)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -279,6 +330,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.configs:
+        config_table(hip)
+        return
     if args.ensemble_only:
         print(json.dumps({"ensemble": time_ensemble(args.ensemble_steps, hip,
                                                     graph=not args.ensemble_eager,
@@ -294,16 +348,20 @@ def main():
         splits["fp64"] = autotune.tune(sc, "fp64", use_cache=not args.retune,
                                        verbose=args.retune)
         fp64 = time_gpu(sc, "fp64", args.steps, args.warmup, hip)
-    value = sc.n * args.steps / mixed["wall_s"]
+    value = sc.n / (mixed["ms_per_step"] * 1e-3)
     achieved = mixed["flop_per_launch"] / (mixed["interact_ms"] * 1e-3) / 1e12
     out = {
         "metric": "particle-steps/s of WCSPH step, mixed-FP32 vs FP64 on 1 GPU, + ensemble batch",
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": mixed["steps"],
         "warmup": args.warmup,
         "ms_per_step": mixed["ms_per_step"],
+        "timing": f"median over {len(mixed['segment_ms'])} consecutive segments of the "
+                  f"{mixed['steps']} timed steps (events on the library's stream)",
+        "fluid_particle_steps_per_s": sc.n_fluid / (mixed["ms_per_step"] * 1e-3),
+        "pairs_per_s": sum(mixed["pairs_per_step"]) / (mixed["ms_per_step"] * 1e-3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -335,7 +393,7 @@ def main():
         },
     }
     if fp64 is not None:
-        v64 = sc.n * args.steps / fp64["wall_s"]
+        v64 = sc.n / (fp64["ms_per_step"] * 1e-3)
         out["fp64"] = {"value": v64, "ms_per_step": fp64["ms_per_step"],
                        "interact_ms": fp64["interact_ms"]}
         out["mixed_over_fp64"] = value / v64

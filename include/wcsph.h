@@ -296,7 +296,7 @@ int sph_run(const sph_params *p, sph_state *s, void *ws, int64_t nsteps, double 
 /* Regions of a step that sph_run_profiled can bracket with events. */
 typedef enum {
     SPH_REGION_INTERACT = 0, /* the interaction kernel */
-    SPH_REGION_SORT = 1,     /* all passes of the radix sort */
+    SPH_REGION_SORT = 1,     /* the cell keys and all passes of the radix sort */
     SPH_REGION_REORDER = 2,  /* the gather into cell order (+ interaction view) */
     SPH_REGION_STEP = 3      /* the whole step */
 } sph_region;

@@ -284,10 +284,9 @@ struct Marks {
 static int build_cells(const Problem &P, sph_state &s, const Ws &w, hipStream_t st,
                        bool lagged = false, double dt = 0.0, const Marks &m = Marks()) {
     if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
-    if (int rc = launch_encode(P, s, w, st)) return rc;
     uint32_t *keys = nullptr, *perm = nullptr;
     if (int rc = m.at(SPH_REGION_SORT, true, st)) return rc;
-    if (int rc = launch_sort(w, st, &keys, &perm)) return rc;
+    if (int rc = launch_sort(P, s, w, st, &keys, &perm)) return rc;  // cell keys included
     if (int rc = m.at(SPH_REGION_SORT, false, st)) return rc;
     if (int rc = m.at(SPH_REGION_REORDER, true, st)) return rc;
     if (int rc = launch_reorder(P, s, w, keys, perm, st)) return rc;

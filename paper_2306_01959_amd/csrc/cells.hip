@@ -26,28 +26,77 @@ __device__ __forceinline__ int axis_cell(double v, double o, double cs, int n) {
     return (int)f;
 }
 
-// key of the particle's cell in its half-row (fluid or boundary) of the
-// instance's grid: sorted, each cell row holds its fluid particles, x-cell by
-// x-cell, then its boundary particles
-__global__ void k_encode(const double *__restrict__ x, const double *__restrict__ y,
-                         const double *__restrict__ z, const uint32_t *__restrict__ id,
-                         int64_t n, Insts I, uint32_t *__restrict__ keys) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const Inst ip = I.get(I.of_id(id[i] & 0x7fffffffu));
-    const int cx = axis_cell(x[i], ip.ox, ip.cs, ip.nx);
-    const int cy = axis_cell(y[i], ip.oy, ip.cs, ip.ny);
-    const int cz = axis_cell(z[i], ip.oz, ip.cs, ip.nz);
+// Key of particle i's cell in its half-row (fluid or boundary) of its
+// instance's grid: sorted, each cell row holds its fluid particles, x-cell
+// by x-cell, then its boundary particles.  Computed by the first histogram
+// pass of the sort, which stores the keys.
+struct EncodeArgs {
+    const double *x, *y, *z;
+    const uint32_t *id;
+    Insts I;
+    uint32_t *keys;
+};
+
+__device__ __forceinline__ uint32_t encode_key(const EncodeArgs &e, const Inst &ip, int64_t i,
+                                               uint32_t id) {
+    const int cx = axis_cell(e.x[i], ip.ox, ip.cs, ip.nx);
+    const int cy = axis_cell(e.y[i], ip.oy, ip.cs, ip.ny);
+    const int cz = axis_cell(e.z[i], ip.oz, ip.cs, ip.nz);
     const uint32_t lrow = (uint32_t)cz * (uint32_t)ip.ny + (uint32_t)cy;
-    keys[i] = half_row_key(ip.cell_base, ip.nx, lrow, id[i] >> 31) + (uint32_t)cx;
+    return half_row_key(ip.cell_base, ip.nx, lrow, id >> 31) + (uint32_t)cx;
 }
 
-int launch_encode(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st) {
-    int64_t n = s.n;
-    int blocks = (int)((n + 255) / 256);
-    hipLaunchKernelGGL(k_encode, dim3(blocks), dim3(256), 0, st, s.x, s.y, s.z, s.id, n,
-                       insts_of(P, w), w.keys());
-    return launch_check("encode");
+// The keys of a thread's kItems particles (block-strided, 0 past n).  The
+// particles of an instance are contiguous in every order the library keeps,
+// so a wave's particles nearly always share one instance: it is looked up
+// once (from the wave's first particle) and read once for the wave; a wave
+// that straddles instances looks them up particle by particle.
+template <int kItems>
+__device__ __forceinline__ void encode_keys(const EncodeArgs &e, int64_t base, int64_t n,
+                                            uint32_t key[kItems]) {
+    const int tid = threadIdx.x;
+    uint32_t id[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int64_t idx = base + (int64_t)it * kSortThreads + tid;
+        id[it] = idx < n ? e.id[idx] : 0u;
+    }
+    int k0 = 0;
+    bool one = true;
+    if (e.I.n > 1) {
+        // items are block-strided: item 0 holds the wave's first particle
+        const uint64_t act = __ballot(base + tid < n);
+        if (act == 0ull) {  // the wave lies past n: no particle at all
+#pragma unroll
+            for (int it = 0; it < kItems; ++it) key[it] = 0u;
+            return;
+        }
+        const int l0 = __builtin_amdgcn_readfirstlane(__ffsll((long long)act) - 1);
+        k0 = e.I.of_id((uint32_t)__builtin_amdgcn_readlane((int)id[0], l0) & 0x7fffffffu);
+        const uint32_t lo = e.I.tab[k0].pstart, hi = e.I.tab[k0].pend;
+        bool mine = true;
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const uint32_t v = id[it] & 0x7fffffffu;
+            mine = mine && (base + (int64_t)it * kSortThreads + tid >= n || (v >= lo && v < hi));
+        }
+        one = __all(mine);
+    }
+    if (one) {
+        const Inst ip = e.I.get(k0);
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const int64_t idx = base + (int64_t)it * kSortThreads + tid;
+            key[it] = idx < n ? encode_key(e, ip, idx, id[it]) : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const int64_t idx = base + (int64_t)it * kSortThreads + tid;
+            key[it] = idx < n ? encode_key(e, e.I.get(e.I.of_id(id[it] & 0x7fffffffu)), idx, id[it])
+                              : 0u;
+        }
+    }
 }
 
 // ------------------------------------------------------------ radix sort
@@ -74,31 +123,50 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
     return peers;
 }
 
-template <int kItems>
+// kEncode: the first pass, which computes the keys (encode_key) and stores
+// them instead of reading them.
+template <int kItems, bool kEncode>
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t *__restrict__ keys,
                                                             int64_t n, int shift,
                                                             uint32_t *__restrict__ hist,
-                                                            int ntiles) {
+                                                            int ntiles, EncodeArgs e) {
     __shared__ uint32_t h[kRadix];
     const int tid = threadIdx.x;
     for (int d = tid; d < kRadix; d += kSortThreads) h[d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortThreads * kItems;
+    uint32_t key[kItems];
+    if constexpr (kEncode) {
+        encode_keys<kItems>(e, base, n, key);
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            const int64_t idx = base + (int64_t)it * kSortThreads + tid;
+            if (idx < n) e.keys[idx] = key[it];
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {  // all loads first
+            const int64_t idx = base + (int64_t)it * kSortThreads + tid;
+            key[it] = idx < n ? keys[idx] : 0u;
+        }
+    }
+#pragma unroll
     for (int it = 0; it < kItems; ++it) {
-        int64_t idx = base + (int64_t)it * kSortThreads + tid;
-        bool ok = idx < n;
-        uint32_t d = ok ? (keys[idx] >> shift) & (kRadix - 1) : 0u;
-        uint64_t peers = match_digit(d, __ballot(ok));
+        const bool ok = base + (int64_t)it * kSortThreads + tid < n;
+        const uint32_t d = (key[it] >> shift) & (kRadix - 1);
+        const uint64_t peers = match_digit(d, __ballot(ok));
         if (ok && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
     for (int d = tid; d < kRadix; d += kSortThreads) hist[(int64_t)d * ntiles + blockIdx.x] = h[d];
 }
 
-// Exclusive scan of the (digit, tile) counts.  A block of 1024 threads
-// scans a span of kScanSpan values (4 consecutive values per thread, wave
-// prefix sums by shuffles, one LDS exchange of the 16 wave totals).  Small
-// arrays: one block walks all spans with a carry.  Large arrays: span
+// Exclusive scan (the (digit, tile) counts, the chunks per half-row).  A
+// block of 1024 threads scans a span of kScanSpan values (4 consecutive
+// values per thread, wave prefix sums by shuffles, one LDS exchange of the
+// 16 wave totals).  Up to kScanRedundantSpans spans: one launch, block b
+// sums the input before its span itself.  Up to kScanSumSpans: span totals,
+// then block b sums the totals before it and scans its span.  Beyond: span
 // totals -> scan of the totals (one block) -> spans scanned with their
 // offsets, all spans in parallel.
 
@@ -210,11 +278,30 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_spans(const uint32_t *__r
     span_scan(in, out, m, (int64_t)blockIdx.x * kScanSpan, off[blockIdx.x], wsum);
 }
 
+// Block b: the totals of spans 0..b-1 summed (a few per thread), then span b
+// scanned from there.
+__global__ __launch_bounds__(kScanThreads) void k_scan_spans_sum(const uint32_t *__restrict__ in,
+                                                                 uint32_t *__restrict__ out,
+                                                                 int64_t m,
+                                                                 const uint32_t *__restrict__ tot) {
+    __shared__ uint32_t wsum[kScanThreads / kWave + 1];
+    uint32_t part = 0;
+    for (int64_t s = threadIdx.x; s < (int64_t)blockIdx.x; s += kScanThreads) part += tot[s];
+    uint32_t offset;
+    block_excl_scan(part, wsum, offset);
+    span_scan(in, out, m, (int64_t)blockIdx.x * kScanSpan, offset, wsum);
+}
+
 int launch_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tot, hipStream_t st) {
     const int64_t spans = (m + kScanSpan - 1) / kScanSpan;
     if (spans <= kScanRedundantSpans) {
         hipLaunchKernelGGL(k_scan_redundant, dim3((unsigned)spans), dim3(kScanThreads), 0, st, in,
                            out, m);
+    } else if (spans <= kScanSumSpans) {
+        hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)spans), dim3(kScanThreads), 0, st, in, m,
+                           tot);
+        hipLaunchKernelGGL(k_scan_spans_sum, dim3((unsigned)spans), dim3(kScanThreads), 0, st, in,
+                           out, m, tot);
     } else {
         hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)spans), dim3(kScanThreads), 0, st, in, m,
                            tot);
@@ -225,56 +312,73 @@ int launch_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tot, hip
     return launch_check("scan");
 }
 
+// Stable scatter of one tile.  Wave w of the tile owns its keys
+// [w 64 kItems, (w + 1) 64 kItems) (input order = wave, item, lane), loads
+// them all up front, and ranks them item by item against a per-wave digit
+// count in LDS that only this wave touches (no workgroup barrier per item).
+// One barrier later the per-wave counts become start slots (the tile's
+// offset per digit from the scan, then the waves in order), and every key
+// goes to its slot + rank.
 template <int kItems>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ hist,
     int ntiles) {
     constexpr int kWaves = kSortThreads / kWave;
-    __shared__ uint32_t run[kRadix];          // next free slot per digit for this tile
-    __shared__ uint32_t wpos[kWaves][kRadix]; // per-wave counts, then start slots
+    static_assert(kSortThreads == kRadix, "one thread per digit for the start slots");
+    __shared__ uint32_t wcnt[kWaves][kRadix];  // per-wave counts, then start slots
     const int tid = threadIdx.x;
-    const int w = tid / kWave;
-    for (int d = tid; d < kRadix; d += kSortThreads) {
-        run[d] = hist[(int64_t)d * ntiles + blockIdx.x];
-        for (int k = 0; k < kWaves; ++k) wpos[k][d] = 0;
+    const int w = tid / kWave, lane = tid % kWave;
+    for (int d = lane; d < kRadix; d += kWave) wcnt[w][d] = 0u;
+    const int64_t wbase = (int64_t)blockIdx.x * kSortThreads * kItems + (int64_t)w * kWave * kItems;
+    uint32_t key[kItems], val[kItems], rank[kItems];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int64_t idx = wbase + (int64_t)it * kWave + lane;
+        const bool ok = idx < n;
+        key[it] = ok ? kin[idx] : 0u;
+        val[it] = ok ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
+    }
+    wave_sync();  // the zeroed counts
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const bool ok = wbase + (int64_t)it * kWave + lane < n;
+        const uint32_t d = (key[it] >> shift) & (kRadix - 1);
+        const uint64_t peers = match_digit(d, __ballot(ok));
+        const uint32_t r = (uint32_t)__popcll(peers & lt);
+        const uint32_t before = wcnt[w][d];
+        rank[it] = before + r;
+        wave_sync();  // every lane has read before the leader updates
+        if (ok && r == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+        wave_sync();
     }
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortThreads * kItems;
-    const uint64_t lt = lanemask_lt();
+    {
+        const int d = tid;
+        uint32_t run = hist[(int64_t)d * ntiles + blockIdx.x];
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            const uint32_t c = wcnt[k][d];
+            wcnt[k][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
     for (int it = 0; it < kItems; ++it) {
-        int64_t idx = base + (int64_t)it * kSortThreads + tid;
-        bool ok = idx < n;
-        uint32_t key = ok ? kin[idx] : 0u;
-        uint32_t val = ok ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
-        uint32_t d = (key >> shift) & (kRadix - 1);
-        uint64_t peers = match_digit(d, __ballot(ok));
-        uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (ok && rank == 0) wpos[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        for (int dd = tid; dd < kRadix; dd += kSortThreads) {
-            uint32_t r = run[dd];
-            for (int k = 0; k < kWaves; ++k) {
-                uint32_t c = wpos[k][dd];
-                wpos[k][dd] = r;
-                r += c;
-            }
-            run[dd] = r;
-        }
-        __syncthreads();
+        const bool ok = wbase + (int64_t)it * kWave + lane < n;
         if (ok) {
-            uint32_t pos = wpos[w][d] + rank;
-            kout[pos] = key;
-            vout[pos] = val;
+            const uint32_t d = (key[it] >> shift) & (kRadix - 1);
+            const uint32_t pos = wcnt[w][d] + rank[it];
+            kout[pos] = key[it];
+            vout[pos] = val[it];
         }
-        __syncthreads();
-        for (int dd = tid; dd < kRadix; dd += kSortThreads)
-            for (int k = 0; k < kWaves; ++k) wpos[k][dd] = 0;
-        __syncthreads();
     }
 }
 
-int launch_sort(const Ws &w, hipStream_t st, uint32_t **sorted_keys, uint32_t **perm) {
+int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st,
+                uint32_t **sorted_keys, uint32_t **perm) {
     const int64_t n = w.L.n;
     const int ntiles = (int)w.L.ntiles;
     const int passes = w.L.key_bits <= 0 ? 1 : (w.L.key_bits + kRadixBits - 1) / kRadixBits;
@@ -285,12 +389,22 @@ int launch_sort(const Ws &w, hipStream_t st, uint32_t **sorted_keys, uint32_t **
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = pass * kRadixBits;
         uint32_t *vout = vbuf[pass & 1];
-        if (small)
-            hipLaunchKernelGGL(k_sort_hist<kSortItemsSmall>, dim3(ntiles), dim3(kSortThreads), 0,
-                               st, kin, n, shift, w.hist(), ntiles);
-        else
-            hipLaunchKernelGGL(k_sort_hist<kSortItemsLarge>, dim3(ntiles), dim3(kSortThreads), 0,
-                               st, kin, n, shift, w.hist(), ntiles);
+        const EncodeArgs e{s.x, s.y, s.z, s.id, insts_of(P, w), kin};
+        if (small) {
+            if (pass == 0)
+                hipLaunchKernelGGL((k_sort_hist<kSortItemsSmall, true>), dim3(ntiles),
+                                   dim3(kSortThreads), 0, st, kin, n, shift, w.hist(), ntiles, e);
+            else
+                hipLaunchKernelGGL((k_sort_hist<kSortItemsSmall, false>), dim3(ntiles),
+                                   dim3(kSortThreads), 0, st, kin, n, shift, w.hist(), ntiles, e);
+        } else {
+            if (pass == 0)
+                hipLaunchKernelGGL((k_sort_hist<kSortItemsLarge, true>), dim3(ntiles),
+                                   dim3(kSortThreads), 0, st, kin, n, shift, w.hist(), ntiles, e);
+            else
+                hipLaunchKernelGGL((k_sort_hist<kSortItemsLarge, false>), dim3(ntiles),
+                                   dim3(kSortThreads), 0, st, kin, n, shift, w.hist(), ntiles, e);
+        }
         if (int rc = launch_scan(w.hist(), w.hist_off(), (int64_t)kRadix * ntiles, w.scan_tot(), st))
             return rc;
         if (small)
@@ -342,7 +456,12 @@ __device__ __forceinline__ float cell_offset(double v, double o, int c, double c
 // mixed: {offset from the cell centre (FP32), rho - rho0}, {u (FP32), P},
 // {1/rho, +-c}; FP64: {r, rho}, {u, P}, {1/rho, +-c}; c < 0 marks a boundary
 // particle.  P from the Tait equation, c the Tait sound speed (or c0).
-template <bool kMixed>
+// Mixed precision takes them from x = (rho - rho0) / rho0 in FP64 without
+// cancellation: (1 + x)^gamma - 1 = expm1(gamma log1p(x)); kGamma7 (every
+// instance has gamma = 7, the value of all the paper's runs) expands the
+// binomial instead, x (7 + 21 x + ... + x^6) and c0 (1 + x)^3, which needs no
+// transcendental calls and fewer registers.
+template <bool kMixed, bool kGamma7>
 __global__ void k_reorder(ReorderArgs a) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.n) return;
@@ -373,9 +492,16 @@ __global__ void k_reorder(ReorderArgs a) {
         const int cy = (int)(lrow % (uint32_t)ip.ny);
         const int cz = (int)(lrow / (uint32_t)ip.ny);
         const double xr = (double)dr / ip.rho0;
-        const double l1p = log1p(xr);
-        const double P = ip.B * expm1(ip.gamma * l1p);
-        const double cs = ip.c_const ? ip.c0 : ip.c0 * exp(0.5 * (ip.gamma - 1.0) * l1p);
+        double P, cs;
+        if constexpr (kGamma7) {
+            const double q = xr * (7.0 + xr * (21.0 + xr * (35.0 + xr * (35.0 + xr * (21.0 + xr * (7.0 + xr))))));
+            P = ip.B * q;
+            cs = ip.c_const ? ip.c0 : ip.c0 * (1.0 + xr * (3.0 + xr * (3.0 + xr)));
+        } else {
+            const double l1p = log1p(xr);
+            P = ip.B * expm1(ip.gamma * l1p);
+            cs = ip.c_const ? ip.c0 : ip.c0 * exp(0.5 * (ip.gamma - 1.0) * l1p);
+        }
         const double inv = 1.0 / (ip.rho0 + (double)dr);
         float4 v0 = make_float4(cell_offset(x, ip.ox, cx, ip.cs), cell_offset(y, ip.oy, cy, ip.cs),
                                 cell_offset(z, ip.oz, cz, ip.cs), dr);
@@ -419,10 +545,14 @@ int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *
     a.v2 = w.base + w.L.view2;
     a.I = insts_of(P, w);
     int blocks = (int)((s.n + 255) / 256);
-    if (P.precision == SPH_MIXED)
-        hipLaunchKernelGGL(k_reorder<true>, dim3(blocks), dim3(256), 0, st, a);
+    bool g7 = true;
+    for (const Inst &ip : P.host) g7 = g7 && ip.gamma == 7.0;
+    if (P.precision == SPH_MIXED && g7)
+        hipLaunchKernelGGL((k_reorder<true, true>), dim3(blocks), dim3(256), 0, st, a);
+    else if (P.precision == SPH_MIXED)
+        hipLaunchKernelGGL((k_reorder<true, false>), dim3(blocks), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL(k_reorder<false>, dim3(blocks), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_reorder<false, false>), dim3(blocks), dim3(256), 0, st, a);
     if (int rc = launch_check("reorder")) return rc;
     // the gathered arrays are now current
     auto swp = [](auto &u, auto &v) { auto t = u; u = v; v = t; };
@@ -436,16 +566,45 @@ int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *
 // ------------------------------------------------------------ cell table
 
 // start[k] = first sorted position whose key >= k, for k in [0, 2 ncells]
-// (lower bound by binary search; an empty cell gets the start of the next
-// one).  Cells x0..x1 of a half-row with key k0 at x = 0 hold the sorted
-// range [start[k0 + x0], start[k0 + x1 + 1]).
-__global__ void k_cell_table(const uint32_t *__restrict__ keys, int64_t n, int64_t ncells,
+// (lower bound; an empty cell gets the start of the next one).  Cells x0..x1
+// of a half-row with key k0 at x = 0 hold the sorted range
+// [start[k0 + x0], start[k0 + x1 + 1]).  The search starts from the entry's
+// previous value (particles move little between steps, so it is usually
+// exact or close): gallop away from it until the answer is bracketed, then
+// bisect.  The hint only changes the cost: any value gives the exact bound.
+__global__ void k_cell_table(const uint32_t *__restrict__ keys, int64_t n, int64_t nkeys,
                              uint32_t *__restrict__ start) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > ncells) return;
-    int64_t lo = 0, hi = n;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nkeys) return;
+    const int64_t h = start[c] < (uint64_t)n ? (int64_t)start[c] : n;
+    int64_t lo, hi;  // the answer lies in [lo, hi]
+    if (h < n && (int64_t)keys[h] < c) {
+        lo = h + 1;
+        hi = n;
+        for (int64_t step = 1;; step <<= 1) {
+            const int64_t q = h + step;
+            if (q >= n) break;
+            if ((int64_t)keys[q] >= c) {
+                hi = q;
+                break;
+            }
+            lo = q + 1;
+        }
+    } else {
+        lo = 0;
+        hi = h;
+        for (int64_t step = 1;; step <<= 1) {
+            const int64_t q = h - step;
+            if (q < 0) break;
+            if ((int64_t)keys[q] < c) {
+                lo = q + 1;
+                break;
+            }
+            hi = q;
+        }
+    }
     while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
+        const int64_t mid = lo + ((hi - lo) >> 1);
         if ((int64_t)keys[mid] < c)
             lo = mid + 1;
         else

@@ -26,6 +26,7 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kScanThreads = 1024;   // scan workgroup
 constexpr int kScanSpan = 4 * kScanThreads;  // values per scanned span
 constexpr int kScanRedundantSpans = 16;  // up to this many spans: one launch
+constexpr int kScanSumSpans = 16 * kScanThreads;  // up to this many: two (totals, then spans)
 constexpr int kChunk = 64;           // targets per chunk of the row-split interaction
 constexpr int kMinChunk = 8;         // smallest chunk (group-per-wave interaction)
 constexpr int kDiagThreads = 256;
@@ -81,6 +82,14 @@ struct DevScalars {
     unsigned int dt_cfl_violation;   // a step used dt > dt_cfl
     unsigned long long pairs[3];     // interacting pairs since init: FF, FB, BF
 };
+
+// Orders one wave's LDS writes before its later reads (and reads before
+// later overwrites) without involving the other waves of the workgroup.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Sort keys.  Every cell row (fixed cy, cz) of an instance is split into a
 // fluid half-row and a boundary half-row, cells x-fastest within each, so a
@@ -208,8 +217,8 @@ int hip_check(hipError_t e, const char *what);
 int launch_check(const char *what);
 
 // Launchers implemented in the kernel translation units.
-int launch_encode(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st);
-int launch_sort(const Ws &w, hipStream_t st, uint32_t **sorted_keys, uint32_t **perm);
+int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st,
+                uint32_t **sorted_keys, uint32_t **perm);
 // exclusive scan of m values from `in` (left intact) to `out`; tot:
 // ceil(m / kScanSpan) values of scratch
 int launch_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tot, hipStream_t st);

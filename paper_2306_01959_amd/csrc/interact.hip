@@ -103,14 +103,6 @@ __device__ __forceinline__ uint64_t lanes_below() {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Orders one wave's LDS writes before its later reads (and reads before
-// later overwrites) without involving the other waves of the workgroup.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // 32-bit integer mixer (the finaliser of MurmurHash3): neighbour-set hashes
 // are sums of id_hash over the set, so they do not depend on visit order.
 __device__ __forceinline__ uint32_t id_hash(uint32_t v) {
@@ -1303,12 +1295,15 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
 
 // Per-instance minimum of the chunks' time-step bounds and the pair totals.
 // Block b reduces chunks [1024 b, 1024 b + 1024): chunks are ordered by
-// instance, so the block's instances are inst0 .. inst0 + 1023 at most; a
-// minimum per instance in LDS, then one global atomic per instance and
-// block (a handful in all: no contention).
+// instance, so the block's instances are inst0 .. inst0 + 1023 at most.  A
+// wave whose chunks all belong to one instance (nearly every wave) first
+// reduces across its lanes by shuffles and makes one LDS update; a wave that
+// straddles instances updates LDS lane by lane.  Then one global atomic per
+// instance and block (a handful in all: no contention).
 __global__ __launch_bounds__(1024) void k_chunk_reduce(const int4 *__restrict__ chunks,
                                                        const ChunkOut *__restrict__ cout,
                                                        DevScalars *sc, InstState *ist) {
+    constexpr unsigned long long kInf = 0x7ff0000000000000ull;
     __shared__ unsigned long long smin[1024];
     __shared__ unsigned long long spairs[3];
     __shared__ int inst0;
@@ -1316,21 +1311,47 @@ __global__ __launch_bounds__(1024) void k_chunk_reduce(const int4 *__restrict__ 
     const uint32_t c0 = blockIdx.x * 1024u;
     if (c0 >= nch) return;
     const int t = threadIdx.x;
-    smin[t] = 0x7ff0000000000000ull;
+    smin[t] = kInf;
     if (t < 3) spairs[t] = 0ull;
     if (t == 0) inst0 = chunks[c0].w;
     __syncthreads();
     const uint32_t c = c0 + (uint32_t)t;
-    if (c < nch) {
+    const bool ok = c < nch;
+    unsigned long long b = kInf;
+    unsigned long long p0 = 0, p1 = 0, p2 = 0;  // 64-bit: wave sums of 32-bit counts
+    int slot = -1;
+    if (ok) {
         const ChunkOut o = cout[c];
-        const int slot = chunks[c].w - inst0;
-        atomicMin(&smin[slot], (unsigned long long)__double_as_longlong(o.bound));
-        if (o.pairs[0]) atomicAdd(&spairs[0], (unsigned long long)o.pairs[0]);
-        if (o.pairs[1]) atomicAdd(&spairs[1], (unsigned long long)o.pairs[1]);
-        if (o.pairs[2]) atomicAdd(&spairs[2], (unsigned long long)o.pairs[2]);
+        b = (unsigned long long)__double_as_longlong(o.bound);
+        p0 = o.pairs[0];
+        p1 = o.pairs[1];
+        p2 = o.pairs[2];
+        slot = chunks[c].w - inst0;
+    }
+    const int s0 = __shfl(slot, 0, kWave);
+    if (__all(slot == s0 || slot < 0)) {
+        // bounds are non-negative doubles: their bit patterns order alike
+        for (int off = 1; off < kWave; off <<= 1) {
+            const unsigned long long ob = __shfl_xor(b, off, kWave);
+            b = ob < b ? ob : b;
+            p0 += __shfl_xor(p0, off, kWave);
+            p1 += __shfl_xor(p1, off, kWave);
+            p2 += __shfl_xor(p2, off, kWave);
+        }
+        if (t % kWave == 0) {
+            atomicMin(&smin[s0], b);
+            atomicAdd(&spairs[0], p0);
+            atomicAdd(&spairs[1], p1);
+            atomicAdd(&spairs[2], p2);
+        }
+    } else if (ok) {
+        atomicMin(&smin[slot], b);
+        atomicAdd(&spairs[0], p0);
+        atomicAdd(&spairs[1], p1);
+        atomicAdd(&spairs[2], p2);
     }
     __syncthreads();
-    if (smin[t] != 0x7ff0000000000000ull) atomicMin(&ist[inst0 + t].dt_min_bits, smin[t]);
+    if (smin[t] != kInf) atomicMin(&ist[inst0 + t].dt_min_bits, smin[t]);
     if (t < 3 && spairs[t]) atomicAdd(&sc->pairs[t], spairs[t]);
 }
 
