@@ -28,8 +28,9 @@
  *     asynchronous on that stream except sph_diagnostics, which
  *     synchronises it.
  *   - Particle arrays are structure-of-arrays of length n.  After
- *     sph_build_cells the arrays are in cell order; id[] carries each
- *     particle's original index.
+ *     sph_build_cells the arrays are in cell order (cell row, then fluid
+ *     before boundary, then cell x); id[] carries each particle's original
+ *     index.
  *   - One state/workspace pair must not be used by two overlapping calls.
  */
 #ifndef WCSPH_H
@@ -174,12 +175,14 @@ int sph_check_params(const sph_params *p);
 /* Decomposition of the interaction kernel. */
 typedef enum {
     SPH_KERNEL_AUTO = 0,
-    SPH_KERNEL_ROWS = 1,   /* chunks of up to 64 targets of one cell row; `split`
+    SPH_KERNEL_ROWS = 1,   /* chunks of up to 64 targets of one half-row (the
+                              fluid or the boundary particles of a cell row,
+                              never across an empty cell); `split`
                               waves (1, 3 or 9) divide the 9 stencil rows; inside
                               a wave the targets form groups of `group` (8, 16
                               or 64), each culled on its own */
     SPH_KERNEL_GROUPS = 2, /* one independent wave per group of up to `group`
-                              targets of one cell row (8, 16 or 64), streaming
+                              targets of one half-row (8, 16 or 64), streaming
                               and culling its own candidates; `split` unused */
     SPH_KERNEL_COOP = 3,   /* four groups of `group` targets (8 or 16; 64 acts
                               as 16) per workgroup, which loads and culls their
@@ -236,13 +239,14 @@ int sph_get_density(const sph_params *p, const sph_state *s, double *rho, int32_
 
 /*
  * Cell-linked list (neighbour search set-up).  Hashes every position to its
- * cell (clamped to the grid), sorts the particles stably by cell (LSD radix
- * sort of 32-bit cell keys), gathers every state array into cell order (the
- * *_alt buffers, then swaps the pointers) and builds the cell table and the
- * interaction view (per-particle pressure, sound speed, 1/rho, and for
- * SPH_MIXED the FP32 offset of each particle from its cell centre).
- * Stable: particles of one cell keep their previous relative order, so the
- * result is deterministic.
+ * cell (clamped to the grid), sorts the particles stably by cell row (fixed
+ * y, z), then class (fluid before boundary), then cell x (LSD radix sort of
+ * 32-bit keys), gathers every state array into that order (the *_alt
+ * buffers, then swaps the pointers) and builds the cell table, the chunk list
+ * and the interaction view (per-particle pressure, sound speed, 1/rho, and
+ * for SPH_MIXED the FP32 offset of each particle from its cell centre).
+ * Stable: particles of one cell and class keep their previous relative
+ * order, so the result is deterministic.
  */
 int sph_build_cells(const sph_params *p, sph_state *s, void *ws, void *stream);
 
