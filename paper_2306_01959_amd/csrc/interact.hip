@@ -567,6 +567,42 @@ __device__ __forceinline__ void stencil_range(const InteractArgs &a, const Inst 
     }
 }
 
+// The pair steps of one target group over n staged records: step s0 = 0,
+// kG, 2 kG, ... < n, lane slot s taking record slot s0 + s (record index
+// idx(slot), which must be valid for every slot, also past n).  body(slot,
+// r0, r1, r2, r3) evaluates one step (its lanes with slot >= n are idle).
+// kPipe: two register sets in alternation, the next step's records (and the
+// index after it) read from LDS while this step's pair terms are evaluated;
+// it costs 16 (FP32) or 32 (FP64) registers, so kernels take it only where
+// their occupancy does not drop.
+template <class V4, int kG, bool kPipe, class Idx, class Rec, class Body>
+__device__ __forceinline__ void pair_steps(int n, int slot_s, Idx idx, Rec rec, Body body) {
+    if (n <= 0) return;
+    if constexpr (!kPipe) {
+        for (int s0 = 0; s0 < n; s0 += kG) {
+            V4 r0, r1, r2, r3;
+            rec(idx(s0 + slot_s), r0, r1, r2, r3);
+            body(s0 + slot_s, r0, r1, r2, r3);
+        }
+        return;
+    }
+    V4 a0, a1, a2, a3, b0, b1, b2, b3;
+    int sl = slot_s;
+    rec(idx(sl), a0, a1, a2, a3);
+    int kb = idx(sl + kG);
+    for (int s0 = 0; s0 < n; s0 += 2 * kG) {
+        const bool more = s0 + kG < n;
+        if (more) rec(kb, b0, b1, b2, b3);
+        const int ka = idx(sl + 2 * kG);
+        body(sl, a0, a1, a2, a3);
+        if (!more) break;
+        if (s0 + 2 * kG < n) rec(ka, a0, a1, a2, a3);
+        kb = idx(sl + 3 * kG);
+        body(sl + kG, b0, b1, b2, b3);
+        sl += 2 * kG;
+    }
+}
+
 // ================================================================ skeleton
 
 template <class P, int kSplit, int kT, bool kStats, bool kFuse>
@@ -724,15 +760,19 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
                 tg.b = tgt[1][tidx];
                 tg.c = tgt[2][tidx];
                 const int ti = cs0 + tidx;
-                for (int s0 = 0; s0 < gcnt[g]; s0 += kG) {
-                    const int sl = s0 + slot_s;
-                    const bool valid = sl < gcnt[g] && tidx < ntgt;
-                    const int k = sl < gcnt[g] ? (int)glist[w][g][sl] : 0;
-                    const V4 r0 = stg[w][0][k], r1 = stg[w][1][k];
-                    const V4 r2 = stg[w][2][k], r3 = stg[w][3][k];
-                    P::template pair<kStats>(a, ip, tg, ti, valid, r0, r1, r2, r3, acc[g], cn,
-                                             sts[g]);
-                }
+                const int gn = gcnt[g];
+                pair_steps<V4, kG, false>(
+                    gn, slot_s, [&](int sl) { return sl < gn ? (int)glist[w][g][sl] : 0; },
+                    [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
+                        r0 = stg[w][0][k];
+                        r1 = stg[w][1][k];
+                        r2 = stg[w][2][k];
+                        r3 = stg[w][3][k];
+                    },
+                    [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
+                        P::template pair<kStats>(a, ip, tg, ti, sl < gn && tidx < ntgt, r0, r1,
+                                                 r2, r3, acc[g], cn, sts[g]);
+                    });
             }
         }
         wave_sync();
@@ -955,14 +995,18 @@ __global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(Interact
             }
             wave_sync();
             const int cnt = __popcll(m);
-            for (int s0 = 0; s0 < cnt; s0 += kG) {
-                const int sl = s0 + slot_s;
-                const bool valid = sl < cnt && act;
-                const int k = sl < cnt ? sl : 0;
-                const V4 r0 = stg[0][k], r1 = stg[1][k];
-                const V4 r2 = stg[2][k], r3 = stg[3][k];
-                P::template pair<kStats>(a, ip, tg, it, valid, r0, r1, r2, r3, acc, cn, sts);
-            }
+            pair_steps<V4, kG, P::kMixed>(
+                cnt, slot_s, [&](int sl) { return sl < cnt ? sl : 0; },
+                [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
+                    r0 = stg[0][k];
+                    r1 = stg[1][k];
+                    r2 = stg[2][k];
+                    r3 = stg[3][k];
+                },
+                [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
+                    P::template pair<kStats>(a, ip, tg, it, sl < cnt && act, r0, r1, r2, r3, acc,
+                                             cn, sts);
+                });
             wave_sync();
         };
 
@@ -1223,17 +1267,20 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
                     P::template body<kStats>(a, ip, tg, valid, r0, r1, r2, r3, acc, sts);
                 }
             } else {
-                for (int s0 = 0; s0 < n; s0 += kG) {
-                    const int sl = s0 + slot_s;
-                    const bool valid = sl < n && act;
-                    // idle lanes read a record staged in this batch (entry 0):
-                    // their terms are multiplied by zero and must stay finite
-                    const int k = (int)glist[w][sl < n ? sl : 0];
-                    const V4 r0 = pool[buf][0][k], r1 = pool[buf][1][k];
-                    const V4 r2 = pool[buf][2][k], r3 = pool[buf][3][k];
-                    P::template pair<kStats>(a, ip, tg, it, valid, r0, r1, r2, r3, acc, cn,
-                                             sts);
-                }
+                // idle lanes read a record staged in this batch (entry 0):
+                // their terms are multiplied by zero and must stay finite
+                pair_steps<V4, kG, true>(
+                    n, slot_s, [&](int sl) { return (int)glist[w][sl < n ? sl : 0]; },
+                    [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
+                        r0 = pool[buf][0][k];
+                        r1 = pool[buf][1][k];
+                        r2 = pool[buf][2][k];
+                        r3 = pool[buf][3][k];
+                    },
+                    [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
+                        P::template pair<kStats>(a, ip, tg, it, sl < n && act, r0, r1, r2, r3,
+                                                 acc, cn, sts);
+                    });
             }
             wave_sync();
         }
