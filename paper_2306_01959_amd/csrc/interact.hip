@@ -256,16 +256,17 @@ struct Mixed {
         const float F = in ? Fr : 0.f;
         const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const float vr = vx * dx + vy * dy + vz * dz;               // u_ij . r_ij
-        const float mu = (float)ip.h * vr * __builtin_amdgcn_rcpf(rr + (float)ip.eta2);
+        // one reciprocal for mu = h vr / (r^2 + eta^2) and the viscosity's
+        // mu / (rho_i + rho_j): hvi = h vr / ((r^2 + eta^2)(rho_i + rho_j))
+        const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r3.x;  // rho_i + rho_j
+        const float hvi = (float)ip.h * vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
+        const float mu = hvi * rsum;
         const float amu = in ? fabsf(mu) : 0.f;
         acc.mu = amu > acc.mu ? amu : acc.mu;
         acc.dr -= F * vr;                                    // m (u_i - u_j) . grad_i W_ij
         const float Fd = fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;             // delta term
-        const float visc =
-            vr < 0.f ? -(float)ip.alpha * (t.c.z + fabsf(r3.y)) * mu *
-                           __builtin_amdgcn_rcpf((float)(2.0 * ip.rho0) + t.c.y + r3.x)
-                     : 0.f;
+        const float visc = vr < 0.f ? -(float)ip.alpha * (t.c.z + fabsf(r3.y)) * hvi : 0.f;
         const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -308,15 +309,14 @@ struct Mixed {
         const float F = valid ? (float)ip.Fm * q2 * q2 * q2 : 0.f;
         const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const float vr = vx * dx + vy * dy + vz * dz;
-        const float mu = (float)ip.h * vr * __builtin_amdgcn_rcpf(rr + (float)ip.eta2);
+        const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r3.x;  // rho_i + rho_j
+        const float hvi = (float)ip.h * vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
+        const float mu = hvi * rsum;
         acc.mu = valid ? fmaxf(acc.mu, fabsf(mu)) : acc.mu;
         acc.dr -= F * vr;
         const float Fd = fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;
-        const float visc =
-            vr < 0.f ? -(float)ip.alpha * (t.c.z + fabsf(r3.y)) * mu *
-                           __builtin_amdgcn_rcpf((float)(2.0 * ip.rho0) + t.c.y + r3.x)
-                     : 0.f;
+        const float visc = vr < 0.f ? -(float)ip.alpha * (t.c.z + fabsf(r3.y)) * hvi : 0.f;
         const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -459,14 +459,17 @@ struct Fp64 {
         const double F = in ? Fr : 0.0;
         const double vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const double vr = vx * dx + vy * dy + vz * dz;
-        const double mu = ip.h * vr / (rr + ip.eta2);
+        // one division for mu = h vr / (r^2 + eta^2) and the viscosity's
+        // mu / (rho_i + rho_j)
+        const double rsum = t.c.y + r2.z;  // rho_i + rho_j
+        const double hvi = ip.h * vr / ((rr + ip.eta2) * rsum);
+        const double mu = hvi * rsum;
         const double amu = in ? fabs(mu) : 0.0;
         acc.mu = amu > acc.mu ? amu : acc.mu;
         acc.dr -= F * vr;
         const double Fd = fi ? F : 0.0;
         acc.dr += (r2.z - t.c.y) * r2.y * Fd;
-        const double visc =
-            vr < 0.0 ? -ip.alpha * (t.c.z + fabs(r3.y)) * mu / (t.c.y + r2.z) : 0.0;
+        const double visc = vr < 0.0 ? -ip.alpha * (t.c.z + fabs(r3.y)) * hvi : 0.0;
         const double s = (fma(t.b.w, r2.x, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -497,13 +500,14 @@ struct Fp64 {
         const double F = valid ? ip.Fm * q2 * q2 * q2 : 0.0;
         const double vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const double vr = vx * dx + vy * dy + vz * dz;
-        const double mu = ip.h * vr / (rr + ip.eta2);
+        const double rsum = t.c.y + r2.z;  // rho_i + rho_j
+        const double hvi = ip.h * vr / ((rr + ip.eta2) * rsum);
+        const double mu = hvi * rsum;
         acc.mu = valid ? fmax(acc.mu, fabs(mu)) : acc.mu;
         acc.dr -= F * vr;
         const double Fd = fi ? F : 0.0;
         acc.dr += (r2.z - t.c.y) * r2.y * Fd;
-        const double visc =
-            vr < 0.0 ? -ip.alpha * (t.c.z + fabs(r3.y)) * mu / (t.c.y + r2.z) : 0.0;
+        const double visc = vr < 0.0 ? -ip.alpha * (t.c.z + fabs(r3.y)) * hvi : 0.0;
         const double s = (fma(t.b.w, r2.x, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
