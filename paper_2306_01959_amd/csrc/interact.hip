@@ -121,8 +121,23 @@ struct Acc {
 };
 
 // Wave-uniform pair counters, and per-lane neighbour statistics of a group.
+// Pair counts, per lane: pairs inside the support, and those of them with a
+// fluid j.  A chunk's targets are all fluid or all boundary (one half-row),
+// so the wave totals split into the three classes by the chunk's class alone.
 struct Counters {
-    uint32_t ff = 0, fb = 0, bf = 0;
+    uint32_t in = 0, fj = 0;
+    // wave totals (every lane of the wave calls it; uniform results)
+    __device__ __forceinline__ void totals(bool fluid_chunk, uint32_t &ff, uint32_t &fb,
+                                           uint32_t &bf) const {
+        uint32_t a = in, b = fj;
+        for (int off = 1; off < kWave; off <<= 1) {
+            a += __shfl_xor(a, off, kWave);
+            b += __shfl_xor(b, off, kWave);
+        }
+        ff = fluid_chunk ? b : 0u;
+        fb = fluid_chunk ? a - b : 0u;
+        bf = fluid_chunk ? 0u : b;  // a boundary target pairs with fluid j only
+    }
 };
 struct Stats {
     int32_t f = 0, b = 0;
@@ -234,13 +249,8 @@ struct Mixed {
         const float rr = sq_sum_f32(dx, dy, dz);
         const int j = __float_as_int(r3.z);
         const bool in = valid && rr < (float)ip.r2max && j != ti && (fi || fj);
-        const uint64_t inm = __ballot(in);
-        if (inm == 0) return;
-        const uint64_t fim = __ballot(fi);
-        const uint64_t fjm = __ballot(fj);
-        cn.ff += (uint32_t)__popcll(inm & fim & fjm);
-        cn.fb += (uint32_t)__popcll(inm & fim & ~fjm);
-        cn.bf += (uint32_t)__popcll(inm & ~fim & fjm);
+        cn.in += in ? 1u : 0u;
+        cn.fj += (in && fj) ? 1u : 0u;
         if (kStats && in) {
             if (fj)
                 ++st.f;
@@ -438,13 +448,8 @@ struct Fp64 {
         const double rr = sq_sum_f64(dx, dy, dz);
         const int j = (int)r0.w;
         const bool in = valid && rr < ip.r2max && j != ti && (fi || fj);
-        const uint64_t inm = __ballot(in);
-        if (inm == 0) return;
-        const uint64_t fim = __ballot(fi);
-        const uint64_t fjm = __ballot(fj);
-        cn.ff += (uint32_t)__popcll(inm & fim & fjm);
-        cn.fb += (uint32_t)__popcll(inm & fim & ~fjm);
-        cn.bf += (uint32_t)__popcll(inm & ~fim & fjm);
+        cn.in += in ? 1u : 0u;
+        cn.fj += (in && fj) ? 1u : 0u;
         if (kStats && in) {
             if (fj)
                 ++st.f;
@@ -845,10 +850,14 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
         }
     }
     // the waves' pair counts (integer, order-free) for the chunk's record
-    if (lane == 0) {
-        atomicAdd(&wg_pairs[0], cn.ff);
-        atomicAdd(&wg_pairs[1], cn.fb);
-        atomicAdd(&wg_pairs[2], cn.bf);
+    {
+        uint32_t ff, fb, bf;
+        cn.totals(any_fluid, ff, fb, bf);
+        if (lane == 0) {
+            atomicAdd(&wg_pairs[0], ff);
+            atomicAdd(&wg_pairs[1], fb);
+            atomicAdd(&wg_pairs[2], bf);
+        }
     }
     __syncthreads();
     if (w == 0) {
@@ -1062,7 +1071,9 @@ __global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(Interact
             }
         }
         bound = group_min(bound, kWave);
-        if (lane == 0) a.cout[item] = ChunkOut{bound, {cn.ff, cn.fb, cn.bf}, 0u};
+        uint32_t ff, fb, bf;
+        cn.totals(any_fluid, ff, fb, bf);
+        if (lane == 0) a.cout[item] = ChunkOut{bound, {ff, fb, bf}, 0u};
     }
 }
 
@@ -1136,7 +1147,6 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
     }
     if (threadIdx.x == 0) anyf = 0;
     __syncthreads();
-    const uint64_t fim = __ballot(tg.fluid());      // lanes whose target is fluid
     const bool my_fluid = __ballot(fi_own) != 0ull;  // (every lane takes part)
     if (lane == 0 && my_fluid) atomicOr(&anyf, 1);
     // lanes that work on the same target as this one: t_in + m kT
@@ -1249,10 +1259,8 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
                     bool fj;
                     const bool in = P::filter(ip, tg, it, r0, r3, fj) && sl < n && act;
                     const uint64_t inm = __ballot(in);
-                    const uint64_t fjm = __ballot(fj);
-                    cn.ff += (uint32_t)__popcll(inm & fim & fjm);
-                    cn.fb += (uint32_t)__popcll(inm & fim & ~fjm);
-                    cn.bf += (uint32_t)__popcll(inm & ~fim & fjm);
+                    cn.in += in ? 1u : 0u;
+                    cn.fj += (in && fj) ? 1u : 0u;
                     const uint64_t mine = inm & same_t;
                     if (in) tl[nn + __popcll(mine & below)] = (uint8_t)k;
                     nn += __popcll(mine);
@@ -1333,11 +1341,13 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
     }
     __syncthreads();
     bound = group_min(bound, kWave);
+    uint32_t ff, fb, bf;
+    cn.totals(any_fluid, ff, fb, bf);
     if (lane == 0) {
         atomicMin(&wb, (unsigned long long)__double_as_longlong(bound));
-        atomicAdd(&wp[0], cn.ff);
-        atomicAdd(&wp[1], cn.fb);
-        atomicAdd(&wp[2], cn.bf);
+        atomicAdd(&wp[0], ff);
+        atomicAdd(&wp[1], fb);
+        atomicAdd(&wp[2], bf);
     }
     __syncthreads();
     if (threadIdx.x == 0)
