@@ -924,15 +924,21 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
 constexpr int kWavesPerGroupWG = 4;  // independent waves per workgroup
 
 template <class P, int kT, bool kStats, bool kFuse>
-__global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(InteractArgs a) {
+__global__ __launch_bounds__(kWave *kWavesPerGroupWG)
+__attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(InteractArgs a) {
     using R = typename P::R;
     using V4 = typename P::V4;
     constexpr int kG = kWave / kT;
     static_assert(kT == 8 || kT == 16 || kT == 64, "group size");
-    __shared__ V4 stg_all[kWavesPerGroupWG][4][kWave];
+    // staged records per wave: the mixed form keeps up to two batches, and
+    // evaluates pairs once more than one batch's worth has gathered (fewer
+    // part-filled pair steps); the FP64 records are twice as large and stay
+    // at one batch (more LDS would cost occupancy)
+    constexpr int kCap = P::kMixed ? 2 * kWave : kWave;
+    __shared__ V4 stg_all[kWavesPerGroupWG][4][kCap];
     const int w = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    V4(*stg)[kWave] = stg_all[w];
+    V4(*stg)[kCap] = stg_all[w];
     const int t_in = lane % kT;
     const int slot_s = lane / kT;
     const uint64_t below = lanes_below();
@@ -987,6 +993,26 @@ __global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(Interact
 
         Acc<R> acc;
         Stats sts;
+        int nst = 0;  // records staged and not yet evaluated
+        // the pairs of the staged records (slots [0, nst)), then an empty stage
+        auto flush = [&]() __attribute__((always_inline)) {
+            wave_sync();
+            const int cnt = nst;
+            pair_steps<V4, kG, P::kMixed>(
+                cnt, slot_s, [&](int sl) { return sl < cnt ? sl : 0; },
+                [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
+                    r0 = stg[0][k];
+                    r1 = stg[1][k];
+                    r2 = stg[2][k];
+                    r3 = stg[3][k];
+                },
+                [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
+                    P::template pair<kStats>(a, ip, tg, it, sl < cnt && act, r0, r1, r2, r3, acc,
+                                             cn, sts);
+                });
+            wave_sync();
+            nst = 0;
+        };
         auto process = [&](const typename P::Cand &cur, int q, int jb) __attribute__((always_inline)) {
             const int code = __builtin_amdgcn_readlane(r_code, q);
             const int nbase = __builtin_amdgcn_readlane(r_nb, q);
@@ -1002,25 +1028,12 @@ __global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(Interact
             }
             const uint64_t m = __ballot(keep);
             if (keep) {
-                const int slot = __popcll(m & below);
+                const int slot = nst + __popcll(m & below);
                 P::stage(a, ip, cur, nbase, jb + lane, dy, dz, &stg[0][slot], &stg[1][slot],
                          &stg[2][slot], &stg[3][slot]);
             }
-            wave_sync();
-            const int cnt = __popcll(m);
-            pair_steps<V4, kG, P::kMixed>(
-                cnt, slot_s, [&](int sl) { return sl < cnt ? sl : 0; },
-                [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
-                    r0 = stg[0][k];
-                    r1 = stg[1][k];
-                    r2 = stg[2][k];
-                    r3 = stg[3][k];
-                },
-                [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
-                    P::template pair<kStats>(a, ip, tg, it, sl < cnt && act, r0, r1, r2, r3, acc,
-                                             cn, sts);
-                });
-            wave_sync();
+            nst += __popcll(m);
+            if (nst > kCap - kWave) flush();  // the next batch might not fit
         };
 
         // two candidate register sets in alternation (see the chunk kernel)
@@ -1038,6 +1051,7 @@ __global__ __launch_bounds__(kWave *kWavesPerGroupWG) void k_interact_g(Interact
             load_batch(qa, ja, ca);
             process(cb, qb, jbb);
         }
+        if (nst > 0) flush();
 
         // sum the slot lanes of each target (fixed shuffle tree)
         for (int off = kT; off < kWave; off <<= 1) {
