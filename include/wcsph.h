@@ -79,7 +79,7 @@ typedef enum {
  * metres, SI units.  Validation (SPH_E_INVAL): dp > 0, h > 0, rho0 > 0,
  * c0 > 0, gamma >= 1, alpha >= 0, 0 <= delta <= 1, eta2_coef >= 0,
  * 0 < cfl <= 1, mass > 0, cell_size >= 2h, dims[k] >= 1 and
- * dims[0]*dims[1]*dims[2] < 2^30 (SPH_E_RANGE), finite values, enums in range.
+ * dims[0]*dims[1]*dims[2] < 2^29 (SPH_E_RANGE), finite values, enums in range.
  */
 typedef struct sph_params {
     double dp;         /* initial particle spacing l0 */
@@ -364,7 +364,7 @@ typedef struct sph_batch {
                             synchronises the stream before it returns */
 
 /* Workspace bytes of a batch; SPH_E_RANGE if the sum of particles reaches
- * 2^31 or the sum of cells 2^30. */
+ * 2^31 or the sum of cells 2^29. */
 int sph_batch_workspace_bytes(const sph_batch *b, size_t *bytes);
 
 /*

@@ -42,8 +42,7 @@ WsLayout make_layout(const Problem &P) {
     L.max_chunks = (n + kMinChunk - 1) / kMinChunk + 4 * L.nrows;
     int bits = 0;
     while (bits < 32 && ((int64_t)1 << bits) < 2 * L.ncells) ++bits;
-    L.key_bits = bits;
-    const int passes = bits <= 0 ? 1 : (bits + kRadixBits - 1) / kRadixBits;
+    L.key_bits = bits + kSubBits;
     const bool mixed = P.precision == SPH_MIXED;
     L.view_elem = mixed ? 16 : 32;
     L.rate_elem = mixed ? 4 : 8;
@@ -57,7 +56,7 @@ WsLayout make_layout(const Problem &P) {
     L.keys_alt = take(4 * (size_t)n);
     L.vals = take(4 * (size_t)n);
     L.vals_alt = take(4 * (size_t)n);
-    L.sorted_keys = (passes & 1) ? L.keys_alt : L.keys;
+    L.sorted_keys = L.keys;
     L.hist = take(4 * (size_t)kRadix * (size_t)L.ntiles);
     L.hist_off = take(4 * (size_t)kRadix * (size_t)L.ntiles);
     const size_t scanned = std::max((size_t)kRadix * (size_t)L.ntiles, (size_t)(2 * L.nrows));
@@ -164,7 +163,7 @@ static int check_params(const sph_params *p) {
     for (int k = 0; k < 3; ++k)
         if (p->dims[k] < 1) return fail(SPH_E_INVAL, "dims must be >= 1");
     const int64_t nc = (int64_t)p->dims[0] * p->dims[1] * p->dims[2];
-    if (nc >= ((int64_t)1 << 30)) return fail(SPH_E_RANGE, "too many cells (>= 2^30)");
+    if (nc >= ((int64_t)1 << 29)) return fail(SPH_E_RANGE, "too many cells (>= 2^29)");
     if (p->precision != SPH_FP64 && p->precision != SPH_MIXED)
         return fail(SPH_E_INVAL, "unknown precision");
     if (p->c_mode != SPH_C_TAIT && p->c_mode != SPH_C_CONST)
@@ -247,8 +246,8 @@ static int batch_problem(const sph_batch *b, Problem *P) {
         const int64_t nc = (int64_t)p.dims[0] * p.dims[1] * p.dims[2];
         const int64_t nr = (int64_t)p.dims[1] * p.dims[2];
         if (n + c >= ((int64_t)1 << 31)) return fail(SPH_E_RANGE, "total particles must be < 2^31");
-        if (cells + nc >= ((int64_t)1 << 30))
-            return fail(SPH_E_RANGE, "total cells must be < 2^30");
+        if (cells + nc >= ((int64_t)1 << 29))
+            return fail(SPH_E_RANGE, "total cells must be < 2^29");
         P->host.push_back(inst_from(p, (uint32_t)cells, (uint32_t)rows, (uint32_t)n,
                                     (uint32_t)(n + c)));
         n += c;
@@ -281,12 +280,15 @@ struct Marks {
     }
 };
 
+// full: sort on the sub-cell bits too (see kSubBits); the steps between
+// refreshes sort on the cell key alone.
 static int build_cells(const Problem &P, sph_state &s, const Ws &w, hipStream_t st,
-                       bool lagged = false, double dt = 0.0, const Marks &m = Marks()) {
+                       bool lagged = false, double dt = 0.0, const Marks &m = Marks(),
+                       bool full = true) {
     if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
     uint32_t *keys = nullptr, *perm = nullptr;
     if (int rc = m.at(SPH_REGION_SORT, true, st)) return rc;
-    if (int rc = launch_sort(P, s, w, st, &keys, &perm)) return rc;  // cell keys included
+    if (int rc = launch_sort(P, s, w, st, full, &keys, &perm)) return rc;  // keys included
     if (int rc = m.at(SPH_REGION_SORT, false, st)) return rc;
     if (int rc = m.at(SPH_REGION_REORDER, true, st)) return rc;
     if (int rc = launch_reorder(P, s, w, keys, perm, st)) return rc;
@@ -297,12 +299,23 @@ static int build_cells(const Problem &P, sph_state &s, const Ws &w, hipStream_t 
     return SPH_OK;
 }
 
+static int64_t graph_period(const Problem &P);
+
+// Steps whose cell list sorts on every key bit: multiples of this period (the
+// graph period when there is one, so that a replayed graph refreshes at the
+// same steps as eager launches would).
+static int64_t refresh_period(const Problem &P) {
+    const int64_t L = graph_period(P);
+    return L > 0 ? L : 40;
+}
+
 // One step.  fused: the lagged-dt form, where the interaction also advances
 // the state (one kernel instead of interaction + update).
 static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
                     bool fused, hipStream_t st, const Marks &m = Marks()) {
     if (!s.cells_valid) {
-        if (int rc = build_cells(P, s, w, st, fused, dt, m)) return rc;
+        const bool full = step % refresh_period(P) == 0;
+        if (int rc = build_cells(P, s, w, st, fused, dt, m, full)) return rc;
     } else {
         if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
         if (int rc = launch_chunks(P, w, fused, dt, st)) return rc;  // fresh dt bound

@@ -16,13 +16,17 @@ namespace wcsph {
 
 // ---------------------------------------------------------------- encode
 
-__device__ __forceinline__ int axis_cell(double v, double o, double cs, int n) {
+__device__ __forceinline__ int axis_cell(double v, double o, double cs, int n, uint32_t &upper) {
     // floor((v - o) / cs) with an IEEE division, clamped to [0, n - 1]
     // (NaN -> 0).  Clamping is monotone, so pairs closer than cs still land
-    // in adjacent cells.
-    double f = floor((v - o) / cs);
+    // in adjacent cells.  upper: the position lies in the cell's upper half
+    // (ordering only; 0 where clamped).
+    const double t = (v - o) / cs;
+    const double f = floor(t);
+    upper = 0u;
     if (!(f >= 0.0)) return 0;
     if (f > (double)(n - 1)) return n - 1;
+    upper = t - f >= 0.5 ? 1u : 0u;
     return (int)f;
 }
 
@@ -39,11 +43,13 @@ struct EncodeArgs {
 
 __device__ __forceinline__ uint32_t encode_key(const EncodeArgs &e, const Inst &ip, int64_t i,
                                                uint32_t id) {
-    const int cx = axis_cell(e.x[i], ip.ox, ip.cs, ip.nx);
-    const int cy = axis_cell(e.y[i], ip.oy, ip.cs, ip.ny);
-    const int cz = axis_cell(e.z[i], ip.oz, ip.cs, ip.nz);
+    uint32_t ux, uy, uz;
+    const int cx = axis_cell(e.x[i], ip.ox, ip.cs, ip.nx, ux);
+    const int cy = axis_cell(e.y[i], ip.oy, ip.cs, ip.ny, uy);
+    const int cz = axis_cell(e.z[i], ip.oz, ip.cs, ip.nz, uz);
     const uint32_t lrow = (uint32_t)cz * (uint32_t)ip.ny + (uint32_t)cy;
-    return half_row_key(ip.cell_base, ip.nx, lrow, id >> 31) + (uint32_t)cx;
+    const uint32_t cell = half_row_key(ip.cell_base, ip.nx, lrow, id >> 31) + (uint32_t)cx;
+    return (cell << kSubBits) | (uy << 1) | ux;
 }
 
 // The keys of a thread's kItems particles (block-strided, 0 past n).  The
@@ -377,17 +383,24 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     }
 }
 
-int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st,
+// full: sort on every key bit; else on the cell key only (the sub-cell bits
+// keep the order of the input).  The sorted keys always end in w.keys(): the
+// first pass reads the keys from the buffer that makes the ping-pong end
+// there.
+int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st, bool full,
                 uint32_t **sorted_keys, uint32_t **perm) {
     const int64_t n = w.L.n;
     const int ntiles = (int)w.L.ntiles;
-    const int passes = w.L.key_bits <= 0 ? 1 : (w.L.key_bits + kRadixBits - 1) / kRadixBits;
+    const int low = full ? 0 : kSubBits;
+    const int bits = w.L.key_bits - low;
+    const int passes = bits <= 0 ? 1 : (bits + kRadixBits - 1) / kRadixBits;
     const bool small = sort_tile(n) == (int64_t)kSortThreads * kSortItemsSmall;
-    uint32_t *kin = w.keys(), *kout = w.keys_alt();
+    uint32_t *kin = (passes & 1) ? w.keys_alt() : w.keys();
+    uint32_t *kout = (passes & 1) ? w.keys() : w.keys_alt();
     uint32_t *vbuf[2] = {w.vals(), w.vals_alt()};
     uint32_t *vin = nullptr;  // first pass ranks the identity permutation
     for (int pass = 0; pass < passes; ++pass) {
-        const int shift = pass * kRadixBits;
+        const int shift = low + pass * kRadixBits;
         uint32_t *vout = vbuf[pass & 1];
         const EncodeArgs e{s.x, s.y, s.z, s.id, insts_of(P, w), kin};
         if (small) {
@@ -480,7 +493,7 @@ __global__ void k_reorder(ReorderArgs a) {
     a.uzm2[k] = a.uzm[src];
     a.id2[k] = id;
     const bool bnd = (id >> 31) != 0;
-    const uint32_t key = a.keys[k];
+    const uint32_t key = key_cell(a.keys[k]);
     const Inst ip = a.I.get(a.I.of_cell(key_row_cell(key)));
     if constexpr (kMixed) {
         const float dr = static_cast<const float *>(a.rho)[src];
@@ -565,7 +578,7 @@ int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *
 
 // ------------------------------------------------------------ cell table
 
-// start[k] = first sorted position whose key >= k, for k in [0, 2 ncells]
+// start[k] = first sorted position whose cell key >= k, for k in [0, 2 ncells]
 // (lower bound; an empty cell gets the start of the next one).  Cells x0..x1
 // of a half-row with key k0 at x = 0 hold the sorted range
 // [start[k0 + x0], start[k0 + x1 + 1]).  The search starts from the entry's
@@ -578,13 +591,13 @@ __global__ void k_cell_table(const uint32_t *__restrict__ keys, int64_t n, int64
     if (c > nkeys) return;
     const int64_t h = start[c] < (uint64_t)n ? (int64_t)start[c] : n;
     int64_t lo, hi;  // the answer lies in [lo, hi]
-    if (h < n && (int64_t)keys[h] < c) {
+    if (h < n && (int64_t)key_cell(keys[h]) < c) {
         lo = h + 1;
         hi = n;
         for (int64_t step = 1;; step <<= 1) {
             const int64_t q = h + step;
             if (q >= n) break;
-            if ((int64_t)keys[q] >= c) {
+            if ((int64_t)key_cell(keys[q]) >= c) {
                 hi = q;
                 break;
             }
@@ -596,7 +609,7 @@ __global__ void k_cell_table(const uint32_t *__restrict__ keys, int64_t n, int64
         for (int64_t step = 1;; step <<= 1) {
             const int64_t q = h - step;
             if (q < 0) break;
-            if ((int64_t)keys[q] < c) {
+            if ((int64_t)key_cell(keys[q]) < c) {
                 lo = q + 1;
                 break;
             }
@@ -605,7 +618,7 @@ __global__ void k_cell_table(const uint32_t *__restrict__ keys, int64_t n, int64
     }
     while (lo < hi) {
         const int64_t mid = lo + ((hi - lo) >> 1);
-        if ((int64_t)keys[mid] < c)
+        if ((int64_t)key_cell(keys[mid]) < c)
             lo = mid + 1;
         else
             hi = mid;

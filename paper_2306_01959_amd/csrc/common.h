@@ -101,8 +101,18 @@ __host__ __device__ __forceinline__ uint32_t half_row_key(uint32_t cell_base, ui
                                                           uint32_t lrow, uint32_t half) {
     return 2u * cell_base + (2u * lrow + half) * nx;
 }
-// a global cell of the key's row (enough to find the key's instance)
+// a global cell of the cell key's row (enough to find the key's instance)
 __host__ __device__ __forceinline__ uint32_t key_row_cell(uint32_t key) { return key >> 1; }
+
+// The sort key appends kSubBits to the cell key: the half of the cell the
+// particle lies in along y and along x.  Sorted on every bit, the particles
+// of a cell come in four columns of half the cell's width, so runs of 8
+// consecutive particles are compact (about 1.4 x 1.3 x 1.3 spacings on the
+// lattice instead of 3.3 x 1.6 x 0.2): more of a group's evaluated pairs lie
+// inside the support.  Steps between refreshes sort on the cell key alone
+// (stable, so the cells keep the order of the last full sort).
+constexpr int kSubBits = 2;
+__host__ __device__ __forceinline__ uint32_t key_cell(uint32_t key) { return key >> kSubBits; }
 
 // Device-side access to the instances: a table in the workspace (batches) or
 // a single instance passed by value.
@@ -162,7 +172,7 @@ struct WsLayout {
     int32_t key_bits = 0;
     int32_t precision = 0;
     size_t keys = 0, keys_alt = 0, vals = 0, vals_alt = 0;
-    size_t sorted_keys = 0;  // keys or keys_alt, whichever holds the sort output
+    size_t sorted_keys = 0;  // where the sort leaves the keys (keys)
     size_t hist = 0;         // (digit, tile) counts of a sort pass
     size_t hist_off = 0;     // their exclusive scan: first output slot per (digit, tile)
     size_t scan_tot = 0;     // span totals of a scan (counts of the sort, chunks per row)
@@ -217,7 +227,7 @@ int hip_check(hipError_t e, const char *what);
 int launch_check(const char *what);
 
 // Launchers implemented in the kernel translation units.
-int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st,
+int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st, bool full,
                 uint32_t **sorted_keys, uint32_t **perm);
 // exclusive scan of m values from `in` (left intact) to `out`; tot:
 // ceil(m / kScanSpan) values of scratch

@@ -49,7 +49,7 @@ struct InteractArgs {
     DevScalars *sc;
     InstState *ist;
     Insts I;
-    const uint32_t *keys;        // sorted half-row cell keys
+    const uint32_t *keys;        // sorted keys (cell key, sub-cell bits)
     const uint32_t *cell_start;  // first sorted position of every key, 2 ncells + 1
     const void *v0, *v1, *v2;    // interaction view
     void *ax, *ay, *az, *drho, *mumax;
@@ -178,7 +178,7 @@ struct Mixed {
             v0 = static_cast<const float4 *>(a.v0)[i];
             v1 = static_cast<const float4 *>(a.v1)[i];
             v2 = static_cast<const float2 *>(a.v2)[i];
-            cix = (int)a.keys[i] - rowbase;
+            cix = (int)key_cell(a.keys[i]) - rowbase;
         }
         fi = act && v2.y > 0.f;
         t0 = make_float4(v0.x, v0.y, v0.z, (float)cix);
@@ -198,7 +198,7 @@ struct Mixed {
         c.v0 = static_cast<const float4 *>(a.v0)[jj];
         c.v1 = static_cast<const float4 *>(a.v1)[jj];
         c.v2 = static_cast<const float2 *>(a.v2)[jj];
-        c.key = a.keys[jj];
+        c.key = key_cell(a.keys[jj]);
     }
     // position of a candidate in the chunk frame (cell cxa of the chunk's
     // row), for culling only; nbase = key of cell x = 0 of its half-row
@@ -653,8 +653,8 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     const Inst ip = a.I.get(inst);
     const int ntgt = cs1 - cs0;
     const int rowbase = (int)half_row_key(ip.cell_base, ip.nx, lh >> 1, lh & 1);
-    const int cxa = uni((int)a.keys[cs0] - rowbase);
-    const int cxb = uni((int)a.keys[cs1 - 1] - rowbase);
+    const int cxa = uni((int)key_cell(a.keys[cs0]) - rowbase);
+    const int cxb = uni((int)key_cell(a.keys[cs1 - 1]) - rowbase);
 
     // targets (lane = target index in the chunk) and their group boxes
     const int it = cs0 + lane;
@@ -951,8 +951,8 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
         const Inst ip = a.I.get(inst);
         const int ntgt = cs1 - cs0;
         const int rowbase = (int)half_row_key(ip.cell_base, ip.nx, lh >> 1, lh & 1);
-        const int cxa = uni((int)a.keys[cs0] - rowbase);
-        const int cxb = uni((int)a.keys[cs1 - 1] - rowbase);
+        const int cxa = uni((int)key_cell(a.keys[cs0]) - rowbase);
+        const int cxb = uni((int)key_cell(a.keys[cs1 - 1]) - rowbase);
 
         // the target of this lane (every slot lane of target t loads it)
         const int it = cs0 + t_in;
@@ -1132,8 +1132,8 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
     const int cs0 = uni(ch.x), cs1 = uni(ch.y), lh = uni(ch.z), inst = uni(ch.w);
     const Inst ip = a.I.get(inst);
     const int rowbase = (int)half_row_key(ip.cell_base, ip.nx, lh >> 1, lh & 1);
-    const int cxa = uni((int)a.keys[cs0] - rowbase);
-    const int cxb = uni((int)a.keys[cs1 - 1] - rowbase);
+    const int cxa = uni((int)key_cell(a.keys[cs0]) - rowbase);
+    const int cxb = uni((int)key_cell(a.keys[cs1 - 1]) - rowbase);
     const int g0 = cs0 + w * kT;                    // this wave's first target
     const int ntgt = uni(cs1 - g0 < 0 ? 0 : (cs1 - g0 > kT ? kT : cs1 - g0));
     const int t_in = lane % kT;

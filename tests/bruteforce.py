@@ -38,6 +38,15 @@ def cell_coords(v, o: float, cs: float, n: int) -> np.ndarray:
     return np.clip(f, 0, n - 1).astype(np.int64)
 
 
+def upper_half(v, o: float, cs: float, n: int) -> np.ndarray:
+    """1 where the position lies in the upper half of its (unclamped) cell
+    along this axis, 0 elsewhere and where the cell index is clamped."""
+    t = (np.asarray(v, np.float64) - o) / cs
+    f = np.floor(t)
+    ok = (f >= 0) & (f <= n - 1)
+    return (ok & (t - f >= 0.5)).astype(np.int64)
+
+
 def cells_and_offsets(x, y, z, origin: Sequence[float], cs: float,
                       dims: Sequence[int]):
     cs_ = float(cs)

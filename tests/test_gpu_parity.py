@@ -48,8 +48,25 @@ def _sim(gpu, sc, precision, prev=None, **kw):
 
 # ---------------------------------------------------------------- cells
 
+def _sort_keys(sc_or_xyz, prm, isb, full):
+    """The library's sort key from FP64 positions: cell row, class, cell x,
+    then (full) the upper-half flags along y and x."""
+    x, y, z = sc_or_xyz
+    (cx, cy, cz), _ = bruteforce.cells_and_offsets(x, y, z, prm["origin"], prm["cell_size"],
+                                                   prm["dims"])
+    nx, ny = prm["dims"][0], prm["dims"][1]
+    key = (2 * (cy + ny * cz) + isb) * nx + cx
+    if not full:
+        return key
+    ux = bruteforce.upper_half(x, prm["origin"][0], prm["cell_size"], prm["dims"][0])
+    uy = bruteforce.upper_half(y, prm["origin"][1], prm["cell_size"], prm["dims"][1])
+    return key * 4 + uy * 2 + ux
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_build_cells_invariants(gpu, precision):
+    """sph_build_cells sorts on the full key (cell row, class, cell x, the
+    halves of the cell along y and x), stably."""
     s = scene.config_scene(1)
     sim = _sim(gpu, s, precision)
     sim.build_cells()
@@ -59,34 +76,42 @@ def test_build_cells_invariants(gpu, precision):
     x = sim._cur("x").cpu().numpy()
     y = sim._cur("y").cpu().numpy()
     z = sim._cur("z").cpu().numpy()
-    prm = s.params
-    (cx, cy, cz), _ = bruteforce.cells_and_offsets(x, y, z, prm["origin"], prm["cell_size"],
-                                                   prm["dims"])
-    nx, ny = prm["dims"][0], prm["dims"][1]
-    # cell row, then fluid before boundary, then cell x
-    key = (2 * (cy + ny * cz) + s.is_boundary[ids]) * nx + cx
+    key = _sort_keys((x, y, z), s.params, s.is_boundary[ids], True)
     assert np.all(np.diff(key) >= 0)
-    # stable: inside a cell's fluid or boundary particles the original order is kept
+    # stable: particles with equal keys keep the original order
     same = np.diff(key) == 0
     assert np.all(np.diff(ids)[same] > 0)
     # positions travelled with their ids
     assert np.array_equal(x, s.x[ids]) and np.array_equal(z, s.z[ids])
 
 
+def test_step_between_refreshes_sorts_cells_only(gpu):
+    """A step whose index is not a multiple of the refresh period sorts on the
+    cell key alone: cells in order, and inside a cell the previous order."""
+    s = scene.config_scene(1)
+    sim = _sim(gpu, s, "fp64")
+    sim.run(1, 1e-5, 1)  # step 1: cells of the uploaded (id) order
+    ids = sim.ids()
+    assert np.array_equal(np.sort(ids), np.arange(s.n))
+    key = _sort_keys((s.x[ids], s.y[ids], s.z[ids]), s.params, s.is_boundary[ids], False)
+    assert np.all(np.diff(key) >= 0)
+    same = np.diff(key) == 0
+    assert np.all(np.diff(ids)[same] > 0)
+    # and not by the sub-cell bits (the scene's lattice order is not theirs)
+    full = _sort_keys((s.x[ids], s.y[ids], s.z[ids]), s.params, s.is_boundary[ids], True)
+    assert not np.all(np.diff(full) >= 0)
+
+
 def test_build_cells_large_sort(gpu):
     """700k particles: the counts scan of the radix sort runs on many spans
     in parallel (not one block); the order must still be the stable sort by
-    (cell row, boundary flag, cell x)."""
+    the full key."""
     sc = scene.random_cloud(700_000, 3, dp=0.002, box=0.2)
     sim = _sim(gpu, sc, "mixed")
     sim.build_cells()
     sim.sync()
     ids = sim.ids()
-    prm = sc.params
-    (cx, cy, cz), _ = bruteforce.cells_and_offsets(sc.x, sc.y, sc.z, prm["origin"],
-                                                   prm["cell_size"], prm["dims"])
-    nx, ny = prm["dims"][0], prm["dims"][1]
-    key = (2 * (cy + ny * cz) + sc.is_boundary) * nx + cx
+    key = _sort_keys((sc.x, sc.y, sc.z), sc.params, sc.is_boundary, True)
     assert np.array_equal(ids, np.argsort(key, kind="stable"))
 
 
