@@ -38,6 +38,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "common.h"
 #include "update.h"
@@ -121,6 +122,10 @@ struct Acc {
 };
 
 // Wave-uniform pair counters, and per-lane neighbour statistics of a group.
+// Target classes a pair body may be specialised for: a chunk is one
+// half-row, so all its targets are fluid or all boundary.
+constexpr int kAnyTargets = 0, kFluidTargets = 1, kBoundaryTargets = 2;
+
 // Pair counts, per lane: pairs inside the support, and those of them with a
 // fluid j.  A chunk's targets are all fluid or all boundary (one half-row),
 // so the wave totals split into the three classes by the chunk's class alone.
@@ -155,7 +160,7 @@ struct Mixed {
     using V4 = float4;
     static constexpr bool kMixed = true;
     // target: {o_x, o_y, o_z, own cell x}, {u, P}, {1/rho (0 for boundary),
-    // rho - rho0, |c|, -}
+    // rho - rho0, -alpha |c|, -}
     struct T {
         float4 a, b, c;
         __device__ bool fluid() const { return c.x > 0.f; }
@@ -183,7 +188,7 @@ struct Mixed {
         fi = act && v2.y > 0.f;
         t0 = make_float4(v0.x, v0.y, v0.z, (float)cix);
         t1 = v1;
-        t2 = make_float4(fi ? v2.x : 0.f, v0.w, fabsf(v2.y), 0.f);
+        t2 = make_float4(fi ? v2.x : 0.f, v0.w, -(float)ip.alpha * fabsf(v2.y), 0.f);
         const float csf = (float)ip.cs;
         bx = v0.x + (float)(cix - cxa) * csf;
         by = v0.y;
@@ -219,7 +224,7 @@ struct Mixed {
     __device__ static bool rec_fluid(const float4 &r3) { return r3.y > 0.f; }
     // record: {o_x, c_x, o_y + dy cs, o_z + dz cs}, {u, P/rho}, {-, 1/rho,
     // (rho - rho0) B, B} with B = 2 delta h c0 / rho (0 when the pair carries
-    // no delta term), {rho - rho0, +-c (- = boundary), index bits, -}
+    // no delta term), {rho - rho0, +-c (- = boundary), index bits, -alpha |c|}
     __device__ static void stage(const InteractArgs &a, const Inst &ip, const Cand &c, int nbase,
                                  int j, int dy, int dz, float4 *rec0, float4 *rec1, float4 *rec2,
                                  float4 *rec3) {
@@ -232,15 +237,16 @@ struct Mixed {
                             c.v0.z + (float)dz * csf);
         *rec1 = make_float4(c.v1.x, c.v1.y, c.v1.z, c.v1.w * invr);
         *rec2 = make_float4(0.f, invr, c.v0.w * B, B);
-        *rec3 = make_float4(c.v0.w, c.v2.y, __int_as_float(j), 0.f);
+        *rec3 = make_float4(c.v0.w, c.v2.y, __int_as_float(j), -(float)ip.alpha * fabsf(c.v2.y));
     }
-    // one (target, record) pair; `valid` is false for idle lanes
-    template <bool kStats>
+    // one (target, record) pair; `valid` is false for idle lanes; kCls: the
+    // class of every target (kAnyTargets: read per target)
+    template <bool kStats, int kCls = kAnyTargets>
     __device__ static void pair(const InteractArgs &a, const Inst &ip, const T &t, int ti, bool valid,
                                 const float4 &r0, const float4 &r1, const float4 &r2,
                                 const float4 &r3, Acc<float> &acc, Counters &cn, Stats &st) {
         const float csf = (float)ip.cs;
-        const bool fi = t.fluid();
+        const bool fi = kCls == kFluidTargets ? true : kCls == kBoundaryTargets ? false : t.fluid();
         const bool fj = r3.y > 0.f;
         const float sx = fmaf(r0.y - t.a.w, csf, r0.x);
         const float dx = sx - t.a.x;
@@ -266,6 +272,14 @@ struct Mixed {
         const float F = in ? Fr : 0.f;
         const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const float vr = vx * dx + vy * dy + vz * dz;               // u_ij . r_ij
+        if constexpr (kCls == kBoundaryTargets) {
+            // continuity over fluid j, and |mu| for the time step; nothing else
+            const float mu = (float)ip.h * vr * __builtin_amdgcn_rcpf(rr + (float)ip.eta2);
+            const float amu = in ? fabsf(mu) : 0.f;
+            acc.mu = amu > acc.mu ? amu : acc.mu;
+            acc.dr -= F * vr;
+            return;
+        }
         // one reciprocal for mu = h vr / (r^2 + eta^2) and the viscosity's
         // mu / (rho_i + rho_j): hvi = h vr / ((r^2 + eta^2)(rho_i + rho_j))
         const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r3.x;  // rho_i + rho_j
@@ -274,9 +288,9 @@ struct Mixed {
         const float amu = in ? fabsf(mu) : 0.f;
         acc.mu = amu > acc.mu ? amu : acc.mu;
         acc.dr -= F * vr;                                    // m (u_i - u_j) . grad_i W_ij
-        const float Fd = fi ? F : 0.f;
+        const float Fd = kCls == kFluidTargets ? F : fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;             // delta term
-        const float visc = vr < 0.f ? -(float)ip.alpha * (t.c.z + fabsf(r3.y)) * hvi : 0.f;
+        const float visc = vr < 0.f ? (t.c.z + r3.w) * hvi : 0.f;  // -alpha (c_i + c_j) hvi
         const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -326,7 +340,7 @@ struct Mixed {
         acc.dr -= F * vr;
         const float Fd = fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;
-        const float visc = vr < 0.f ? -(float)ip.alpha * (t.c.z + fabsf(r3.y)) * hvi : 0.f;
+        const float visc = vr < 0.f ? (t.c.z + r3.w) * hvi : 0.f;  // -alpha (c_i + c_j) hvi
         const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -365,7 +379,7 @@ struct Fp64 {
     using R = double;
     using V4 = double4;
     static constexpr bool kMixed = false;
-    // target: {x, y, z, -}, {u, P}, {1/rho (0 for boundary), rho, |c|, -}
+    // target: {x, y, z, -}, {u, P}, {1/rho (0 for boundary), rho, -alpha |c|, -}
     struct T {
         double4 a, b, c;
         __device__ bool fluid() const { return c.x > 0.0; }
@@ -390,7 +404,7 @@ struct Fp64 {
         fi = act && v2.y > 0.0;
         t0 = make_double4(v0.x, v0.y, v0.z, 0.0);
         t1 = v1;
-        t2 = make_double4(fi ? v2.x : 0.0, v0.w, fabs(v2.y), 0.0);
+        t2 = make_double4(fi ? v2.x : 0.0, v0.w, -ip.alpha * fabs(v2.y), 0.0);
         bx = v0.x;
         by = v0.y;
         bz = v0.z;
@@ -423,7 +437,7 @@ struct Fp64 {
     }
     __device__ static bool cand_fluid(const Cand &c) { return c.v2.y > 0.0; }
     __device__ static bool rec_fluid(const double4 &r3) { return r3.y > 0.0; }
-    // record: {x, y, z, index}, {u, P/rho}, {1/rho, B, rho, -}, {-, +-c, -, -}
+    // record: {x, y, z, index}, {u, P/rho}, {1/rho, B, rho, -}, {-, +-c, -, -alpha |c|}
     __device__ static void stage(const InteractArgs &a, const Inst &ip, const Cand &c, int nbase,
                                  int j, int dy, int dz, double4 *rec0, double4 *rec1, double4 *rec2,
                                  double4 *rec3) {
@@ -436,13 +450,13 @@ struct Fp64 {
         *rec0 = make_double4(c.v0.x, c.v0.y, c.v0.z, (double)j);
         *rec1 = make_double4(c.v1.x, c.v1.y, c.v1.z, c.v1.w * invr);
         *rec2 = make_double4(invr, B, c.v0.w, 0.0);
-        *rec3 = make_double4(0.0, c.v2.y, 0.0, 0.0);
+        *rec3 = make_double4(0.0, c.v2.y, 0.0, -ip.alpha * fabs(c.v2.y));
     }
-    template <bool kStats>
+    template <bool kStats, int kCls = kAnyTargets>
     __device__ static void pair(const InteractArgs &a, const Inst &ip, const T &t, int ti, bool valid,
                                 const double4 &r0, const double4 &r1, const double4 &r2,
                                 const double4 &r3, Acc<double> &acc, Counters &cn, Stats &st) {
-        const bool fi = t.fluid();
+        const bool fi = kCls == kFluidTargets ? true : kCls == kBoundaryTargets ? false : t.fluid();
         const bool fj = r3.y > 0.0;
         const double dx = r0.x - t.a.x, dy = r0.y - t.a.y, dz = r0.z - t.a.z;
         const double rr = sq_sum_f64(dx, dy, dz);
@@ -464,6 +478,14 @@ struct Fp64 {
         const double F = in ? Fr : 0.0;
         const double vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const double vr = vx * dx + vy * dy + vz * dz;
+        if constexpr (kCls == kBoundaryTargets) {
+            // continuity over fluid j, and |mu| for the time step; nothing else
+            const double mu = ip.h * vr / (rr + ip.eta2);
+            const double amu = in ? fabs(mu) : 0.0;
+            acc.mu = amu > acc.mu ? amu : acc.mu;
+            acc.dr -= F * vr;
+            return;
+        }
         // one division for mu = h vr / (r^2 + eta^2) and the viscosity's
         // mu / (rho_i + rho_j)
         const double rsum = t.c.y + r2.z;  // rho_i + rho_j
@@ -472,9 +494,9 @@ struct Fp64 {
         const double amu = in ? fabs(mu) : 0.0;
         acc.mu = amu > acc.mu ? amu : acc.mu;
         acc.dr -= F * vr;
-        const double Fd = fi ? F : 0.0;
+        const double Fd = kCls == kFluidTargets ? F : fi ? F : 0.0;
         acc.dr += (r2.z - t.c.y) * r2.y * Fd;
-        const double visc = vr < 0.0 ? -ip.alpha * (t.c.z + fabs(r3.y)) * hvi : 0.0;
+        const double visc = vr < 0.0 ? (t.c.z + r3.w) * hvi : 0.0;  // -alpha (c_i + c_j) hvi
         const double s = (fma(t.b.w, r2.x, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -512,7 +534,7 @@ struct Fp64 {
         acc.dr -= F * vr;
         const double Fd = fi ? F : 0.0;
         acc.dr += (r2.z - t.c.y) * r2.y * Fd;
-        const double visc = vr < 0.0 ? -ip.alpha * (t.c.z + fabs(r3.y)) * hvi : 0.0;
+        const double visc = vr < 0.0 ? (t.c.z + r3.w) * hvi : 0.0;  // -alpha (c_i + c_j) hvi
         const double s = (fma(t.b.w, r2.x, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -770,6 +792,8 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
                 tg.c = tgt[2][tidx];
                 const int ti = cs0 + tidx;
                 const int gn = gcnt[g];
+                // (one pair body for both target classes: two would cost this
+                // kernel's occupancy)
                 pair_steps<V4, kG, false>(
                     gn, slot_s, [&](int sl) { return sl < gn ? (int)glist[w][g][sl] : 0; },
                     [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
@@ -998,18 +1022,24 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
         auto flush = [&]() __attribute__((always_inline)) {
             wave_sync();
             const int cnt = nst;
-            pair_steps<V4, kG, P::kMixed>(
-                cnt, slot_s, [&](int sl) { return sl < cnt ? sl : 0; },
-                [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
-                    r0 = stg[0][k];
-                    r1 = stg[1][k];
-                    r2 = stg[2][k];
-                    r3 = stg[3][k];
-                },
-                [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
-                    P::template pair<kStats>(a, ip, tg, it, sl < cnt && act, r0, r1, r2, r3, acc,
-                                             cn, sts);
-                });
+            auto steps = [&](auto cls) __attribute__((always_inline)) {
+                pair_steps<V4, kG, P::kMixed>(
+                    cnt, slot_s, [&](int sl) { return sl < cnt ? sl : 0; },
+                    [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
+                        r0 = stg[0][k];
+                        r1 = stg[1][k];
+                        r2 = stg[2][k];
+                        r3 = stg[3][k];
+                    },
+                    [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
+                        P::template pair<kStats, decltype(cls)::value>(
+                            a, ip, tg, it, sl < cnt && act, r0, r1, r2, r3, acc, cn, sts);
+                    });
+            };
+            if (any_fluid)
+                steps(std::integral_constant<int, kFluidTargets>{});
+            else
+                steps(std::integral_constant<int, kBoundaryTargets>{});
             wave_sync();
             nst = 0;
         };
@@ -1295,18 +1325,24 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
             } else {
                 // idle lanes read a record staged in this batch (entry 0):
                 // their terms are multiplied by zero and must stay finite
-                pair_steps<V4, kG, true>(
-                    n, slot_s, [&](int sl) { return (int)glist[w][sl < n ? sl : 0]; },
-                    [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
-                        r0 = pool[buf][0][k];
-                        r1 = pool[buf][1][k];
-                        r2 = pool[buf][2][k];
-                        r3 = pool[buf][3][k];
-                    },
-                    [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
-                        P::template pair<kStats>(a, ip, tg, it, sl < n && act, r0, r1, r2, r3,
-                                                 acc, cn, sts);
-                    });
+                auto steps = [&](auto cls) __attribute__((always_inline)) {
+                    pair_steps<V4, kG, true>(
+                        n, slot_s, [&](int sl) { return (int)glist[w][sl < n ? sl : 0]; },
+                        [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
+                            r0 = pool[buf][0][k];
+                            r1 = pool[buf][1][k];
+                            r2 = pool[buf][2][k];
+                            r3 = pool[buf][3][k];
+                        },
+                        [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
+                            P::template pair<kStats, decltype(cls)::value>(
+                                a, ip, tg, it, sl < n && act, r0, r1, r2, r3, acc, cn, sts);
+                        });
+                };
+                if (any_fluid)
+                    steps(std::integral_constant<int, kFluidTargets>{});
+                else
+                    steps(std::integral_constant<int, kBoundaryTargets>{});
             }
             wave_sync();
         }
