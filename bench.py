@@ -234,8 +234,11 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False):
         step += 21
     assert all(d["n_nonfinite"] == 0 for d in d1), "non-finite state"
     n = ens.n
-    key_bits = int(np.ceil(np.log2(sum(int(np.prod(s.params["dims"])) for s in scenes))))
-    passes = max(1, (key_bits + 7) // 8)
+    # sort key: 2 x (cells) keys of the cell list plus 2 sub-cell bits; the
+    # sub-cell bits are sorted only once per graph period, the passes below
+    # are those of the other steps
+    key_bits = int(np.ceil(np.log2(2 * sum(int(np.prod(s.params["dims"])) for s in scenes)))) + 2
+    passes = max(1, (key_bits - 2 + 7) // 8)
     sort_bytes = n * (SORT_BYTES_FIRST + SORT_BYTES_PASS * (passes - 1))
     reorder_bytes = n * REORDER_BYTES
     pairs = [(d1[0][k] - d0[0][k]) / steps for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
