@@ -176,7 +176,9 @@ struct Mixed {
     __device__ static void target(const InteractArgs &a, const Inst &ip, int i, bool act, int rowbase, int cxa,
                                   V4 &t0, V4 &t1, V4 &t2, float &bx, float &by, float &bz,
                                   bool &fi) {
-        float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
+        // an absent target sits far away (+1e15 m): no record is within its
+        // support, not even a sentinel (which sits at -1e15 m)
+        float4 v0 = make_float4(1e15f, 1e15f, 1e15f, 0.f), v1 = make_float4(0.f, 0.f, 0.f, 0.f);
         float2 v2 = make_float2(1.f, 1.f);
         int cix = cxa;
         if (act) {
@@ -222,6 +224,14 @@ struct Mixed {
     }
     __device__ static bool cand_fluid(const Cand &c) { return c.v2.y > 0.f; }
     __device__ static bool rec_fluid(const float4 &r3) { return r3.y > 0.f; }
+    // a record that lies outside every target's support (at -1e15 m; every
+    // term stays finite and is zeroed through F)
+    __device__ static void sentinel(float4 *rec0, float4 *rec1, float4 *rec2, float4 *rec3) {
+        *rec0 = make_float4(-1e15f, 0.f, -1e15f, -1e15f);
+        *rec1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        *rec2 = *rec1;
+        *rec3 = *rec1;
+    }
     // record: {o_x, c_x, o_y + dy cs, o_z + dz cs}, {u, P/rho}, {-, 1/rho,
     // (rho - rho0) B, B} with B = 2 delta h c0 / rho (0 when the pair carries
     // no delta term), {rho - rho0, +-c (- = boundary), index bits, -alpha |c|}
@@ -394,7 +404,8 @@ struct Fp64 {
                                   bool &fi) {
         (void)rowbase;
         (void)cxa;
-        double4 v0 = make_double4(0, 0, 0, 1), v1 = make_double4(0, 0, 0, 0);
+        // absent target far away (+1e150 m), sentinels at -1e150 m
+        double4 v0 = make_double4(1e150, 1e150, 1e150, 1), v1 = make_double4(0, 0, 0, 0);
         double2 v2 = make_double2(1, 1);
         if (act) {
             v0 = static_cast<const double4 *>(a.v0)[i];
@@ -437,6 +448,12 @@ struct Fp64 {
     }
     __device__ static bool cand_fluid(const Cand &c) { return c.v2.y > 0.0; }
     __device__ static bool rec_fluid(const double4 &r3) { return r3.y > 0.0; }
+    __device__ static void sentinel(double4 *rec0, double4 *rec1, double4 *rec2, double4 *rec3) {
+        *rec0 = make_double4(-1e150, -1e150, -1e150, -1.0);
+        *rec1 = make_double4(0.0, 0.0, 0.0, 0.0);
+        *rec2 = *rec1;
+        *rec3 = *rec1;
+    }
     // record: {x, y, z, index}, {u, P/rho}, {1/rho, B, rho, -}, {-, +-c, -, -alpha |c|}
     __device__ static void stage(const InteractArgs &a, const Inst &ip, const Cand &c, int nbase,
                                  int j, int dy, int dz, double4 *rec0, double4 *rec1, double4 *rec2,
@@ -959,10 +976,15 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
     // part-filled pair steps); the FP64 records are twice as large and stay
     // at one batch (more LDS would cost occupancy)
     constexpr int kCap = P::kMixed ? 2 * kWave : kWave;
-    __shared__ V4 stg_all[kWavesPerGroupWG][4][kCap];
+    // mixed: up to kG sentinel records after the staged ones, so the last
+    // pair step of a flush reads them instead of testing its slot index (the
+    // FP64 form keeps the slot test: its registers are at their limit)
+    constexpr bool kSentinel = P::kMixed;
+    constexpr int kSlots = kCap + (kSentinel ? kG : 0);
+    __shared__ V4 stg_all[kWavesPerGroupWG][4][kSlots];
     const int w = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    V4(*stg)[kCap] = stg_all[w];
+    V4(*stg)[kSlots] = stg_all[w];
     const int t_in = lane % kT;
     const int slot_s = lane / kT;
     const uint64_t below = lanes_below();
@@ -1020,11 +1042,19 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
         int nst = 0;  // records staged and not yet evaluated
         // the pairs of the staged records (slots [0, nst)), then an empty stage
         auto flush = [&]() __attribute__((always_inline)) {
-            wave_sync();
             const int cnt = nst;
+            if constexpr (kSentinel) {
+                if (lane < kG)
+                    P::sentinel(&stg[0][cnt + lane], &stg[1][cnt + lane], &stg[2][cnt + lane],
+                                &stg[3][cnt + lane]);
+            }
+            wave_sync();
+            // with sentinels every slot of a step is a staged record or a
+            // sentinel, and an absent target lies far away: no slot or
+            // target test per pair
             auto steps = [&](auto cls) __attribute__((always_inline)) {
                 pair_steps<V4, kG, P::kMixed>(
-                    cnt, slot_s, [&](int sl) { return sl < cnt ? sl : 0; },
+                    cnt, slot_s, [&](int sl) { return kSentinel || sl < cnt ? sl : 0; },
                     [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
                         r0 = stg[0][k];
                         r1 = stg[1][k];
@@ -1033,7 +1063,8 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
                     },
                     [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
                         P::template pair<kStats, decltype(cls)::value>(
-                            a, ip, tg, it, sl < cnt && act, r0, r1, r2, r3, acc, cn, sts);
+                            a, ip, tg, it, kSentinel || (sl < cnt && act), r0, r1, r2, r3, acc,
+                            cn, sts);
                     });
             };
             if (any_fluid)
