@@ -659,10 +659,14 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
     using V4 = typename P::V4;
     constexpr int kRows = 2 * (9 / kSplit);  // candidate ranges per wave
     constexpr int kG = kWave / kT;  // target groups per chunk = records per step
-    __shared__ V4 stg[kSplit][4][kWave];          // staged candidate records (per wave)
-    __shared__ V4 tgt[3][kWave];                  // the chunk's targets
-    __shared__ R gbox[kG][6];                     // group bounding boxes, chunk frame
-    __shared__ uint8_t glist[kSplit][kG][kWave];  // per group: staged records that reach it
+    // mixed: record slot kWave holds a sentinel (a record outside every
+    // support) and each group's list is padded with it up to a whole pair
+    // step, so a step tests neither its slot nor its target
+    constexpr bool kSentinel = P::kMixed;
+    __shared__ V4 stg[kSplit][4][kWave + 1];           // staged candidate records (per wave)
+    __shared__ V4 tgt[3][kWave];                       // the chunk's targets
+    __shared__ R gbox[kG][6];                          // group bounding boxes, chunk frame
+    __shared__ uint8_t glist[kSplit][kG][kWave + kG];  // per group: staged records that reach it
     __shared__ int4 rows[kSplit][kRows];
     // after its loop a wave reuses its own staging region for its per-target
     // sums (5 values of R and 3 int32 per target fit in 4 V4 per lane)
@@ -738,7 +742,11 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
         stencil_range(a, ip, w * kRows + lane, lh, cxa, cxb, js, je, hb, code);
         rows[w][lane] = make_int4(js, je, hb, code);
     }
-    __syncthreads();  // targets, group boxes and rows are in LDS
+    if constexpr (kSentinel) {
+        if (lane == 0) P::sentinel(&stg[w][0][kWave], &stg[w][1][kWave], &stg[w][2][kWave],
+                                   &stg[w][3][kWave]);
+    }
+    __syncthreads();  // targets, group boxes, rows (and the sentinel) are in LDS
 
     auto next_row = [&](int q) {
         while (q < kRows && rows[w][q].x >= rows[w][q].y) ++q;
@@ -797,6 +805,9 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
                 const uint64_t gm = __ballot(k);
                 if (k) glist[w][g][__popcll(gm & below)] = (uint8_t)lane;
                 gcnt[g] = __popcll(gm);
+                if constexpr (kSentinel) {
+                    if (lane < kG) glist[w][g][gcnt[g] + lane] = (uint8_t)kWave;
+                }
             }
             wave_sync();
 #pragma unroll
@@ -812,7 +823,8 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
                 // (one pair body for both target classes: two would cost this
                 // kernel's occupancy)
                 pair_steps<V4, kG, false>(
-                    gn, slot_s, [&](int sl) { return sl < gn ? (int)glist[w][g][sl] : 0; },
+                    gn, slot_s,
+                    [&](int sl) { return kSentinel || sl < gn ? (int)glist[w][g][sl] : 0; },
                     [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
                         r0 = stg[w][0][k];
                         r1 = stg[w][1][k];
@@ -820,7 +832,8 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
                         r3 = stg[w][3][k];
                     },
                     [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
-                        P::template pair<kStats>(a, ip, tg, ti, sl < gn && tidx < ntgt, r0, r1,
+                        P::template pair<kStats>(a, ip, tg, ti,
+                                                 kSentinel || (sl < gn && tidx < ntgt), r0, r1,
                                                  r2, r3, acc[g], cn, sts[g]);
                     });
             }
