@@ -54,6 +54,7 @@ WsLayout make_layout(const Problem &P) {
     };
     L.keys = take(4 * (size_t)n);
     L.keys_alt = take(4 * (size_t)n);
+    L.keys_next = take(4 * (size_t)n);
     L.vals = take(4 * (size_t)n);
     L.vals_alt = take(4 * (size_t)n);
     L.sorted_keys = L.keys;
@@ -281,14 +282,16 @@ struct Marks {
 };
 
 // full: sort on the sub-cell bits too (see kSubBits); the steps between
-// refreshes sort on the cell key alone.
+// refreshes sort on the cell key alone.  keys_ready: the previous update of
+// this same run wrote the keys of the current positions (else they are
+// computed from the positions here).
 static int build_cells(const Problem &P, sph_state &s, const Ws &w, hipStream_t st,
                        bool lagged = false, double dt = 0.0, const Marks &m = Marks(),
-                       bool full = true) {
+                       bool full = true, bool keys_ready = false) {
     if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
     uint32_t *keys = nullptr, *perm = nullptr;
     if (int rc = m.at(SPH_REGION_SORT, true, st)) return rc;
-    if (int rc = launch_sort(P, s, w, st, full, &keys, &perm)) return rc;  // keys included
+    if (int rc = launch_sort(P, s, w, st, full, keys_ready, &keys, &perm)) return rc;
     if (int rc = m.at(SPH_REGION_SORT, false, st)) return rc;
     if (int rc = m.at(SPH_REGION_REORDER, true, st)) return rc;
     if (int rc = launch_reorder(P, s, w, keys, perm, st)) return rc;
@@ -312,10 +315,10 @@ static int64_t refresh_period(const Problem &P) {
 // One step.  fused: the lagged-dt form, where the interaction also advances
 // the state (one kernel instead of interaction + update).
 static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
-                    bool fused, hipStream_t st, const Marks &m = Marks()) {
+                    bool fused, hipStream_t st, const Marks &m = Marks(), bool keys_ready = false) {
     if (!s.cells_valid) {
         const bool full = step % refresh_period(P) == 0;
-        if (int rc = build_cells(P, s, w, st, fused, dt, m, full)) return rc;
+        if (int rc = build_cells(P, s, w, st, fused, dt, m, full, keys_ready)) return rc;
     } else {
         if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
         if (int rc = launch_chunks(P, w, fused, dt, st)) return rc;  // fresh dt bound
@@ -373,8 +376,12 @@ static int graph_steps(const Problem &P, sph_state &s, const Ws &w, double dt, i
     if (int rc = hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed), "capture"))
         return rc;
     int rc = SPH_OK;
+    // the first captured step computes its keys from the positions (a replay
+    // may follow anything); the later ones take those of the update before,
+    // unless that was a fused step, which writes none
     for (int64_t k = 0; k < len && rc == SPH_OK; ++k)
-        rc = one_step(P, s, w, dt, step + k, lagged && step + k > 0, st);
+        rc = one_step(P, s, w, dt, step + k, lagged && step + k > 0, st, Marks(),
+                      k > 0 && !(lagged && step + k - 1 > 0));
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(st, &g);
     if (rc == SPH_OK) rc = hip_check(ec, "end capture");
@@ -403,6 +410,10 @@ static int run_steps(const Problem &P, sph_state &s, const Ws &w, int64_t nsteps
     const bool lagged = (mode & SPH_RUN_LAGGED) != 0;
     const int64_t L = (mode & SPH_RUN_GRAPH) ? graph_period(P) : 0;
     int64_t k = 0;
+    // the first step of a call computes its keys from the positions (the
+    // caller may have moved particles); later steps take the keys the
+    // previous step's update wrote (a fused step writes none)
+    bool keys_ready = false;
     while (k < nsteps) {
         const int64_t idx = step0 + k;
         if (L > 0 && idx > 0 && idx % L == 0 && nsteps - k >= L && !ev_begin) {
@@ -410,6 +421,7 @@ static int run_steps(const Problem &P, sph_state &s, const Ws &w, int64_t nsteps
             s.cells_valid = 0;  // every captured step rebuilds its cells
             if (int rc = graph_steps(P, s, w, dt, idx, L, reps, lagged, st)) return rc;
             k += reps * L;
+            keys_ready = !lagged;
             continue;
         }
         Marks m;
@@ -418,7 +430,8 @@ static int run_steps(const Problem &P, sph_state &s, const Ws &w, int64_t nsteps
             m.e0 = static_cast<hipEvent_t>(ev_begin[k]);
             m.e1 = static_cast<hipEvent_t>(ev_end[k]);
         }
-        if (int rc = one_step(P, s, w, dt, idx, lagged && idx > 0, st, m)) return rc;
+        if (int rc = one_step(P, s, w, dt, idx, lagged && idx > 0, st, m, keys_ready)) return rc;
+        keys_ready = !(lagged && idx > 0);
         ++k;
     }
     return SPH_OK;

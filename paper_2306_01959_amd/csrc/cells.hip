@@ -16,19 +16,6 @@ namespace wcsph {
 
 // ---------------------------------------------------------------- encode
 
-__device__ __forceinline__ int axis_cell(double v, double o, double cs, int n, uint32_t &upper) {
-    // floor((v - o) / cs) with an IEEE division, clamped to [0, n - 1]
-    // (NaN -> 0).  Clamping is monotone, so pairs closer than cs still land
-    // in adjacent cells.  upper: the position lies in the cell's upper half
-    // (ordering only; 0 where clamped).
-    const double t = (v - o) / cs;
-    const double f = floor(t);
-    upper = 0u;
-    if (!(f >= 0.0)) return 0;
-    if (f > (double)(n - 1)) return n - 1;
-    upper = t - f >= 0.5 ? 1u : 0u;
-    return (int)f;
-}
 
 // Key of particle i's cell in its half-row (fluid or boundary) of its
 // instance's grid: sorted, each cell row holds its fluid particles, x-cell
@@ -43,13 +30,7 @@ struct EncodeArgs {
 
 __device__ __forceinline__ uint32_t encode_key(const EncodeArgs &e, const Inst &ip, int64_t i,
                                                uint32_t id) {
-    uint32_t ux, uy, uz;
-    const int cx = axis_cell(e.x[i], ip.ox, ip.cs, ip.nx, ux);
-    const int cy = axis_cell(e.y[i], ip.oy, ip.cs, ip.ny, uy);
-    const int cz = axis_cell(e.z[i], ip.oz, ip.cs, ip.nz, uz);
-    const uint32_t lrow = (uint32_t)cz * (uint32_t)ip.ny + (uint32_t)cy;
-    const uint32_t cell = half_row_key(ip.cell_base, ip.nx, lrow, id >> 31) + (uint32_t)cx;
-    return (cell << kSubBits) | (uy << 1) | ux;
+    return sort_key(ip, e.x[i], e.y[i], e.z[i], id);
 }
 
 // The keys of a thread's kItems particles (block-strided, 0 past n).  The
@@ -384,34 +365,37 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 }
 
 // full: sort on every key bit; else on the cell key only (the sub-cell bits
-// keep the order of the input).  The sorted keys always end in w.keys(): the
-// first pass reads the keys from the buffer that makes the ping-pong end
-// there.
+// keep the order of the input).  keys_ready: w.keys_next() holds the keys of
+// the current positions (the previous update wrote them); else the first
+// histogram pass computes them there.  The first pass reads w.keys_next() and
+// writes the buffer that makes the keys/keys_alt ping-pong end in w.keys().
 int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st, bool full,
-                uint32_t **sorted_keys, uint32_t **perm) {
+                bool keys_ready, uint32_t **sorted_keys, uint32_t **perm) {
     const int64_t n = w.L.n;
     const int ntiles = (int)w.L.ntiles;
     const int low = full ? 0 : kSubBits;
     const int bits = w.L.key_bits - low;
     const int passes = bits <= 0 ? 1 : (bits + kRadixBits - 1) / kRadixBits;
     const bool small = sort_tile(n) == (int64_t)kSortThreads * kSortItemsSmall;
-    uint32_t *kin = (passes & 1) ? w.keys_alt() : w.keys();
+    uint32_t *kin = w.keys_next();
     uint32_t *kout = (passes & 1) ? w.keys() : w.keys_alt();
+    uint32_t *kother = (passes & 1) ? w.keys_alt() : w.keys();  // the ping-pong's second buffer
     uint32_t *vbuf[2] = {w.vals(), w.vals_alt()};
     uint32_t *vin = nullptr;  // first pass ranks the identity permutation
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = low + pass * kRadixBits;
         uint32_t *vout = vbuf[pass & 1];
         const EncodeArgs e{s.x, s.y, s.z, s.id, insts_of(P, w), kin};
+        const bool encode = pass == 0 && !keys_ready;
         if (small) {
-            if (pass == 0)
+            if (encode)
                 hipLaunchKernelGGL((k_sort_hist<kSortItemsSmall, true>), dim3(ntiles),
                                    dim3(kSortThreads), 0, st, kin, n, shift, w.hist(), ntiles, e);
             else
                 hipLaunchKernelGGL((k_sort_hist<kSortItemsSmall, false>), dim3(ntiles),
                                    dim3(kSortThreads), 0, st, kin, n, shift, w.hist(), ntiles, e);
         } else {
-            if (pass == 0)
+            if (encode)
                 hipLaunchKernelGGL((k_sort_hist<kSortItemsLarge, true>), dim3(ntiles),
                                    dim3(kSortThreads), 0, st, kin, n, shift, w.hist(), ntiles, e);
             else
@@ -427,9 +411,9 @@ int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t s
             hipLaunchKernelGGL(k_sort_scatter<kSortItemsLarge>, dim3(ntiles), dim3(kSortThreads),
                                0, st, kin, vin, kout, vout, n, shift, w.hist_off(), ntiles);
         if (int rc = launch_check("radix sort")) return rc;
-        uint32_t *t = kin;
         kin = kout;
-        kout = t;
+        kout = kother;
+        kother = kin;
         vin = vout;
     }
     *sorted_keys = kin;

@@ -114,6 +114,35 @@ __host__ __device__ __forceinline__ uint32_t key_row_cell(uint32_t key) { return
 constexpr int kSubBits = 2;
 __host__ __device__ __forceinline__ uint32_t key_cell(uint32_t key) { return key >> kSubBits; }
 
+// Cell coordinate along one axis and its half (see kSubBits).
+__device__ __forceinline__ int axis_cell(double v, double o, double cs, int n, uint32_t &upper) {
+    // floor((v - o) / cs) with an IEEE division, clamped to [0, n - 1]
+    // (NaN -> 0).  Clamping is monotone, so pairs closer than cs still land
+    // in adjacent cells.  upper: the position lies in the cell's upper half
+    // (ordering only; 0 where clamped).
+    const double t = (v - o) / cs;
+    const double f = floor(t);
+    upper = 0u;
+    if (!(f >= 0.0)) return 0;
+    if (f > (double)(n - 1)) return n - 1;
+    upper = t - f >= 0.5 ? 1u : 0u;
+    return (int)f;
+}
+
+// The sort key of a particle of instance ip at (x, y, z) (id: bit 31 =
+// boundary).  Computed by the first sort pass from the positions, or by the
+// update that produced them (the next step's keys).
+__device__ __forceinline__ uint32_t sort_key(const Inst &ip, double x, double y, double z,
+                                             uint32_t id) {
+    uint32_t ux, uy, uz;
+    const int cx = axis_cell(x, ip.ox, ip.cs, ip.nx, ux);
+    const int cy = axis_cell(y, ip.oy, ip.cs, ip.ny, uy);
+    const int cz = axis_cell(z, ip.oz, ip.cs, ip.nz, uz);
+    const uint32_t lrow = (uint32_t)cz * (uint32_t)ip.ny + (uint32_t)cy;
+    const uint32_t cell = half_row_key(ip.cell_base, ip.nx, lrow, id >> 31) + (uint32_t)cx;
+    return (cell << kSubBits) | (uy << 1) | ux;
+}
+
 // Device-side access to the instances: a table in the workspace (batches) or
 // a single instance passed by value.
 struct Insts {
@@ -172,6 +201,7 @@ struct WsLayout {
     int32_t key_bits = 0;
     int32_t precision = 0;
     size_t keys = 0, keys_alt = 0, vals = 0, vals_alt = 0;
+    size_t keys_next = 0;    // the next sort's input keys (written by the update)
     size_t sorted_keys = 0;  // where the sort leaves the keys (keys)
     size_t hist = 0;         // (digit, tile) counts of a sort pass
     size_t hist_off = 0;     // their exclusive scan: first output slot per (digit, tile)
@@ -202,6 +232,7 @@ struct Ws {
     T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
     uint32_t *keys() const { return at<uint32_t>(L.keys); }
     uint32_t *keys_alt() const { return at<uint32_t>(L.keys_alt); }
+    uint32_t *keys_next() const { return at<uint32_t>(L.keys_next); }
     uint32_t *vals() const { return at<uint32_t>(L.vals); }
     uint32_t *vals_alt() const { return at<uint32_t>(L.vals_alt); }
     uint32_t *hist() const { return at<uint32_t>(L.hist); }
@@ -228,7 +259,7 @@ int launch_check(const char *what);
 
 // Launchers implemented in the kernel translation units.
 int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st, bool full,
-                uint32_t **sorted_keys, uint32_t **perm);
+                bool keys_ready, uint32_t **sorted_keys, uint32_t **perm);
 // exclusive scan of m values from `in` (left intact) to `out`; tot:
 // ceil(m / kScanSpan) values of scratch
 int launch_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tot, hipStream_t st);

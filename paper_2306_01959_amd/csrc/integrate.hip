@@ -67,7 +67,7 @@ __global__ void k_integrate(IntegrateArgs a) {
         az = r[2 * n + i];
         dr = r[3 * n + i];
     }
-    advance<kMixed>(a.state, i, dt, euler, ax, ay, az, dr);
+    advance<kMixed, true>(a.state, ip, i, dt, euler, ax, ay, az, dr);
 }
 
 static void rotate_levels(sph_state &s) {
@@ -84,7 +84,7 @@ int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int
     IntegrateArgs a;
     a.n = s.n;
     a.state = StateArrays{s.x,   s.y,   s.z,   s.ux,  s.uy,   s.uz,
-                          s.uxm, s.uym, s.uzm, s.rho, s.rhom, s.id};
+                          s.uxm, s.uym, s.uzm, s.rho, s.rhom, s.id, w.keys_next()};
     a.rates = w.base + w.L.rates;
     a.I = insts_of(P, w);
     a.sc = w.scalars();

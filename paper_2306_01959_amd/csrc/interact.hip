@@ -953,7 +953,7 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
             const double dt = a.ist[inst].dt_last;
             const bool euler =
                 a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
-            wcsph::advance<P::kMixed>(a.state, it, dt, euler, fax, fay, faz, (double)sd);
+            wcsph::advance<P::kMixed, false>(a.state, ip, it, dt, euler, fax, fay, faz, (double)sd);
         }
     }
     bound = group_min(bound, kWave);
@@ -1155,7 +1155,7 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
                 const double dt = a.ist[inst].dt_last;
                 const bool euler =
                     a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
-                wcsph::advance<P::kMixed>(a.state, it, dt, euler, fax, fay, faz, (double)acc.dr);
+                wcsph::advance<P::kMixed, false>(a.state, ip, it, dt, euler, fax, fay, faz, (double)acc.dr);
             }
         }
         bound = group_min(bound, kWave);
@@ -1423,7 +1423,7 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
         if constexpr (kFuse) {
             const double dt = a.ist[inst].dt_last;
             const bool euler = a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
-            wcsph::advance<P::kMixed>(a.state, it, dt, euler, fax, fay, faz, (double)acc.dr);
+            wcsph::advance<P::kMixed, false>(a.state, ip, it, dt, euler, fax, fay, faz, (double)acc.dr);
         }
     }
     // the workgroup's bound and pair counts for the chunk's record
@@ -1706,7 +1706,7 @@ int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream
     a.st_nb = st_nb;
     a.st_hash = st_hash;
     a.state = StateArrays{s.x,   s.y,   s.z,   s.ux,   s.uy,  s.uz,
-                          s.uxm, s.uym, s.uzm, s.rho,  s.rhom, s.id};
+                          s.uxm, s.uym, s.uzm, s.rho,  s.rhom, s.id, nullptr};
     a.step = step;
     const bool stats = st_nf != nullptr;
     // chunks of <= csz targets: at most ceil(particles / csz) + 1 per half-row

@@ -3,12 +3,18 @@
 // particles update r, u, rho; dynamic boundary particles rho only.  The new
 // level is written over the previous one (um, rhom); the caller then swaps the
 // (u, um) and (rho, rhom) pointers.  FP64 accumulators for r and u; the mixed
-// path keeps rho - rho0 in FP32, updated in FP64 and rounded once.
+// path keeps rho - rho0 in FP32, updated in FP64 and rounded once.  With kKeys
+// and keys_next set, the update also writes the particle's sort key at its new
+// position, which the next step's sort reads instead of the positions (the
+// interaction kernels that advance the state themselves leave it out: the key's
+// divisions would cost them occupancy).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+
+#include "common.h"
 
 namespace wcsph {
 
@@ -19,11 +25,12 @@ struct StateArrays {
     const void *rho;
     void *rhom;
     const uint32_t *id;
+    uint32_t *keys_next;  // or null
 };
 
-template <bool kMixed>
-__device__ __forceinline__ void advance(const StateArrays &s, int64_t i, double dt, bool euler,
-                                        double ax, double ay, double az, double dr) {
+template <bool kMixed, bool kKeys>
+__device__ __forceinline__ void advance(const StateArrays &s, const Inst &ip, int64_t i, double dt,
+                                        bool euler, double ax, double ay, double az, double dr) {
     const double w = euler ? dt : 2.0 * dt;
     if constexpr (kMixed) {
         const double cur = (double)static_cast<const float *>(s.rho)[i];
@@ -37,19 +44,25 @@ __device__ __forceinline__ void advance(const StateArrays &s, int64_t i, double 
         pm[i] = base + w * dr;
     }
     const double ux = s.ux[i], uy = s.uy[i], uz = s.uz[i];
-    if ((s.id[i] >> 31) != 0) {  // boundary: does not move
+    const uint32_t id = s.id[i];
+    if ((id >> 31) != 0) {  // boundary: does not move
         s.uxm[i] = ux;
         s.uym[i] = uy;
         s.uzm[i] = uz;
+        if (kKeys && s.keys_next) s.keys_next[i] = sort_key(ip, s.x[i], s.y[i], s.z[i], id);
         return;
     }
     const double hdt2 = 0.5 * dt * dt;
     const double bx = euler ? ux : s.uxm[i];
     const double by = euler ? uy : s.uym[i];
     const double bz = euler ? uz : s.uzm[i];
-    s.x[i] = s.x[i] + dt * ux + hdt2 * ax;
-    s.y[i] = s.y[i] + dt * uy + hdt2 * ay;
-    s.z[i] = s.z[i] + dt * uz + hdt2 * az;
+    const double x = s.x[i] + dt * ux + hdt2 * ax;
+    const double y = s.y[i] + dt * uy + hdt2 * ay;
+    const double z = s.z[i] + dt * uz + hdt2 * az;
+    s.x[i] = x;
+    s.y[i] = y;
+    s.z[i] = z;
+    if (kKeys && s.keys_next) s.keys_next[i] = sort_key(ip, x, y, z, id);
     s.uxm[i] = bx + w * ax;
     s.uym[i] = by + w * ay;
     s.uzm[i] = bz + w * az;
