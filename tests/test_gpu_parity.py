@@ -271,6 +271,35 @@ def test_diagnostics_match_oracle(gpu, oracle_lib, developed, precision):
     assert pp[2] == 0.0          # dry probe
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_front_and_probe_series_match_oracle(gpu, oracle_lib, precision):
+    """Short horizon of the configuration-1 dam break from rest (240 steps,
+    the oracle's CFL dt sequence fed to the GPU): the surge front and three
+    probe pressures sampled every 12 steps stay within 1 % of each series'
+    range of the oracle's."""
+    s = scene.config_scene(1)
+    p = oracle_lib.par(s.params)
+    st = oracle_lib.State(s)
+    sim = _sim(gpu, s, precision)
+    probes = np.array([[0.2, 0.3, 0.03], [0.45, 0.3, 0.02], [0.3, 0.3, 0.15]])
+    ref, got = [], []
+    step = 0
+    for _ in range(20):
+        dts, _ = oracle_lib.run(p, st, 12, dt_mode=1)
+        for dt in dts:
+            sim.step(float(dt), step)
+            step += 1
+        od = oracle_lib.diagnostics(p, st)
+        ref.append([od["x_front"], *oracle_lib.probes(p, st, probes)])
+        d, pp = sim.diagnostics(probes)
+        got.append([d["x_front"], *pp])
+    ref, got = np.array(ref), np.array(got)
+    span = ref.max(axis=0) - ref.min(axis=0)
+    assert span[0] > 0.05 and (span[1:] > 100.0).all(), span  # the flow does develop
+    err = np.abs(got - ref).max(axis=0)
+    assert (err <= 0.01 * span).all(), (err / span)
+
+
 def test_pair_totals_match_oracle(gpu, oracle_lib, developed):
     params, st = developed
     sc, prev = scene_from_oracle(st, params)
