@@ -323,9 +323,13 @@ static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int6
         if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
         if (int rc = launch_chunks(P, w, fused, dt, st)) return rc;  // fresh dt bound
     }
+    // the interaction region ends with the kernel (before the reduction of
+    // its chunk records)
     if (int rc = m.at(SPH_REGION_INTERACT, true, st)) return rc;
-    if (int rc = launch_interact(P, s, w, st, nullptr, nullptr, nullptr, fused, step)) return rc;
-    if (int rc = m.at(SPH_REGION_INTERACT, false, st)) return rc;
+    hipEvent_t after = m.region == SPH_REGION_INTERACT ? m.e1 : nullptr;
+    if (!m.e0) after = nullptr;
+    if (int rc = launch_interact(P, s, w, st, nullptr, nullptr, nullptr, fused, step, after))
+        return rc;
     if (fused) {
         after_fused_step(s);
     } else {

@@ -270,9 +270,12 @@ int launch_cell_table(const Ws &w, const uint32_t *keys, hipStream_t st);
 int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStream_t st);
 // fuse: the interaction also advances every target (time update of step
 // `step`) with the dt already stored per instance, instead of storing rates.
+// after_kernel (optional): recorded between the interaction kernel and the
+// per-instance reduction of its chunk records.
 int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st,
                     int32_t *st_nf = nullptr, int32_t *st_nb = nullptr,
-                    uint32_t *st_hash = nullptr, bool fuse = false, int64_t step = 0);
+                    uint32_t *st_hash = nullptr, bool fuse = false, int64_t step = 0,
+                    hipEvent_t after_kernel = nullptr);
 int launch_export_rates(const Problem &P, const Ws &w, double *ax, double *ay, double *az,
                         double *drho, double *mumax, hipStream_t st);
 int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,

@@ -1681,7 +1681,7 @@ static void launch_prec(int kernel, int split, int group, uint32_t nb, bool stat
 
 int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st,
                     int32_t *st_nf, int32_t *st_nb, uint32_t *st_hash, bool fuse,
-                    int64_t step) {
+                    int64_t step, hipEvent_t after_kernel) {
     InteractArgs a;
     a.chunks = w.chunks();
     a.sc = w.scalars();
@@ -1720,6 +1720,8 @@ int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream
     else
         launch_prec<Fp64>(kernel, split, group, nb, stats, fuse && !stats, a, st);
     if (int rc = launch_check("interact")) return rc;
+    if (after_kernel)
+        if (int rc = hip_check(hipEventRecord(after_kernel, st), "event record")) return rc;
     hipLaunchKernelGGL(k_chunk_reduce, dim3((nb + 1023) / 1024), dim3(1024), 0, st, w.chunks(),
                        w.chunk_out(), w.scalars(), w.inst_state());
     return launch_check("chunk reduce");
