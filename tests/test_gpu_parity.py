@@ -233,6 +233,22 @@ def test_trajectory_matches_oracle(gpu, oracle_lib, developed, precision):
     assert np.abs(out["x"] - st.x).max() < 1e-6 * params["dp"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_run_equals_step_by_step(gpu, precision):
+    """A run of 50 steps (each update writes the next sort's keys, across the
+    full-key refresh at step 40) equals 50 single steps (each sort computes
+    its keys from the positions), bit for bit."""
+    s = scene.config_scene(1)
+    a = _sim(gpu, s, precision)
+    a.run(50, -1.0, 0)
+    b = _sim(gpu, s, precision)
+    for k in range(50):
+        b.step(-1.0, k)
+    ra, rb = a.fetch(), b.fetch()
+    for key in ra:
+        assert np.array_equal(ra[key], rb[key]), key
+
+
 def test_determinism_bitwise(gpu):
     s = scene.config_scene(1)
     outs = []
