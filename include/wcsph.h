@@ -240,13 +240,18 @@ int sph_get_density(const sph_params *p, const sph_state *s, double *rho, int32_
 /*
  * Cell-linked list (neighbour search set-up).  Hashes every position to its
  * cell (clamped to the grid), sorts the particles stably by cell row (fixed
- * y, z), then class (fluid before boundary), then cell x (LSD radix sort of
- * 32-bit keys), gathers every state array into that order (the *_alt
- * buffers, then swaps the pointers) and builds the cell table, the chunk list
- * and the interaction view (per-particle pressure, sound speed, 1/rho, and
- * for SPH_MIXED the FP32 offset of each particle from its cell centre).
- * Stable: particles of one cell and class keep their previous relative
- * order, so the result is deterministic.
+ * y, z), then class (fluid before boundary), then cell x, then half of the
+ * cell along y, then half along x (LSD radix sort of 32-bit keys), gathers
+ * every state array into that order (the *_alt buffers, then swaps the
+ * pointers) and builds the cell table, the chunk list and the interaction
+ * view (per-particle pressure, sound speed, 1/rho, and for SPH_MIXED the FP32
+ * offset of each particle from its cell centre).  Stable: particles with the
+ * same key keep their previous relative order, so the result is
+ * deterministic.  Inside sph_run / sph_batch_run the steps between refreshes
+ * (step indices that are not multiples of the graph period, else of 40) sort
+ * on the cell alone, so the halves within a cell keep the order of the last
+ * refresh; neighbour sets and results do not depend on that order beyond
+ * rounding.
  */
 int sph_build_cells(const sph_params *p, sph_state *s, void *ws, void *stream);
 

@@ -16,11 +16,11 @@ namespace wcsph {
 
 // ---------------------------------------------------------------- encode
 
-
 // Key of particle i's cell in its half-row (fluid or boundary) of its
 // instance's grid: sorted, each cell row holds its fluid particles, x-cell
-// by x-cell, then its boundary particles.  Computed by the first histogram
-// pass of the sort, which stores the keys.
+// by x-cell, then its boundary particles.  Written by the previous step's
+// update where it ran as its own kernel; otherwise computed by the first
+// histogram pass of the sort, which stores the keys.
 struct EncodeArgs {
     const double *x, *y, *z;
     const uint32_t *id;
