@@ -193,6 +193,8 @@ SORT_BYTES_FIRST = 44   # pass 0: histogram reads x, y, z, id and writes the key
 SORT_BYTES_PASS = 20    # later passes: + the index read
 REORDER_BYTES = 4 + 4 + 84 + 84 + 40  # perm + key in, state gathered (84 B) and written,
                                       # interaction view written (40 B)
+TABLE_BYTES = 4 + 4 + 4  # per cell-table entry (same launch as the reorder): its previous
+                         # value read as the search hint, one key probed, the entry written
 
 
 def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False):
@@ -240,7 +242,8 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False):
     key_bits = int(np.ceil(np.log2(2 * sum(int(np.prod(s.params["dims"])) for s in scenes)))) + 2
     passes = max(1, (key_bits - 2 + 7) // 8)
     sort_bytes = n * (SORT_BYTES_FIRST + SORT_BYTES_PASS * (passes - 1))
-    reorder_bytes = n * REORDER_BYTES
+    cells = sum(int(np.prod(s.params["dims"])) for s in scenes)
+    reorder_bytes = n * REORDER_BYTES + (2 * cells + 1) * TABLE_BYTES
     pairs = [(d1[0][k] - d0[0][k]) / steps for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
     flop = FLOP_FF * pairs[0] + FLOP_FB * pairs[1] + FLOP_BF * pairs[2]
 

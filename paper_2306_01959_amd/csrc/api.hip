@@ -296,7 +296,6 @@ static int build_cells(const Problem &P, sph_state &s, const Ws &w, hipStream_t 
     if (int rc = m.at(SPH_REGION_REORDER, true, st)) return rc;
     if (int rc = launch_reorder(P, s, w, keys, perm, st)) return rc;
     if (int rc = m.at(SPH_REGION_REORDER, false, st)) return rc;
-    if (int rc = launch_cell_table(w, keys, st)) return rc;
     if (int rc = launch_chunks(P, w, lagged, dt, st)) return rc;
     s.cells_valid = 1;
     return SPH_OK;

@@ -421,6 +421,55 @@ int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t s
     return 0;
 }
 
+// ------------------------------------------------------------ cell table
+
+// start[k] = first sorted position whose cell key >= k, for k in [0, 2 ncells]
+// (lower bound; an empty cell gets the start of the next one).  Cells x0..x1
+// of a half-row with key k0 at x = 0 hold the sorted range
+// [start[k0 + x0], start[k0 + x1 + 1]).  The search starts from the entry's
+// previous value (particles move little between steps, so it is usually
+// exact or close): gallop away from it until the answer is bracketed, then
+// bisect.  The hint only changes the cost: any value gives the exact bound.
+__device__ __forceinline__ void cell_table_entry(const uint32_t *__restrict__ keys, int64_t n, int64_t c,
+                                 uint32_t *__restrict__ start) {
+    const int64_t h = start[c] < (uint64_t)n ? (int64_t)start[c] : n;
+    int64_t lo, hi;  // the answer lies in [lo, hi]
+    if (h < n && (int64_t)key_cell(keys[h]) < c) {
+        lo = h + 1;
+        hi = n;
+        for (int64_t step = 1;; step <<= 1) {
+            const int64_t q = h + step;
+            if (q >= n) break;
+            if ((int64_t)key_cell(keys[q]) >= c) {
+                hi = q;
+                break;
+            }
+            lo = q + 1;
+        }
+    } else {
+        lo = 0;
+        hi = h;
+        for (int64_t step = 1;; step <<= 1) {
+            const int64_t q = h - step;
+            if (q < 0) break;
+            if ((int64_t)key_cell(keys[q]) < c) {
+                lo = q + 1;
+                break;
+            }
+            hi = q;
+        }
+    }
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)key_cell(keys[mid]) < c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    start[c] = (uint32_t)lo;
+}
+
+
 // ----------------------------------------------------- reorder and view
 
 struct ReorderArgs {
@@ -438,6 +487,10 @@ struct ReorderArgs {
     // view
     void *v0, *v1, *v2;
     Insts I;
+    // cell table, built by the blocks from table_block0 on
+    uint32_t *start;
+    int64_t nkeys;
+    uint32_t table_block0;
 };
 
 // Offset of coordinate v from the centre of cell c, computed in FP64 with
@@ -458,8 +511,15 @@ __device__ __forceinline__ float cell_offset(double v, double o, int c, double c
 // instance has gamma = 7, the value of all the paper's runs) expands the
 // binomial instead, x (7 + 21 x + ... + x^6) and c0 (1 + x)^3, which needs no
 // transcendental calls and fewer registers.
+// The same launch also builds the cell table from the sorted keys (the two
+// are independent): blocks from table_block0 on compute its entries.
 template <bool kMixed, bool kGamma7>
 __global__ void k_reorder(ReorderArgs a) {
+    if (blockIdx.x >= a.table_block0) {
+        const int64_t c = (int64_t)(blockIdx.x - a.table_block0) * blockDim.x + threadIdx.x;
+        if (c <= a.nkeys) cell_table_entry(a.keys, a.n, c, a.start);
+        return;
+    }
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.n) return;
     const uint32_t src = a.perm[k];
@@ -541,7 +601,10 @@ int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *
     a.v1 = w.base + w.L.view1;
     a.v2 = w.base + w.L.view2;
     a.I = insts_of(P, w);
-    int blocks = (int)((s.n + 255) / 256);
+    a.start = w.cell_start();
+    a.nkeys = 2 * w.L.ncells;
+    a.table_block0 = (uint32_t)((s.n + 255) / 256);
+    const int blocks = (int)(a.table_block0 + (a.nkeys + 1 + 255) / 256);
     bool g7 = true;
     for (const Inst &ip : P.host) g7 = g7 && ip.gamma == 7.0;
     if (P.precision == SPH_MIXED && g7)
@@ -558,64 +621,6 @@ int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *
     swp(s.uxm, s.uxm_alt); swp(s.uym, s.uym_alt); swp(s.uzm, s.uzm_alt);
     swp(s.rho, s.rho_alt); swp(s.rhom, s.rhom_alt); swp(s.id, s.id_alt);
     return 0;
-}
-
-// ------------------------------------------------------------ cell table
-
-// start[k] = first sorted position whose cell key >= k, for k in [0, 2 ncells]
-// (lower bound; an empty cell gets the start of the next one).  Cells x0..x1
-// of a half-row with key k0 at x = 0 hold the sorted range
-// [start[k0 + x0], start[k0 + x1 + 1]).  The search starts from the entry's
-// previous value (particles move little between steps, so it is usually
-// exact or close): gallop away from it until the answer is bracketed, then
-// bisect.  The hint only changes the cost: any value gives the exact bound.
-__global__ void k_cell_table(const uint32_t *__restrict__ keys, int64_t n, int64_t nkeys,
-                             uint32_t *__restrict__ start) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > nkeys) return;
-    const int64_t h = start[c] < (uint64_t)n ? (int64_t)start[c] : n;
-    int64_t lo, hi;  // the answer lies in [lo, hi]
-    if (h < n && (int64_t)key_cell(keys[h]) < c) {
-        lo = h + 1;
-        hi = n;
-        for (int64_t step = 1;; step <<= 1) {
-            const int64_t q = h + step;
-            if (q >= n) break;
-            if ((int64_t)key_cell(keys[q]) >= c) {
-                hi = q;
-                break;
-            }
-            lo = q + 1;
-        }
-    } else {
-        lo = 0;
-        hi = h;
-        for (int64_t step = 1;; step <<= 1) {
-            const int64_t q = h - step;
-            if (q < 0) break;
-            if ((int64_t)key_cell(keys[q]) < c) {
-                lo = q + 1;
-                break;
-            }
-            hi = q;
-        }
-    }
-    while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if ((int64_t)key_cell(keys[mid]) < c)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    start[c] = (uint32_t)lo;
-}
-
-int launch_cell_table(const Ws &w, const uint32_t *keys, hipStream_t st) {
-    int64_t m = 2 * w.L.ncells + 1;
-    int blocks = (int)((m + 255) / 256);
-    hipLaunchKernelGGL(k_cell_table, dim3(blocks), dim3(256), 0, st, keys, w.L.n,
-                       2 * w.L.ncells, w.cell_start());
-    return launch_check("cell table");
 }
 
 // ------------------------------------------------------------ chunk list

@@ -265,7 +265,6 @@ int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t s
 int launch_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tot, hipStream_t st);
 int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *keys,
                    const uint32_t *perm, hipStream_t st);
-int launch_cell_table(const Ws &w, const uint32_t *keys, hipStream_t st);
 // lagged: also fix this step's dt from the previous interaction's bound (or dt > 0)
 int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStream_t st);
 // fuse: the interaction also advances every target (time update of step
