@@ -283,8 +283,8 @@ struct Marks {
 
 // full: sort on the sub-cell bits too (see kSubBits); the steps between
 // refreshes sort on the cell key alone.  keys_ready: the previous update of
-// this same run wrote the keys of the current positions (else they are
-// computed from the positions here).
+// this same run wrote the keys of the current positions and their first
+// digit counts (else both are computed from the positions here).
 static int build_cells(const Problem &P, sph_state &s, const Ws &w, hipStream_t st,
                        bool lagged = false, double dt = 0.0, const Marks &m = Marks(),
                        bool full = true, bool keys_ready = false) {
@@ -332,7 +332,9 @@ static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int6
     if (fused) {
         after_fused_step(s);
     } else {
-        if (int rc = launch_integrate(P, s, w, dt, step, st)) return rc;
+        // the update also counts the first digits of the next step's sort
+        const int next_low = (step + 1) % refresh_period(P) == 0 ? 0 : kSubBits;
+        if (int rc = launch_integrate(P, s, w, dt, step, st, next_low)) return rc;
     }
     if (int rc = m.at(SPH_REGION_STEP, false, st)) return rc;
     s.cells_valid = 0;

@@ -94,22 +94,6 @@ __device__ __forceinline__ void encode_keys(const EncodeArgs &e, int64_t base, i
 // ballots), so a tile's keys keep their input order: the sort is stable and
 // deterministic.
 
-__device__ __forceinline__ uint64_t lanemask_lt() {
-    uint32_t lane = __lane_id();
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
-// Lanes of the wave whose digit equals this lane's (restricted to `valid`).
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
-    uint64_t peers = valid;
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-        uint64_t bal = __ballot((d >> b) & 1u);
-        peers &= ((d >> b) & 1u) ? bal : ~bal;
-    }
-    return peers;
-}
-
 // kEncode: the first pass, which computes the keys (encode_key) and stores
 // them instead of reading them.
 template <int kItems, bool kEncode>
@@ -138,12 +122,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t *__re
         }
     }
 #pragma unroll
-    for (int it = 0; it < kItems; ++it) {
-        const bool ok = base + (int64_t)it * kSortThreads + tid < n;
-        const uint32_t d = (key[it] >> shift) & (kRadix - 1);
-        const uint64_t peers = match_digit(d, __ballot(ok));
-        if (ok && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
-    }
+    for (int it = 0; it < kItems; ++it)
+        tile_hist_add(h, key[it], base + (int64_t)it * kSortThreads + tid < n, shift);
     __syncthreads();
     for (int d = tid; d < kRadix; d += kSortThreads) hist[(int64_t)d * ntiles + blockIdx.x] = h[d];
 }
@@ -366,8 +346,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 
 // full: sort on every key bit; else on the cell key only (the sub-cell bits
 // keep the order of the input).  keys_ready: w.keys_next() holds the keys of
-// the current positions (the previous update wrote them); else the first
-// histogram pass computes them there.  The first pass reads w.keys_next() and
+// the current positions and w.hist() the first pass's digit counts (the
+// previous update wrote both, for this step's `full`); else the first
+// histogram pass computes the keys and counts them.  The first pass reads w.keys_next() and
 // writes the buffer that makes the keys/keys_alt ping-pong end in w.keys().
 int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st, bool full,
                 bool keys_ready, uint32_t **sorted_keys, uint32_t **perm) {
@@ -387,14 +368,16 @@ int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t s
         uint32_t *vout = vbuf[pass & 1];
         const EncodeArgs e{s.x, s.y, s.z, s.id, insts_of(P, w), kin};
         const bool encode = pass == 0 && !keys_ready;
-        if (small) {
+        // with keys_ready the update has also counted the first pass's digits
+        const bool counted = pass == 0 && keys_ready;
+        if (!counted && small) {
             if (encode)
                 hipLaunchKernelGGL((k_sort_hist<kSortItemsSmall, true>), dim3(ntiles),
                                    dim3(kSortThreads), 0, st, kin, n, shift, w.hist(), ntiles, e);
             else
                 hipLaunchKernelGGL((k_sort_hist<kSortItemsSmall, false>), dim3(ntiles),
                                    dim3(kSortThreads), 0, st, kin, n, shift, w.hist(), ntiles, e);
-        } else {
+        } else if (!counted) {
             if (encode)
                 hipLaunchKernelGGL((k_sort_hist<kSortItemsLarge, true>), dim3(ntiles),
                                    dim3(kSortThreads), 0, st, kin, n, shift, w.hist(), ntiles, e);

@@ -83,6 +83,32 @@ struct DevScalars {
     unsigned long long pairs[3];     // interacting pairs since init: FF, FB, BF
 };
 
+// Lanes below this one in the wave.
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Lanes of the wave whose radix digit equals this lane's (restricted to
+// `valid`): one ballot per digit bit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
+    uint64_t peers = valid;
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        uint64_t bal = __ballot((d >> b) & 1u);
+        peers &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    return peers;
+}
+
+// Adds a wave's keys (those with ok) to a sort tile's digit counts in LDS:
+// one atomic per distinct digit of the wave.  All lanes of the wave call it.
+__device__ __forceinline__ void tile_hist_add(uint32_t *h, uint32_t key, bool ok, int shift) {
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    const uint64_t peers = match_digit(d, __ballot(ok));
+    if (ok && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+}
+
 // Orders one wave's LDS writes before its later reads (and reads before
 // later overwrites) without involving the other waves of the workgroup.
 __device__ __forceinline__ void wave_sync() {
@@ -277,8 +303,10 @@ int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream
                     hipEvent_t after_kernel = nullptr);
 int launch_export_rates(const Problem &P, const Ws &w, double *ax, double *ay, double *az,
                         double *drho, double *mumax, hipStream_t st);
+// hist_shift >= 0: the update also counts the digits (from that bit) of the
+// keys it writes, per sort tile, for the first pass of the next step's sort.
 int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
-                     hipStream_t st);
+                     hipStream_t st, int hist_shift = -1);
 int launch_diag(const Problem &P, const sph_state &s, const Ws &w, const double *probes,
                 int32_t np, sph_diag *out, double *probe_p, hipStream_t st);
 int launch_set_density(const Problem &P, sph_state &s, const Ws &w, const double *rho,

@@ -22,6 +22,9 @@ struct IntegrateArgs {
     InstState *ist;
     double dt_arg;
     long long step;
+    uint32_t *hist;  // digit counts per sort tile (digit-major), or null
+    int hist_shift;
+    int ntiles;
 };
 
 // dt of the instance for this step: the caller's, or Cr times the bound
@@ -31,12 +34,19 @@ __device__ __forceinline__ double step_dt(const IntegrateArgs &a, const Inst &ip
     return a.dt_arg > 0.0 ? a.dt_arg : ip.cfl * b;
 }
 
-template <bool kMixed>
-__global__ void k_integrate(IntegrateArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Block b updates the particles of sort tile b (kItems per thread, block-
+// strided) and, with a.hist, counts the digits of the keys it writes: the
+// histogram of the next sort's first pass.  Blocks of kUpdateThreads, so that
+// a small tile is one particle per thread (a thread's particles are updated
+// one after the other).
+constexpr int kUpdateThreads = 1024;
+template <bool kMixed, int kItems>
+__global__ __launch_bounds__(kUpdateThreads) void k_integrate(IntegrateArgs a) {
+    __shared__ uint32_t h[kRadix];
+    const int tid = threadIdx.x;
     if (blockIdx.x == 0) {
         // per-instance clock
-        for (int k = threadIdx.x; k < a.I.n; k += blockDim.x) {
+        for (int k = tid; k < a.I.n; k += blockDim.x) {
             const Inst ip = a.I.get(k);
             const double b = __longlong_as_double((long long)a.ist[k].dt_min_bits);
             const double dt = step_dt(a, ip, k);
@@ -45,29 +55,47 @@ __global__ void k_integrate(IntegrateArgs a) {
             a.ist[k].time += dt;
             if (dt > ip.cfl * b) a.sc->dt_cfl_violation = 1u;
         }
-        if (threadIdx.x == 0) a.sc->steps += 1;
+        if (tid == 0) a.sc->steps += 1;
     }
-    if (i >= a.n) return;
-    const int k = a.I.of_id(a.state.id[i] & 0x7fffffffu);
-    const Inst ip = a.I.get(k);
-    const double dt = step_dt(a, ip, k);
-    const bool euler = a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
+    if (a.hist) {
+        for (int d = tid; d < kRadix; d += kUpdateThreads) h[d] = 0;
+        __syncthreads();
+    }
     const int64_t n = a.n;
-    double ax, ay, az, dr;
-    if constexpr (kMixed) {
-        const float *r = static_cast<const float *>(a.rates);
-        ax = r[i];
-        ay = r[n + i];
-        az = r[2 * n + i];
-        dr = r[3 * n + i];
-    } else {
-        const double *r = static_cast<const double *>(a.rates);
-        ax = r[i];
-        ay = r[n + i];
-        az = r[2 * n + i];
-        dr = r[3 * n + i];
+    const int64_t base = (int64_t)blockIdx.x * kUpdateThreads * kItems;
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+        const int64_t i = base + (int64_t)it * kUpdateThreads + tid;
+        const bool ok = i < n;
+        uint32_t key = 0;
+        if (ok) {
+            const int k = a.I.of_id(a.state.id[i] & 0x7fffffffu);
+            const Inst ip = a.I.get(k);
+            const double dt = step_dt(a, ip, k);
+            const bool euler = a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
+            double ax, ay, az, dr;
+            if constexpr (kMixed) {
+                const float *r = static_cast<const float *>(a.rates);
+                ax = r[i];
+                ay = r[n + i];
+                az = r[2 * n + i];
+                dr = r[3 * n + i];
+            } else {
+                const double *r = static_cast<const double *>(a.rates);
+                ax = r[i];
+                ay = r[n + i];
+                az = r[2 * n + i];
+                dr = r[3 * n + i];
+            }
+            key = advance<kMixed, true>(a.state, ip, i, dt, euler, ax, ay, az, dr);
+        }
+        if (a.hist) tile_hist_add(h, key, ok, a.hist_shift);
     }
-    advance<kMixed, true>(a.state, ip, i, dt, euler, ax, ay, az, dr);
+    if (a.hist) {
+        __syncthreads();
+        for (int d = tid; d < kRadix; d += kUpdateThreads)
+            a.hist[(int64_t)d * a.ntiles + blockIdx.x] = h[d];
+    }
 }
 
 static void rotate_levels(sph_state &s) {
@@ -80,7 +108,7 @@ static void rotate_levels(sph_state &s) {
 }
 
 int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
-                     hipStream_t st) {
+                     hipStream_t st, int hist_shift) {
     IntegrateArgs a;
     a.n = s.n;
     a.state = StateArrays{s.x,   s.y,   s.z,   s.ux,  s.uy,   s.uz,
@@ -91,11 +119,28 @@ int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int
     a.ist = w.inst_state();
     a.dt_arg = dt;
     a.step = step;
-    const int blocks = (int)((s.n + 255) / 256);
-    if (P.precision == SPH_MIXED)
-        hipLaunchKernelGGL(k_integrate<true>, dim3(blocks), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_integrate<false>, dim3(blocks), dim3(256), 0, st, a);
+    a.hist = hist_shift >= 0 ? w.hist() : nullptr;
+    a.hist_shift = hist_shift;
+    a.ntiles = (int)w.L.ntiles;
+    // one block per sort tile (the tiling of the sort's histogram pass)
+    constexpr int kSmall = kSortThreads * kSortItemsSmall / kUpdateThreads;
+    constexpr int kLarge = kSortThreads * kSortItemsLarge / kUpdateThreads;
+    static_assert(kSmall * kUpdateThreads == kSortThreads * kSortItemsSmall &&
+                      kLarge * kUpdateThreads == kSortThreads * kSortItemsLarge,
+                  "update blocks cover whole sort tiles");
+    const bool small = sort_tile(s.n) == (int64_t)kSortThreads * kSortItemsSmall;
+    const dim3 grid((unsigned)w.L.ntiles), block(kUpdateThreads);
+    if (P.precision == SPH_MIXED) {
+        if (small)
+            hipLaunchKernelGGL((k_integrate<true, kSmall>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_integrate<true, kLarge>), grid, block, 0, st, a);
+    } else {
+        if (small)
+            hipLaunchKernelGGL((k_integrate<false, kSmall>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_integrate<false, kLarge>), grid, block, 0, st, a);
+    }
     if (int rc = launch_check("integrate")) return rc;
     rotate_levels(s);
     return 0;

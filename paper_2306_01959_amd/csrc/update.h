@@ -28,9 +28,11 @@ struct StateArrays {
     uint32_t *keys_next;  // or null
 };
 
+// Returns the key written (0 without kKeys).
 template <bool kMixed, bool kKeys>
-__device__ __forceinline__ void advance(const StateArrays &s, const Inst &ip, int64_t i, double dt,
-                                        bool euler, double ax, double ay, double az, double dr) {
+__device__ __forceinline__ uint32_t advance(const StateArrays &s, const Inst &ip, int64_t i,
+                                            double dt, bool euler, double ax, double ay,
+                                            double az, double dr) {
     const double w = euler ? dt : 2.0 * dt;
     if constexpr (kMixed) {
         const double cur = (double)static_cast<const float *>(s.rho)[i];
@@ -49,8 +51,12 @@ __device__ __forceinline__ void advance(const StateArrays &s, const Inst &ip, in
         s.uxm[i] = ux;
         s.uym[i] = uy;
         s.uzm[i] = uz;
-        if (kKeys && s.keys_next) s.keys_next[i] = sort_key(ip, s.x[i], s.y[i], s.z[i], id);
-        return;
+        uint32_t key = 0;
+        if (kKeys && s.keys_next) {
+            key = sort_key(ip, s.x[i], s.y[i], s.z[i], id);
+            s.keys_next[i] = key;
+        }
+        return key;
     }
     const double hdt2 = 0.5 * dt * dt;
     const double bx = euler ? ux : s.uxm[i];
@@ -62,10 +68,15 @@ __device__ __forceinline__ void advance(const StateArrays &s, const Inst &ip, in
     s.x[i] = x;
     s.y[i] = y;
     s.z[i] = z;
-    if (kKeys && s.keys_next) s.keys_next[i] = sort_key(ip, x, y, z, id);
+    uint32_t key = 0;
+    if (kKeys && s.keys_next) {
+        key = sort_key(ip, x, y, z, id);
+        s.keys_next[i] = key;
+    }
     s.uxm[i] = bx + w * ax;
     s.uym[i] = by + w * ay;
     s.uzm[i] = bz + w * az;
+    return key;
 }
 
 }  // namespace wcsph
