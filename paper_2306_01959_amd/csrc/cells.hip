@@ -722,18 +722,37 @@ __global__ __launch_bounds__(256) void k_row_counts(const uint32_t *__restrict__
     if (g % kWave == 0) cnt[r] = nch;
 }
 
+// kScan: `first` holds the chunk counts themselves (few half-rows): the block
+// sums the counts of the half-rows before its own (each thread a strided
+// share), and each wave adds those of the block's waves before it.
+constexpr int kRowScanMax = 4096;  // half-rows up to which k_row_chunks scans itself
+template <bool kScan>
 __global__ __launch_bounds__(256) void k_row_chunks(const uint32_t *__restrict__ start, Insts I,
                                                     int64_t nhalf, uint32_t csz,
                                                     const uint32_t *__restrict__ first,
                                                     int4 *__restrict__ chunks, DevScalars *sc) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t r = g / kWave;
+    uint32_t f = 0;
+    if constexpr (kScan) {
+        __shared__ uint32_t part[256 / kWave];
+        const int64_t r0 = (int64_t)blockIdx.x * (256 / kWave);  // the block's first half-row
+        uint32_t s = 0;
+        for (int64_t q = threadIdx.x; q < r0; q += 256) s += first[q];
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) s += __shfl_xor(s, off, kWave);
+        const int w = threadIdx.x / kWave;
+        if (threadIdx.x % kWave == 0) part[w] = s;
+        __syncthreads();
+        f = part[0] + part[1] + part[2] + part[3];
+        for (int64_t q = r0; q < r && q < nhalf; ++q) f += first[q];
+    }
     if (r >= nhalf) return;  // whole waves
     const int lane = (int)(g % kWave);
     int inst, lhalf, nx;
     uint32_t k0;
     half_row(I, r, inst, lhalf, k0, nx);
-    const uint32_t f = first[r];
+    if constexpr (!kScan) f = first[r];
     const uint32_t nch =
         half_row_chunks(start, k0, nx, csz, [&](uint32_t k, uint32_t r0, uint32_t r1) {
             const uint32_t np = pieces(r1 - r0, csz);
@@ -754,9 +773,15 @@ int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStre
     hipLaunchKernelGGL(k_row_counts, dim3(blocks), dim3(256), 0, st, w.cell_start(), I, nhalf,
                        csz, w.row_cnt(), w.scalars(), w.inst_state(), (int)lagged, dt);
     if (int rc = launch_check("chunk counts")) return rc;
-    if (int rc = launch_scan(w.row_cnt(), w.row_first(), nhalf, w.scan_tot(), st)) return rc;
-    hipLaunchKernelGGL(k_row_chunks, dim3((unsigned)((nhalf * kWave + 255) / 256)), dim3(256), 0,
-                       st, w.cell_start(), I, nhalf, csz, w.row_first(), w.chunks(), w.scalars());
+    const dim3 grid((unsigned)((nhalf * kWave + 255) / 256));
+    if (nhalf <= kRowScanMax) {
+        hipLaunchKernelGGL(k_row_chunks<true>, grid, dim3(256), 0, st, w.cell_start(), I, nhalf,
+                           csz, w.row_cnt(), w.chunks(), w.scalars());
+    } else {
+        if (int rc = launch_scan(w.row_cnt(), w.row_first(), nhalf, w.scan_tot(), st)) return rc;
+        hipLaunchKernelGGL(k_row_chunks<false>, grid, dim3(256), 0, st, w.cell_start(), I, nhalf,
+                           csz, w.row_first(), w.chunks(), w.scalars());
+    }
     return launch_check("chunk list");
 }
 
