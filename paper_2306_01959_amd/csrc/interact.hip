@@ -103,6 +103,16 @@ __device__ __forceinline__ uint64_t lanes_below() {
 }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// wave-uniform floating values (e.g. a wave-wide min) kept in scalar registers
+__device__ __forceinline__ float uni(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uni(double v) {
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 
 // 32-bit integer mixer (the finaliser of MurmurHash3): neighbour-set hashes
 // are sums of id_hash over the set, so they do not depend on visit order.
@@ -728,9 +738,9 @@ __global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
             gbox[g][5] = hz;
         }
     }
-    const R lox = group_min(act ? bx : big, kWave), hix = group_max(act ? bx : -big, kWave);
-    const R loy = group_min(act ? by : big, kWave), hiy = group_max(act ? by : -big, kWave);
-    const R loz = group_min(act ? bz : big, kWave), hiz = group_max(act ? bz : -big, kWave);
+    const R lox = uni(group_min(act ? bx : big, kWave)), hix = uni(group_max(act ? bx : -big, kWave));
+    const R loy = uni(group_min(act ? by : big, kWave)), hiy = uni(group_max(act ? by : -big, kWave));
+    const R loz = uni(group_min(act ? bz : big, kWave)), hiz = uni(group_max(act ? bz : -big, kWave));
     const uint64_t fluid_tgts = __ballot(fi_own);
     const bool any_fluid = fluid_tgts != 0ull;
     const R cull2 = (R)(ip.r2max * (1.0 + 1e-3));
@@ -1021,9 +1031,10 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
         bool fi_own;
         P::target(a, ip, it, act, rowbase, cxa, tg.a, tg.b, tg.c, bx, by, bz, fi_own);
         const R big = (R)3.0e38f;
-        const R lox = group_min(act ? bx : big, kWave), hix = group_max(act ? bx : -big, kWave);
-        const R loy = group_min(act ? by : big, kWave), hiy = group_max(act ? by : -big, kWave);
-        const R loz = group_min(act ? bz : big, kWave), hiz = group_max(act ? bz : -big, kWave);
+        // the group's box, uniform over the wave (scalar registers)
+        const R lox = uni(group_min(act ? bx : big, kWave)), hix = uni(group_max(act ? bx : -big, kWave));
+        const R loy = uni(group_min(act ? by : big, kWave)), hiy = uni(group_max(act ? by : -big, kWave));
+        const R loz = uni(group_min(act ? bz : big, kWave)), hiz = uni(group_max(act ? bz : -big, kWave));
         const bool any_fluid = __ballot(fi_own) != 0ull;
         const R cull2 = (R)(ip.r2max * (1.0 + 1e-3));
 
