@@ -30,7 +30,7 @@ constexpr int kScanSumSpans = 16 * kScanThreads;  // up to this many: two (total
 constexpr int kChunk = 64;           // targets per chunk of the row-split interaction
 constexpr int kMinChunk = 8;         // smallest chunk (group-per-wave interaction)
 constexpr int kDiagThreads = 256;
-constexpr int kDiagBlocks = 256;     // partial sums of a single system (fixed: deterministic)
+constexpr int kDiagBlocks = 1024;    // partial sums of a single system (fixed: deterministic)
 constexpr int kDiagBlocksBatch = 32; // partial sums per instance of a batch
 constexpr int kDiagFields = 16;
 constexpr int kMaxProbes = 1024;     // probe points per sph_diagnostics call

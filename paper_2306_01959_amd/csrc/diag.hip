@@ -55,7 +55,7 @@ __device__ __forceinline__ double density_at(const DiagArgs &a, const Inst &ip, 
 // end of its last cell) of the current (cell) order, split over
 // bpi blocks with a fixed stride: fixed summation order.
 __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(DiagArgs a) {
-    __shared__ double red[kDiagThreads];
+    __shared__ double red[F_COUNT * (kDiagThreads / kWave)];
     const int k = blockIdx.y;
     const Inst ip = a.I.get(k);
     const int64_t ncell = (int64_t)ip.nx * ip.ny * ip.nz;
@@ -67,76 +67,104 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(DiagArgs a) {
     acc[F_FRONT] = -INFINITY;
     const int64_t stride = (int64_t)a.bpi * blockDim.x;
     const double gm1 = gamma - 1.0;
-    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += stride) {
-        const double x = a.x[i], y = a.y[i], z = a.z[i];
-        const double ux = a.ux[i], uy = a.uy[i], uz = a.uz[i];
-        const double rho = density_at(a, ip, i);
-        const bool bnd = (a.id[i] >> 31) != 0;
-        acc[F_MASS] += mass;
-        const double rr = rho / rho0;
-        acc[F_EINT] += mass * (B / rho0) * (pow(rr, gm1) / gm1 + 1.0 / rr - gamma / gm1);
-        const double vals[7] = {x, y, z, ux, uy, uz, rho};
-        for (int q = 0; q < 7; ++q)
-            if (!isfinite(vals[q])) acc[F_NONFIN] += 1.0;
-        bool out = false;
-        const int cx = diag_axis(x, ip.ox, ip.cs, ip.nx, &out);
-        const int cy = diag_axis(y, ip.oy, ip.cs, ip.ny, &out);
-        const int cz = diag_axis(z, ip.oz, ip.cs, ip.nz, &out);
-        if (out) acc[F_OUTSIDE] += 1.0;
-        acc[F_DENS] = fmax(acc[F_DENS], fabs(rho - rho0) / rho0);
-        if (bnd) continue;
-        acc[F_NFLUID] += 1.0;
-        acc[F_PX] += mass * ux;
-        acc[F_PY] += mass * uy;
-        acc[F_PZ] += mass * uz;
-        const double u2 = (ux * ux + uy * uy) + uz * uz;
-        acc[F_EKIN] += 0.5 * mass * u2;
-        acc[F_EPOT] -= mass * ((ip.gx * x + ip.gy * y) + ip.gz * z);
-        acc[F_UMAX] = fmax(acc[F_UMAX], sqrt(u2));
-        if (!(x > acc[F_FRONT])) continue;
-        // surge front: fluid particle with at least one fluid neighbour
-        bool found = false;
-        for (int dz = -1; dz <= 1 && !found; ++dz)
-            for (int dy = -1; dy <= 1 && !found; ++dy) {
-                const int czn = cz + dz, cyn = cy + dy;
-                if (czn < 0 || czn >= ip.nz || cyn < 0 || cyn >= ip.ny) continue;
-                // the fluid half of the stencil row
-                const uint32_t hb = half_row_key(ip.cell_base, ip.nx, czn * ip.ny + cyn, 0);
-                const int xl = cx > 0 ? cx - 1 : 0, xh = cx + 1 < ip.nx ? cx + 1 : ip.nx - 1;
-                const uint32_t js = a.cell_start[hb + xl], je = a.cell_start[hb + xh + 1];
-                for (uint32_t j = js; j < je; ++j) {
-                    if ((int64_t)j == i || (a.id[j] >> 31) != 0) continue;
-                    const double dx = a.x[j] - x, dy_ = a.y[j] - y, dz_ = a.z[j] - z;
-                    if ((dx * dx + dy_ * dy_) + dz_ * dz_ < ip.r2max) {
-                        found = true;
-                        break;
-                    }
-                }
-            }
-        if (found) acc[F_FRONT] = x;
-    }
-    double *part = a.part + ((size_t)k * a.bpi + blockIdx.x) * kDiagFields;
-    for (int f = 0; f < F_COUNT; ++f) {
-        red[threadIdx.x] = acc[f];
-        __syncthreads();
-        for (int off = kDiagThreads / 2; off > 0; off >>= 1) {
-            if ((int)threadIdx.x < off) {
-                const double o = red[threadIdx.x + off];
-                red[threadIdx.x] = is_max_field(f) ? fmax(red[threadIdx.x], o) : red[threadIdx.x] + o;
-            }
-            __syncthreads();
+    // a fluid particle within 2h of (x, y, z), other than i, at j?
+    auto near = [&](int64_t j, int64_t i, double x, double y, double z) {
+        if (j < lo || j >= hi || j == i || (a.id[j] >> 31) != 0) return false;
+        const double dx = a.x[j] - x, dy_ = a.y[j] - y, dz_ = a.z[j] - z;
+        return (dx * dx + dy_ * dy_) + dz_ * dz_ < ip.r2max;
+    };
+    // the block's rounds are uniform (every lane takes part in the wave
+    // operations of the surge-front test)
+    for (int64_t b0 = lo + (int64_t)blockIdx.x * blockDim.x; b0 < hi; b0 += stride) {
+        const int64_t i = b0 + threadIdx.x;
+        const bool live = i < hi;
+        const int64_t ii = live ? i : lo;
+        const double x = a.x[ii], y = a.y[ii], z = a.z[ii];
+        const double ux = a.ux[ii], uy = a.uy[ii], uz = a.uz[ii];
+        const double rho = density_at(a, ip, ii);
+        const bool bnd = (a.id[ii] >> 31) != 0;
+        const bool fluid = live && !bnd;
+        int cx = 0, cy = 0, cz = 0;
+        if (live) {
+            acc[F_MASS] += mass;
+            const double rr = rho / rho0;
+            acc[F_EINT] += mass * (B / rho0) * (pow(rr, gm1) / gm1 + 1.0 / rr - gamma / gm1);
+            const double vals[7] = {x, y, z, ux, uy, uz, rho};
+            for (int q = 0; q < 7; ++q)
+                if (!isfinite(vals[q])) acc[F_NONFIN] += 1.0;
+            bool out = false;
+            cx = diag_axis(x, ip.ox, ip.cs, ip.nx, &out);
+            cy = diag_axis(y, ip.oy, ip.cs, ip.ny, &out);
+            cz = diag_axis(z, ip.oz, ip.cs, ip.nz, &out);
+            if (out) acc[F_OUTSIDE] += 1.0;
+            acc[F_DENS] = fmax(acc[F_DENS], fabs(rho - rho0) / rho0);
         }
-        if (threadIdx.x == 0) part[f] = red[0];
-        __syncthreads();
+        if (fluid) {
+            acc[F_NFLUID] += 1.0;
+            acc[F_PX] += mass * ux;
+            acc[F_PY] += mass * uy;
+            acc[F_PZ] += mass * uz;
+            const double u2 = (ux * ux + uy * uy) + uz * uz;
+            acc[F_EKIN] += 0.5 * mass * u2;
+            acc[F_EPOT] -= mass * ((ip.gx * x + ip.gy * y) + ip.gz * z);
+            acc[F_UMAX] = fmax(acc[F_UMAX], sqrt(u2));
+        }
+        // surge front: the largest x of a fluid particle with at least one
+        // fluid neighbour.  The particles next to i in cell order (usually
+        // within 2h) settle most; the 27 cells are searched only for a
+        // particle that could still raise the maximum, i.e. beyond every
+        // particle of its wave settled so far.
+        const bool quick = fluid && (near(i + 1, i, x, y, z) || near(i - 1, i, x, y, z));
+        double mq = quick ? x : -INFINITY;
+        for (int off = kWave / 2; off > 0; off >>= 1) mq = fmax(mq, __shfl_xor(mq, off, kWave));
+        if (quick) acc[F_FRONT] = fmax(acc[F_FRONT], x);
+        if (fluid && !quick && x > fmax(mq, acc[F_FRONT])) {
+            bool found = false;
+            for (int dz = -1; dz <= 1 && !found; ++dz)
+                for (int dy = -1; dy <= 1 && !found; ++dy) {
+                    const int czn = cz + dz, cyn = cy + dy;
+                    if (czn < 0 || czn >= ip.nz || cyn < 0 || cyn >= ip.ny) continue;
+                    // the fluid half of the stencil row
+                    const uint32_t hb = half_row_key(ip.cell_base, ip.nx, czn * ip.ny + cyn, 0);
+                    const int xl = cx > 0 ? cx - 1 : 0, xh = cx + 1 < ip.nx ? cx + 1 : ip.nx - 1;
+                    const uint32_t js = a.cell_start[hb + xl], je = a.cell_start[hb + xh + 1];
+                    for (uint32_t j = js; j < je && !found; ++j) found = near(j, i, x, y, z);
+                }
+            if (found) acc[F_FRONT] = x;
+        }
+    }
+    // fixed reduction trees: shuffles within each wave, then the waves in
+    // order (one barrier)
+    double *part = a.part + ((size_t)k * a.bpi + blockIdx.x) * kDiagFields;
+    constexpr int kWaves = kDiagThreads / kWave;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+#pragma unroll
+    for (int f = 0; f < F_COUNT; ++f) {
+        double v = acc[f];
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const double o = __shfl_xor(v, off, kWave);
+            v = is_max_field(f) ? fmax(v, o) : v + o;
+        }
+        if (lane == 0) red[f * kWaves + w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < F_COUNT) {
+        const int f = threadIdx.x;
+        double v = red[f * kWaves];
+        for (int q = 1; q < kWaves; ++q)
+            v = is_max_field(f) ? fmax(v, red[f * kWaves + q]) : v + red[f * kWaves + q];
+        part[f] = v;
     }
 }
 
 // One block per instance: its bpi partials -> kDiagFields results.
 __global__ __launch_bounds__(kDiagThreads) void k_diag_final(const double *__restrict__ part_all,
                                                              int nparts, double *__restrict__ res_all) {
-    __shared__ double red[kDiagThreads];
+    constexpr int kWaves = kDiagThreads / kWave;
+    __shared__ double red[F_COUNT * kWaves];
     const double *part = part_all + (size_t)blockIdx.x * nparts * kDiagFields;
     double *res = res_all + (size_t)blockIdx.x * kDiagFields;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     for (int f = 0; f < F_COUNT; ++f) {
         const bool mx = is_max_field(f);
         double v = mx ? -INFINITY : 0.0;
@@ -144,17 +172,19 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_final(const double *__res
             const double o = part[b * kDiagFields + f];
             v = mx ? fmax(v, o) : v + o;
         }
-        red[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = kDiagThreads / 2; off > 0; off >>= 1) {
-            if ((int)threadIdx.x < off) {
-                const double o = red[threadIdx.x + off];
-                red[threadIdx.x] = mx ? fmax(red[threadIdx.x], o) : red[threadIdx.x] + o;
-            }
-            __syncthreads();
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const double o = __shfl_xor(v, off, kWave);
+            v = mx ? fmax(v, o) : v + o;
         }
-        if (threadIdx.x == 0) res[f] = red[0];
-        __syncthreads();
+        if (lane == 0) red[f * kWaves + w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < F_COUNT) {
+        const int f = threadIdx.x;
+        double v = red[f * kWaves];
+        for (int q = 1; q < kWaves; ++q)
+            v = is_max_field(f) ? fmax(v, red[f * kWaves + q]) : v + red[f * kWaves + q];
+        res[f] = v;
     }
 }
 
