@@ -124,11 +124,14 @@ EVENT_EVERY = 10   # interaction kernels timed with HIP events: every 10th step
 REPEATS = 5  # timed segments; the step time reported is their median
 
 
-def time_gpu(scene_obj, precision, steps, warmup, hip, repeats=REPEATS):
+def time_gpu(scene_obj, precision, steps, warmup, hip, repeats=REPEATS, diag_every=0,
+             probes=None):
     """`warmup` untimed steps, then `steps` steps in `repeats` consecutive
     segments, each bracketed by events on the library's stream (device
     time); the interaction kernel is timed by events inside the library every
-    EVENT_EVERY-th step."""
+    EVENT_EVERY-th step.  diag_every > 0: diagnostics (with `probes`) after
+    every step index that is a multiple of it, inside the timed segments (the
+    cell list they build is the next step's)."""
     import torch
     from paper_2306_01959_amd import lib
     sim = lib.Simulation(scene_obj, precision)
@@ -141,22 +144,34 @@ def time_gpu(scene_obj, precision, steps, warmup, hip, repeats=REPEATS):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step = warmup
+    nd = 0
     for seg in lens:  # exactly `steps` steps in all
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        sim.run_profiled(seg, -1.0, step, ev.begin, ev.end)
+        k = 0
+        while k < seg:
+            m = seg - k
+            if diag_every > 0:
+                m = min(m, diag_every - step % diag_every)
+            sub = [(C.c_void_p * m).from_address(C.addressof(arr) + k * C.sizeof(C.c_void_p))
+                   for arr in (ev.begin, ev.end)]
+            sim.run_profiled(m, -1.0, step, sub[0], sub[1])
+            step += m
+            k += m
+            if diag_every > 0 and step % diag_every == 0:
+                sim.diagnostics(probes)
+                nd += 1
         b.record()
         b.synchronize()
         seg_ms.append(a.elapsed_time(b) / seg)
         kern.append(ev.mean_ms_upto(seg))
-        step += seg
     t1 = time.perf_counter()
     d1, _ = sim.diagnostics()
     ev.close()
     pairs = [(d1[k] - d0[k]) / steps for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
     flop = FLOP_FF * pairs[0] + FLOP_FB * pairs[1] + FLOP_BF * pairs[2]
     assert d1["n_nonfinite"] == 0, "non-finite state"
-    return dict(wall_s=t1 - t0, steps=steps, ms_per_step=float(np.median(seg_ms)),
+    return dict(wall_s=t1 - t0, steps=steps, diagnostics=nd, ms_per_step=float(np.median(seg_ms)),
                 segment_ms=seg_ms, interact_ms=float(np.median(kern)), pairs_per_step=pairs,
                 flop_per_launch=flop, sim_time=d1["time"] - d0["time"], umax=d1["umax"],
                 x_front=d1["x_front"])
@@ -168,11 +183,18 @@ def config_table(hip, steps_scale=1.0):
     autotuned launch shape."""
     from paper_2306_01959_amd import autotune, scene
     rows = []
-    for cfg, steps in ((1, 400), (2, 400), (3, 200), (5, 50)):
+    # diagnostics cadence of the workloads: configuration 3 reads four probes
+    # (x = 0.84 - dp, y = 0.3, z = 0.02 ... 0.14) every 10 steps,
+    # configuration 5 the global diagnostics every 100 steps
+    cadence = {3: (10, [[0.84 - 0.005, 0.3, z] for z in (0.02, 0.06, 0.10, 0.14)]),
+               5: (100, None)}
+    for cfg, steps in ((1, 400), (2, 400), (3, 200), (5, 100)):
         sc = scene.config_scene(cfg)
+        every, probes = cadence.get(cfg, (0, None))
         for prec in ("mixed", "fp64"):
             shape = autotune.tune(sc, prec)
-            r = time_gpu(sc, prec, max(REPEATS, int(steps * steps_scale)), 20, hip)
+            r = time_gpu(sc, prec, max(REPEATS, int(steps * steps_scale)), 20, hip,
+                         diag_every=every, probes=probes)
             pps = sc.n / (r["ms_per_step"] * 1e-3)
             rows.append({
                 "config": cfg, "precision": prec, "particles": sc.n, "fluid": sc.n_fluid,
@@ -182,6 +204,7 @@ def config_table(hip, steps_scale=1.0):
                 "pairs_per_s": sum(r["pairs_per_step"]) / (r["ms_per_step"] * 1e-3),
                 "interact_ms": r["interact_ms"],
                 "interact_tflops": r["flop_per_launch"] / (r["interact_ms"] * 1e-3) / 1e12,
+                "diagnostics_every": every, "diagnostics_in_timed_steps": r["diagnostics"],
             })
             print(json.dumps(rows[-1]), flush=True)
     return rows
