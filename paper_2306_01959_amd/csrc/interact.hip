@@ -663,8 +663,12 @@ __device__ __forceinline__ void pair_steps(int n, int slot_s, Idx idx, Rec rec, 
 
 // ================================================================ skeleton
 
+// Mixed precision with groups of 16 or more: the accumulators of the chunk's
+// groups fit 128 registers, four waves per SIMD (a few spilled values
+// outside the pair loop cost less than the occupancy)
 template <class P, int kSplit, int kT, bool kStats, bool kFuse>
-__global__ __launch_bounds__(kWave *kSplit) void k_interact(InteractArgs a) {
+__global__ __launch_bounds__(kWave *kSplit)
+__attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_interact(InteractArgs a) {
     using R = typename P::R;
     using V4 = typename P::V4;
     constexpr int kRows = 2 * (9 / kSplit);  // candidate ranges per wave
