@@ -232,8 +232,12 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False):
     period = 40
     steps = max(period, (steps + period - 1) // period * period)
     mode = lib.RUN_LAGGED
+    # the table's launch shape from the first step on (else tuned on the
+    # warmed-up batch)
+    shape = None if retune else autotune.cached_ensemble_shape(ens, "mixed")
     ens.run(period, -1.0, 0, mode)                      # eager warm-up, steps 0..39
-    shape = autotune.tune_ensemble(ens, "mixed", use_cache=not retune, verbose=retune)
+    if shape is None:
+        shape = autotune.tune_ensemble(ens, "mixed", use_cache=not retune, verbose=retune)
     # restart from the scenes so the timed steps follow the warm-up directly
     ens = lib.Ensemble(scenes, "mixed", stream=ens.stream)
     ens.run(period, -1.0, 0, mode)

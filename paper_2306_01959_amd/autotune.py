@@ -99,6 +99,16 @@ def tune(scene, precision: str = "mixed", steps: int = 30, warmup: int = 5,
     return best
 
 
+def cached_ensemble_shape(ens, precision: str = "mixed"):
+    """The table's (kernel, split, group) for this batch, applied, or None."""
+    tab = _load()
+    key = f"ensemble:{precision}:n={ens.n}:inst={ens.ninst}"
+    if key in tab and "shape" in tab[key]:
+        apply(precision, tab[key]["shape"])
+        return tuple(tab[key]["shape"])
+    return None
+
+
 def tune_ensemble(ens, precision: str = "mixed", steps: int = 20, step0: int = 40,
                   use_cache: bool = True, verbose: bool = False):
     """(kernel, split, group) for a batch (lib.Ensemble), timed on the batch
