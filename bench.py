@@ -213,6 +213,8 @@ def config_table(hip, steps_scale=1.0):
 # algorithmic HBM bytes per particle of the cell-list kernels (mixed state)
 SORT_BYTES_FIRST = 44   # pass 0: histogram reads x, y, z, id and writes the key; scatter
                         # reads the key, writes key + index
+SORT_BYTES_FIRST_KEYS = 16  # pass 0 when the previous (fused) step wrote the keys:
+                            # histogram reads the key; scatter as above
 SORT_BYTES_PASS = 20    # later passes: + the index read
 REORDER_BYTES = 4 + 4 + 84 + 84 + 40  # perm + key in, state gathered (84 B) and written,
                                       # interaction view written (40 B)
@@ -268,7 +270,12 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False):
     # are those of the other steps
     key_bits = int(np.ceil(np.log2(2 * sum(int(np.prod(s.params["dims"])) for s in scenes)))) + 2
     passes = max(1, (key_bits - 2 + 7) // 8)
-    sort_bytes = n * (SORT_BYTES_FIRST + SORT_BYTES_PASS * (passes - 1))
+    # the fused interaction writes the next sort's keys when its occupancy is
+    # fixed (mixed: wave per group, or row split with groups of 16 or more);
+    # the sampled steps follow a fused step
+    keys_written = shape[0] == 2 or (shape[0] == 1 and shape[2] >= 16)
+    first = SORT_BYTES_FIRST_KEYS if keys_written else SORT_BYTES_FIRST
+    sort_bytes = n * (first + SORT_BYTES_PASS * (passes - 1))
     cells = sum(int(np.prod(s.params["dims"])) for s in scenes)
     reorder_bytes = n * REORDER_BYTES + (2 * cells + 1) * TABLE_BYTES
     pairs = [(d1[0][k] - d0[0][k]) / steps for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
@@ -293,7 +300,9 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False):
         "interaction_shape": list(shape),
         "particles": n,
         "particles_per_instance": {"min": min(counts), "max": max(counts)},
-        "sort": dict(bw(sort_bytes, kern["sort"]), passes=passes, key_bits=key_bits),
+        "sort": dict(bw(sort_bytes, kern["sort"]), passes=passes, key_bits=key_bits,
+                     first_pass_keys="written by the fused update" if keys_written
+                     else "computed from the positions"),
         "reorder": bw(reorder_bytes, kern["reorder"]),
         "interact": {"kernel_ms": kern["interact"], "achieved": flop / (kern["interact"] * 1e-3)
                      / 1e12, "unit": "TFLOP/s", "peak": PEAK_FP32_TFLOPS,

@@ -282,19 +282,19 @@ struct Marks {
 };
 
 // full: sort on the sub-cell bits too (see kSubBits); the steps between
-// refreshes sort on the cell key alone.  keys_ready: the previous update of
-// this same run wrote the keys of the current positions and their first
-// digit counts (else both are computed from the positions here).
+// refreshes sort on the cell key alone.  keys (KeysLeft): what the previous
+// step of this same run left (else the keys and counts are computed from the
+// positions here).
 static int build_cells(const Problem &P, sph_state &s, const Ws &w, hipStream_t st,
                        bool lagged = false, double dt = 0.0, const Marks &m = Marks(),
-                       bool full = true, bool keys_ready = false) {
+                       bool full = true, int keys = kNoKeys) {
     if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
-    uint32_t *keys = nullptr, *perm = nullptr;
+    uint32_t *sorted = nullptr, *perm = nullptr;
     if (int rc = m.at(SPH_REGION_SORT, true, st)) return rc;
-    if (int rc = launch_sort(P, s, w, st, full, keys_ready, &keys, &perm)) return rc;
+    if (int rc = launch_sort(P, s, w, st, full, keys, &sorted, &perm)) return rc;
     if (int rc = m.at(SPH_REGION_SORT, false, st)) return rc;
     if (int rc = m.at(SPH_REGION_REORDER, true, st)) return rc;
-    if (int rc = launch_reorder(P, s, w, keys, perm, st)) return rc;
+    if (int rc = launch_reorder(P, s, w, sorted, perm, st)) return rc;
     if (int rc = m.at(SPH_REGION_REORDER, false, st)) return rc;
     if (int rc = launch_chunks(P, w, lagged, dt, st)) return rc;
     s.cells_valid = 1;
@@ -314,10 +314,10 @@ static int64_t refresh_period(const Problem &P) {
 // One step.  fused: the lagged-dt form, where the interaction also advances
 // the state (one kernel instead of interaction + update).
 static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
-                    bool fused, hipStream_t st, const Marks &m = Marks(), bool keys_ready = false) {
+                    bool fused, hipStream_t st, const Marks &m = Marks(), int keys = kNoKeys) {
     if (!s.cells_valid) {
         const bool full = step % refresh_period(P) == 0;
-        if (int rc = build_cells(P, s, w, st, fused, dt, m, full, keys_ready)) return rc;
+        if (int rc = build_cells(P, s, w, st, fused, dt, m, full, keys)) return rc;
     } else {
         if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
         if (int rc = launch_chunks(P, w, fused, dt, st)) return rc;  // fresh dt bound
@@ -339,6 +339,14 @@ static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int6
     if (int rc = m.at(SPH_REGION_STEP, false, st)) return rc;
     s.cells_valid = 0;
     return SPH_OK;
+}
+
+// What a step leaves for the next sort (KeysLeft): the update kernel writes
+// the keys and counts their first digits; a fused interaction may write the
+// keys.
+static int keys_after(const Problem &P, bool fused) {
+    if (!fused) return kKeysCounted;
+    return fused_writes_keys(P) ? kKeysOnly : kNoKeys;
 }
 
 static int64_t gcd64(int64_t a, int64_t b) {
@@ -382,11 +390,10 @@ static int graph_steps(const Problem &P, sph_state &s, const Ws &w, double dt, i
         return rc;
     int rc = SPH_OK;
     // the first captured step computes its keys from the positions (a replay
-    // may follow anything); the later ones take those of the update before,
-    // unless that was a fused step, which writes none
+    // may follow anything); the later ones take what the step before left
     for (int64_t k = 0; k < len && rc == SPH_OK; ++k)
         rc = one_step(P, s, w, dt, step + k, lagged && step + k > 0, st, Marks(),
-                      k > 0 && !(lagged && step + k - 1 > 0));
+                      k > 0 ? keys_after(P, lagged && step + k - 1 > 0) : kNoKeys);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(st, &g);
     if (rc == SPH_OK) rc = hip_check(ec, "end capture");
@@ -416,9 +423,9 @@ static int run_steps(const Problem &P, sph_state &s, const Ws &w, int64_t nsteps
     const int64_t L = (mode & SPH_RUN_GRAPH) ? graph_period(P) : 0;
     int64_t k = 0;
     // the first step of a call computes its keys from the positions (the
-    // caller may have moved particles); later steps take the keys the
-    // previous step's update wrote (a fused step writes none)
-    bool keys_ready = false;
+    // caller may have moved particles); later steps take what the previous
+    // step left
+    int keys = kNoKeys;
     while (k < nsteps) {
         const int64_t idx = step0 + k;
         if (L > 0 && idx > 0 && idx % L == 0 && nsteps - k >= L && !ev_begin) {
@@ -426,7 +433,7 @@ static int run_steps(const Problem &P, sph_state &s, const Ws &w, int64_t nsteps
             s.cells_valid = 0;  // every captured step rebuilds its cells
             if (int rc = graph_steps(P, s, w, dt, idx, L, reps, lagged, st)) return rc;
             k += reps * L;
-            keys_ready = !lagged;
+            keys = keys_after(P, lagged);  // the graph's last step has index > 0
             continue;
         }
         Marks m;
@@ -435,8 +442,8 @@ static int run_steps(const Problem &P, sph_state &s, const Ws &w, int64_t nsteps
             m.e0 = static_cast<hipEvent_t>(ev_begin[k]);
             m.e1 = static_cast<hipEvent_t>(ev_end[k]);
         }
-        if (int rc = one_step(P, s, w, dt, idx, lagged && idx > 0, st, m, keys_ready)) return rc;
-        keys_ready = !(lagged && idx > 0);
+        if (int rc = one_step(P, s, w, dt, idx, lagged && idx > 0, st, m, keys)) return rc;
+        keys = keys_after(P, lagged && idx > 0);
         ++k;
     }
     return SPH_OK;

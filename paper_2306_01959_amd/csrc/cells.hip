@@ -345,13 +345,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 }
 
 // full: sort on every key bit; else on the cell key only (the sub-cell bits
-// keep the order of the input).  keys_ready: w.keys_next() holds the keys of
-// the current positions and w.hist() the first pass's digit counts (the
-// previous update wrote both, for this step's `full`); else the first
-// histogram pass computes the keys and counts them.  The first pass reads w.keys_next() and
-// writes the buffer that makes the keys/keys_alt ping-pong end in w.keys().
+// keep the order of the input).  keys (KeysLeft): kKeysOnly, w.keys_next()
+// holds the keys of the current positions; kKeysCounted, w.hist() also holds
+// the first pass's digit counts (both for this step's `full`); kNoKeys, the
+// first histogram pass computes the keys and counts them.
 int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st, bool full,
-                bool keys_ready, uint32_t **sorted_keys, uint32_t **perm) {
+                int keys, uint32_t **sorted_keys, uint32_t **perm) {
     const int64_t n = w.L.n;
     const int ntiles = (int)w.L.ntiles;
     const int low = full ? 0 : kSubBits;
@@ -367,9 +366,9 @@ int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t s
         const int shift = low + pass * kRadixBits;
         uint32_t *vout = vbuf[pass & 1];
         const EncodeArgs e{s.x, s.y, s.z, s.id, insts_of(P, w), kin};
-        const bool encode = pass == 0 && !keys_ready;
-        // with keys_ready the update has also counted the first pass's digits
-        const bool counted = pass == 0 && keys_ready;
+        const bool encode = pass == 0 && keys == kNoKeys;
+        // the update kernel has also counted the first pass's digits
+        const bool counted = pass == 0 && keys == kKeysCounted;
         if (!counted && small) {
             if (encode)
                 hipLaunchKernelGGL((k_sort_hist<kSortItemsSmall, true>), dim3(ntiles),

@@ -284,8 +284,14 @@ int hip_check(hipError_t e, const char *what);
 int launch_check(const char *what);
 
 // Launchers implemented in the kernel translation units.
+// What the previous step of a run leaves for the next sort: nothing, the keys
+// of the current positions (a fused interaction that writes them), or the
+// keys and their first-pass digit counts (the update kernel).
+enum KeysLeft { kNoKeys = 0, kKeysOnly = 1, kKeysCounted = 2 };
 int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st, bool full,
-                bool keys_ready, uint32_t **sorted_keys, uint32_t **perm);
+                int keys, uint32_t **sorted_keys, uint32_t **perm);
+// the fused interaction launched for P also writes the next sort's keys
+bool fused_writes_keys(const Problem &P);
 // exclusive scan of m values from `in` (left intact) to `out`; tot:
 // ceil(m / kScanSpan) values of scratch
 int launch_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tot, hipStream_t st);

@@ -663,6 +663,12 @@ __device__ __forceinline__ void pair_steps(int n, int slot_s, Idx idx, Rec rec, 
 
 // ================================================================ skeleton
 
+// Fused steps that also write the next sort's keys: the kernels whose
+// occupancy is fixed by their launch attributes (mixed precision, wave per
+// group; row split with groups of 16 or more), so the key costs no waves.
+template <class P, int kT>
+constexpr bool kFusedKeys = P::kMixed && kT >= 16;
+
 // Mixed precision with groups of 16 or more: the accumulators of the chunk's
 // groups fit 128 registers, four waves per SIMD (a few spilled values
 // outside the pair loop cost less than the occupancy)
@@ -967,7 +973,7 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
             const double dt = a.ist[inst].dt_last;
             const bool euler =
                 a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
-            wcsph::advance<P::kMixed, false>(a.state, ip, it, dt, euler, fax, fay, faz, (double)sd);
+            wcsph::advance<P::kMixed, kFusedKeys<P, kT>>(a.state, ip, it, dt, euler, fax, fay, faz, (double)sd);
         }
     }
     bound = group_min(bound, kWave);
@@ -1170,7 +1176,7 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
                 const double dt = a.ist[inst].dt_last;
                 const bool euler =
                     a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
-                wcsph::advance<P::kMixed, false>(a.state, ip, it, dt, euler, fax, fay, faz, (double)acc.dr);
+                wcsph::advance<P::kMixed, P::kMixed>(a.state, ip, it, dt, euler, fax, fay, faz, (double)acc.dr);
             }
         }
         bound = group_min(bound, kWave);
@@ -1547,6 +1553,13 @@ int kernel_for(const Problem &P) {
     return g_kernel[pr] ? g_kernel[pr] : SPH_KERNEL_ROWS;
 }
 
+bool fused_writes_keys(const Problem &P) {
+    // the kernels instantiated with kFusedKeys
+    if (P.precision != SPH_MIXED) return false;
+    const int k = kernel_for(P);
+    return k == SPH_KERNEL_GROUPS || (k == SPH_KERNEL_ROWS && group_for(P) >= 16);
+}
+
 int chunk_for(const Problem &P) {
     const int k = kernel_for(P);
     if (k == SPH_KERNEL_GROUPS) return group_for(P);
@@ -1721,7 +1734,7 @@ int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream
     a.st_nb = st_nb;
     a.st_hash = st_hash;
     a.state = StateArrays{s.x,   s.y,   s.z,   s.ux,   s.uy,  s.uz,
-                          s.uxm, s.uym, s.uzm, s.rho,  s.rhom, s.id, nullptr};
+                          s.uxm, s.uym, s.uzm, s.rho,  s.rhom, s.id, w.keys_next()};
     a.step = step;
     const bool stats = st_nf != nullptr;
     // chunks of <= csz targets: at most ceil(particles / csz) + 1 per half-row
