@@ -200,7 +200,7 @@ struct Mixed {
         fi = act && v2.y > 0.f;
         t0 = make_float4(v0.x, v0.y, v0.z, (float)cix);
         t1 = v1;
-        t2 = make_float4(fi ? v2.x : 0.f, v0.w, -(float)ip.alpha * fabsf(v2.y), 0.f);
+        t2 = make_float4(fi ? v2.x : 0.f, v0.w, -(float)(ip.alpha * ip.h) * fabsf(v2.y), 0.f);
         const float csf = (float)ip.cs;
         bx = v0.x + (float)(cix - cxa) * csf;
         by = v0.y;
@@ -257,7 +257,7 @@ struct Mixed {
                             c.v0.z + (float)dz * csf);
         *rec1 = make_float4(c.v1.x, c.v1.y, c.v1.z, c.v1.w * invr);
         *rec2 = make_float4(0.f, invr, c.v0.w * B, B);
-        *rec3 = make_float4(c.v0.w, c.v2.y, __int_as_float(j), -(float)ip.alpha * fabsf(c.v2.y));
+        *rec3 = make_float4(c.v0.w, c.v2.y, __int_as_float(j), -(float)(ip.alpha * ip.h) * fabsf(c.v2.y));
     }
     // one (target, record) pair; `valid` is false for idle lanes; kCls: the
     // class of every target (kAnyTargets: read per target)
@@ -288,29 +288,30 @@ struct Mixed {
         // are zeroed through F and the |mu| select
         const float r = __builtin_amdgcn_sqrtf(rr);
         const float q2 = fmaf(r, -0.5f * (float)ip.invh, 1.f);  // 1 - q/2
-        const float Fr = (float)ip.Fm * q2 * q2 * q2;              // m 5 w_D/h^2 (1-q/2)^3
+        const float Fr = q2 * q2 * q2;  // (1-q/2)^3; store() applies m 5 w_D/h^2
         const float F = in ? Fr : 0.f;
         const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const float vr = vx * dx + vy * dy + vz * dz;               // u_ij . r_ij
         if constexpr (kCls == kBoundaryTargets) {
             // continuity over fluid j, and |mu| for the time step; nothing else
-            const float mu = (float)ip.h * vr * __builtin_amdgcn_rcpf(rr + (float)ip.eta2);
+            const float mu = vr * __builtin_amdgcn_rcpf(rr + (float)ip.eta2);  // mu / h
             const float amu = in ? fabsf(mu) : 0.f;
             acc.mu = amu > acc.mu ? amu : acc.mu;
             acc.dr -= F * vr;
             return;
         }
-        // one reciprocal for mu = h vr / (r^2 + eta^2) and the viscosity's
-        // mu / (rho_i + rho_j): hvi = h vr / ((r^2 + eta^2)(rho_i + rho_j))
+        // one reciprocal for mu / h = vr / (r^2 + eta^2) and the viscosity's
+        // mu / (h (rho_i + rho_j)) = hvi; the factor h is in the -alpha |c|
+        // terms of target and record, and store() applies it to max |mu|
         const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r3.x;  // rho_i + rho_j
-        const float hvi = (float)ip.h * vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
+        const float hvi = vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
         const float mu = hvi * rsum;
         const float amu = in ? fabsf(mu) : 0.f;
         acc.mu = amu > acc.mu ? amu : acc.mu;
         acc.dr -= F * vr;                                    // m (u_i - u_j) . grad_i W_ij
         const float Fd = kCls == kFluidTargets ? F : fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;             // delta term
-        const float visc = vr < 0.f ? (t.c.z + r3.w) * hvi : 0.f;  // -alpha (c_i + c_j) hvi
+        const float visc = vr < 0.f ? (t.c.z + r3.w) * hvi : 0.f;  // -alpha h (c_i + c_j) hvi
         const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -350,17 +351,17 @@ struct Mixed {
         }
         const float r = __builtin_amdgcn_sqrtf(rr);
         const float q2 = fmaf(r, -0.5f * (float)ip.invh, 1.f);
-        const float F = valid ? (float)ip.Fm * q2 * q2 * q2 : 0.f;
+        const float F = valid ? q2 * q2 * q2 : 0.f;
         const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const float vr = vx * dx + vy * dy + vz * dz;
         const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r3.x;  // rho_i + rho_j
-        const float hvi = (float)ip.h * vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
+        const float hvi = vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
         const float mu = hvi * rsum;
         acc.mu = valid ? fmaxf(acc.mu, fabsf(mu)) : acc.mu;
         acc.dr -= F * vr;
         const float Fd = fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;
-        const float visc = vr < 0.f ? (t.c.z + r3.w) * hvi : 0.f;  // -alpha (c_i + c_j) hvi
+        const float visc = vr < 0.f ? (t.c.z + r3.w) * hvi : 0.f;  // -alpha h (c_i + c_j) hvi
         const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -368,9 +369,17 @@ struct Mixed {
     }
     // final sums of target i: + g for fluid; optional store of the rates;
     // the particle's time-step bound (eq. sphdt); FP64 accelerations out
-    __device__ static void store(const InteractArgs &a, const Inst &ip, int i, bool fi, float ax,
-                                 float ay, float az, float dr, float mum, bool write,
+    // (the sums arrive without the factors the pair terms leave out: m 5 w_D /
+    // h^2 of the gradient and h of mu; they are applied here, in place)
+    __device__ static void store(const InteractArgs &a, const Inst &ip, int i, bool fi, float &ax,
+                                 float &ay, float &az, float &dr, float &mum, bool write,
                                  double &bound, double &oax, double &oay, double &oaz) {
+        const float fm = (float)ip.Fm;
+        ax *= fm;
+        ay *= fm;
+        az *= fm;
+        dr *= fm;
+        mum *= (float)ip.h;
         float fax = 0.f, fay = 0.f, faz = 0.f;
         if (fi) {
             fax = ax + (float)ip.gx;
@@ -425,7 +434,7 @@ struct Fp64 {
         fi = act && v2.y > 0.0;
         t0 = make_double4(v0.x, v0.y, v0.z, 0.0);
         t1 = v1;
-        t2 = make_double4(fi ? v2.x : 0.0, v0.w, -ip.alpha * fabs(v2.y), 0.0);
+        t2 = make_double4(fi ? v2.x : 0.0, v0.w, -(ip.alpha * ip.h) * fabs(v2.y), 0.0);
         bx = v0.x;
         by = v0.y;
         bz = v0.z;
@@ -477,7 +486,7 @@ struct Fp64 {
         *rec0 = make_double4(c.v0.x, c.v0.y, c.v0.z, (double)j);
         *rec1 = make_double4(c.v1.x, c.v1.y, c.v1.z, c.v1.w * invr);
         *rec2 = make_double4(invr, B, c.v0.w, 0.0);
-        *rec3 = make_double4(0.0, c.v2.y, 0.0, -ip.alpha * fabs(c.v2.y));
+        *rec3 = make_double4(0.0, c.v2.y, 0.0, -(ip.alpha * ip.h) * fabs(c.v2.y));
     }
     template <bool kStats, int kCls = kAnyTargets>
     __device__ static void pair(const InteractArgs &a, const Inst &ip, const T &t, int ti, bool valid,
@@ -501,13 +510,13 @@ struct Fp64 {
         // evaluated on every lane (no branch); lanes outside the support
         // are zeroed through F and the |mu| select
         const double q2 = 1.0 - 0.5 * (sqrt(rr) * ip.invh);
-        const double Fr = ip.Fm * q2 * q2 * q2;
+        const double Fr = q2 * q2 * q2;  // store() applies m 5 w_D/h^2
         const double F = in ? Fr : 0.0;
         const double vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const double vr = vx * dx + vy * dy + vz * dz;
         if constexpr (kCls == kBoundaryTargets) {
             // continuity over fluid j, and |mu| for the time step; nothing else
-            const double mu = ip.h * vr / (rr + ip.eta2);
+            const double mu = vr / (rr + ip.eta2);  // mu / h
             const double amu = in ? fabs(mu) : 0.0;
             acc.mu = amu > acc.mu ? amu : acc.mu;
             acc.dr -= F * vr;
@@ -516,14 +525,14 @@ struct Fp64 {
         // one division for mu = h vr / (r^2 + eta^2) and the viscosity's
         // mu / (rho_i + rho_j)
         const double rsum = t.c.y + r2.z;  // rho_i + rho_j
-        const double hvi = ip.h * vr / ((rr + ip.eta2) * rsum);
+        const double hvi = vr / ((rr + ip.eta2) * rsum);  // h and the -alpha h |c| terms as in Mixed
         const double mu = hvi * rsum;
         const double amu = in ? fabs(mu) : 0.0;
         acc.mu = amu > acc.mu ? amu : acc.mu;
         acc.dr -= F * vr;
         const double Fd = kCls == kFluidTargets ? F : fi ? F : 0.0;
         acc.dr += (r2.z - t.c.y) * r2.y * Fd;
-        const double visc = vr < 0.0 ? (t.c.z + r3.w) * hvi : 0.0;  // -alpha (c_i + c_j) hvi
+        const double visc = vr < 0.0 ? (t.c.z + r3.w) * hvi : 0.0;  // -alpha h (c_i + c_j) hvi
         const double s = (fma(t.b.w, r2.x, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -551,26 +560,31 @@ struct Fp64 {
             st.h += id_hash(a.id[(int)r0.w] & 0x7fffffffu);
         }
         const double q2 = 1.0 - 0.5 * (sqrt(rr) * ip.invh);
-        const double F = valid ? ip.Fm * q2 * q2 * q2 : 0.0;
+        const double F = valid ? q2 * q2 * q2 : 0.0;
         const double vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const double vr = vx * dx + vy * dy + vz * dz;
         const double rsum = t.c.y + r2.z;  // rho_i + rho_j
-        const double hvi = ip.h * vr / ((rr + ip.eta2) * rsum);
+        const double hvi = vr / ((rr + ip.eta2) * rsum);  // h and the -alpha h |c| terms as in Mixed
         const double mu = hvi * rsum;
         acc.mu = valid ? fmax(acc.mu, fabs(mu)) : acc.mu;
         acc.dr -= F * vr;
         const double Fd = fi ? F : 0.0;
         acc.dr += (r2.z - t.c.y) * r2.y * Fd;
-        const double visc = vr < 0.0 ? (t.c.z + r3.w) * hvi : 0.0;  // -alpha (c_i + c_j) hvi
+        const double visc = vr < 0.0 ? (t.c.z + r3.w) * hvi : 0.0;  // -alpha h (c_i + c_j) hvi
         const double s = (fma(t.b.w, r2.x, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
         acc.az -= s * dz;
     }
     __device__ static void store(const InteractArgs &a, const Inst &ip, int i, bool fi,
-                                 double ax, double ay, double az, double dr, double mum,
+                                 double &ax, double &ay, double &az, double &dr, double &mum,
                                  bool write, double &bound, double &oax, double &oay,
                                  double &oaz) {
+        ax *= ip.Fm;
+        ay *= ip.Fm;
+        az *= ip.Fm;
+        dr *= ip.Fm;
+        mum *= ip.h;
         double fax = 0, fay = 0, faz = 0;
         if (fi) {
             fax = ax + ip.gx;
