@@ -296,7 +296,7 @@ struct Mixed {
             // continuity over fluid j, and |mu| for the time step; nothing else
             const float mu = vr * __builtin_amdgcn_rcpf(rr + (float)ip.eta2);  // mu / h
             const float amu = in ? fabsf(mu) : 0.f;
-            acc.mu = amu > acc.mu ? amu : acc.mu;
+            acc.mu = fmaxf(acc.mu, amu);
             acc.dr -= F * vr;
             return;
         }
@@ -307,11 +307,11 @@ struct Mixed {
         const float hvi = vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
         const float mu = hvi * rsum;
         const float amu = in ? fabsf(mu) : 0.f;
-        acc.mu = amu > acc.mu ? amu : acc.mu;
+        acc.mu = fmaxf(acc.mu, amu);
         acc.dr -= F * vr;                                    // m (u_i - u_j) . grad_i W_ij
         const float Fd = kCls == kFluidTargets ? F : fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;             // delta term
-        const float visc = vr < 0.f ? (t.c.z + r3.w) * hvi : 0.f;  // -alpha h (c_i + c_j) hvi
+        const float visc = (t.c.z + r3.w) * fminf(hvi, 0.f);  // -alpha h (c_i + c_j) hvi if vr < 0
         const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -361,7 +361,7 @@ struct Mixed {
         acc.dr -= F * vr;
         const float Fd = fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;
-        const float visc = vr < 0.f ? (t.c.z + r3.w) * hvi : 0.f;  // -alpha h (c_i + c_j) hvi
+        const float visc = (t.c.z + r3.w) * fminf(hvi, 0.f);  // -alpha h (c_i + c_j) hvi if vr < 0
         const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -518,7 +518,7 @@ struct Fp64 {
             // continuity over fluid j, and |mu| for the time step; nothing else
             const double mu = vr / (rr + ip.eta2);  // mu / h
             const double amu = in ? fabs(mu) : 0.0;
-            acc.mu = amu > acc.mu ? amu : acc.mu;
+            acc.mu = fmax(acc.mu, amu);
             acc.dr -= F * vr;
             return;
         }
@@ -528,11 +528,11 @@ struct Fp64 {
         const double hvi = vr / ((rr + ip.eta2) * rsum);  // h and the -alpha h |c| terms as in Mixed
         const double mu = hvi * rsum;
         const double amu = in ? fabs(mu) : 0.0;
-        acc.mu = amu > acc.mu ? amu : acc.mu;
+        acc.mu = fmax(acc.mu, amu);
         acc.dr -= F * vr;
         const double Fd = kCls == kFluidTargets ? F : fi ? F : 0.0;
         acc.dr += (r2.z - t.c.y) * r2.y * Fd;
-        const double visc = vr < 0.0 ? (t.c.z + r3.w) * hvi : 0.0;  // -alpha h (c_i + c_j) hvi
+        const double visc = (t.c.z + r3.w) * fmin(hvi, 0.0);  // -alpha h (c_i + c_j) hvi if vr < 0
         const double s = (fma(t.b.w, r2.x, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -570,7 +570,7 @@ struct Fp64 {
         acc.dr -= F * vr;
         const double Fd = fi ? F : 0.0;
         acc.dr += (r2.z - t.c.y) * r2.y * Fd;
-        const double visc = vr < 0.0 ? (t.c.z + r3.w) * hvi : 0.0;  // -alpha h (c_i + c_j) hvi
+        const double visc = (t.c.z + r3.w) * fmin(hvi, 0.0);  // -alpha h (c_i + c_j) hvi if vr < 0
         const double s = (fma(t.b.w, r2.x, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
