@@ -25,7 +25,9 @@
 // support.  Each lane accumulates per group; at the end the lanes that share
 // a target are summed with a fixed shuffle tree (gather form: no atomics,
 // deterministic).  Candidate-only quantities (P_j/rho_j, the delta-term
-// factors) are computed once at staging.
+// factors) are computed once at staging; factors common to all of a target's
+// pairs (m 5 w_D / h^2 of the gradient, h of mu) are applied to its sums once,
+// in store().
 //
 // Mixed precision: positions are an integer cell plus an FP32 offset from the
 // cell centre.  The displacement r_j - r_i along an axis is
