@@ -99,9 +99,10 @@ __device__ __forceinline__ T group_max(T v, int width) {
     return v;
 }
 
-__device__ __forceinline__ uint64_t lanes_below() {
-    uint32_t lane = __lane_id();
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+// Lanes below this one among those set in m (the hardware lane-rank count).
+__device__ __forceinline__ int rank_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -770,7 +771,6 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
     const uint64_t fluid_tgts = __ballot(fi_own);
     const bool any_fluid = fluid_tgts != 0ull;
     const R cull2 = (R)(ip.r2max * (1.0 + 1e-3));
-    const uint64_t below = lanes_below();
 
     // this wave's candidate ranges: {first, end, half-row key base, code}
     if (lane < kRows) {
@@ -813,7 +813,7 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
         }
         const uint64_t m = __ballot(keep);
         if (keep) {
-            const int slot = __popcll(m & below);
+            const int slot = rank_below(m);
             P::stage(a, ip, cur, rq.z, jb + lane, dy, dz, &stg[w][0][slot], &stg[w][1][slot],
                      &stg[w][2][slot], &stg[w][3][slot]);
         }
@@ -839,7 +839,7 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
                 const R ez = fmax(fmax(gbox[g][4] - pz, pz - gbox[g][5]), (R)0);
                 const bool k = lane < cnt && (ex * ex + ey * ey + ez * ez) <= cull2 && (gf || rf);
                 const uint64_t gm = __ballot(k);
-                if (k) glist[w][g][__popcll(gm & below)] = (uint8_t)lane;
+                if (k) glist[w][g][rank_below(gm)] = (uint8_t)lane;
                 gcnt[g] = __popcll(gm);
                 if constexpr (kSentinel) {
                     if (lane < kG) glist[w][g][gcnt[g] + lane] = (uint8_t)kWave;
@@ -1036,7 +1036,6 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
     V4(*stg)[kSlots] = stg_all[w];
     const int t_in = lane % kT;
     const int slot_s = lane / kT;
-    const uint64_t below = lanes_below();
     Counters cn;
     {
         const uint32_t item = blockIdx.x * kWavesPerGroupWG + w;
@@ -1139,7 +1138,7 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
             }
             const uint64_t m = __ballot(keep);
             if (keep) {
-                const int slot = nst + __popcll(m & below);
+                const int slot = nst + rank_below(m);
                 P::stage(a, ip, cur, nbase, jb + lane, dy, dz, &stg[0][slot], &stg[1][slot],
                          &stg[2][slot], &stg[3][slot]);
             }
@@ -1236,7 +1235,6 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
     __shared__ int anyf;
     const int w = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const uint64_t below = lanes_below();
     const uint32_t chunk = blockIdx.x;
     if (chunk >= a.sc->nchunks) return;
     const int4 ch = a.chunks[chunk];
@@ -1341,7 +1339,7 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
         }
         const uint64_t m = __ballot(keep);
         if (keep) {
-            const int slot = w * kWave + __popcll(m & below);
+            const int slot = w * kWave + rank_below(m);
             P::stage(a, ip, cur, nbase, jb + w * kWave + lane, dy, dz, &pool[buf][0][slot],
                      &pool[buf][1][slot], &pool[buf][2][slot], &pool[buf][3][slot]);
         }
@@ -1369,7 +1367,7 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
                     kk = (ex * ex + ey * ey + ez * ez) <= cull2 && (my_fluid || P::rec_fluid(r3));
                 }
                 const uint64_t gm = __ballot(kk);
-                if (kk) glist[w][n + __popcll(gm & below)] = (uint8_t)(k * kWave + lane);
+                if (kk) glist[w][n + rank_below(gm)] = (uint8_t)(k * kWave + lane);
                 n += __popcll(gm);
             }
             wave_sync();
@@ -1387,7 +1385,7 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
                     cn.in += in ? 1u : 0u;
                     cn.fj += (in && fj) ? 1u : 0u;
                     const uint64_t mine = inm & same_t;
-                    if (in) tl[nn + __popcll(mine & below)] = (uint8_t)k;
+                    if (in) tl[nn + rank_below(mine)] = (uint8_t)k;
                     nn += __popcll(mine);
                 }
                 wave_sync();
