@@ -856,22 +856,34 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
                 tg.c = tgt[2][tidx];
                 const int ti = cs0 + tidx;
                 const int gn = gcnt[g];
-                // (one pair body for both target classes: two would cost this
-                // kernel's occupancy)
-                pair_steps<V4, kG, false>(
-                    gn, slot_s,
-                    [&](int sl) { return kSentinel || sl < gn ? (int)glist[w][g][sl] : 0; },
-                    [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
-                        r0 = stg[w][0][k];
-                        r1 = stg[w][1][k];
-                        r2 = stg[w][2][k];
-                        r3 = stg[w][3][k];
-                    },
-                    [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
-                        P::template pair<kStats>(a, ip, tg, ti,
-                                                 kSentinel || (sl < gn && tidx < ntgt), r0, r1,
-                                                 r2, r3, acc[g], cn, sts[g]);
-                    });
+                auto steps = [&](auto cls) __attribute__((always_inline)) {
+                    pair_steps<V4, kG, false>(
+                        gn, slot_s,
+                        [&](int sl) { return kSentinel || sl < gn ? (int)glist[w][g][sl] : 0; },
+                        [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
+                            r0 = stg[w][0][k];
+                            r1 = stg[w][1][k];
+                            r2 = stg[w][2][k];
+                            r3 = stg[w][3][k];
+                        },
+                        [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
+                            P::template pair<kStats, decltype(cls)::value>(
+                                a, ip, tg, ti, kSentinel || (sl < gn && tidx < ntgt), r0, r1,
+                                r2, r3, acc[g], cn, sts[g]);
+                        });
+                };
+                // a pair body per target class (the chunk is all fluid or all
+                // boundary) where the occupancy is fixed by the launch
+                // attributes; elsewhere one body for both (two would cost
+                // this kernel's occupancy)
+                if constexpr (P::kMixed && kT >= 16) {
+                    if (any_fluid)
+                        steps(std::integral_constant<int, kFluidTargets>{});
+                    else
+                        steps(std::integral_constant<int, kBoundaryTargets>{});
+                } else {
+                    steps(std::integral_constant<int, kAnyTargets>{});
+                }
             }
         }
         wave_sync();
