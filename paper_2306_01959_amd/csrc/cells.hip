@@ -105,7 +105,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t *__re
     const int tid = threadIdx.x;
     for (int d = tid; d < kRadix; d += kSortThreads) h[d] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortThreads * kItems;
+    const int tile = tile_of_block(blockIdx.x, ntiles);
+    const int64_t base = (int64_t)tile * kSortThreads * kItems;
     uint32_t key[kItems];
     if constexpr (kEncode) {
         encode_keys<kItems>(e, base, n, key);
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t *__re
     for (int it = 0; it < kItems; ++it)
         tile_hist_add(h, key[it], base + (int64_t)it * kSortThreads + tid < n, shift);
     __syncthreads();
-    for (int d = tid; d < kRadix; d += kSortThreads) hist[(int64_t)d * ntiles + blockIdx.x] = h[d];
+    for (int d = tid; d < kRadix; d += kSortThreads) hist[(int64_t)d * ntiles + tile] = h[d];
 }
 
 // Exclusive scan (the (digit, tile) counts, the chunks per half-row).  A
@@ -297,7 +298,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const int tid = threadIdx.x;
     const int w = tid / kWave, lane = tid % kWave;
     for (int d = lane; d < kRadix; d += kWave) wcnt[w][d] = 0u;
-    const int64_t wbase = (int64_t)blockIdx.x * kSortThreads * kItems + (int64_t)w * kWave * kItems;
+    const int tile = tile_of_block(blockIdx.x, ntiles);
+    const int64_t wbase = (int64_t)tile * kSortThreads * kItems + (int64_t)w * kWave * kItems;
     uint32_t key[kItems], val[kItems], rank[kItems];
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     __syncthreads();
     {
         const int d = tid;
-        uint32_t run = hist[(int64_t)d * ntiles + blockIdx.x];
+        uint32_t run = hist[(int64_t)d * ntiles + tile];
 #pragma unroll
         for (int k = 0; k < kWaves; ++k) {
             const uint32_t c = wcnt[k][d];

@@ -101,6 +101,19 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
     return peers;
 }
 
+// The sort tile that block b of a one-block-per-tile launch handles.  The
+// hardware deals consecutive workgroups to the 8 XCDs in turn, and each XCD
+// has its own L2; the blocks an XCD receives (b mod 8 equal) take a
+// contiguous run of tiles, so the per-tile digit counts (digit-major,
+// neighbouring tiles in one cache line) are written and read through one
+// L2 instead of being written back a few bytes at a time from eight.  A
+// bijection on [0, ntiles) whatever the placement.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int tile_of_block(int b, int ntiles) {
+    const int per = ntiles / kXcds, rem = ntiles % kXcds, x = b % kXcds;
+    return x * per + (x < rem ? x : rem) + b / kXcds;
+}
+
 // Adds a wave's keys (those with ok) to a sort tile's digit counts in LDS:
 // one atomic per distinct digit of the wave.  All lanes of the wave call it.
 __device__ __forceinline__ void tile_hist_add(uint32_t *h, uint32_t key, bool ok, int shift) {

@@ -62,7 +62,8 @@ __global__ __launch_bounds__(kUpdateThreads) void k_integrate(IntegrateArgs a) {
         __syncthreads();
     }
     const int64_t n = a.n;
-    const int64_t base = (int64_t)blockIdx.x * kUpdateThreads * kItems;
+    const int tile = tile_of_block(blockIdx.x, a.ntiles);
+    const int64_t base = (int64_t)tile * kUpdateThreads * kItems;
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
         const int64_t i = base + (int64_t)it * kUpdateThreads + tid;
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(kUpdateThreads) void k_integrate(IntegrateArgs a) {
     if (a.hist) {
         __syncthreads();
         for (int d = tid; d < kRadix; d += kUpdateThreads)
-            a.hist[(int64_t)d * a.ntiles + blockIdx.x] = h[d];
+            a.hist[(int64_t)d * a.ntiles + tile] = h[d];
     }
 }
 
