@@ -314,12 +314,28 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     for (int it = 0; it < kItems; ++it) {
         const bool ok = wbase + (int64_t)it * kWave + lane < n;
         const uint32_t d = (key[it] >> shift) & (kRadix - 1);
-        const uint64_t peers = match_digit(d, __ballot(ok));
-        const uint32_t r = (uint32_t)__popcll(peers & lt);
+        // r: earlier lanes of this wave with the same digit; cnt (on the
+        // first of them): all of them.  Where the wave's digits do not
+        // decrease from lane to lane (nearly sorted keys, the usual case)
+        // equal digits are one run of consecutive lanes; else match digits.
+        const uint32_t dk = ok ? d : (uint32_t)kRadix;  // kRadix: no key
+        uint32_t r, cnt;
+        // (the shuffle outside the condition: every lane takes part in it)
+        const uint32_t dprev = __shfl_up(dk, 1, kWave);
+        if (__ballot(lane > 0 && dk < dprev) == 0) {
+            const uint64_t starts = run_starts(dk);
+            const uint64_t at_or_below = starts & (lt | (1ull << lane));
+            r = (uint32_t)(lane - (63 - __builtin_clzll(at_or_below)));
+            cnt = run_length(starts);
+        } else {
+            const uint64_t peers = match_digit(d, __ballot(ok));
+            r = (uint32_t)__popcll(peers & lt);
+            cnt = (uint32_t)__popcll(peers);
+        }
         const uint32_t before = wcnt[w][d];
         rank[it] = before + r;
         wave_sync();  // every lane has read before the leader updates
-        if (ok && r == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+        if (ok && r == 0) wcnt[w][d] = before + cnt;
         wave_sync();
     }
     __syncthreads();

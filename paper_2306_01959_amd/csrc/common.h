@@ -114,12 +114,29 @@ __device__ __forceinline__ int tile_of_block(int b, int ntiles) {
     return x * per + (x < rem ? x : rem) + b / kXcds;
 }
 
+// Lanes that start a run of equal values v in consecutive lanes (lane 0
+// always does).
+__device__ __forceinline__ uint64_t run_starts(uint32_t v) {
+    const int lane = __lane_id();
+    const uint32_t prev = __shfl_up(v, 1, kWave);
+    return __ballot(lane == 0 || prev != v);
+}
+
+// Length of the run that starts at this lane (starts as from run_starts).
+__device__ __forceinline__ uint32_t run_length(uint64_t starts) {
+    const int lane = __lane_id();
+    const uint64_t later = (starts >> lane) >> 1;  // run starts above this lane
+    return later ? (uint32_t)__builtin_ctzll(later) + 1u : (uint32_t)(kWave - lane);
+}
+
 // Adds a wave's keys (those with ok) to a sort tile's digit counts in LDS:
-// one atomic per distinct digit of the wave.  All lanes of the wave call it.
+// one atomic per run of equal digits in consecutive lanes (nearly sorted
+// keys come in a few long runs; a digit in several runs takes one atomic
+// per run).  All lanes of the wave call it.
 __device__ __forceinline__ void tile_hist_add(uint32_t *h, uint32_t key, bool ok, int shift) {
-    const uint32_t d = (key >> shift) & (kRadix - 1);
-    const uint64_t peers = match_digit(d, __ballot(ok));
-    if (ok && (peers & lanemask_lt()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    const uint32_t d = ok ? (key >> shift) & (kRadix - 1) : (uint32_t)kRadix;  // kRadix: no key
+    const uint64_t starts = run_starts(d);
+    if (ok && ((starts >> __lane_id()) & 1u)) atomicAdd(&h[d], run_length(starts));
 }
 
 // Orders one wave's LDS writes before its later reads (and reads before
