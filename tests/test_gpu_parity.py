@@ -115,6 +115,35 @@ def test_build_cells_large_sort(gpu):
     assert np.array_equal(ids, np.argsort(key, kind="stable"))
 
 
+@pytest.mark.parametrize("case", ["dambreak_146752", "cloud_2500000"])
+def test_sort_of_nearly_sorted_input_with_outliers(gpu, case):
+    """Upload order: the stable sort by the full key, then in every aligned
+    group of 64 particles the sixth moved to the front.  Lane 0 of a wave
+    then holds a larger digit than lane 1, one that recurs a few lanes on
+    (the wave's digits decrease once); the order must still be the stable
+    sort by the full key.  Both tile sizes of the radix sort (the cloud is
+    above the small-array limit)."""
+    import dataclasses
+    if case.startswith("dambreak"):
+        sc = scene.config_scene(2)
+    else:
+        sc = scene.random_cloud(2_500_000, 4, dp=0.002, box=0.3)
+    key = _sort_keys((sc.x, sc.y, sc.z), sc.params, sc.is_boundary, True)
+    order = np.argsort(key, kind="stable")
+    m = order.size // 64 * 64
+    g = order[:m].reshape(-1, 64).copy()
+    g[:, :6] = np.roll(g[:, :6], 1, axis=1)  # element 5 first
+    perm = np.concatenate([g.ravel(), order[m:]])
+    assert np.any(key[perm][0:m:64] > key[perm][1:m:64])
+    sp = dataclasses.replace(sc, x=sc.x[perm], y=sc.y[perm], z=sc.z[perm], ux=sc.ux[perm],
+                             uy=sc.uy[perm], uz=sc.uz[perm], rho=sc.rho[perm],
+                             is_boundary=sc.is_boundary[perm])
+    sim = _sim(gpu, sp, "mixed")
+    sim.build_cells()
+    sim.sync()
+    assert np.array_equal(sim.ids(), np.argsort(key[perm], kind="stable"))
+
+
 # ----------------------------------------------------------- neighbours
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
