@@ -60,8 +60,11 @@ def cells_and_offsets(x, y, z, origin: Sequence[float], cs: float,
     return out_c, out_o
 
 
-def pairs_mixed(x, y, z, h: float, origin, cs: float, dims
+def pairs_mixed(x, y, z, h: float, origin, cs: float, dims, stencil: bool = False
                 ) -> Set[Tuple[int, int]]:
+    """Every pair the FP32 cell + offset predicate accepts, over all cells
+    (stencil=True: only pairs whose cells differ by at most one per axis, the
+    27 cells a cell-list search visits)."""
     (cx, cy, cz), (ox, oy, oz) = cells_and_offsets(x, y, z, origin, cs, dims)
     cs32 = np.float64(np.float32(cs))
     d = []
@@ -76,7 +79,8 @@ def pairs_mixed(x, y, z, h: float, origin, cs: float, dims
     near = ((np.abs(cx[None, :] - cx[:, None]) <= 1)
             & (np.abs(cy[None, :] - cy[:, None]) <= 1)
             & (np.abs(cz[None, :] - cz[:, None]) <= 1))
-    ok &= near
+    if stencil:
+        ok &= near
     np.fill_diagonal(ok, False)
     i, j = np.nonzero(ok)
     return set(zip(i.tolist(), j.tolist()))

@@ -487,3 +487,23 @@ def test_hydrostatic_column_settles(oracle_lib):
     d = orc.diagnostics(p, st)
     assert d["mass"] == pytest.approx(s.n * s.params["mass"], rel=1e-12)
     assert d["umax"] < 0.1
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_mixed_predicate_stays_in_stencil(seed):
+    """The cell edge 2h(1 + 2^-20) is wide enough that the FP32 cell + offset
+    predicate never accepts a pair whose cells are two apart: over all pairs
+    of the adversarial clouds (points on cell faces, at 2h and 2h -+ 1 ulp,
+    coincident, clamped from outside the grid) the accepted set equals the
+    set found in the 27-cell stencil.  So the mixed neighbour-set tests, which
+    compare a 27-cell search with this brute force, see every pair."""
+    prm = scene.make_params(0.02, lo=(0, 0, 0), hi=(0.5, 0.45, 0.4))
+    x, y, z = bruteforce.adversarial_cloud(seed, prm)
+    args = (x, y, z, prm["h"], prm["origin"], prm["cell_size"], prm["dims"])
+    full = bruteforce.pairs_mixed(*args)
+    assert full == bruteforce.pairs_mixed(*args, stencil=True)
+    # the FP32 decision differs from FP64 only at the edge of the support
+    ref = bruteforce.pairs_fp64(x, y, z, prm["h"])
+    for i, j in full ^ ref:
+        r = math.sqrt((x[j] - x[i]) ** 2 + (y[j] - y[i]) ** 2 + (z[j] - z[i]) ** 2)
+        assert abs(r - 2 * prm["h"]) < 1e-6 * prm["h"]
