@@ -2,16 +2,19 @@
 
 One step = cell hash + stable radix sort + reorder (cell list), the pair
 interaction (continuity, momentum with Tait pressure and Monaghan viscosity),
-the device-side adaptive time step and the Verlet update, on the synthetic
-dam break at dp = 0.01 m (146,752 particles: 72,000 fluid + 74,752 dynamic
+the device-side adaptive time step and the Verlet update.  The headline
+workload is the largest single-GPU dam break: the tank with the obstacle at
+dp = 0.0025 m (5,798,336 particles: 4,608,000 fluid + 1,190,336 dynamic
 boundary), mixed precision (FP32 pair arithmetic on cell + offset positions,
-FP64 integration).  Inputs are resident in HBM before the timed region.
+FP64 integration), FP64 global diagnostics every 100 steps inside the timed
+steps.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: particle-steps/s of the mixed step, the FP64 step on the
 same workload for the ratio, the interaction kernel's roofline (achieved
-algorithmic FP32 FLOP/s over HIP-event kernel time), the batched ensemble of
-64 dam breaks (throughput, sort/reorder HBM bandwidth against peak) and the
-FP64 CPU oracle timed on this host.
+algorithmic FP32 FLOP/s over HIP-event kernel time), the same pair for the
+dam break at dp = 0.01 m, the batched ensemble of 64 dam breaks (throughput,
+sort/reorder HBM bandwidth against peak) and the FP64 CPU oracle timed on this
+host.
 """
 import argparse
 import ctypes as C
@@ -34,7 +37,8 @@ PEAK_FP32_SCALAR_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 HBM_TBS = 8.0
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_interact_mixed_dambreak_dp0.01.txt")
+#: counter summary of the headline workload's interaction kernel
+PROFILE = os.path.join(ROOT, "profiles", "k_interact_mixed_dambreak_obstacle_dp0.0025.txt")
 KERNEL_SOURCES = ("paper_2306_01959_amd/csrc/interact.hip", "paper_2306_01959_amd/csrc/update.h",
                   "paper_2306_01959_amd/csrc/common.h")
 
@@ -53,14 +57,14 @@ def kernel_name(shape, precision="Mixed"):
     return "k_interact<%s, %d, %d, false, false>" % (precision, shape[1], shape[2])
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, profile=PROFILE):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel's), or None when the
     summary is for another kernel or the kernel's sources changed since."""
     import hashlib
     try:
         kv = {}
-        with open(PROFILE) as f:
+        with open(profile) as f:
             for ln in f:
                 if " = " in ln:
                     k, v = ln.split(" = ", 1)
@@ -210,7 +214,15 @@ def config_table(hip, steps_scale=1.0):
     return rows
 
 
-# algorithmic HBM bytes per particle of the cell-list kernels (mixed state)
+# Algorithmic HBM bytes of the cell list per particle-step: 16 (the key
+# written, read by the histogram, read again with the permutation written in
+# one stable counting pass) + twice the resident state (gathered and written:
+# x, y, z, u, u at t - dt as FP64, 72 B; rho - rho0 at both levels as FP32,
+# 8 B; the id, 4 B) + 4 B per cell of the cell table.
+ALG_KEY_BYTES = 16
+STATE_BYTES = {"mixed": 84, "fp64": 92}
+CELL_TABLE_BYTES = 4
+# The bytes this design moves (design overhead over the algorithmic ones):
 SORT_BYTES_FIRST = 44   # pass 0: histogram reads x, y, z, id and writes the key; scatter
                         # reads the key, writes key + index
 SORT_BYTES_FIRST_KEYS = 16  # pass 0 when the previous (fused) step wrote the keys:
@@ -222,13 +234,17 @@ TABLE_BYTES = 4 + 4 + 4  # per cell-table entry (same launch as the reorder): it
                          # value read as the search hint, one key probed, the entry written
 
 
-def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False):
+def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False, scenes=None,
+                  workload=None):
     """The batched ensemble: n_inst dam breaks with dp drawn from {0.02,
-    0.015, 0.01} m and alpha from U[0, 0.1], mixed precision, lagged-dt fused
-    interaction + update, replayed 40-step HIP graphs."""
+    0.015, 0.01} m and alpha from U[0, 0.1] (or the given scenes), mixed
+    precision, lagged-dt fused interaction + update, replayed 40-step HIP
+    graphs."""
     import torch
     from paper_2306_01959_amd import lib, scene
-    scenes = scene.ensemble(n_inst, master_seed=seed)
+    if scenes is None:
+        scenes = scene.ensemble(n_inst, master_seed=seed)
+    n_inst = len(scenes)
     from paper_2306_01959_amd import autotune
     ens = lib.Ensemble(scenes, "mixed", stream=torch.cuda.Stream())
     period = 40
@@ -278,6 +294,7 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False):
     sort_bytes = n * (first + SORT_BYTES_PASS * (passes - 1))
     cells = sum(int(np.prod(s.params["dims"])) for s in scenes)
     reorder_bytes = n * REORDER_BYTES + (2 * cells + 1) * TABLE_BYTES
+    alg_bytes = n * (ALG_KEY_BYTES + 2 * STATE_BYTES["mixed"]) + CELL_TABLE_BYTES * cells
     pairs = [(d1[0][k] - d0[0][k]) / steps for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
     flop = FLOP_FF * pairs[0] + FLOP_FB * pairs[1] + FLOP_BF * pairs[2]
 
@@ -292,18 +309,26 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False):
         "unit": "particle-steps/s",
         "ms_per_step": (t1 - t0) / steps * 1e3,
         "steps": steps,
-        "workload": f"{n_inst} dam-break instances (same tank), dp from {{0.02, 0.015, 0.01}} m, "
-                    "alpha ~ U[0, 0.1], mixed FP32, lagged CFL dt per instance, fused "
-                    "interaction + update, "
+        "workload": (workload or f"{n_inst} dam-break instances (same tank), dp from "
+                     "{0.02, 0.015, 0.01} m, alpha ~ U[0, 0.1]") +
+                    ", mixed FP32, lagged CFL dt per instance, fused interaction + update, "
                     + ("40-step HIP graph replays" if graph else "eager launches"),
         "instances": n_inst,
         "interaction_shape": list(shape),
         "particles": n,
         "particles_per_instance": {"min": min(counts), "max": max(counts)},
+        # the sort and reorder together against the algorithmic bytes
+        "sort_reorder": dict(
+            bw(alg_bytes, kern["sort"] + kern["reorder"]),
+            bytes_model="16 B key + 2 x 84 B state per particle + 4 B per cell",
+            design_bytes_per_launch=sort_bytes + reorder_bytes,
+            design_over_algorithmic=(sort_bytes + reorder_bytes) / alg_bytes),
+        # each launch sequence against the bytes this design moves
         "sort": dict(bw(sort_bytes, kern["sort"]), passes=passes, key_bits=key_bits,
+                     bytes_model="design bytes",
                      first_pass_keys="written by the fused update" if keys_written
                      else "computed from the positions"),
-        "reorder": bw(reorder_bytes, kern["reorder"]),
+        "reorder": dict(bw(reorder_bytes, kern["reorder"]), bytes_model="design bytes"),
         "interact": {"kernel_ms": kern["interact"], "achieved": flop / (kern["interact"] * 1e-3)
                      / 1e12, "unit": "TFLOP/s", "peak": PEAK_FP32_TFLOPS,
                      "flop_per_launch": flop},
@@ -311,38 +336,82 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False):
     }
 
 
-def cpu_baseline(scene_obj, seconds=10.0):
-    """The FP64 oracle on this host's cores: 2 warm-up steps, then steps of
-    the same workload until `seconds` elapse (at least 3)."""
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.lower().startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_window(scene_obj, threads, seconds, warm=1, max_steps=2000):
+    """The FP64 oracle on this host: `warm` steps, then single steps of the
+    same workload until `seconds` elapse (at least 3); particle-steps/s.
+    threads: OpenMP threads (None: the OpenMP default, which follows
+    OMP_NUM_THREADS, i.e. this host's share of cores)."""
     from oracle import orc
     orc.build(force=False)
+    if threads:
+        orc.set_threads(threads)
+    used = orc.max_threads()
     p = orc.par(scene_obj.params)
     st = orc.State(scene_obj)
-    orc.run(p, st, 2, dt_mode=1)
+    orc.run(p, st, warm, dt_mode=1)
     k = 0
     t0 = time.perf_counter()
     while True:
         orc.run(p, st, 1, dt_mode=1)
         k += 1
         el = time.perf_counter() - t0
-        if (el >= seconds and k >= 3) or k >= 2000:
+        if (el >= seconds and k >= 3) or k >= max_steps:
             break
-    return dict(value=scene_obj.n * k / el, unit="particle-steps/s", cores=orc.max_threads(),
-                kind="oracle",
-                sample=f"{k} steps of the same dam break (dp=0.01 m, {scene_obj.n} particles) "
-                       f"after 2 warm-up steps, FP64 C oracle, OpenMP over particles, "
-                       f"{el:.1f} s")
+    return dict(value=scene_obj.n * k / el, threads=used, steps=k, warm=warm, seconds=el)
+
+
+def cpu_baseline(sc_head, sc_small, seconds_all=12.0, seconds_one=8.0):
+    """The FP64 C oracle, untuned, on this host's cores: a window of the
+    headline workload with every hardware thread, and the dp = 0.01 m dam
+    break on one thread."""
+    head = oracle_window(sc_head, None, seconds_all)
+    one = oracle_window(sc_small, 1, seconds_one)
+    model = cpu_model()
+    return {
+        "value": head["value"], "unit": "particle-steps/s", "cores": head["threads"],
+        "kind": "oracle",
+        "sample": f"{head['steps']} steps of the headline workload ({sc_head.n} particles) "
+                  f"after {head['warm']} warm-up step, FP64 C oracle (OpenMP over particles, "
+                  f"{head['threads']} threads), {head['seconds']:.1f} s; CPU {model}",
+        "cpu_model": model,
+        "one_thread": {"value": one["value"], "unit": "particle-steps/s", "cores": 1,
+                       "sample": f"{one['steps']} steps of the dp = 0.01 m dam break "
+                                 f"({sc_small.n} particles) after {one['warm']} warm-up step, "
+                                 f"{one['seconds']:.1f} s"},
+    }
+
+
+def headline_workload(sc):
+    return ("3D dam break with obstacle: tank 1.6x0.6x0.6 m, water 0.4x0.6x0.3 m, box "
+            "0.12x0.12x0.16 m at x=0.9 m, dp=0.0025 m, h=1.2*sqrt(3)*dp, Wendland C2, "
+            "alpha=0.01, delta=0.1, CFL 0.2 (device-side adaptive dt), full sort every step, "
+            "FP64 diagnostics every 100 steps; mixed FP32 interaction + FP64 integration")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=600)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
     ap.add_argument("--retune", action="store_true", help="ignore the autotune table")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble")
+    ap.add_argument("--no-small", action="store_true", help="skip the dp = 0.01 m dam break")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched ensemble (profiling its kernels alone)")
     ap.add_argument("--ensemble-eager", action="store_true",
@@ -353,6 +422,8 @@ def main():
                     help="also run one 512 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--configs", action="store_true",
                     help="only the per-configuration table (configs 1, 2, 3, 5; both precisions)")
+    ap.add_argument("--small-only", action="store_true",
+                    help="only the dp = 0.01 m dam break, mixed (profiling its kernels alone)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -360,7 +431,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2306_01959_amd import scene
+    from paper_2306_01959_amd import autotune, scene
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     hip = hip_runtime()
 
@@ -380,18 +451,31 @@ def main():
                                                     graph=not args.ensemble_eager,
                                                     retune=args.retune)}), flush=True)
         return
-    from paper_2306_01959_amd import autotune
-    sc = scene.config_scene(2)
-    splits = {"mixed": autotune.tune(sc, "mixed", use_cache=not args.retune,
+    sc2 = scene.config_scene(2)
+    if args.small_only:
+        autotune.tune(sc2, "mixed", use_cache=not args.retune)
+        r = time_gpu(sc2, "mixed", args.steps, args.warmup, hip)
+        print(json.dumps({"small_mixed_ms_per_step": r["ms_per_step"],
+                          "interact_ms": r["interact_ms"]}), flush=True)
+        return
+
+    # headline: the dam break with the obstacle at dp = 0.0025 m, diagnostics
+    # every 100 steps (FP64 mass, momentum, energy) inside the timed steps
+    sc = scene.config_scene(5)
+    shapes = {"mixed": autotune.tune(sc, "mixed", use_cache=not args.retune,
                                      verbose=args.retune)}
-    mixed = time_gpu(sc, "mixed", args.steps, args.warmup, hip)
+    mixed = time_gpu(sc, "mixed", args.steps, args.warmup, hip, diag_every=100)
+    print(f"# headline mixed: {mixed['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     fp64 = None
     if not args.no_fp64:
-        splits["fp64"] = autotune.tune(sc, "fp64", use_cache=not args.retune,
+        shapes["fp64"] = autotune.tune(sc, "fp64", use_cache=not args.retune,
                                        verbose=args.retune)
-        fp64 = time_gpu(sc, "fp64", args.steps, args.warmup, hip)
+        fp64 = time_gpu(sc, "fp64", args.steps, args.warmup, hip, diag_every=100)
+        print(f"# headline fp64: {fp64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
     value = sc.n / (mixed["ms_per_step"] * 1e-3)
     achieved = mixed["flop_per_launch"] / (mixed["interact_ms"] * 1e-3) / 1e12
+    kname = kernel_name(shapes["mixed"])
     out = {
         "metric": "particle-steps/s of WCSPH step, mixed-FP32 vs FP64 on 1 GPU, + ensemble batch",
         "value": value,
@@ -410,24 +494,24 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "3D dam break, tank 1.6x0.6x0.6 m, water 0.4x0.6x0.3 m, dp=0.01 m, "
-                        "h=1.2*sqrt(3)*dp, Wendland C2, alpha=0.01, delta=0.1, CFL 0.2 "
-                        "(device-side adaptive dt), hydrostatic start, mixed FP32 "
-                        "interaction + FP64 integration",
+            "workload": headline_workload(sc),
             "particles": sc.n, "fluid": sc.n_fluid, "boundary": sc.n_boundary,
             "precision": "mixed", "parallelism": "single GPU",
-            "interaction_shape": splits,
+            "diagnostics_in_timed_steps": mixed["diagnostics"],
+            "interaction_shape": {k: list(v) for k, v in shapes.items()},
         },
         "roofline": {
-            "kernel": kernel_name(splits["mixed"]),
+            "kernel": kname,
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": measured_traffic(kernel_name(splits["mixed"])),
+            "traffic": measured_traffic(kname),
             "kernel_ms": mixed["interact_ms"],
             "flop_per_launch": mixed["flop_per_launch"],
+            "flop_model": f"{FLOP_FF} per fluid-fluid, {FLOP_FB} per fluid-boundary, "
+                          f"{FLOP_BF} per boundary-fluid interacting ordered pair",
             "pairs_per_launch": {"ff": mixed["pairs_per_step"][0],
                                  "fb": mixed["pairs_per_step"][1],
                                  "bf": mixed["pairs_per_step"][2]},
@@ -437,12 +521,26 @@ def main():
     if fp64 is not None:
         v64 = sc.n / (fp64["ms_per_step"] * 1e-3)
         out["fp64"] = {"value": v64, "ms_per_step": fp64["ms_per_step"],
-                       "interact_ms": fp64["interact_ms"]}
+                       "interact_ms": fp64["interact_ms"],
+                       "kernel": kernel_name(shapes["fp64"], "Fp64")}
         out["mixed_over_fp64"] = value / v64
+    if not args.no_small:
+        small = {"workload": "3D dam break, same tank without the obstacle, dp=0.01 m, "
+                             "hydrostatic start", "particles": sc2.n}
+        for prec in ("mixed",) + (() if args.no_fp64 else ("fp64",)):
+            shp = autotune.tune(sc2, prec, use_cache=not args.retune)
+            r = time_gpu(sc2, prec, max(REPEATS, 2 * args.steps), args.warmup, hip)
+            small[prec] = {"value": sc2.n / (r["ms_per_step"] * 1e-3),
+                           "ms_per_step": r["ms_per_step"], "interact_ms": r["interact_ms"],
+                           "interact_tflops": r["flop_per_launch"] / (r["interact_ms"] * 1e-3)
+                           / 1e12, "shape": list(shp)}
+        if "fp64" in small:
+            small["mixed_over_fp64"] = small["mixed"]["value"] / small["fp64"]["value"]
+        out["dambreak_dp0.01"] = small
     if not args.no_ensemble:
         out["ensemble"] = time_ensemble(args.ensemble_steps, hip, retune=args.retune)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sc)
+        out["cpu_baseline"] = cpu_baseline(sc, sc2)
     print(json.dumps(out), flush=True)
 
 

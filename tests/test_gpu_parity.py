@@ -138,10 +138,63 @@ def test_sort_of_nearly_sorted_input_with_outliers(gpu, case):
     sp = dataclasses.replace(sc, x=sc.x[perm], y=sc.y[perm], z=sc.z[perm], ux=sc.ux[perm],
                              uy=sc.uy[perm], uz=sc.uz[perm], rho=sc.rho[perm],
                              is_boundary=sc.is_boundary[perm])
+    # every radix pass (8-bit digits, least significant first) sees some
+    # 64-key wave whose digit decreases from one lane to the next, so the
+    # scatter's digit-matching fallback runs in each pass
+    assert _decreasing_digit_in_every_pass(key[perm])
     sim = _sim(gpu, sp, "mixed")
     sim.build_cells()
     sim.sync()
     assert np.array_equal(sim.ids(), np.argsort(key[perm], kind="stable"))
+
+
+def _decreasing_digit_in_every_pass(keys, bits=8):
+    """LSD passes over `keys` (input order) as the library runs them: for
+    each pass, whether some aligned group of 64 consecutive keys of that
+    pass's input holds a digit smaller than its left neighbour's."""
+    keys = np.asarray(keys, np.int64)
+    order = np.arange(keys.size)
+    nbits = max(1, int(keys.max()).bit_length())
+    ok = []
+    for shift in range(0, nbits, bits):
+        d = (keys[order] >> shift) & ((1 << bits) - 1)
+        m = d.size // 64 * 64
+        w = d[:m].reshape(-1, 64)
+        ok.append(bool(np.any(np.diff(w, axis=1) < 0)))
+        order = order[np.argsort(d, kind="stable")]
+    return all(ok) and len(ok) >= 2
+
+
+def test_sort_of_update_written_keys_with_outliers(gpu):
+    """The sort of a run's second step takes the keys the first step's update
+    wrote and the digit counts it took per sort tile (not the positions).
+    Make that input nearly sorted with outliers: the first particle of every
+    aligned group of 64 (in the first step's order) moves one cell along x
+    in the first step, so lane 0 of a wave holds a larger key than lane 1.
+    The second step's order must be the stable sort of those keys (cells
+    only: step 1 is not a refresh step) of the first step's order."""
+    s = scene.dam_break(0.01, 2, alpha=0.0, hydrostatic=True, name="outliers")
+    prm = s.params
+    order0 = np.argsort(_sort_keys((s.x, s.y, s.z), prm, s.is_boundary, True), kind="stable")
+    dt = 1e-4
+    lead = order0[::64]
+    lead = lead[~s.is_boundary[lead]]       # boundary particles do not move
+    s.ux[lead] = prm["cell_size"] / dt       # one cell along x in one step
+    a = _sim(gpu, s, "mixed")
+    a.run(1, dt, 0)
+    a.sync()
+    ids_a = a.ids()
+    assert np.array_equal(ids_a, order0)
+    xa = a._cur("x").cpu().numpy()
+    ya = a._cur("y").cpu().numpy()
+    za = a._cur("z").cpu().numpy()
+    key1 = _sort_keys((xa, ya, za), prm, s.is_boundary[ids_a], False)
+    assert np.any(key1[0:key1.size // 64 * 64:64] > key1[1:key1.size // 64 * 64 + 1:64])
+    assert _decreasing_digit_in_every_pass(key1)
+    b = _sim(gpu, s, "mixed")
+    b.run(2, dt, 0)
+    b.sync()
+    assert np.array_equal(b.ids(), ids_a[np.argsort(key1, kind="stable")])
 
 
 # ----------------------------------------------------------- neighbours
