@@ -24,6 +24,8 @@
  *     library never allocates or frees device memory in these calls and holds
  *     no device state between calls; everything it needs lives in the caller's
  *     workspace buffer (size from sph_workspace_bytes, 256-byte aligned).
+ *     The one exception is sph_run_noalloc, whose workspace is a static
+ *     device array of the library.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Calls are
  *     asynchronous on that stream except sph_diagnostics, which
  *     synchronises it.
@@ -301,6 +303,26 @@ int sph_step(const sph_params *p, sph_state *s, void *ws, double dt, int64_t ste
  */
 int sph_run(const sph_params *p, sph_state *s, void *ws, int64_t nsteps, double dt,
             int64_t step0, void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sph_run
+ * without a caller workspace.  The workspace is a static device array of
+ * SPH_NOALLOC_WS_BYTES inside the library; every GPU the library runs on holds
+ * its own copy until the process ends (its address is looked up once per
+ * device, on the stream's device).  The call allocates and frees nothing.
+ * Problems whose workspace (sph_workspace_bytes) exceeds the array are
+ * rejected with SPH_E_SIZE before anything is launched.
+ * Every call starts a fresh clock: simulated time, step and pair counters
+ * restart (as after sph_workspace_init), and the cell list is rebuilt from the
+ * positions (cells_valid is cleared).  Calls on one GPU share the array:
+ * calls that overlap in time on the same GPU (other streams, other threads)
+ * race and must not be made.  Results equal those of sph_run on a fresh
+ * workspace.
+ */
+#define SPH_NOALLOC_WS_BYTES (32u << 20)
+int sph_run_noalloc(const sph_params *p, sph_state *s, int64_t nsteps, double dt, int64_t step0,
+                    void *stream);
 
 /* Regions of a step that sph_run_profiled can bracket with events. */
 typedef enum {

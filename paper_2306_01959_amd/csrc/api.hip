@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <string>
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 
@@ -504,6 +505,48 @@ static int density_io(const Problem &P, sph_state *s, const Ws &w, double *rho, 
                : launch_get_density(P, *s, w, rho, which, st);
 }
 
+// ------------------------------------------------------- no-alloc scratch
+//
+// sph_run_noalloc's workspace: a file-scope device array, of which every GPU
+// the library runs on holds its own copy for the life of the process.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): scratch_base() asks the runtime for the array's
+// device address once per device, with that device current, and every later
+// use goes through that address.
+static __device__ __align__(256) unsigned char scratch[SPH_NOALLOC_WS_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[kMaxDevices] = {};
+
+// Device of the stream (the current device for the null stream).
+static int stream_device(hipStream_t st, int *dev) {
+    if (st) return hip_check(hipStreamGetDevice(st, dev), "stream device");
+    return hip_check(hipGetDevice(dev), "current device");
+}
+
+static int scratch_base(hipStream_t st, char **base) {
+    int dev = 0;
+    if (int rc = stream_device(st, &dev)) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return fail(SPH_E_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        int cur = 0;
+        if (int rc = hip_check(hipGetDevice(&cur), "current device")) return rc;
+        if (cur != dev)
+            if (int rc = hip_check(hipSetDevice(dev), "select the stream's device")) return rc;
+        void *addr = nullptr;
+        const int rc = hip_check(hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)),
+                                 "scratch symbol address");
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (rc) return rc;
+        if (!addr) return fail(SPH_E_HIP, "scratch symbol address is NULL");
+        g_scratch_addr[dev] = addr;
+    }
+    *base = static_cast<char *>(g_scratch_addr[dev]);
+    return SPH_OK;
+}
+
 }  // namespace wcsph
 
 using namespace wcsph;
@@ -646,6 +689,28 @@ int sph_run_profiled(const sph_params *p, sph_state *s, void *ws, int64_t nsteps
     if (int rc = check_events(nsteps, region, ev_begin, ev_end)) return rc;
     return run_steps(P, *s, w, nsteps, dt, step0, 0, static_cast<hipStream_t>(stream), region,
                      ev_begin, ev_end);
+}
+
+int sph_run_noalloc(const sph_params *p, sph_state *s, int64_t nsteps, double dt, int64_t step0,
+                    void *stream) {
+    if (int rc = check_params(p)) return rc;
+    if (int rc = check_state(p->precision, s)) return rc;
+    if (int rc = check_run_args(dt, nsteps, step0, 0)) return rc;
+    const Problem P = single_problem(*p, s->n);
+    Ws w;
+    w.L = make_layout(P);
+    if (w.L.total > (size_t)SPH_NOALLOC_WS_BYTES)
+        return fail(SPH_E_SIZE, "sph_run_noalloc: the problem needs " + std::to_string(w.L.total) +
+                                    " bytes of workspace, the static scratch holds " +
+                                    std::to_string((size_t)SPH_NOALLOC_WS_BYTES));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (int rc = scratch_base(st, &w.base)) return rc;
+    // the scratch keeps whatever the last call left: restart the clock and
+    // counters (a kernel, no memset), and rebuild the cell list from the
+    // state's positions
+    if (int rc = launch_ws_init(P, w, st)) return rc;
+    s->cells_valid = 0;
+    return run_steps(P, *s, w, nsteps, dt, step0, 0, st);
 }
 
 int sph_diagnostics(const sph_params *p, const sph_state *s, void *ws, const double *probes_xyz,

@@ -31,7 +31,8 @@ MAX_INSTANCES = 4096
 EXPORTS = ("sph_version", "sph_last_error", "sph_check_params", "sph_set_tuning",
            "sph_get_split", "sph_workspace_bytes",
            "sph_workspace_init", "sph_set_density", "sph_get_density", "sph_build_cells",
-           "sph_interact", "sph_neighbour_stats", "sph_step", "sph_run", "sph_run_profiled",
+           "sph_interact", "sph_neighbour_stats", "sph_step", "sph_run", "sph_run_noalloc",
+           "sph_run_profiled",
            "sph_diagnostics", "sph_batch_workspace_bytes", "sph_batch_workspace_init",
            "sph_batch_set_density", "sph_batch_get_density", "sph_batch_build_cells",
            "sph_batch_interact", "sph_batch_run", "sph_batch_run_profiled",
@@ -129,6 +130,7 @@ def load(path: str = LIB_PATH):
     L.sph_neighbour_stats.argtypes = [PP, PS, _P, _P, _P, _P, _P]
     L.sph_step.argtypes = [PP, PS, _P, C.c_double, C.c_int64, _P]
     L.sph_run.argtypes = [PP, PS, _P, C.c_int64, C.c_double, C.c_int64, _P]
+    L.sph_run_noalloc.argtypes = [PP, PS, C.c_int64, C.c_double, C.c_int64, _P]
     L.sph_run_profiled.argtypes = [PP, PS, _P, C.c_int64, C.c_double, C.c_int64, C.c_int32,
                                    _P, _P, _P]
     L.sph_diagnostics.argtypes = [PP, PS, _P, _P, C.c_int32, PD, _P, _P]
@@ -389,6 +391,12 @@ class Simulation(_System):
     def run(self, nsteps: int, dt: float, step0: int) -> None:
         check(self.lib.sph_run(C.byref(self.params), C.byref(self.state), self.ws_ptr,
                                int(nsteps), float(dt), int(step0), self._s()))
+
+    def run_noalloc(self, nsteps: int, dt: float, step0: int) -> None:
+        """run() through sph_run_noalloc: the library's static scratch array
+        instead of this system's workspace (whose clock it does not touch)."""
+        check(self.lib.sph_run_noalloc(C.byref(self.params), C.byref(self.state), int(nsteps),
+                                       float(dt), int(step0), self._s()))
 
     def run_profiled(self, nsteps: int, dt: float, step0: int, ev_begin, ev_end,
                      region: int = REGION_INTERACT) -> None:
