@@ -355,6 +355,37 @@ int sph_run_profiled(const sph_params *p, sph_state *s, void *ws, int64_t nsteps
 int sph_diagnostics(const sph_params *p, const sph_state *s, void *ws, const double *probes_xyz,
                     int32_t np, sph_diag *out, double *probe_p, void *stream);
 
+/*
+ * Load on a solid (Section 3, the force on the block): the sum over the
+ * boundary particles inside the box [box[0], box[1]] x [box[2], box[3]] x
+ * [box[4], box[5]] of m a_i, a_i being the pressure and viscosity terms of the
+ * momentum equation (eqs. sphu, pi, cpmu, tait) that i's fluid neighbours
+ * exert on it, as for a fluid particle; the body force is not included and
+ * boundary-boundary pairs do not act (the wall particles stay where they are;
+ * their accelerations serve only to obtain the force).  Arithmetic in FP64
+ * from the state arrays in both precisions (the mixed state's densities are
+ * FP32 rho - rho0).  box: host array of 6 finite values with lo <= hi
+ * (SPH_E_INVAL otherwise).  force: host array of 3 doubles (N); count: the
+ * boundary particles in the box (may be NULL).  Requires current cells
+ * (SPH_E_STATE); synchronises the stream; the sum has a fixed order.
+ */
+int sph_boundary_force(const sph_params *p, const sph_state *s, void *ws, const double *box,
+                       double *force, int64_t *count, void *stream);
+
+/*
+ * Probe pressures (eq. sphpa, as sph_diagnostics) and their pressure
+ * impulse I_p = integral of P dt (Section 3, Table 2), accumulated in the
+ * workspace by the trapezoidal rule over the samples of successive calls,
+ * with the simulated time the steps have accumulated (sph_diag.time).  The
+ * first call after sph_workspace_init, and any call with reset = 1, starts
+ * the integral at this sample (impulse 0).  Successive calls must pass the
+ * same probe points.  probes_xyz: host, 3 np finite values, 1 <= np <= 1024;
+ * probe_p, impulse: host arrays of np doubles (Pa, Pa s).  Requires current
+ * cells; synchronises the stream.
+ */
+int sph_probe_impulse(const sph_params *p, const sph_state *s, void *ws, const double *probes_xyz,
+                      int32_t np, int32_t reset, double *probe_p, double *impulse, void *stream);
+
 /* ======================================================================
  * Batches: an ensemble of independent systems advanced together, as in the
  * paper's artificial-viscosity study (Section 4: several alpha values on one

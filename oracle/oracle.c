@@ -8,7 +8,9 @@
  * Tait equation of state (eq. tait), the Verlet scheme with an Euler reset
  * every N_s steps (eqs. sphu1-sphrho1, sphu2-sphrho2), the adaptive time step
  * (eq. sphdt) and dynamic boundary particles.  Probe pressures follow the
- * Shepard filter of eq. sphpa (Section 3.1).
+ * Shepard filter of eq. sphpa (Section 3.1); the load on a solid is the sum
+ * of its wall particles' accelerations times their mass and the pressure
+ * impulse the time integral of a probe pressure (Section 3).
  *
  * Only the test-suite, the package's smoke check and the benchmark's CPU
  * baseline may load this library.  It shares no code with the HIP library.
@@ -598,6 +600,90 @@ void orc_probes(const orc_par *p, int64_t n, const double *x, const double *y,
         }
         out[a] = den > 0.0 ? num / den : 0.0;
     }
+}
+
+/* ------------------------------------------------------------ loads */
+
+/* Hydrodynamic load on a solid (Section 3, force on the block): the sum over
+ * the boundary particles i inside the box [box[0], box[1]] x [box[2], box[3]]
+ * x [box[4], box[5]] of m a_i, where a_i is the momentum-equation
+ * acceleration (eq. sphu: pressure and viscosity terms) exerted on i by its
+ * fluid neighbours j, as for a fluid particle.  Body forces are left out and
+ * boundary-boundary pairs do not act (the wall accelerations serve only to
+ * obtain the force).  out[0..2]: the force; out[3]: particles in the box. */
+int orc_boundary_force(const orc_par *p, int64_t n, const double *x,
+                       const double *y, const double *z, const double *ux,
+                       const double *uy, const double *uz, const double *rho,
+                       const uint8_t *is_bnd, const double *box, double *out)
+{
+    orc_grid g;
+    if (orc_grid_build(p, n, x, y, z, &g) != 0) {
+        orc_grid_free(&g);
+        return -1;
+    }
+    const double h = p->h, m = p->mass;
+    const double r2max = 4.0 * h * h;
+    const double eta2 = p->eta2_coef * h * h;
+    double fx = 0.0, fy = 0.0, fz = 0.0, cnt = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_bnd[i])
+            continue;
+        if (!(x[i] >= box[0] && x[i] <= box[1] && y[i] >= box[2] && y[i] <= box[3] &&
+              z[i] >= box[4] && z[i] <= box[5]))
+            continue;
+        cnt += 1.0;
+        const double Pi = orc_pressure(p, rho[i]), Ci = orc_sound(p, rho[i]);
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int32_t cxn = g.cx[i] + dx, cyn = g.cy[i] + dy, czn = g.cz[i] + dz;
+                    if (cxn < 0 || cyn < 0 || czn < 0 || cxn >= p->nx || cyn >= p->ny || czn >= p->nz)
+                        continue;
+                    int64_t c = cxn + (int64_t)p->nx * (cyn + (int64_t)p->ny * czn);
+                    for (int64_t s = g.start[c]; s < g.start[c + 1]; ++s) {
+                        int64_t j = g.order[s];
+                        if (is_bnd[j])
+                            continue;
+                        double rx = x[j] - x[i], ry = y[j] - y[i], rz = z[j] - z[i];
+                        double r2 = orc_r2(rx, ry, rz);
+                        if (!(r2 < r2max))
+                            continue;
+                        double F = orc_kernel_f(sqrt(r2) / h, h);
+                        double vx = ux[j] - ux[i], vy = uy[j] - uy[i], vz = uz[j] - uz[i];
+                        double vr = (vx * rx + vy * ry) + vz * rz;
+                        double visc = 0.0;
+                        if (vr < 0.0) {
+                            double mu = h * vr / (r2 + eta2);
+                            double cbar = 0.5 * (Ci + orc_sound(p, rho[j]));
+                            double rbar = 0.5 * (rho[i] + rho[j]);
+                            visc = -p->alpha * cbar * mu / rbar;
+                        }
+                        double Pj = orc_pressure(p, rho[j]);
+                        double coef = m * ((Pi + Pj) / (rho[i] * rho[j]) + visc);
+                        ax -= coef * F * rx;
+                        ay -= coef * F * ry;
+                        az -= coef * F * rz;
+                    }
+                }
+        fx += m * ax;
+        fy += m * ay;
+        fz += m * az;
+    }
+    orc_grid_free(&g);
+    out[0] = fx;
+    out[1] = fy;
+    out[2] = fz;
+    out[3] = cnt;
+    return 0;
+}
+
+/* Pressure impulse I_p = integral of P dt (Section 3, Table 2), advanced
+ * over one sampling interval dt by the trapezoidal rule from the pressures
+ * at its two ends. */
+double orc_impulse_step(double I, double p_prev, double p_now, double dt)
+{
+    return I + 0.5 * (p_prev + p_now) * dt;
 }
 
 int orc_max_threads(void)

@@ -92,6 +92,11 @@ def lib():
         L.orc_probes.restype = None
         L.orc_probes.argtypes = [P, C.c_int64, _D, _D, _D, _D, _U8, C.c_int32,
                                  _D, _D]
+        L.orc_boundary_force.restype = C.c_int
+        L.orc_boundary_force.argtypes = [P, C.c_int64, _D, _D, _D, _D, _D, _D, _D, _U8,
+                                         _D, _D]
+        L.orc_impulse_step.restype = C.c_double
+        L.orc_impulse_step.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
         L.orc_max_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -283,3 +288,26 @@ def probes(p: OrcPar, st_or_arrays, pts) -> np.ndarray:
     lib().orc_probes(C.byref(p), x.size, _d(x), _d(y), _d(z), _d(rho),
                      isb.ctypes.data_as(_U8), npts, _d(pts), _d(out))
     return out[:npts]
+
+
+def boundary_force(p: OrcPar, st_or_arrays, box):
+    """(force vector, particle count) of the boundary particles inside
+    box = (x0, x1, y0, y1, z0, z1)."""
+    if isinstance(st_or_arrays, State):
+        st = st_or_arrays
+        arrs = (st.x, st.y, st.z, st.ux, st.uy, st.uz, st.rho)
+        isb = st.is_bnd
+    else:
+        *arrs, isb = st_or_arrays
+        arrs = [_f64(a) for a in arrs]
+        isb = _u8(isb)
+    b = _f64(np.asarray(box, np.float64).reshape(6))
+    out = np.zeros(4)
+    rc = lib().orc_boundary_force(C.byref(p), arrs[0].size, *[_d(a) for a in arrs],
+                                  isb.ctypes.data_as(_U8), _d(b), _d(out))
+    assert rc == 0
+    return out[:3].copy(), int(out[3])
+
+
+def impulse_step(I: float, p_prev: float, p_now: float, dt: float) -> float:
+    return float(lib().orc_impulse_step(float(I), float(p_prev), float(p_now), float(dt)))

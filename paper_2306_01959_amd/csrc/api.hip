@@ -77,6 +77,8 @@ WsLayout make_layout(const Problem &P) {
     L.inst_state = take(sizeof(InstState) * (size_t)L.ninst);
     L.diag_part = take(sizeof(double) * ((size_t)L.ninst * diag_blocks(L.ninst) * kDiagFields +
                                          (size_t)L.ninst * kDiagFields + 4 * (size_t)kMaxProbes));
+    L.loads = take(sizeof(double) * (4 * (size_t)L.nrows + 4));
+    L.impulse = take(256 + sizeof(double) * 2 * (size_t)kMaxProbes);
     L.total = off;
     return L;
 }
@@ -723,6 +725,36 @@ int sph_diagnostics(const sph_params *p, const sph_state *s, void *ws, const dou
     if (np > 0 && (!probes_xyz || !probe_p)) return fail(SPH_E_INVAL, "probe arrays are NULL");
     if (!s->cells_valid) return fail(SPH_E_STATE, "sph_diagnostics needs current cells");
     return launch_diag(P, *s, w, probes_xyz, np, out, probe_p, static_cast<hipStream_t>(stream));
+}
+
+int sph_boundary_force(const sph_params *p, const sph_state *s, void *ws, const double *box,
+                       double *force, int64_t *count, void *stream) {
+    Problem P;
+    Ws w;
+    if (int rc = validate(p, s, ws, &P, &w)) return rc;
+    if (!box || !force) return fail(SPH_E_INVAL, "box and force must not be NULL");
+    for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(box[2 * k]) || !std::isfinite(box[2 * k + 1]))
+            return fail(SPH_E_INVAL, "box must be finite");
+        if (!(box[2 * k] <= box[2 * k + 1])) return fail(SPH_E_INVAL, "box needs lo <= hi");
+    }
+    if (!s->cells_valid) return fail(SPH_E_STATE, "sph_boundary_force needs current cells");
+    return launch_boundary_force(P, *s, w, box, force, count, static_cast<hipStream_t>(stream));
+}
+
+int sph_probe_impulse(const sph_params *p, const sph_state *s, void *ws, const double *probes_xyz,
+                      int32_t np, int32_t reset, double *probe_p, double *impulse, void *stream) {
+    Problem P;
+    Ws w;
+    if (int rc = validate(p, s, ws, &P, &w)) return rc;
+    if (np < 1 || np > kMaxProbes) return fail(SPH_E_INVAL, "np must be in [1, 1024]");
+    if (!probes_xyz || !probe_p || !impulse) return fail(SPH_E_INVAL, "probe arrays are NULL");
+    if (reset != 0 && reset != 1) return fail(SPH_E_INVAL, "reset must be 0 or 1");
+    for (int k = 0; k < 3 * np; ++k)
+        if (!std::isfinite(probes_xyz[k])) return fail(SPH_E_INVAL, "probe points must be finite");
+    if (!s->cells_valid) return fail(SPH_E_STATE, "sph_probe_impulse needs current cells");
+    return launch_probe_impulse(P, *s, w, probes_xyz, np, reset, probe_p, impulse,
+                                static_cast<hipStream_t>(stream));
 }
 
 // ------------------------------------------------------------------ batch

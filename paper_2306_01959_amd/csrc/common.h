@@ -75,6 +75,15 @@ struct ChunkOut {
     uint32_t pad;
 };
 
+// Running pressure impulse of the probe points (trapezoidal rule over the
+// samples of sph_probe_impulse), followed in the workspace by kMaxProbes
+// impulses and kMaxProbes previous pressures.
+struct ImpulseState {
+    double t_prev;   // simulated time of the previous sample
+    int32_t has_prev;  // a previous sample exists (0 after init or reset)
+    int32_t np;      // probes of the previous sample
+};
+
 // Device-wide scalars.
 struct DevScalars {
     long long steps;                 // steps taken
@@ -273,6 +282,8 @@ struct WsLayout {
     size_t inst_tab = 0;     // Inst[ninst]
     size_t inst_state = 0;   // InstState[ninst]
     size_t diag_part = 0;
+    size_t loads = 0;        // boundary-force partial sums: 4 doubles per cell row
+    size_t impulse = 0;      // ImpulseState, then 2 x kMaxProbes doubles
     size_t total = 0;
     size_t view_elem = 0;    // bytes of one view record (first two arrays)
     size_t rate_elem = 0;    // bytes of one rate value
@@ -303,6 +314,10 @@ struct Ws {
     Inst *inst_tab() const { return at<Inst>(L.inst_tab); }
     InstState *inst_state() const { return at<InstState>(L.inst_state); }
     double *diag_part() const { return at<double>(L.diag_part); }
+    double *loads() const { return at<double>(L.loads); }
+    ImpulseState *impulse() const { return at<ImpulseState>(L.impulse); }
+    double *impulse_sum() const { return at<double>(L.impulse + 256); }
+    double *impulse_prev() const { return at<double>(L.impulse + 256) + kMaxProbes; }
 };
 
 // Accessor for the kernels of one call.
@@ -345,6 +360,17 @@ int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int
                      hipStream_t st, int hist_shift = -1);
 int launch_diag(const Problem &P, const sph_state &s, const Ws &w, const double *probes,
                 int32_t np, sph_diag *out, double *probe_p, hipStream_t st);
+// probe pressures (eq. sphpa) of instance 0 at np host points into the
+// device array pout (np values); the points are staged in the workspace
+int launch_probes(const Problem &P, const sph_state &s, const Ws &w, const double *probes,
+                  int32_t np, double *pout, hipStream_t st);
+// force on the boundary particles inside a box (instance 0), to the host
+int launch_boundary_force(const Problem &P, const sph_state &s, const Ws &w, const double *box,
+                          double *force, int64_t *count, hipStream_t st);
+// probe pressures and their running impulse, to the host
+int launch_probe_impulse(const Problem &P, const sph_state &s, const Ws &w, const double *probes,
+                         int32_t np, int32_t reset, double *probe_p, double *impulse,
+                         hipStream_t st);
 int launch_set_density(const Problem &P, sph_state &s, const Ws &w, const double *rho,
                        int which, hipStream_t st);
 int launch_get_density(const Problem &P, const sph_state &s, const Ws &w, double *rho,

@@ -245,10 +245,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_probes(DiagArgs a, const doubl
 
 int diag_blocks(int ninst) { return ninst == 1 ? kDiagBlocks : kDiagBlocksBatch; }
 
-// out: ninst results (instance order); probes: instance 0 only.
-int launch_diag(const Problem &P, const sph_state &s, const Ws &w, const double *probes,
-                int32_t np, sph_diag *out, double *probe_p, hipStream_t st) {
-    const int ninst = (int)P.host.size();
+static DiagArgs diag_args(const Problem &P, const sph_state &s, const Ws &w) {
     DiagArgs a;
     a.x = s.x;
     a.y = s.y;
@@ -261,22 +258,37 @@ int launch_diag(const Problem &P, const sph_state &s, const Ws &w, const double 
     a.cell_start = w.cell_start();
     a.mixed = P.precision == SPH_MIXED;
     a.I = insts_of(P, w);
-    a.bpi = diag_blocks(ninst);
+    a.bpi = diag_blocks((int)P.host.size());
     a.part = w.diag_part();
+    return a;
+}
+
+int launch_probes(const Problem &P, const sph_state &s, const Ws &w, const double *probes,
+                  int32_t np, double *pout, hipStream_t st) {
+    if (np <= 0) return SPH_OK;
+    const DiagArgs a = diag_args(P, s, w);
+    double *pts = a.part + (size_t)P.host.size() * a.bpi * kDiagFields +
+                  (size_t)P.host.size() * kDiagFields;
+    if (int rc = hip_check(hipMemcpyAsync(pts, probes, sizeof(double) * 3 * np,
+                                          hipMemcpyHostToDevice, st),
+                           "probe upload"))
+        return rc;
+    hipLaunchKernelGGL(k_probes, dim3(np), dim3(kDiagThreads), 0, st, a, pts, pout);
+    return launch_check("probes");
+}
+
+// out: ninst results (instance order); probes: instance 0 only.
+int launch_diag(const Problem &P, const sph_state &s, const Ws &w, const double *probes,
+                int32_t np, sph_diag *out, double *probe_p, hipStream_t st) {
+    const int ninst = (int)P.host.size();
+    const DiagArgs a = diag_args(P, s, w);
     double *res = a.part + (size_t)ninst * a.bpi * kDiagFields;
     double *pts = res + (size_t)ninst * kDiagFields;
     double *pout = pts + 3 * kMaxProbes;
     hipLaunchKernelGGL(k_diag_partial, dim3(a.bpi, ninst), dim3(kDiagThreads), 0, st, a);
     hipLaunchKernelGGL(k_diag_final, dim3(ninst), dim3(kDiagThreads), 0, st, a.part, a.bpi, res);
     if (int rc = launch_check("diagnostics")) return rc;
-    if (np > 0) {
-        if (int rc = hip_check(hipMemcpyAsync(pts, probes, sizeof(double) * 3 * np,
-                                              hipMemcpyHostToDevice, st),
-                               "probe upload"))
-            return rc;
-        hipLaunchKernelGGL(k_probes, dim3(np), dim3(kDiagThreads), 0, st, a, pts, pout);
-        if (int rc = launch_check("probes")) return rc;
-    }
+    if (int rc = launch_probes(P, s, w, probes, np, pout, st)) return rc;
     std::vector<double> host((size_t)ninst * kDiagFields);
     std::vector<InstState> ist(ninst);
     DevScalars sc;

@@ -196,9 +196,12 @@ int launch_get_density(const Problem &P, const sph_state &s, const Ws &w, double
 
 // ------------------------------------------------------ workspace scalars
 
-__global__ void k_ws_init(DevScalars *sc, InstState *ist, int ninst) {
+__global__ void k_ws_init(DevScalars *sc, InstState *ist, int ninst, ImpulseState *imp) {
     const int t = threadIdx.x;
     if (t == 0) {
+        imp->t_prev = 0.0;
+        imp->has_prev = 0;
+        imp->np = 0;
         sc->steps = 0;
         sc->nchunks = 0;
         sc->dt_cfl_violation = 0;
@@ -226,7 +229,7 @@ int launch_ws_init(const Problem &P, const Ws &w, hipStream_t st) {
         if (int rc = hip_check(hipStreamSynchronize(st), "instance table upload")) return rc;
     }
     hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(256), 0, st, w.scalars(), w.inst_state(),
-                       (int)P.host.size());
+                       (int)P.host.size(), w.impulse());
     return launch_check("workspace init");
 }
 

@@ -33,7 +33,8 @@ EXPORTS = ("sph_version", "sph_last_error", "sph_check_params", "sph_set_tuning"
            "sph_workspace_init", "sph_set_density", "sph_get_density", "sph_build_cells",
            "sph_interact", "sph_neighbour_stats", "sph_step", "sph_run", "sph_run_noalloc",
            "sph_run_profiled",
-           "sph_diagnostics", "sph_batch_workspace_bytes", "sph_batch_workspace_init",
+           "sph_diagnostics", "sph_boundary_force", "sph_probe_impulse",
+           "sph_batch_workspace_bytes", "sph_batch_workspace_init",
            "sph_batch_set_density", "sph_batch_get_density", "sph_batch_build_cells",
            "sph_batch_interact", "sph_batch_run", "sph_batch_run_profiled",
            "sph_batch_diagnostics")
@@ -134,6 +135,8 @@ def load(path: str = LIB_PATH):
     L.sph_run_profiled.argtypes = [PP, PS, _P, C.c_int64, C.c_double, C.c_int64, C.c_int32,
                                    _P, _P, _P]
     L.sph_diagnostics.argtypes = [PP, PS, _P, _P, C.c_int32, PD, _P, _P]
+    L.sph_boundary_force.argtypes = [PP, PS, _P, _P, _P, _P, _P]
+    L.sph_probe_impulse.argtypes = [PP, PS, _P, _P, C.c_int32, C.c_int32, _P, _P, _P]
     PB = C.POINTER(SphBatch)
     L.sph_batch_workspace_bytes.argtypes = [PB, C.POINTER(C.c_size_t)]
     L.sph_batch_workspace_init.argtypes = [PB, _P, C.c_size_t, _P]
@@ -419,6 +422,32 @@ class Simulation(_System):
             pts.ctypes.data if npts else None, npts, C.byref(out),
             pp.ctypes.data if npts else None, self._s()))
         return out.as_dict(), pp[:npts]
+
+
+    def boundary_force(self, box):
+        """(force vector, particle count) of the boundary particles inside
+        box = (x0, x1, y0, y1, z0, z1)."""
+        if not self.state.cells_valid:
+            self.build_cells()
+        b = np.ascontiguousarray(np.asarray(box, np.float64).reshape(6))
+        f = np.zeros(3)
+        cnt = C.c_int64(0)
+        check(self.lib.sph_boundary_force(C.byref(self.params), C.byref(self.state), self.ws_ptr,
+                                          b.ctypes.data, f.ctypes.data, C.byref(cnt), self._s()))
+        return f, int(cnt.value)
+
+    def probe_impulse(self, probes, reset: bool = False):
+        """(probe pressures, pressure impulses since the last reset)."""
+        if not self.state.cells_valid:
+            self.build_cells()
+        pts = np.ascontiguousarray(np.asarray(probes, np.float64).reshape(-1))
+        npts = pts.size // 3
+        pp = np.zeros(npts)
+        ip = np.zeros(npts)
+        check(self.lib.sph_probe_impulse(C.byref(self.params), C.byref(self.state), self.ws_ptr,
+                                         pts.ctypes.data, npts, int(bool(reset)), pp.ctypes.data,
+                                         ip.ctypes.data, self._s()))
+        return pp, ip
 
 
 class Ensemble(_System):

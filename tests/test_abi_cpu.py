@@ -224,3 +224,37 @@ def test_batch_rejected_before_launch(L):
     assert L.sph_batch_interact(C.byref(b), C.byref(st), 1 << 30, *outs, None,
                                 None) == lib.SPH_E_STATE
     assert L.sph_batch_workspace_init(C.byref(b), 1 << 30, 64, None) == lib.SPH_E_SIZE
+
+
+def test_loads_rejected_before_launch(L):
+    """sph_boundary_force and sph_probe_impulse validate their arguments
+    before touching the device (fake, aligned device pointers)."""
+    import ctypes as C
+    from paper_2306_01959_amd import lib, scene
+    sc = scene.config_scene(1)
+    p = lib.make_params(sc.params, "mixed")
+    st = lib.SphState()
+    st.n = sc.n
+    for name, _ in lib.SphState._fields_[1:25]:
+        setattr(st, name, 1 << 20)
+    ws = C.c_void_p(1 << 24)
+    f = (C.c_double * 3)()
+    bad_box = (C.c_double * 6)(0.5, 0.4, 0.0, 1.0, 0.0, 1.0)       # lo > hi along x
+    assert L.sph_boundary_force(C.byref(p), C.byref(st), ws, bad_box, f, None, None) == \
+        lib.SPH_E_INVAL
+    nan_box = (C.c_double * 6)(0.0, float("nan"), 0.0, 1.0, 0.0, 1.0)
+    assert L.sph_boundary_force(C.byref(p), C.byref(st), ws, nan_box, f, None, None) == \
+        lib.SPH_E_INVAL
+    box = (C.c_double * 6)(0.0, 1.0, 0.0, 1.0, 0.0, 1.0)
+    st.cells_valid = 0                                              # stale cells
+    assert L.sph_boundary_force(C.byref(p), C.byref(st), ws, box, f, None, None) == \
+        lib.SPH_E_STATE
+    pts = (C.c_double * 3)(0.1, 0.1, 0.1)
+    out = (C.c_double * 1)()
+    imp = (C.c_double * 1)()
+    assert L.sph_probe_impulse(C.byref(p), C.byref(st), ws, pts, 0, 0, out, imp, None) == \
+        lib.SPH_E_INVAL
+    assert L.sph_probe_impulse(C.byref(p), C.byref(st), ws, pts, 1, 2, out, imp, None) == \
+        lib.SPH_E_INVAL
+    assert L.sph_probe_impulse(C.byref(p), C.byref(st), ws, pts, 1, 0, out, imp, None) == \
+        lib.SPH_E_STATE

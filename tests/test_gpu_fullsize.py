@@ -4,9 +4,9 @@ uses (the autotuner's table), through the C ABI.
 * Obstacle dam break at dp = 0.005 (875,904 particles) and dp = 0.0025
   (5,798,336 particles): rates of every particle at a state the oracle
   produced (a few oracle steps from the initial set), against the oracle's
-  rates at that state: mixed <= 1e-5 relative L2 (plus the interaction-only
-  norm), FP64 <= 1e-12; interacting pair counts equal to the oracle's in
-  FP64.
+  rates at that state: mixed <= 1e-5 relative L2 (the interaction-only
+  norm too), FP64 <= 1e-12 (interaction-only 1e-11); interacting pair counts
+  equal to the oracle's in FP64.  The achieved errors are printed.
 * The 64-instance ensemble (4,526,960 particles): every instance's rates
   against the oracle at its own oracle-advanced state; the lagged, fused,
   graph-replayed run equal bit for bit to eager launches of the same steps.
@@ -70,9 +70,7 @@ def check_rates(gpu, orc, sc, p, st, precision):
           f"interaction-only {e_int:.2e}", flush=True)
     for k in range(4):
         assert errs[k] < tol, (precision, k, errs[k])
-    # a few oracle steps from rest a - g is small next to g, and the FP32
-    # rounding of the cancelling pressure sums dominates it (hence 10 x)
-    assert e_int < (1e-11 if precision == "fp64" else 1e-4)
+    assert e_int < (1e-11 if precision == "fp64" else 1e-5)
     if precision == "fp64":
         pairs = [d1[k] - d0[k] for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
         assert pairs == [int(c) for c in ref_cnt], (pairs, ref_cnt)

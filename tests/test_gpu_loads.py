@@ -1,0 +1,114 @@
+"""Loads on solids on the GPU (sph_boundary_force, sph_probe_impulse)
+against the oracle, through the C ABI (needs an MI355X).
+
+* Same state: the obstacle dam break at dp = 0.02 m advanced by the oracle
+  into the wave's impact on the obstacle; the force on the obstacle's
+  upstream (weather) face, on the whole obstacle and on all walls, against
+  the oracle's at that state: FP64 to 1e-10 of the force's scale, mixed
+  (FP32 densities) to 1e-5; the particle counts exactly.
+* Time series: the same run from rest with the oracle's dt sequence fed to
+  the GPU, the face force and the four probes' pressure impulse (Table 2's
+  quantity) sampled every 10 steps: the force within 1 % of its series'
+  range, the impulses within 1 % of the integral of |P| (the probes also
+  see suction, so an impulse can pass through zero).
+"""
+import numpy as np
+import pytest
+
+from paper_2306_01959_amd import scene
+from tests.gpu_helpers import scene_from_oracle
+
+pytestmark = pytest.mark.gpu
+
+DP = 0.02
+BIG = 10.0
+# upstream face of the obstacle: its two particle layers at x in [0.84, 0.88]
+FACE = (0.84, 0.84 + 2 * DP, 0.24, 0.36, 0.0, 0.16)
+OBSTACLE = (0.84, 0.96, 0.24, 0.36, 0.0, 0.16)
+ALL = (-BIG, BIG, -BIG, BIG, -BIG, BIG)
+PROBES = np.array([[0.84 - DP, 0.3, z] for z in (0.02, 0.06, 0.10, 0.14)])
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_01959_amd import lib
+    lib.load()
+    return lib
+
+
+def _scene():
+    return scene.dam_break(DP, 3, alpha=0.01, obstacle=True, name="obstacle_dp0.02")
+
+
+@pytest.fixture(scope="module")
+def impact_state(oracle_lib):
+    s = _scene()
+    p = oracle_lib.par(s.params)
+    st = oracle_lib.State(s)
+    oracle_lib.run(p, st, 665, dt_mode=1)
+    return s, p, st
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_boundary_force_same_state(gpu, oracle_lib, impact_state, precision):
+    s, p, st = impact_state
+    sc, prev = scene_from_oracle(st, s.params)
+    sim = gpu.Simulation(sc, precision)
+    sim.upload(sc, prev)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    for name, box in (("face", FACE), ("obstacle", OBSTACLE), ("all walls", ALL)):
+        ref, nref = oracle_lib.boundary_force(p, st, box)
+        got, n = sim.boundary_force(box)
+        scale = np.abs(ref).max()
+        err = np.abs(got - ref).max() / scale
+        print(f"\n{precision} {name}: force {np.round(ref, 3)} N over {nref} particles, "
+              f"relative error {err:.2e}", flush=True)
+        assert n == nref
+        assert err <= tol, (name, err)
+    assert np.abs(oracle_lib.boundary_force(p, st, FACE)[0][0]) > 1.0   # the wave is there
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_force_and_impulse_series(gpu, oracle_lib, precision):
+    orc = oracle_lib
+    s = _scene()
+    p = orc.par(s.params)
+    st = orc.State(s)
+    sim = gpu.Simulation(s, precision)
+    ref_f, got_f = [], []
+    I_ref = np.zeros(len(PROBES))
+    I_abs = np.zeros(len(PROBES))
+    P_prev = None
+    step = 0
+    for k in range(72):
+        if k > 0:
+            dts, _ = orc.run(p, st, 10, dt_mode=1)
+            for dt in dts:
+                sim.step(float(dt), step)
+                step += 1
+        P_now = orc.probes(p, st, PROBES)
+        if P_prev is not None:
+            for a in range(len(PROBES)):
+                I_ref[a] = orc.impulse_step(I_ref[a], P_prev[a], P_now[a], float(dts.sum()))
+                I_abs[a] = orc.impulse_step(I_abs[a], abs(P_prev[a]), abs(P_now[a]),
+                                            float(dts.sum()))
+        P_prev = P_now
+        ref_f.append(orc.boundary_force(p, st, FACE)[0])
+        pp, I_got = sim.probe_impulse(PROBES, reset=(k == 0))
+        got_f.append(sim.boundary_force(FACE)[0])
+        assert np.allclose(pp, P_now, rtol=1e-5, atol=1e-3 * max(1.0, np.abs(P_now).max()))
+    ref_f, got_f = np.array(ref_f), np.array(got_f)
+    span = ref_f.max(axis=0) - ref_f.min(axis=0)
+    err = np.abs(got_f - ref_f).max(axis=0)
+    ierr = np.abs(I_got - I_ref) / I_abs
+    print(f"\n{precision}: face force x range {span[0]:.2f} N, max error / range "
+          f"{np.round(err / span, 6)}; impulses {np.round(I_ref, 3)} Pa s, relative error "
+          f"{np.round(ierr, 6)}", flush=True)
+    assert span[0] > 50.0 and np.all(I_abs > 50.0)     # the wave hit the face
+    # the load normal to the face (x); its tangential parts are near zero
+    assert err[0] <= 0.01 * span[0], err / span
+    assert np.abs(got_f[:, 1:] - ref_f[:, 1:]).max() <= 0.01 * span[0]
+    assert (ierr <= 0.01).all(), ierr

@@ -244,7 +244,7 @@ def test_rates_developed_state(gpu, oracle_lib, developed, precision, tol):
     # interaction-only norm (gravity removed)
     a_got = np.stack([got[k][f] - g[k] for k in range(3)])
     a_ref = np.stack([ref[k][f] - g[k] for k in range(3)])
-    assert rel_l2(a_got, a_ref) < 10 * tol
+    assert rel_l2(a_got, a_ref) < tol
     assert rel_l2(got[3], ref[3]) < tol
     assert rel_l2(got[4], ref[4]) < tol
 
