@@ -333,9 +333,26 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False, scene
                      / 1e12, "unit": "TFLOP/s", "peak": PEAK_FP32_TFLOPS,
                      "flop_per_launch": flop},
         "eager_step_ms": kern["step"],
+        "pairs_per_step": sum(pairs),
+        "pairs_per_s": sum(pairs) * steps / (t1 - t0),
     }
 
 
+
+
+def time_alpha_study(steps, hip, retune=False, graph=True, dp=0.005):
+    """The paper's artificial-viscosity study as one batch: the obstacle dam
+    break at dp = 0.005 m once per alpha0 in {0.1, 0.01, 0.001, 0.0001}, with
+    the paper's 2h = 3 l0 and c0 = 20 sqrt(g H_W)."""
+    from paper_2306_01959_amd import scene
+    scenes = scene.alpha_study(dp)
+    r = time_ensemble(steps, hip, scenes=scenes, retune=retune, graph=graph,
+                      workload=f"{len(scenes)} obstacle dam breaks at dp={dp:g} m, one per "
+                               "alpha0 in {0.1, 0.01, 0.001, 0.0001}, 2h = 3 l0, "
+                               "c0 = 20 sqrt(g 0.3)")
+    r["instances_by_name"] = [s.name for s in scenes]
+    r["nu0"] = [scene.viscosity_label(s.params) for s in scenes]
+    return r
 
 
 def cpu_model():
@@ -424,6 +441,9 @@ def main():
                     help="only the per-configuration table (configs 1, 2, 3, 5; both precisions)")
     ap.add_argument("--small-only", action="store_true",
                     help="only the dp = 0.01 m dam break, mixed (profiling its kernels alone)")
+    ap.add_argument("--no-alpha", action="store_true", help="skip the alpha-study batch")
+    ap.add_argument("--alpha-only", action="store_true",
+                    help="only the alpha-study batch (profiling its kernels alone)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -450,6 +470,12 @@ def main():
         print(json.dumps({"ensemble": time_ensemble(args.ensemble_steps, hip,
                                                     graph=not args.ensemble_eager,
                                                     retune=args.retune)}), flush=True)
+        return
+    if args.alpha_only:
+        print(json.dumps({"alpha_study": time_alpha_study(args.ensemble_steps, hip,
+                                                          retune=args.retune,
+                                                          graph=not args.ensemble_eager)}),
+              flush=True)
         return
     sc2 = scene.config_scene(2)
     if args.small_only:
@@ -539,6 +565,8 @@ def main():
         out["dambreak_dp0.01"] = small
     if not args.no_ensemble:
         out["ensemble"] = time_ensemble(args.ensemble_steps, hip, retune=args.retune)
+    if not args.no_alpha:
+        out["alpha_study"] = time_alpha_study(args.ensemble_steps, hip, retune=args.retune)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, sc2)
     print(json.dumps(out), flush=True)

@@ -247,6 +247,35 @@ def dam_break(dp: float, seed: int, *, alpha: float = 0.01,
                     wet)
 
 
+#: vertical speed of the gate of the paper's gate-release case (Section 3)
+GATE_SPEED = 1.25
+
+
+def gate_release(dp: float, seed: int, *, alpha: float = 0.01, speed: float = GATE_SPEED,
+                 **kw) -> Scene:
+    """A gate-release dam break, a stand-in for the paper's force case (its
+    geometry figure is not available): the water block of the dam break held
+    by a gate, two layers of boundary particles across the tank at
+    x in (0.4, 0.4 + 2 dp), y in (0, 0.6), from the floor to 2 dp above the
+    water, that moves up at `speed` (1.25 m/s in the paper) from t = 0.  The
+    gate particles carry that velocity; everything starts hydrostatic."""
+    params = make_params(dp, alpha=alpha, **kw)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fluid = fluid_block(dp, WATER, rng)
+    x0 = WATER[0]
+    xs = _axis_points(dp, x0, x0 + 2.0 * dp)
+    ys = _axis_points(dp, 0.0, TANK[1])
+    zs = _axis_points(dp, 0.0, WATER[2] + 2.0 * dp)
+    zz, yy, xx = np.meshgrid(zs, ys, xs, indexing="ij")
+    gate = (xx.ravel(), yy.ravel(), zz.ravel())
+    rho_f = hydrostatic_density(fluid[2], WATER[2], params)
+    sc = assemble(f"gate_dp{dp:g}", fluid, [tank_walls(dp), gate], params, rho_f,
+                  (((0.0, WATER[0]), (0.0, WATER[1])), WATER[2]))
+    ng = gate[0].size
+    sc.uz[sc.n - ng:] = speed
+    return sc
+
+
 def resting_column(dp: float, seed: int, *, tank=(0.2, 0.2, 0.4),
                    H: float = 0.3, alpha: float = 0.1, jitter: float = 0.0,
                    **kw) -> Scene:
@@ -295,6 +324,40 @@ def ensemble(n_instances: int = 64, master_seed: int = 4,
         alpha = float(rng.uniform(*alpha_range))
         seed = int(rng.integers(0, 2 ** 31 - 1))
         out.append(dam_break(dp, seed, alpha=alpha, name=f"inst{k}"))
+    return out
+
+
+#: artificial viscosities of the paper's study (Table 1; Table 3 uses the
+#: first three)
+PAPER_ALPHAS = (0.1, 0.01, 0.001, 0.0001)
+
+
+def viscosity_label(params: Dict[str, object]) -> float:
+    """The kinematic viscosity nu0 = alpha h c0 / (2 (dim + 2)) that the paper
+    pairs with an artificial viscosity alpha (eq. visc0, dim = 3)."""
+    return float(params["alpha"]) * float(params["h"]) * float(params["c0"]) / 10.0
+
+
+def alpha_study(dp: float = 0.005, alphas: Sequence[float] = PAPER_ALPHAS,
+                master_seed: int = 6, obstacle: bool = True) -> List[Scene]:
+    """The paper's artificial-viscosity study as an ensemble: one dam break
+    (with the obstacle, as in the wave-height and pressure case) per alpha,
+    with the paper's own settings, 2h = 3 l0 and c0 = 20 sqrt(g H_W) (H_W =
+    0.3 m, the water column), each instance with its own seeded jitter.
+    Every scene's name carries its alpha and nu0 (eq. visc0)."""
+    children = np.random.SeedSequence(master_seed).spawn(len(alphas))
+    out = []
+    for a, ss in zip(alphas, children):
+        rng = np.random.Generator(np.random.PCG64(ss))
+        seed = int(rng.integers(0, 2 ** 31 - 1))
+        params = paper_params(dp, WATER[2], a)
+        sc_rng = np.random.Generator(np.random.PCG64(seed))
+        fluid = fluid_block(dp, WATER, sc_rng)
+        parts = [tank_walls(dp)]
+        if obstacle:
+            parts.append(obstacle_shell(dp))
+        name = f"alpha{a:g}_nu{viscosity_label(params):.1e}_dp{dp:g}"
+        out.append(assemble(name, fluid, parts, params))
     return out
 
 

@@ -507,3 +507,33 @@ def test_mixed_predicate_stays_in_stencil(seed):
     for i, j in full ^ ref:
         r = math.sqrt((x[j] - x[i]) ** 2 + (y[j] - y[i]) ** 2 + (z[j] - z[i]) ** 2)
         assert abs(r - 2 * prm["h"]) < 1e-6 * prm["h"]
+
+
+def test_alpha_study_settings_and_neighbours(oracle_lib):
+    """The alpha-study instances carry the paper's settings: 2h = 3 l0,
+    c0 = 20 sqrt(g H_W) with H_W = 0.3 m, the four alphas of Table 1, each
+    labelled by nu0 of eq. visc0.  With 2h = 3 l0 a bulk lattice particle has
+    exactly the 92 lattice points with |k|^2 <= 8 as neighbours."""
+    orc = oracle_lib
+    insts = scene.alpha_study(0.02)
+    assert [s.params["alpha"] for s in insts] == [0.1, 0.01, 0.001, 0.0001]
+    for s in insts:
+        prm = s.params
+        assert 2 * prm["h"] == pytest.approx(3 * prm["dp"], rel=1e-15)
+        assert prm["c0"] == pytest.approx(20.0 * math.sqrt(9.81 * 0.3), rel=1e-15)
+        nu = prm["alpha"] * prm["h"] * prm["c0"] / (2 * (3 + 2))
+        assert f"nu{nu:.1e}" in s.name and scene.viscosity_label(prm) == pytest.approx(nu)
+    # uneven seeds: the instances differ in their jitter only
+    assert not np.array_equal(insts[0].x, insts[1].x)
+    # dp a power of two: lattice differences are exact, so the points at
+    # |k|^2 = 9 lie exactly at 2h and stay outside the strict support
+    n, dp = 12, 2.0 ** -7
+    x, y, z = lattice(n, dp)
+    prm = scene.make_params(dp, h_factor=1.5, lo=(-0.05,) * 3, hi=(n * dp + 0.05,) * 3)
+    cnt, _ = orc.neighbours(orc.par(prm), x, y, z)
+    k = np.arange(-3, 4)
+    kk = k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2
+    expect = int(np.count_nonzero((kk > 0) & (kk <= 8)))
+    assert expect == 92
+    inner = interior(x, y, z, n * dp, 1.6 * 3 * dp)
+    assert inner.sum() > 0 and np.all(cnt[inner] == expect)
