@@ -13,7 +13,8 @@
  *   - Verlet update with an Euler reset every N_s steps (eqs. sphu1-sphrho1,
  *     sphu2-sphrho2), adaptive time step (eq. sphdt);
  *   - dynamic boundary particles: they obey continuity and the equation of
- *     state but do not move.
+ *     state but are not moved by the forces (a wall stays put, a gate moves
+ *     with its prescribed velocity).
  *
  * Conventions for every entry point:
  *   - extern "C"; the return value is an sph_status (0 = success).  On
@@ -77,11 +78,32 @@ typedef enum {
 } sph_delta_pairs;
 
 /*
+ * Time-integration scheme of sph_step / sph_run / sph_batch_run.
+ * SPH_SCHEME_VERLET: the paper's Verlet scheme with the Euler reset every
+ * N_s steps (eqs. sphu1-sphrho1, sphu2-sphrho2), one interaction per step.
+ * SPH_SCHEME_SYMPLECTIC: a two-stage symplectic predictor-corrector
+ * (position Verlet, which the paper cites among the alternatives without
+ * writing it out), two interactions per step:
+ *   rates at t:   r* = r + dt/2 u,  u* = u + dt/2 a,  rho* = rho + dt/2 drho
+ *   rates at t*:  u' = u + dt a*,   r' = r* + dt/2 u', rho' = rho + dt drho*
+ * with dt fixed by the first stage (the caller's dt, or eq. sphdt on the
+ * rates at t); afterwards (um, rhom) hold the level at t.  In both schemes
+ * boundary particles update rho and move with their own constant velocity
+ * (zero for fixed walls; the prescribed velocity of a moving gate, as in the
+ * paper's gate-release case).
+ */
+typedef enum {
+    SPH_SCHEME_VERLET = 0,
+    SPH_SCHEME_SYMPLECTIC = 1
+} sph_scheme;
+
+/*
  * Problem parameters (Section 2.2 and Section 3 of the paper).  All lengths in
  * metres, SI units.  Validation (SPH_E_INVAL): dp > 0, h > 0, rho0 > 0,
  * c0 > 0, gamma >= 1, alpha >= 0, 0 <= delta <= 1, eta2_coef >= 0,
  * 0 < cfl <= 1, mass > 0, cell_size >= 2h, dims[k] >= 1 and
- * dims[0]*dims[1]*dims[2] < 2^29 (SPH_E_RANGE), finite values, enums in range.
+ * dims[0]*dims[1]*dims[2] < 2^29 (SPH_E_RANGE), finite values, enums in range
+ * (scheme included).
  */
 typedef struct sph_params {
     double dp;         /* initial particle spacing l0 */
@@ -103,7 +125,7 @@ typedef struct sph_params {
     int32_t precision; /* sph_precision */
     int32_t c_mode;    /* sph_c_mode */
     int32_t delta_pairs; /* sph_delta_pairs */
-    int32_t reserved;  /* must be 0 */
+    int32_t scheme;    /* sph_scheme (0: the paper's Verlet scheme) */
 } sph_params;
 
 /*

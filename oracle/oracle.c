@@ -397,8 +397,9 @@ double orc_dt_cfl(const orc_par *p, int64_t n, const double *ax,
 }
 
 /* Time update (eqs. sphu1-sphrho1; Euler reset eqs. sphu2-sphrho2).  Fluid
- * particles update r, u, rho; boundary particles only rho.  Afterwards the
- * previous level holds the old current level. */
+ * particles update r, u, rho; boundary particles rho, and their position with
+ * their own constant velocity (a moving gate; zero for fixed walls).
+ * Afterwards the previous level holds the old current level. */
 void orc_update(const orc_par *p, int64_t n, int euler, double dt, double *x,
                 double *y, double *z, double *ux, double *uy, double *uz,
                 double *uxm, double *uym, double *uzm, double *rho,
@@ -416,8 +417,14 @@ void orc_update(const orc_par *p, int64_t n, int euler, double dt, double *x,
             rn = rhom[i] + 2.0 * dt * drho[i];
         rhom[i] = rho[i];
         rho[i] = rn;
-        if (is_bnd[i])
+        if (is_bnd[i]) {
+            /* boundary particles keep their velocity (zero for a fixed wall,
+             * the prescribed velocity of a moving one) and move with it */
+            x[i] = x[i] + dt * ux[i];
+            y[i] = y[i] + dt * uy[i];
+            z[i] = z[i] + dt * uz[i];
             continue;
+        }
         double vx, vy, vz;
         if (euler) {
             vx = ux[i] + dt * ax[i];
@@ -481,6 +488,79 @@ int orc_run(const orc_par *p, int64_t n, double *x, double *y, double *z,
     }
     if (rates_out)
         memcpy(rates_out, buf, sizeof(double) * nn * 5);
+    free(buf);
+    return 0;
+}
+
+/* ------------------------------------------------- symplectic scheme */
+
+/* One step of the two-stage symplectic predictor-corrector (position
+ * Verlet), with two evaluations of the rates per step:
+ *   predictor, rates at t:      r* = r + dt/2 u,  u* = u + dt/2 a,
+ *                               rho* = rho + dt/2 drho
+ *   corrector, rates at t*:     u' = u + dt a*,   r' = r* + dt/2 u',
+ *                               rho' = rho + dt drho*
+ * Fluid particles update r, u, rho; boundary particles rho, and r with their
+ * own constant velocity.  Afterwards (um, rhom) hold the level at t.
+ * dt_mode 0: dt = dt_in[k]; 1: the bound of eq. sphdt from the rates at t.
+ * dt_out (nullable) receives the dt of each step. */
+int orc_run_symplectic(const orc_par *p, int64_t n, double *x, double *y, double *z,
+                       double *ux, double *uy, double *uz, double *uxm, double *uym,
+                       double *uzm, double *rho, double *rhom, const uint8_t *is_bnd,
+                       int64_t nsteps, int dt_mode, const double *dt_in, double *dt_out)
+{
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double *buf = (double *)malloc(sizeof(double) * nn * 5);
+    if (!buf)
+        return -1;
+    double *ax = buf, *ay = buf + nn, *az = buf + 2 * nn, *dr = buf + 3 * nn,
+           *mm = buf + 4 * nn;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (orc_rates(p, n, x, y, z, ux, uy, uz, rho, is_bnd, ax, ay, az, dr, mm, 0) != 0) {
+            free(buf);
+            return -1;
+        }
+        double dt = dt_mode == 0 ? dt_in[k] : orc_dt_cfl(p, n, ax, ay, az, mm, is_bnd);
+        if (dt_out)
+            dt_out[k] = dt;
+        const double h2 = 0.5 * dt;
+        /* predictor: the level at t is kept in (um, rhom) */
+        for (int64_t i = 0; i < n; ++i) {
+            rhom[i] = rho[i];
+            rho[i] = rho[i] + h2 * dr[i];
+            uxm[i] = ux[i];
+            uym[i] = uy[i];
+            uzm[i] = uz[i];
+            x[i] = x[i] + h2 * ux[i];
+            y[i] = y[i] + h2 * uy[i];
+            z[i] = z[i] + h2 * uz[i];
+            if (!is_bnd[i]) {
+                ux[i] = ux[i] + h2 * ax[i];
+                uy[i] = uy[i] + h2 * ay[i];
+                uz[i] = uz[i] + h2 * az[i];
+            }
+        }
+        if (orc_rates(p, n, x, y, z, ux, uy, uz, rho, is_bnd, ax, ay, az, dr, mm, 0) != 0) {
+            free(buf);
+            return -1;
+        }
+        /* corrector */
+        for (int64_t i = 0; i < n; ++i) {
+            rho[i] = rhom[i] + dt * dr[i];
+            if (!is_bnd[i]) {
+                ux[i] = uxm[i] + dt * ax[i];
+                uy[i] = uym[i] + dt * ay[i];
+                uz[i] = uzm[i] + dt * az[i];
+            } else {
+                ux[i] = uxm[i];
+                uy[i] = uym[i];
+                uz[i] = uzm[i];
+            }
+            x[i] = x[i] + h2 * ux[i];
+            y[i] = y[i] + h2 * uy[i];
+            z[i] = z[i] + h2 * uz[i];
+        }
+    }
     free(buf);
     return 0;
 }

@@ -86,6 +86,9 @@ def lib():
         L.orc_run.argtypes = [P, C.c_int64] + [_D] * 11 + [_U8, C.c_int64,
                                                          C.c_int64, C.c_int,
                                                          _D, _D, _D]
+        L.orc_run_symplectic.restype = C.c_int
+        L.orc_run_symplectic.argtypes = [P, C.c_int64] + [_D] * 11 + [_U8, C.c_int64, C.c_int,
+                                                                    _D, _D]
         L.orc_diagnostics.restype = C.c_int
         L.orc_diagnostics.argtypes = [P, C.c_int64, _D, _D, _D, _D, _D, _D,
                                       _D, _U8, _D]
@@ -262,6 +265,21 @@ def run(p: OrcPar, st: State, nsteps: int, dt_mode: int = 1,
     st.step += nsteps
     rates5 = tuple(rbuf.reshape(5, n)) if rbuf is not None else None
     return dts[:nsteps], rates5
+
+
+def run_symplectic(p: OrcPar, st: State, nsteps: int, dt_mode: int = 1,
+                   dt_in: Optional[np.ndarray] = None) -> np.ndarray:
+    """Advance `st` by nsteps of the two-stage symplectic scheme; returns
+    the dt of every step."""
+    n = st.n
+    dts = np.zeros(max(nsteps, 1))
+    dti = _f64(dt_in if dt_in is not None else np.zeros(max(nsteps, 1)))
+    rc = lib().orc_run_symplectic(C.byref(p), n, *[_d(a) for a in st.arrays()],
+                                  st.is_bnd.ctypes.data_as(_U8), nsteps, dt_mode, _d(dti),
+                                  _d(dts))
+    assert rc == 0
+    st.step += nsteps
+    return dts[:nsteps]
 
 
 def diagnostics(p: OrcPar, st: State) -> Dict[str, float]:

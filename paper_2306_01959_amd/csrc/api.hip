@@ -133,6 +133,7 @@ static Inst inst_from(const sph_params &p, uint32_t cell_base, uint32_t row_base
 static Problem single_problem(const sph_params &p, int64_t n) {
     Problem P;
     P.precision = p.precision;
+    P.scheme = p.scheme;
     P.n = n;
     P.ncells = (int64_t)p.dims[0] * p.dims[1] * p.dims[2];
     P.nrows = (int64_t)p.dims[1] * p.dims[2];
@@ -174,7 +175,8 @@ static int check_params(const sph_params *p) {
         return fail(SPH_E_INVAL, "unknown c_mode");
     if (p->delta_pairs != SPH_DELTA_FLUID && p->delta_pairs != SPH_DELTA_ALL)
         return fail(SPH_E_INVAL, "unknown delta_pairs");
-    if (p->reserved != 0) return fail(SPH_E_INVAL, "reserved must be 0");
+    if (p->scheme != SPH_SCHEME_VERLET && p->scheme != SPH_SCHEME_SYMPLECTIC)
+        return fail(SPH_E_INVAL, "unknown scheme");
     return SPH_OK;
 }
 
@@ -238,6 +240,7 @@ static int batch_problem(const sph_batch *b, Problem *P) {
     P->host.clear();
     P->batch = true;
     P->precision = b->params[0].precision;
+    P->scheme = b->params[0].scheme;
     int64_t n = 0, cells = 0, rows = 0;
     for (int k = 0; k < b->ninst; ++k) {
         const sph_params &p = b->params[k];
@@ -245,6 +248,8 @@ static int batch_problem(const sph_batch *b, Problem *P) {
             return fail(rc, "instance " + std::to_string(k) + ": " + g_err);
         if (p.precision != P->precision)
             return fail(SPH_E_INVAL, "all instances must have the same precision");
+        if (p.scheme != P->scheme)
+            return fail(SPH_E_INVAL, "all instances must have the same scheme");
         const int64_t c = b->counts[k];
         if (c < 1) return fail(SPH_E_INVAL, "every instance needs >= 1 particle");
         const int64_t nc = (int64_t)p.dims[0] * p.dims[1] * p.dims[2];
@@ -314,10 +319,37 @@ static int64_t refresh_period(const Problem &P) {
     return L > 0 ? L : 40;
 }
 
+// One step of the two-stage symplectic scheme: cells and rates at t, the
+// predictor (which fixes dt), cells and rates at the predicted state, the
+// corrector.  The cell lists compute their keys from the positions.
+static int symplectic_step(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
+                           hipStream_t st, const Marks &m) {
+    if (!s.cells_valid) {
+        const bool full = step % refresh_period(P) == 0;
+        if (int rc = build_cells(P, s, w, st, false, dt, m, full, kNoKeys)) return rc;
+    } else {
+        if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
+        if (int rc = launch_chunks(P, w, false, dt, st)) return rc;
+    }
+    if (int rc = m.at(SPH_REGION_INTERACT, true, st)) return rc;
+    hipEvent_t after = (m.region == SPH_REGION_INTERACT && m.e0) ? m.e1 : nullptr;
+    if (int rc = launch_interact(P, s, w, st, nullptr, nullptr, nullptr, false, step, after))
+        return rc;
+    if (int rc = launch_symplectic(P, s, w, dt, false, st)) return rc;
+    s.cells_valid = 0;
+    if (int rc = build_cells(P, s, w, st, false, dt, Marks(), false, kNoKeys)) return rc;
+    if (int rc = launch_interact(P, s, w, st)) return rc;
+    if (int rc = launch_symplectic(P, s, w, dt, true, st)) return rc;
+    if (int rc = m.at(SPH_REGION_STEP, false, st)) return rc;
+    s.cells_valid = 0;
+    return SPH_OK;
+}
+
 // One step.  fused: the lagged-dt form, where the interaction also advances
 // the state (one kernel instead of interaction + update).
 static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
                     bool fused, hipStream_t st, const Marks &m = Marks(), int keys = kNoKeys) {
+    if (P.scheme == SPH_SCHEME_SYMPLECTIC) return symplectic_step(P, s, w, dt, step, st, m);
     if (!s.cells_valid) {
         const bool full = step % refresh_period(P) == 0;
         if (int rc = build_cells(P, s, w, st, fused, dt, m, full, keys)) return rc;
@@ -348,6 +380,7 @@ static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int6
 // the keys and counts their first digits; a fused interaction may write the
 // keys.
 static int keys_after(const Problem &P, bool fused) {
+    if (P.scheme == SPH_SCHEME_SYMPLECTIC) return kNoKeys;
     if (!fused) return kKeysCounted;
     return fused_writes_keys(P) ? kKeysOnly : kNoKeys;
 }
@@ -815,6 +848,8 @@ int sph_batch_run(const sph_batch *b, sph_state *s, void *ws, int64_t nsteps, do
     if (int rc = check_run_args(dt, nsteps, step0, mode)) return rc;
     if ((mode & SPH_RUN_GRAPH) && !stream)
         return fail(SPH_E_INVAL, "SPH_RUN_GRAPH needs a stream other than NULL");
+    if ((mode & SPH_RUN_LAGGED) && P.scheme != SPH_SCHEME_VERLET)
+        return fail(SPH_E_INVAL, "SPH_RUN_LAGGED needs the Verlet scheme");
     return run_steps(P, *s, w, nsteps, dt, step0, mode, static_cast<hipStream_t>(stream));
 }
 
@@ -826,6 +861,8 @@ int sph_batch_run_profiled(const sph_batch *b, sph_state *s, void *ws, int64_t n
     if (int rc = validate_batch(b, s, ws, &P, &w)) return rc;
     if (int rc = check_run_args(dt, nsteps, step0, mode & ~SPH_RUN_GRAPH)) return rc;
     if (mode & SPH_RUN_GRAPH) return fail(SPH_E_INVAL, "profiled runs take no graph");
+    if ((mode & SPH_RUN_LAGGED) && P.scheme != SPH_SCHEME_VERLET)
+        return fail(SPH_E_INVAL, "SPH_RUN_LAGGED needs the Verlet scheme");
     if (int rc = check_events(nsteps, region, ev_begin, ev_end)) return rc;
     return run_steps(P, *s, w, nsteps, dt, step0, mode, static_cast<hipStream_t>(stream), region,
                      ev_begin, ev_end);

@@ -248,6 +248,7 @@ struct Insts {
 // A problem: one or more instances sharing precision and particle arrays.
 struct Problem {
     int precision = SPH_MIXED;
+    int scheme = SPH_SCHEME_VERLET;  // sph_scheme, the same for every instance
     int64_t n = 0;          // particles in total
     int64_t ncells = 0;     // cells in total
     int64_t nrows = 0;      // rows in total
@@ -360,6 +361,10 @@ int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int
                      hipStream_t st, int hist_shift = -1);
 int launch_diag(const Problem &P, const sph_state &s, const Ws &w, const double *probes,
                 int32_t np, sph_diag *out, double *probe_p, hipStream_t st);
+// two-stage symplectic step: the predictor (rates at t in the workspace; fixes
+// dt) or the corrector (rates at the predicted state)
+int launch_symplectic(const Problem &P, sph_state &s, const Ws &w, double dt, bool corrector,
+                      hipStream_t st);
 // probe pressures (eq. sphpa) of instance 0 at np host points into the
 // device array pout (np values); the points are staged in the workspace
 int launch_probes(const Problem &P, const sph_state &s, const Ws &w, const double *probes,

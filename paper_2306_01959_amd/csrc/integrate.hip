@@ -150,6 +150,163 @@ int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int
 // The fused interaction advanced the state in place: rotate the levels.
 void after_fused_step(sph_state &s) { rotate_levels(s); }
 
+// ------------------------------------------------ two-stage symplectic step
+//
+// Predictor (rates at t, in the workspace): the level at t is kept in
+// (um, rhom); r* = r + dt/2 u, u* = u + dt/2 a (fluid), rho* = rho + dt/2 drho.
+// Corrector (rates at t*): u' = u(t) + dt a* (fluid), r' = r* + dt/2 u',
+// rho' = rho(t) + dt drho*.  Boundary particles keep u and move with it.  The
+// predictor fixes each instance's dt (the caller's, or Cr x the bound of the
+// rates at t) and the corrector reuses it; no level rotation.
+struct SymArgs {
+    int64_t n;
+    double *x, *y, *z, *ux, *uy, *uz, *uxm, *uym, *uzm;
+    void *rho, *rhom;
+    const uint32_t *id;
+    const void *rates;  // ax, ay, az, drho (n each)
+    Insts I;
+    DevScalars *sc;
+    InstState *ist;
+    double dt_arg;
+};
+
+template <bool kMixed>
+__device__ __forceinline__ void sym_rates(const SymArgs &a, int64_t i, double &ax, double &ay,
+                                          double &az, double &dr) {
+    const int64_t n = a.n;
+    if constexpr (kMixed) {
+        const float *r = static_cast<const float *>(a.rates);
+        ax = r[i];
+        ay = r[n + i];
+        az = r[2 * n + i];
+        dr = r[3 * n + i];
+    } else {
+        const double *r = static_cast<const double *>(a.rates);
+        ax = r[i];
+        ay = r[n + i];
+        az = r[2 * n + i];
+        dr = r[3 * n + i];
+    }
+}
+
+template <bool kMixed>
+__global__ __launch_bounds__(256) void k_sym_predict(SymArgs a) {
+    if (blockIdx.x == 0) {
+        for (int k = threadIdx.x; k < a.I.n; k += blockDim.x) {
+            const Inst ip = a.I.get(k);
+            const double b = __longlong_as_double((long long)a.ist[k].dt_min_bits);
+            const double dt = a.dt_arg > 0.0 ? a.dt_arg : ip.cfl * b;
+            a.ist[k].dt_cfl = ip.cfl * b;
+            a.ist[k].dt_last = dt;
+            if (dt > ip.cfl * b) a.sc->dt_cfl_violation = 1u;
+        }
+    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const uint32_t id = a.id[i];
+    const int k = a.I.of_id(id & 0x7fffffffu);
+    const Inst ip = a.I.get(k);
+    const double b = __longlong_as_double((long long)a.ist[k].dt_min_bits);
+    const double h2 = 0.5 * (a.dt_arg > 0.0 ? a.dt_arg : ip.cfl * b);
+    double ax, ay, az, dr;
+    sym_rates<kMixed>(a, i, ax, ay, az, dr);
+    if constexpr (kMixed) {
+        float *rho = static_cast<float *>(a.rho);
+        const float cur = rho[i];
+        static_cast<float *>(a.rhom)[i] = cur;
+        rho[i] = (float)((double)cur + h2 * dr);
+    } else {
+        double *rho = static_cast<double *>(a.rho);
+        const double cur = rho[i];
+        static_cast<double *>(a.rhom)[i] = cur;
+        rho[i] = cur + h2 * dr;
+    }
+    const double ux = a.ux[i], uy = a.uy[i], uz = a.uz[i];
+    a.uxm[i] = ux;
+    a.uym[i] = uy;
+    a.uzm[i] = uz;
+    a.x[i] = a.x[i] + h2 * ux;
+    a.y[i] = a.y[i] + h2 * uy;
+    a.z[i] = a.z[i] + h2 * uz;
+    if ((id >> 31) == 0) {
+        a.ux[i] = ux + h2 * ax;
+        a.uy[i] = uy + h2 * ay;
+        a.uz[i] = uz + h2 * az;
+    }
+}
+
+template <bool kMixed>
+__global__ __launch_bounds__(256) void k_sym_correct(SymArgs a) {
+    if (blockIdx.x == 0) {
+        for (int k = threadIdx.x; k < a.I.n; k += blockDim.x) a.ist[k].time += a.ist[k].dt_last;
+        if (threadIdx.x == 0) a.sc->steps += 1;
+    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const uint32_t id = a.id[i];
+    const int k = a.I.of_id(id & 0x7fffffffu);
+    const double dt = a.ist[k].dt_last;
+    const double h2 = 0.5 * dt;
+    double ax, ay, az, dr;
+    sym_rates<kMixed>(a, i, ax, ay, az, dr);
+    if constexpr (kMixed) {
+        const float base = static_cast<const float *>(a.rhom)[i];
+        static_cast<float *>(a.rho)[i] = (float)((double)base + dt * dr);
+    } else {
+        const double base = static_cast<const double *>(a.rhom)[i];
+        static_cast<double *>(a.rho)[i] = base + dt * dr;
+    }
+    double ux = a.uxm[i], uy = a.uym[i], uz = a.uzm[i];
+    if ((id >> 31) == 0) {
+        ux += dt * ax;
+        uy += dt * ay;
+        uz += dt * az;
+    }
+    a.ux[i] = ux;
+    a.uy[i] = uy;
+    a.uz[i] = uz;
+    a.x[i] = a.x[i] + h2 * ux;
+    a.y[i] = a.y[i] + h2 * uy;
+    a.z[i] = a.z[i] + h2 * uz;
+}
+
+int launch_symplectic(const Problem &P, sph_state &s, const Ws &w, double dt, bool corrector,
+                      hipStream_t st) {
+    SymArgs a;
+    a.n = s.n;
+    a.x = s.x;
+    a.y = s.y;
+    a.z = s.z;
+    a.ux = s.ux;
+    a.uy = s.uy;
+    a.uz = s.uz;
+    a.uxm = s.uxm;
+    a.uym = s.uym;
+    a.uzm = s.uzm;
+    a.rho = s.rho;
+    a.rhom = s.rhom;
+    a.id = s.id;
+    a.rates = w.base + w.L.rates;
+    a.I = insts_of(P, w);
+    a.sc = w.scalars();
+    a.ist = w.inst_state();
+    a.dt_arg = dt;
+    const dim3 grid((unsigned)((s.n + 255) / 256)), block(256);
+    const bool mixed = P.precision == SPH_MIXED;
+    if (corrector) {
+        if (mixed)
+            hipLaunchKernelGGL((k_sym_correct<true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_sym_correct<false>), grid, block, 0, st, a);
+    } else {
+        if (mixed)
+            hipLaunchKernelGGL((k_sym_predict<true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_sym_predict<false>), grid, block, 0, st, a);
+    }
+    return launch_check(corrector ? "symplectic corrector" : "symplectic predictor");
+}
+
 // --------------------------------------------------- density conversion
 
 __global__ void k_set_density(const double *__restrict__ src, void *dst, int64_t n, Insts I,

@@ -1,6 +1,7 @@
 // Time update of one particle (Section 2.2): Verlet scheme, eqs. sphu1,
 // sphr1, sphrho1, and the Euler reset of eqs. sphu2, sphr2, sphrho2.  Fluid
-// particles update r, u, rho; dynamic boundary particles rho only.  The new
+// particles update r, u, rho; dynamic boundary particles rho, and r with their
+// own constant velocity (zero for a fixed wall, nonzero for a moving gate).  The new
 // level is written over the previous one (um, rhom); the caller then swaps the
 // (u, um) and (rho, rhom) pointers.  FP64 accumulators for r and u; the mixed
 // path keeps rho - rho0 in FP32, updated in FP64 and rounded once.  With kKeys
@@ -47,13 +48,19 @@ __device__ __forceinline__ uint32_t advance(const StateArrays &s, const Inst &ip
     }
     const double ux = s.ux[i], uy = s.uy[i], uz = s.uz[i];
     const uint32_t id = s.id[i];
-    if ((id >> 31) != 0) {  // boundary: does not move
+    if ((id >> 31) != 0) {
+        // boundary: keeps its velocity (zero for a fixed wall, the prescribed
+        // one of a moving gate) and moves with it
         s.uxm[i] = ux;
         s.uym[i] = uy;
         s.uzm[i] = uz;
+        const double x = s.x[i] + dt * ux, y = s.y[i] + dt * uy, z = s.z[i] + dt * uz;
+        s.x[i] = x;
+        s.y[i] = y;
+        s.z[i] = z;
         uint32_t key = 0;
         if (kKeys && s.keys_next) {
-            key = sort_key(ip, s.x[i], s.y[i], s.z[i], id);
+            key = sort_key(ip, x, y, z, id);
             s.keys_next[i] = key;
         }
         return key;

@@ -20,6 +20,7 @@ SPH_OK, SPH_E_INVAL, SPH_E_HIP, SPH_E_RANGE, SPH_E_STATE, SPH_E_SIZE = 0, -1, -2
 SPH_FP64, SPH_MIXED = 0, 1
 SPH_C_TAIT, SPH_C_CONST = 0, 1
 SPH_DELTA_FLUID, SPH_DELTA_ALL = 0, 1
+SCHEME_VERLET, SCHEME_SYMPLECTIC = 0, 1
 FLAG_NONFINITE, FLAG_OUTSIDE, FLAG_DENSITY, FLAG_DT_CFL = 1, 2, 4, 8
 BOUNDARY_BIT = np.uint32(1 << 31)
 
@@ -47,7 +48,7 @@ class SphParams(C.Structure):
         ("g", C.c_double * 3), ("eta2_coef", C.c_double), ("cfl", C.c_double),
         ("mass", C.c_double), ("origin", C.c_double * 3), ("cell_size", C.c_double),
         ("dims", C.c_int32 * 3), ("verlet_ns", C.c_int32), ("precision", C.c_int32),
-        ("c_mode", C.c_int32), ("delta_pairs", C.c_int32), ("reserved", C.c_int32),
+        ("c_mode", C.c_int32), ("delta_pairs", C.c_int32), ("scheme", C.c_int32),
     ]
 
 
@@ -182,7 +183,8 @@ def get_split(params: "SphParams", n: int):
 
 
 def make_params(prm: Dict[str, object], precision: str = "mixed", *,
-                c_mode: int = SPH_C_TAIT, delta_pairs: int = SPH_DELTA_FLUID) -> SphParams:
+                c_mode: int = SPH_C_TAIT, delta_pairs: int = SPH_DELTA_FLUID,
+                scheme: int = SCHEME_VERLET) -> SphParams:
     p = SphParams()
     for k in ("dp", "h", "rho0", "c0", "gamma", "alpha", "delta", "eta2_coef", "cfl", "mass"):
         setattr(p, k, float(prm[k]))
@@ -194,7 +196,7 @@ def make_params(prm: Dict[str, object], precision: str = "mixed", *,
     p.precision = SPH_MIXED if precision == "mixed" else SPH_FP64
     p.c_mode = c_mode
     p.delta_pairs = delta_pairs
-    p.reserved = 0
+    p.scheme = int(scheme)
     return p
 
 
@@ -326,10 +328,11 @@ class Simulation(_System):
     :meth:`fetch`."""
 
     def __init__(self, scene, precision: str = "mixed", device: str = "cuda:0",
-                 stream=None, c_mode: int = SPH_C_TAIT, delta_pairs: int = SPH_DELTA_FLUID):
+                 stream=None, c_mode: int = SPH_C_TAIT, delta_pairs: int = SPH_DELTA_FLUID,
+                 scheme: int = SCHEME_VERLET):
         self.lib = load()
         self.params = make_params(scene.params, precision, c_mode=c_mode,
-                                  delta_pairs=delta_pairs)
+                                  delta_pairs=delta_pairs, scheme=scheme)
         check(self.lib.sph_check_params(C.byref(self.params)))
         nbytes = C.c_size_t(0)
         check(self.lib.sph_workspace_bytes(C.byref(self.params), scene.n, C.byref(nbytes)))
@@ -455,14 +458,15 @@ class Ensemble(_System):
     owns original ids [offsets[k], offsets[k] + counts[k])."""
 
     def __init__(self, scenes, precision: str = "mixed", device: str = "cuda:0", stream=None,
-                 c_mode: int = SPH_C_TAIT, delta_pairs: int = SPH_DELTA_FLUID):
+                 c_mode: int = SPH_C_TAIT, delta_pairs: int = SPH_DELTA_FLUID,
+                 scheme: int = SCHEME_VERLET):
         self.lib = load()
         k = len(scenes)
         self.ninst = k
         self._params = (SphParams * k)()
         for i, sc in enumerate(scenes):
             self._params[i] = make_params(sc.params, precision, c_mode=c_mode,
-                                          delta_pairs=delta_pairs)
+                                          delta_pairs=delta_pairs, scheme=scheme)
         self.counts = np.array([sc.n for sc in scenes], dtype=np.int64)
         self.offsets = np.concatenate([[0], np.cumsum(self.counts)[:-1]]).astype(np.int64)
         self._counts = (C.c_int64 * k)(*[int(c) for c in self.counts])

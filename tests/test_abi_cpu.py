@@ -81,7 +81,7 @@ def params(**over):
     ("h", 0.0), ("h", -1.0), ("dp", 0.0), ("rho0", 0.0), ("c0", -1.0), ("gamma", 0.5),
     ("alpha", -0.1), ("delta", 1.5), ("cfl", 0.0), ("cfl", 1.5), ("mass", 0.0),
     ("cell_size", 0.01), ("precision", 7), ("c_mode", 3), ("delta_pairs", 2),
-    ("reserved", 1), ("h", float("nan")), ("eta2_coef", -1.0),
+    ("scheme", 2), ("h", float("nan")), ("eta2_coef", -1.0),
 ])
 def test_bad_params_rejected(L, field, value):
     p = params(**{field: value})
@@ -258,3 +258,27 @@ def test_loads_rejected_before_launch(L):
         lib.SPH_E_INVAL
     assert L.sph_probe_impulse(C.byref(p), C.byref(st), ws, pts, 1, 0, out, imp, None) == \
         lib.SPH_E_STATE
+
+
+def test_lagged_symplectic_batch_rejected(L):
+    """The lagged fused step is the Verlet scheme's; a symplectic batch asking
+    for it is rejected before anything is launched."""
+    import ctypes as C
+    from paper_2306_01959_amd import lib, scene
+    scs = scene.ensemble(2, master_seed=21, dps=(0.05,))
+    params = (lib.SphParams * 2)(*[lib.make_params(s.params, "mixed",
+                                                   scheme=lib.SCHEME_SYMPLECTIC) for s in scs])
+    counts = (C.c_int64 * 2)(*[s.n for s in scs])
+    b = lib.SphBatch(2, 0, params, counts)
+    st = lib.SphState()
+    st.n = sum(s.n for s in scs)
+    for name, _ in lib.SphState._fields_[1:25]:
+        setattr(st, name, 1 << 20)
+    ws = C.c_void_p(1 << 24)
+    rc = L.sph_batch_run(C.byref(b), C.byref(st), ws, 5, -1.0, 0, lib.RUN_LAGGED, None)
+    assert rc == lib.SPH_E_INVAL
+    assert b"Verlet" in L.sph_last_error()
+    # mixed schemes in one batch
+    params[1] = lib.make_params(scs[1].params, "mixed")
+    rc = L.sph_batch_run(C.byref(b), C.byref(st), ws, 5, -1.0, 0, 0, None)
+    assert rc == lib.SPH_E_INVAL and b"scheme" in L.sph_last_error()

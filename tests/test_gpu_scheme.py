@@ -1,0 +1,169 @@
+"""The two-stage symplectic scheme and moving boundary particles (a gate
+lifted at constant speed) on the GPU against the oracle, through the C ABI
+(needs an MI355X).
+
+* Symplectic steps from a developed dam-break state (the oracle's dt
+  sequence fed to the GPU) in both precisions; the device's own time step
+  (eq. sphdt on the first stage's rates) against the oracle's.
+* The gate-release dam break (gate moving up at 1.25 m/s from t = 0) in the
+  paper's Verlet scheme and in the symplectic one, 500 steps (t ~ 0.2 s, the
+  water flows out under the gate from about step 350): the gate particles
+  follow z0 + 1.25 t, and the fluid's fields, surge front and probe
+  pressures follow the oracle's.
+* Batches: a symplectic batch equals its instances run alone, bit for bit,
+  and its graph replays equal eager launches.
+"""
+import numpy as np
+import pytest
+
+from paper_2306_01959_amd import scene
+from tests.gpu_helpers import rel_l2, scene_from_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_01959_amd import lib
+    lib.load()
+    return lib
+
+
+@pytest.fixture(scope="module")
+def developed(oracle_lib):
+    s = scene.config_scene(1)
+    p = oracle_lib.par(s.params)
+    st = oracle_lib.State(s)
+    oracle_lib.run(p, st, 60, dt_mode=1)
+    return s.params, st
+
+
+def _fields_close(out, st, tol, dp, label, pos_tol=None):
+    """Velocities and density within tol (relative L2), positions within
+    pos_tol (default 1e-9 dp in FP64, 1e-5 dp in mixed precision) of the
+    oracle's."""
+    errs = {k: rel_l2(out[k], getattr(st, k)) for k in ("ux", "uy", "uz")}
+    errs["rho"] = rel_l2(out["rho"] - 1000.0, st.rho - 1000.0)
+    dx = max(np.abs(out[k] - getattr(st, k)).max() for k in ("x", "y", "z"))
+    print(f"\n{label}: rel L2 {({k: f'{v:.1e}' for k, v in errs.items()})}, "
+          f"max |dr| {dx / dp:.1e} dp", flush=True)
+    for k, v in errs.items():
+        assert v < tol, (label, k, v)
+    if pos_tol is None:
+        pos_tol = 1e-9 if tol < 1e-8 else 1e-5
+    assert dx < pos_tol * dp, dx
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_symplectic_trajectory(gpu, oracle_lib, developed, precision, tol):
+    orc = oracle_lib
+    params, st0 = developed
+    sc, _ = scene_from_oracle(st0, params)
+    p = orc.par(params)
+    st = orc.State(sc)
+    dts = orc.run_symplectic(p, st, 50, dt_mode=1)
+    sim = gpu.Simulation(sc, precision, scheme=gpu.SCHEME_SYMPLECTIC)
+    for k in range(50):
+        sim.step(float(dts[k]), k)
+    _fields_close(sim.fetch(), st, tol, params["dp"], f"symplectic {precision}")
+
+
+def test_symplectic_device_dt(gpu, oracle_lib, developed):
+    """sph_run with dt <= 0: each step's dt is Cr x the bound of eq. sphdt
+    on the first stage's rates; 20 steps in FP64 against the oracle."""
+    orc = oracle_lib
+    params, st0 = developed
+    sc, _ = scene_from_oracle(st0, params)
+    p = orc.par(params)
+    st = orc.State(sc)
+    dts = orc.run_symplectic(p, st, 20, dt_mode=1)
+    sim = gpu.Simulation(sc, "fp64", scheme=gpu.SCHEME_SYMPLECTIC)
+    sim.run(20, -1.0, 0)
+    d, _ = sim.diagnostics()
+    assert d["time"] == pytest.approx(dts.sum(), rel=1e-12)
+    assert d["dt_last"] == pytest.approx(dts[-1], rel=1e-12)
+    assert d["steps"] == 20
+    _fields_close(sim.fetch(), st, 1e-10, params["dp"], "symplectic device dt")
+
+
+@pytest.mark.parametrize("scheme", ["verlet", "symplectic"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gate_release(gpu, oracle_lib, scheme, precision):
+    orc = oracle_lib
+    s = scene.gate_release(0.02, 7)
+    gate = s.uz != 0
+    p = orc.par(s.params)
+    st = orc.State(s)
+    code = gpu.SCHEME_SYMPLECTIC if scheme == "symplectic" else gpu.SCHEME_VERLET
+    sim = gpu.Simulation(s, precision, scheme=code)
+    probes = np.array([[0.45, 0.3, 0.02], [0.5, 0.3, 0.02], [0.3, 0.3, 0.1]])
+    ref, got = [], []
+    step = 0
+    t = 0.0
+    for _ in range(50):
+        if scheme == "symplectic":
+            dts = orc.run_symplectic(p, st, 10, dt_mode=1)
+        else:
+            dts, _ = orc.run(p, st, 10, dt_mode=1)
+        for dt in dts:
+            sim.step(float(dt), step)
+            step += 1
+            t += float(dt)
+        od = orc.diagnostics(p, st)
+        ref.append([od["x_front"], *orc.probes(p, st, probes)])
+        d, pp = sim.diagnostics(probes)
+        got.append([d["x_front"], *pp])
+    out = sim.fetch()
+    # the gate moved up with its prescribed speed
+    assert np.allclose(out["z"][gate], s.z[gate] + 1.25 * t, rtol=0, atol=1e-12)
+    assert np.allclose(st.z[gate], s.z[gate] + 1.25 * t, rtol=0, atol=1e-12)
+    assert np.array_equal(out["x"][gate], s.x[gate])
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    # 500 steps of a violent release: mixed-precision positions drift by a
+    # few 1e-5 dp from the oracle's
+    _fields_close(out, st, tol, s.params["dp"], f"gate {scheme} {precision}",
+                  pos_tol=1e-9 if precision == "fp64" else 1e-4)
+    ref, got = np.array(ref), np.array(got)
+    span = ref.max(axis=0) - ref.min(axis=0)
+    err = np.abs(got - ref).max(axis=0)
+    assert span[0] > 0.05 and (span[1:] > 50.0).all(), span   # the water is released
+    assert np.count_nonzero(out["x"][~s.is_boundary] > 0.44) > 100
+    assert (err <= 0.01 * span).all(), err / span
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    return scene.ensemble(3, master_seed=21, dps=(0.04, 0.05))
+
+
+def test_symplectic_batch_equals_single(gpu, small_batch):
+    gpu.set_tuning(3, 3, 16, 16)
+    try:
+        ens = gpu.Ensemble(small_batch, "fp64", scheme=gpu.SCHEME_SYMPLECTIC)
+        ens.run(30, -1.0, 0)
+        got = ens.fetch()
+        for k, sc in enumerate(small_batch):
+            sim = gpu.Simulation(sc, "fp64", scheme=gpu.SCHEME_SYMPLECTIC)
+            sim.run(30, -1.0, 0)
+            one = sim.fetch()
+            o, c = ens.offsets[k], ens.counts[k]
+            for key in ("x", "z", "ux", "uz", "rho"):
+                assert np.array_equal(got[key][o:o + c], one[key]), (k, key)
+    finally:
+        gpu.set_tuning()
+
+
+def test_symplectic_graph_equals_eager(gpu, small_batch):
+    import torch
+    a = gpu.Ensemble(small_batch, "mixed", scheme=gpu.SCHEME_SYMPLECTIC)
+    a.run(40, -1.0, 0)
+    ra = a.fetch()
+    b = gpu.Ensemble(small_batch, "mixed", stream=torch.cuda.Stream(),
+                     scheme=gpu.SCHEME_SYMPLECTIC)
+    b.run(40, -1.0, 0, mode=gpu.RUN_GRAPH)
+    rb = b.fetch()
+    for key in ("x", "y", "z", "ux", "uz", "rho"):
+        assert np.array_equal(ra[key], rb[key]), key
