@@ -408,6 +408,47 @@ int sph_boundary_force(const sph_params *p, const sph_state *s, void *ws, const 
 int sph_probe_impulse(const sph_params *p, const sph_state *s, void *ws, const double *probes_xyz,
                       int32_t np, int32_t reset, double *probe_p, double *impulse, void *stream);
 
+/*
+ * Explicit operators of the moving particle semi-implicit (MPS) method
+ * (Section 2, MPS subsection) on the same cell list, for comparing the two
+ * methods' operators on one particle set.  With r_ij = r_j - r_i and the
+ * weight w_ij = r_e / |r_ij| - 1 for 0 < |r_ij| < r_e, else 0 (eq. mpsw;
+ * coincident particles, where it is unbounded, are left out), over all
+ * other particles j, fluid and boundary:
+ *   pnd_i   = sum_j w_ij                                         (eq. mpspnd)
+ *   grad_i  = (3 / n0) sum_j (phi_j - phi_i) r_ij w_ij / |r_ij|^2 (eq. mpsgrad)
+ *   lap_i   = (6 / (lambda0 n0)) sum_j (phi_j - phi_i) w_ij       (eq. mpslap)
+ *   sigma_i = |sum_j r_ij w_ij| / sum_j w_ij, 0 without neighbours (eq. mpssigmai2)
+ *   surface_i = 1 if pnd_i < beta1 n0 and sigma_i > rho1 l0, else 0
+ *               (the two criteria of the NPCD test, eqs. mpsni, mpsisgmai1)
+ * The pressure Poisson solve of the method is not part of this library.
+ */
+typedef struct sph_mps {
+    double re;       /* effective radius r_e = k_MPS l0 (the paper: 2.1 l0) */
+    double n0;       /* particle number density of a full support */
+    double lambda0;  /* correction parameter of the Laplacian (eq. mpslambda) */
+    double beta1;    /* density criterion, in (0, 1] (the paper: 0.98) */
+    double rho1;     /* centroid criterion in units of l0, >= 0 (the paper: 0.2) */
+    double l0;       /* initial particle distance */
+} sph_mps;
+
+/* n0 and lambda0 (eqs. mpspnd, mpslambda) of the fully filled support on
+ * the cubic lattice of spacing l0; 0 < re <= 64 l0 (SPH_E_INVAL). */
+int sph_mps_constants(double l0, double re, double *n0, double *lambda0);
+
+/*
+ * The operators above at every particle of a single system, in the current
+ * (cell) order.  The current cells (SPH_E_STATE if stale) must be at least
+ * r_e wide: m->re <= p->cell_size (SPH_E_INVAL), e.g. cells built with
+ * h = r_e / 2.  phi: device array of n doubles (may be NULL: then lap and
+ * grad must be NULL too).  Outputs are device arrays, each may be NULL:
+ * pnd, lap, sigma n doubles; grad 3 n doubles (x components, then y, then
+ * z); surface n int32.  Asynchronous on the stream.
+ */
+int sph_mps_operators(const sph_params *p, const sph_state *s, void *ws, const sph_mps *m,
+                      const double *phi, double *pnd, double *lap, double *grad, double *sigma,
+                      int32_t *surface, void *stream);
+
 /* ======================================================================
  * Batches: an ensemble of independent systems advanced together, as in the
  * paper's artificial-viscosity study (Section 4: several alpha values on one

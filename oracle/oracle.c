@@ -10,7 +10,9 @@
  * (eq. sphdt) and dynamic boundary particles.  Probe pressures follow the
  * Shepard filter of eq. sphpa (Section 3.1); the load on a solid is the sum
  * of its wall particles' accelerations times their mass and the pressure
- * impulse the time integral of a probe pressure (Section 3).
+ * impulse the time integral of a probe pressure (Section 3).  The explicit
+ * MPS operators (weight, particle number density, gradient, Laplacian and the
+ * two-criteria free-surface test) follow the MPS subsection of Section 2.
  *
  * Only the test-suite, the package's smoke check and the benchmark's CPU
  * baseline may load this library.  It shares no code with the HIP library.
@@ -764,6 +766,111 @@ int orc_boundary_force(const orc_par *p, int64_t n, const double *x,
 double orc_impulse_step(double I, double p_prev, double p_now, double dt)
 {
     return I + 0.5 * (p_prev + p_now) * dt;
+}
+
+/* ------------------------------------------------------- MPS operators */
+
+/* MPS weight (eq. mpsw): r_e / r - 1 for 0 < r < r_e, else 0.  Coincident
+ * particles (r = 0, where the weight is unbounded) are left out, and the
+ * weight vanishes at r_e, so the strict and inclusive readings agree. */
+double orc_mps_weight(double r, double re)
+{
+    if (!(r > 0.0) || !(r < re))
+        return 0.0;
+    return re / r - 1.0;
+}
+
+/* n0 and lambda0 (eqs. mpspnd, mpslambda) of the fully filled support: the
+ * sums over the points k l0 (k integer, k != 0) of the cubic lattice within
+ * r_e of the origin. */
+void orc_mps_lattice(double l0, double re, double *n0, double *lambda0)
+{
+    int kmax = (int)ceil(re / l0) + 1;
+    double sw = 0.0, sr2w = 0.0;
+    for (int a = -kmax; a <= kmax; ++a)
+        for (int b = -kmax; b <= kmax; ++b)
+            for (int c = -kmax; c <= kmax; ++c) {
+                double dx = a * l0, dy = b * l0, dz = c * l0;
+                double r2 = orc_r2(dx, dy, dz);
+                double w = orc_mps_weight(sqrt(r2), re);
+                sw += w;
+                sr2w += r2 * w;
+            }
+    *n0 = sw;
+    *lambda0 = sr2w / sw;
+}
+
+/* Explicit MPS operators at every particle, over all other particles j
+ * (fluid and wall) with 0 < |r_ij| < r_e, r_ij = r_j - r_i:
+ *   pnd_i  = sum w_ij                                   (eq. mpspnd)
+ *   grad_i = (3 / n0) sum (phi_j - phi_i) r_ij w_ij / |r_ij|^2  (eq. mpsgrad)
+ *   lap_i  = (6 / (lambda0 n0)) sum (phi_j - phi_i) w_ij     (eq. mpslap)
+ *   sigma_i = |sum r_ij w_ij| / sum w_ij   (0 when the sum is 0; eq. mpssigmai2)
+ *   surface_i = pnd_i < beta1 n0 and sigma_i > rho1 l0 (eqs. mpsni, mpsisgmai1)
+ * The cell grid of p must have cells of at least r_e.  phi may be NULL (then
+ * lap and grad are not written); grad holds 3 arrays of n. */
+int orc_mps_operators(const orc_par *p, int64_t n, const double *x, const double *y,
+                      const double *z, const double *phi, double re, double n0,
+                      double lambda0, double beta1, double rho1, double l0,
+                      double *pnd, double *lap, double *grad, double *sigma,
+                      int32_t *surface)
+{
+    orc_grid g;
+    if (orc_grid_build(p, n, x, y, z, &g) != 0) {
+        orc_grid_free(&g);
+        return -1;
+    }
+    const double re2 = re * re;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double sw = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+        double sl = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int32_t cxn = g.cx[i] + dx, cyn = g.cy[i] + dy, czn = g.cz[i] + dz;
+                    if (cxn < 0 || cyn < 0 || czn < 0 || cxn >= p->nx || cyn >= p->ny || czn >= p->nz)
+                        continue;
+                    int64_t c = cxn + (int64_t)p->nx * (cyn + (int64_t)p->ny * czn);
+                    for (int64_t s = g.start[c]; s < g.start[c + 1]; ++s) {
+                        int64_t j = g.order[s];
+                        if (j == i)
+                            continue;
+                        double rx = x[j] - x[i], ry = y[j] - y[i], rz = z[j] - z[i];
+                        double r2 = orc_r2(rx, ry, rz);
+                        if (!(r2 < re2) || !(r2 > 0.0))
+                            continue;
+                        double w = orc_mps_weight(sqrt(r2), re);
+                        sw += w;
+                        sx += rx * w;
+                        sy += ry * w;
+                        sz += rz * w;
+                        if (phi) {
+                            double d = phi[j] - phi[i];
+                            sl += d * w;
+                            gx += d * rx * w / r2;
+                            gy += d * ry * w / r2;
+                            gz += d * rz * w / r2;
+                        }
+                    }
+                }
+        double sig = sw > 0.0 ? sqrt(orc_r2(sx, sy, sz)) / sw : 0.0;
+        if (pnd)
+            pnd[i] = sw;
+        if (sigma)
+            sigma[i] = sig;
+        if (surface)
+            surface[i] = (sw < beta1 * n0 && sig > rho1 * l0) ? 1 : 0;
+        if (phi && lap)
+            lap[i] = 2.0 * 3.0 / (lambda0 * n0) * sl;
+        if (phi && grad) {
+            grad[i] = 3.0 / n0 * gx;
+            grad[n + i] = 3.0 / n0 * gy;
+            grad[2 * n + i] = 3.0 / n0 * gz;
+        }
+    }
+    orc_grid_free(&g);
+    return 0;
 }
 
 int orc_max_threads(void)

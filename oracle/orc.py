@@ -100,6 +100,13 @@ def lib():
                                          _D, _D]
         L.orc_impulse_step.restype = C.c_double
         L.orc_impulse_step.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_mps_weight.restype = C.c_double
+        L.orc_mps_weight.argtypes = [C.c_double, C.c_double]
+        L.orc_mps_lattice.restype = None
+        L.orc_mps_lattice.argtypes = [C.c_double, C.c_double, _D, _D]
+        L.orc_mps_operators.restype = C.c_int
+        L.orc_mps_operators.argtypes = [P, C.c_int64, _D, _D, _D, _D] + [C.c_double] * 6 + \
+            [_D, _D, _D, _D, _I32]
         L.orc_max_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -329,3 +336,37 @@ def boundary_force(p: OrcPar, st_or_arrays, box):
 
 def impulse_step(I: float, p_prev: float, p_now: float, dt: float) -> float:
     return float(lib().orc_impulse_step(float(I), float(p_prev), float(p_now), float(dt)))
+
+
+def mps_weight(r: float, re: float) -> float:
+    return float(lib().orc_mps_weight(float(r), float(re)))
+
+
+def mps_lattice(l0: float, re: float):
+    """(n0, lambda0) of the fully filled support on the cubic lattice."""
+    n0 = C.c_double(0.0)
+    lam = C.c_double(0.0)
+    lib().orc_mps_lattice(float(l0), float(re), C.byref(n0), C.byref(lam))
+    return n0.value, lam.value
+
+
+def mps_operators(p: OrcPar, x, y, z, phi, re, n0, lambda0, beta1=0.98, rho1=0.2, l0=None):
+    """Per particle: (pnd, laplacian of phi, gradient of phi (3, n), sigma,
+    surface flag); phi may be None (laplacian and gradient are then None)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.size
+    ph = _f64(phi) if phi is not None else None
+    pnd = np.zeros(n)
+    lap = np.zeros(n)
+    grad = np.zeros(3 * n)
+    sig = np.zeros(n)
+    surf = np.zeros(n, np.int32)
+    rc = lib().orc_mps_operators(C.byref(p), n, _d(x), _d(y), _d(z),
+                                 _d(ph) if ph is not None else None, float(re), float(n0),
+                                 float(lambda0), float(beta1), float(rho1), float(l0),
+                                 _d(pnd), _d(lap), _d(grad), _d(sig),
+                                 surf.ctypes.data_as(_I32))
+    assert rc == 0
+    if ph is None:
+        return pnd, None, None, sig, surf
+    return pnd, lap, grad.reshape(3, n), sig, surf

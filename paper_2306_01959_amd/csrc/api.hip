@@ -790,6 +790,42 @@ int sph_probe_impulse(const sph_params *p, const sph_state *s, void *ws, const d
                                 static_cast<hipStream_t>(stream));
 }
 
+int sph_mps_constants(double l0, double re, double *n0, double *lambda0) {
+    if (!n0 || !lambda0) return fail(SPH_E_INVAL, "outputs must not be NULL");
+    if (!(std::isfinite(l0) && l0 > 0.0)) return fail(SPH_E_INVAL, "l0 must be > 0");
+    if (!(std::isfinite(re) && re > 0.0 && re <= 64.0 * l0))
+        return fail(SPH_E_INVAL, "re must be in (0, 64 l0]");
+    mps_lattice_constants(l0, re, n0, lambda0);
+    if (!(*n0 > 0.0)) return fail(SPH_E_INVAL, "no lattice point within re");
+    return SPH_OK;
+}
+
+int sph_mps_operators(const sph_params *p, const sph_state *s, void *ws, const sph_mps *m,
+                      const double *phi, double *pnd, double *lap, double *grad, double *sigma,
+                      int32_t *surface, void *stream) {
+    Problem P;
+    Ws w;
+    if (int rc = validate(p, s, ws, &P, &w)) return rc;
+    if (!m) return fail(SPH_E_INVAL, "mps parameters are NULL");
+    if (!finite_all({m->re, m->n0, m->lambda0, m->beta1, m->rho1, m->l0}))
+        return fail(SPH_E_INVAL, "non-finite mps parameter");
+    if (!(m->re > 0.0)) return fail(SPH_E_INVAL, "re must be > 0");
+    if (!(m->re <= p->cell_size)) return fail(SPH_E_INVAL, "re must not exceed the cell size");
+    if (!(m->n0 > 0.0) || !(m->lambda0 > 0.0))
+        return fail(SPH_E_INVAL, "n0 and lambda0 must be > 0");
+    if (!(m->beta1 > 0.0 && m->beta1 <= 1.0)) return fail(SPH_E_INVAL, "beta1 must be in (0, 1]");
+    if (!(m->rho1 >= 0.0) || !(m->l0 > 0.0))
+        return fail(SPH_E_INVAL, "rho1 must be >= 0 and l0 > 0");
+    if (!phi && (lap || grad)) return fail(SPH_E_INVAL, "lap and grad need phi");
+    const void *ptrs[] = {phi, pnd, lap, grad, sigma};
+    for (const void *q : ptrs)
+        if (q && !aligned(q, 8)) return fail(SPH_E_INVAL, "mps array is misaligned");
+    if (surface && !aligned(surface, 4)) return fail(SPH_E_INVAL, "surface is misaligned");
+    if (!s->cells_valid) return fail(SPH_E_STATE, "sph_mps_operators needs current cells");
+    return launch_mps(P, *s, w, m, phi, pnd, lap, grad, sigma, surface,
+                      static_cast<hipStream_t>(stream));
+}
+
 // ------------------------------------------------------------------ batch
 
 int sph_batch_workspace_bytes(const sph_batch *b, size_t *bytes) {

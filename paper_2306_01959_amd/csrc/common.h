@@ -361,6 +361,11 @@ int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int
                      hipStream_t st, int hist_shift = -1);
 int launch_diag(const Problem &P, const sph_state &s, const Ws &w, const double *probes,
                 int32_t np, sph_diag *out, double *probe_p, hipStream_t st);
+// explicit MPS operators of instance 0 (outputs may be null)
+int launch_mps(const Problem &P, const sph_state &s, const Ws &w, const sph_mps *m,
+               const double *phi, double *pnd, double *lap, double *grad, double *sigma,
+               int32_t *surface, hipStream_t st);
+void mps_lattice_constants(double l0, double re, double *n0, double *lambda0);
 // two-stage symplectic step: the predictor (rates at t in the workspace; fixes
 // dt) or the corrector (rates at the predicted state)
 int launch_symplectic(const Problem &P, sph_state &s, const Ws &w, double dt, bool corrector,

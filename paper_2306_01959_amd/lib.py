@@ -35,6 +35,7 @@ EXPORTS = ("sph_version", "sph_last_error", "sph_check_params", "sph_set_tuning"
            "sph_interact", "sph_neighbour_stats", "sph_step", "sph_run", "sph_run_noalloc",
            "sph_run_profiled",
            "sph_diagnostics", "sph_boundary_force", "sph_probe_impulse",
+           "sph_mps_constants", "sph_mps_operators",
            "sph_batch_workspace_bytes", "sph_batch_workspace_init",
            "sph_batch_set_density", "sph_batch_get_density", "sph_batch_build_cells",
            "sph_batch_interact", "sph_batch_run", "sph_batch_run_profiled",
@@ -91,6 +92,19 @@ class SphDiag(C.Structure):
         return d
 
 
+class SphMps(C.Structure):
+    _fields_ = [("re", C.c_double), ("n0", C.c_double), ("lambda0", C.c_double),
+                ("beta1", C.c_double), ("rho1", C.c_double), ("l0", C.c_double)]
+
+
+def mps_constants(l0: float, re: float):
+    """(n0, lambda0) of the full support on the cubic lattice (eq. mpslambda)."""
+    n0 = C.c_double(0.0)
+    lam = C.c_double(0.0)
+    check(load().sph_mps_constants(float(l0), float(re), C.byref(n0), C.byref(lam)))
+    return n0.value, lam.value
+
+
 class SphBatch(C.Structure):
     _fields_ = [("ninst", C.c_int32), ("reserved", C.c_int32),
                 ("params", C.POINTER(SphParams)), ("counts", C.POINTER(C.c_int64))]
@@ -138,6 +152,10 @@ def load(path: str = LIB_PATH):
     L.sph_diagnostics.argtypes = [PP, PS, _P, _P, C.c_int32, PD, _P, _P]
     L.sph_boundary_force.argtypes = [PP, PS, _P, _P, _P, _P, _P]
     L.sph_probe_impulse.argtypes = [PP, PS, _P, _P, C.c_int32, C.c_int32, _P, _P, _P]
+    L.sph_mps_constants.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]
+    L.sph_mps_operators.argtypes = [PP, PS, _P, C.POINTER(SphMps), _P, _P, _P, _P, _P, _P,
+                                    _P]
     PB = C.POINTER(SphBatch)
     L.sph_batch_workspace_bytes.argtypes = [PB, C.POINTER(C.c_size_t)]
     L.sph_batch_workspace_init.argtypes = [PB, _P, C.c_size_t, _P]
@@ -451,6 +469,52 @@ class Simulation(_System):
                                          pts.ctypes.data, npts, int(bool(reset)), pp.ctypes.data,
                                          ip.ctypes.data, self._s()))
         return pp, ip
+
+
+    def mps_operators(self, re: float, l0: float, phi=None, beta1: float = 0.98,
+                      rho1: float = 0.2, n0: Optional[float] = None,
+                      lambda0: Optional[float] = None):
+        """Explicit MPS operators (sph_mps_operators) at the current state:
+        dict of pnd, lap, grad (3, n), sigma, surface, numpy in original
+        particle order.  phi: numpy array in original order (or None)."""
+        torch = self.torch
+        if n0 is None or lambda0 is None:
+            n0, lambda0 = mps_constants(l0, re)
+        if not self.state.cells_valid:
+            self.build_cells()
+        self.sync()
+        ids = self.ids()
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        ph = None
+        if phi is not None:
+            ph = torch.from_numpy(np.ascontiguousarray(np.asarray(phi, np.float64)[ids])).to(
+                self.dev)
+        pnd = torch.empty(self.n, **f64)
+        lap = torch.empty(self.n, **f64)
+        grad = torch.empty(3 * self.n, **f64)
+        sig = torch.empty(self.n, **f64)
+        surf = torch.empty(self.n, dtype=torch.int32, device=self.dev)
+        m = SphMps(float(re), float(n0), float(lambda0), float(beta1), float(rho1), float(l0))
+        self.sync()
+        check(self.lib.sph_mps_operators(
+            C.byref(self.params), C.byref(self.state), self.ws_ptr, C.byref(m),
+            ph.data_ptr() if ph is not None else None, pnd.data_ptr(),
+            lap.data_ptr() if ph is not None else None,
+            grad.data_ptr() if ph is not None else None, sig.data_ptr(), surf.data_ptr(),
+            self._s()))
+        self.sync()
+
+        def orig(t):
+            a = t.cpu().numpy()
+            out = np.empty_like(a)
+            out[ids] = a
+            return out
+        res = {"pnd": orig(pnd), "sigma": orig(sig), "surface": orig(surf)}
+        if ph is not None:
+            res["lap"] = orig(lap)
+            g = grad.view(3, self.n)
+            res["grad"] = np.stack([orig(g[k]) for k in range(3)])
+        return res
 
 
 class Ensemble(_System):

@@ -282,3 +282,44 @@ def test_lagged_symplectic_batch_rejected(L):
     params[1] = lib.make_params(scs[1].params, "mixed")
     rc = L.sph_batch_run(C.byref(b), C.byref(st), ws, 5, -1.0, 0, 0, None)
     assert rc == lib.SPH_E_INVAL and b"scheme" in L.sph_last_error()
+
+
+def test_mps_constants_match_oracle(L, oracle_lib):
+    """sph_mps_constants runs on the host: n0 and lambda0 of the library equal
+    the oracle's lattice sums (eq. mpslambda) for several radii."""
+    from paper_2306_01959_amd import lib
+    for l0, k in ((0.005, 2.1), (1.0, 3.1), (0.01, 4.0)):
+        n0, lam = lib.mps_constants(l0, k * l0)
+        on0, olam = oracle_lib.mps_lattice(l0, k * l0)
+        assert n0 == pytest.approx(on0, rel=1e-14)
+        assert lam == pytest.approx(olam, rel=1e-14)
+    with pytest.raises(lib.SphError):
+        lib.mps_constants(0.01, 0.0)
+    with pytest.raises(lib.SphError):
+        lib.mps_constants(0.01, 1.0)        # re > 64 l0
+
+
+def test_mps_operators_rejected_before_launch(L):
+    import ctypes as C
+    from paper_2306_01959_amd import lib, scene
+    sc = scene.config_scene(1)
+    p = lib.make_params(sc.params, "fp64")
+    st = lib.SphState()
+    st.n = sc.n
+    for name, _ in lib.SphState._fields_[1:25]:
+        setattr(st, name, 1 << 20)
+    st.cells_valid = 1
+    ws = C.c_void_p(1 << 24)
+    buf = C.c_void_p(1 << 22)
+    good = lib.SphMps(0.9 * p.cell_size, 14.4, 1.7, 0.98, 0.2, 0.02)
+
+    def call(m, phi=buf, lap=buf, grad=buf):
+        return L.sph_mps_operators(C.byref(p), C.byref(st), ws, C.byref(m), phi, buf, lap,
+                                   grad, buf, buf, None)
+    bad = lib.SphMps(1.1 * p.cell_size, 14.4, 1.7, 0.98, 0.2, 0.02)     # re > cell
+    assert call(bad) == lib.SPH_E_INVAL
+    bad = lib.SphMps(0.9 * p.cell_size, 14.4, 1.7, 1.5, 0.2, 0.02)      # beta1 > 1
+    assert call(bad) == lib.SPH_E_INVAL
+    assert call(good, phi=None) == lib.SPH_E_INVAL                      # lap without phi
+    st.cells_valid = 0
+    assert call(good) == lib.SPH_E_STATE
