@@ -176,7 +176,10 @@ typedef struct sph_diag {
     int64_t steps;      /* steps taken since sph_workspace_init */
     int64_t pairs_ff;   /* interacting ordered pairs evaluated since
                            sph_workspace_init: fluid i with fluid j, */
-    int64_t pairs_fb;   /* fluid i with boundary j, */
+    int64_t pairs_fb;   /* fluid i with boundary j (counted as pairs_bf: the
+                           neighbour relation is symmetric, exactly in FP64,
+                           up to pairs within one FP32 rounding of 2h in
+                           mixed precision), */
     int64_t pairs_bf;   /* boundary i with fluid j */
     uint32_t flags;     /* SPH_FLAG_* */
     uint32_t reserved;

@@ -68,7 +68,8 @@ struct InstState {
 };
 
 // What the interaction leaves per chunk: the chunk's time-step bound
-// (eq. sphdt, before the Courant factor) and its pair counts FF, FB, BF.
+// (eq. sphdt, before the Courant factor) and its interacting pair counts:
+// {FF + FB, 0, 0} for a chunk of fluid targets, {0, 0, BF} for boundary ones.
 struct ChunkOut {
     double bound;
     uint32_t pairs[3];
@@ -89,7 +90,7 @@ struct DevScalars {
     long long steps;                 // steps taken
     unsigned int nchunks;            // interaction chunks of the current cells
     unsigned int dt_cfl_violation;   // a step used dt > dt_cfl
-    unsigned long long pairs[3];     // interacting pairs since init: FF, FB, BF
+    unsigned long long pairs[3];     // interacting pairs since init: FF + FB, 0, BF
 };
 
 // Lanes below this one in the wave.

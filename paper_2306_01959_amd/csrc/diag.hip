@@ -332,8 +332,10 @@ int launch_diag(const Problem &P, const sph_state &s, const Ws &w, const double 
         o->n_outside = (int64_t)hv[F_OUTSIDE];
         o->n_nonfinite = (int64_t)hv[F_NONFIN];
         o->steps = sc.steps;
-        o->pairs_ff = (int64_t)sc.pairs[0];
-        o->pairs_fb = (int64_t)sc.pairs[1];
+        // the chunk records hold FF + FB (fluid targets) and BF (boundary
+        // targets); FB equals BF (the neighbour relation is symmetric)
+        o->pairs_ff = (int64_t)sc.pairs[0] - (int64_t)sc.pairs[2];
+        o->pairs_fb = (int64_t)sc.pairs[2];
         o->pairs_bf = (int64_t)sc.pairs[2];
         uint32_t flags = 0;
         if (o->n_nonfinite > 0) flags |= SPH_FLAG_NONFINITE;

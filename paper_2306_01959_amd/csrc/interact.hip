@@ -117,6 +117,12 @@ __device__ __forceinline__ double uni(double v) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// max of two non-negative floats: their bit patterns order like integers (one
+// integer max, where fmaxf first quiets possible signalling NaNs)
+__device__ __forceinline__ float max_nonneg(float a, float b) {
+    return __int_as_float(max(__float_as_int(a), __float_as_int(b)));
+}
+
 // 32-bit integer mixer (the finaliser of MurmurHash3): neighbour-set hashes
 // are sums of id_hash over the set, so they do not depend on visit order.
 __device__ __forceinline__ uint32_t id_hash(uint32_t v) {
@@ -139,22 +145,22 @@ struct Acc {
 // half-row, so all its targets are fluid or all boundary.
 constexpr int kAnyTargets = 0, kFluidTargets = 1, kBoundaryTargets = 2;
 
-// Pair counts, per lane: pairs inside the support, and those of them with a
-// fluid j.  A chunk's targets are all fluid or all boundary (one half-row),
-// so the wave totals split into the three classes by the chunk's class alone.
+// Pair counts, per lane: the (target, record) pairs inside the support.  A
+// chunk's targets are all fluid or all boundary (one half-row), and a
+// boundary chunk stages fluid records only.  A fluid chunk's count (which
+// includes each target's pair with itself, r = 0, unless the pair body
+// excludes it) is fluid-fluid + fluid-boundary; a boundary chunk's is
+// boundary-fluid, and fluid-boundary equals it because the neighbour relation
+// is symmetric (exactly in FP64; in mixed precision up to pairs within one
+// FP32 rounding of 2h).  The record keeps {FF + FB, 0, BF}; the diagnostics
+// split them.
 struct Counters {
-    uint32_t in = 0, fj = 0;
-    // wave totals (every lane of the wave calls it; uniform results)
-    __device__ __forceinline__ void totals(bool fluid_chunk, uint32_t &ff, uint32_t &fb,
-                                           uint32_t &bf) const {
-        uint32_t a = in, b = fj;
-        for (int off = 1; off < kWave; off <<= 1) {
-            a += __shfl_xor(a, off, kWave);
-            b += __shfl_xor(b, off, kWave);
-        }
-        ff = fluid_chunk ? b : 0u;
-        fb = fluid_chunk ? a - b : 0u;
-        bf = fluid_chunk ? 0u : b;  // a boundary target pairs with fluid j only
+    uint32_t in = 0;
+    // wave total (every lane of the wave calls it; uniform result)
+    __device__ __forceinline__ uint32_t total() const {
+        uint32_t a = in;
+        for (int off = 1; off < kWave; off <<= 1) a += __shfl_xor(a, off, kWave);
+        return a;
     }
 };
 struct Stats {
@@ -245,9 +251,11 @@ struct Mixed {
         *rec2 = *rec1;
         *rec3 = *rec1;
     }
-    // record: {o_x, c_x, o_y + dy cs, o_z + dz cs}, {u, P/rho}, {-, 1/rho,
-    // (rho - rho0) B, B} with B = 2 delta h c0 / rho (0 when the pair carries
-    // no delta term), {rho - rho0, +-c (- = boundary), index bits, -alpha |c|}
+    // record: {o_x, c_x, o_y + dy cs, o_z + dz cs}, {u, P/rho}, {rho - rho0,
+    // 1/rho, (rho - rho0) B, B} with B = 2 delta h c0 / rho (0 when the pair
+    // carries no delta term), {-alpha h |c|, +-c (- = boundary), index bits, -}
+    // (the fluid pair body reads all of the first three and one value of the
+    // fourth)
     __device__ static void stage(const InteractArgs &a, const Inst &ip, const Cand &c, int nbase,
                                  int j, int dy, int dz, float4 *rec0, float4 *rec1, float4 *rec2,
                                  float4 *rec3) {
@@ -259,8 +267,8 @@ struct Mixed {
         *rec0 = make_float4(c.v0.x, (float)((int)c.key - nbase), c.v0.y + (float)dy * csf,
                             c.v0.z + (float)dz * csf);
         *rec1 = make_float4(c.v1.x, c.v1.y, c.v1.z, c.v1.w * invr);
-        *rec2 = make_float4(0.f, invr, c.v0.w * B, B);
-        *rec3 = make_float4(c.v0.w, c.v2.y, __int_as_float(j), -(float)(ip.alpha * ip.h) * fabsf(c.v2.y));
+        *rec2 = make_float4(c.v0.w, invr, c.v0.w * B, B);
+        *rec3 = make_float4(-(float)(ip.alpha * ip.h) * fabsf(c.v2.y), c.v2.y, __int_as_float(j), 0.f);
     }
     // one (target, record) pair; `valid` is false for idle lanes; kCls: the
     // class of every target (kAnyTargets: read per target)
@@ -277,9 +285,12 @@ struct Mixed {
         const float dz = r0.w - t.a.z;
         const float rr = sq_sum_f32(dx, dy, dz);
         const int j = __float_as_int(r3.z);
-        const bool in = valid && rr < (float)ip.r2max && j != ti && (fi || fj);
+        // boundary-boundary pairs are never staged, so the support decides;
+        // the pair with itself (r = 0) contributes nothing to the sums and is
+        // left out only where the neighbours are counted per particle
+        const bool in = kStats ? valid && rr < (float)ip.r2max && j != ti
+                               : valid && rr < (float)ip.r2max;
         cn.in += in ? 1u : 0u;
-        cn.fj += (in && fj) ? 1u : 0u;
         if (kStats && in) {
             if (fj)
                 ++st.f;
@@ -299,22 +310,22 @@ struct Mixed {
             // continuity over fluid j, and |mu| for the time step; nothing else
             const float mu = vr * __builtin_amdgcn_rcpf(rr + (float)ip.eta2);  // mu / h
             const float amu = in ? fabsf(mu) : 0.f;
-            acc.mu = fmaxf(acc.mu, amu);
+            acc.mu = max_nonneg(acc.mu, amu);
             acc.dr -= F * vr;
             return;
         }
         // one reciprocal for mu / h = vr / (r^2 + eta^2) and the viscosity's
         // mu / (h (rho_i + rho_j)) = hvi; the factor h is in the -alpha |c|
         // terms of target and record, and store() applies it to max |mu|
-        const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r3.x;  // rho_i + rho_j
+        const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r2.x;  // rho_i + rho_j
         const float hvi = vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
         const float mu = hvi * rsum;
         const float amu = in ? fabsf(mu) : 0.f;
-        acc.mu = fmaxf(acc.mu, amu);
+        acc.mu = max_nonneg(acc.mu, amu);
         acc.dr -= F * vr;                                    // m (u_i - u_j) . grad_i W_ij
         const float Fd = kCls == kFluidTargets ? F : fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;             // delta term
-        const float visc = (t.c.z + r3.w) * fminf(hvi, 0.f);  // -alpha h (c_i + c_j) hvi if vr < 0
+        const float visc = (t.c.z + r3.x) * fminf(hvi, 0.f);  // -alpha h (c_i + c_j) hvi if vr < 0
         const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -357,14 +368,14 @@ struct Mixed {
         const float F = valid ? q2 * q2 * q2 : 0.f;
         const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const float vr = vx * dx + vy * dy + vz * dz;
-        const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r3.x;  // rho_i + rho_j
+        const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r2.x;  // rho_i + rho_j
         const float hvi = vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
         const float mu = hvi * rsum;
-        acc.mu = valid ? fmaxf(acc.mu, fabsf(mu)) : acc.mu;
+        acc.mu = valid ? max_nonneg(acc.mu, fabsf(mu)) : acc.mu;
         acc.dr -= F * vr;
         const float Fd = fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;
-        const float visc = (t.c.z + r3.w) * fminf(hvi, 0.f);  // -alpha h (c_i + c_j) hvi if vr < 0
+        const float visc = (t.c.z + r3.x) * fminf(hvi, 0.f);  // -alpha h (c_i + c_j) hvi if vr < 0
         const float s = (fmaf(t.b.w, r2.y, r1.w) * t.c.x + visc) * Fd;
         acc.ax -= s * dx;
         acc.ay -= s * dy;
@@ -500,9 +511,10 @@ struct Fp64 {
         const double dx = r0.x - t.a.x, dy = r0.y - t.a.y, dz = r0.z - t.a.z;
         const double rr = sq_sum_f64(dx, dy, dz);
         const int j = (int)r0.w;
-        const bool in = valid && rr < ip.r2max && j != ti && (fi || fj);
+        // as in Mixed: the support decides; the pair with itself is left out
+        // only where the neighbours are counted per particle
+        const bool in = kStats ? valid && rr < ip.r2max && j != ti : valid && rr < ip.r2max;
         cn.in += in ? 1u : 0u;
-        cn.fj += (in && fj) ? 1u : 0u;
         if (kStats && in) {
             if (fj)
                 ++st.f;
@@ -953,13 +965,8 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
     }
     // the waves' pair counts (integer, order-free) for the chunk's record
     {
-        uint32_t ff, fb, bf;
-        cn.totals(any_fluid, ff, fb, bf);
-        if (lane == 0) {
-            atomicAdd(&wg_pairs[0], ff);
-            atomicAdd(&wg_pairs[1], fb);
-            atomicAdd(&wg_pairs[2], bf);
-        }
+        const uint32_t tot = cn.total();
+        if (lane == 0) atomicAdd(&wg_pairs[any_fluid ? 0 : 2], tot);
     }
     __syncthreads();
     if (w == 0) {
@@ -1005,8 +1012,10 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
         }
     }
     bound = group_min(bound, kWave);
+    // each fluid target met itself once (in the stencil row of its own cell)
+    const uint32_t self = (any_fluid && !kStats) ? (uint32_t)ntgt : 0u;
     if (lane == 0)
-        a.cout[chunk] = ChunkOut{bound, {wg_pairs[0], wg_pairs[1], wg_pairs[2]}, 0u};
+        a.cout[chunk] = ChunkOut{bound, {wg_pairs[0] - self, 0u, wg_pairs[2]}, 0u};
     }  // w == 0
     }  // chunk
 }
@@ -1207,9 +1216,12 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
             }
         }
         bound = group_min(bound, kWave);
-        uint32_t ff, fb, bf;
-        cn.totals(any_fluid, ff, fb, bf);
-        if (lane == 0) a.cout[item] = ChunkOut{bound, {ff, fb, bf}, 0u};
+        const uint32_t tot = cn.total();
+        // each fluid target met itself once
+        const uint32_t self = (any_fluid && !kStats) ? (uint32_t)ntgt : 0u;
+        if (lane == 0)
+            a.cout[item] = ChunkOut{bound, {any_fluid ? tot - self : 0u, 0u, any_fluid ? 0u : tot},
+                                    0u};
     }
 }
 
@@ -1395,7 +1407,6 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
                     const bool in = P::filter(ip, tg, it, r0, r3, fj) && sl < n && act;
                     const uint64_t inm = __ballot(in);
                     cn.in += in ? 1u : 0u;
-                    cn.fj += (in && fj) ? 1u : 0u;
                     const uint64_t mine = inm & same_t;
                     if (in) tl[nn + rank_below(mine)] = (uint8_t)k;
                     nn += __popcll(mine);
@@ -1482,13 +1493,13 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
     }
     __syncthreads();
     bound = group_min(bound, kWave);
-    uint32_t ff, fb, bf;
-    cn.totals(any_fluid, ff, fb, bf);
+    const uint32_t tot = cn.total();
+    // the one-phase pair body met each fluid target itself once; the
+    // two-phase neighbour test leaves that pair out
+    const uint32_t self = (any_fluid && !kStats && !kTwo) ? (uint32_t)ntgt : 0u;
     if (lane == 0) {
         atomicMin(&wb, (unsigned long long)__double_as_longlong(bound));
-        atomicAdd(&wp[0], ff);
-        atomicAdd(&wp[1], fb);
-        atomicAdd(&wp[2], bf);
+        atomicAdd(&wp[any_fluid ? 0 : 2], tot - self);
     }
     __syncthreads();
     if (threadIdx.x == 0)
