@@ -715,7 +715,11 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
     __shared__ V4 stg[kSplit][4][kWave + 1];           // staged candidate records (per wave)
     __shared__ V4 tgt[3][kWave];                       // the chunk's targets
     __shared__ R gbox[kG][6];                          // group bounding boxes, chunk frame
-    __shared__ uint8_t glist[kSplit][kG][kWave + kG];  // per group: staged records that reach it
+    // per group: the staged records that reach it, as byte offsets into the
+    // wave's staging region (a pair step adds them to a constant base)
+    __shared__ uint16_t glist[kSplit][kG][kWave + kG];
+    constexpr int kRecBytes = (int)sizeof(V4);
+    constexpr int kRecStride = (kWave + 1) * kRecBytes;  // between the four record arrays
     __shared__ int4 rows[kSplit][kRows];
     // after its loop a wave reuses its own staging region for its per-target
     // sums (5 values of R and 3 int32 per target fit in 4 V4 per lane)
@@ -851,10 +855,10 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
                 const R ez = fmax(fmax(gbox[g][4] - pz, pz - gbox[g][5]), (R)0);
                 const bool k = lane < cnt && (ex * ex + ey * ey + ez * ez) <= cull2 && (gf || rf);
                 const uint64_t gm = __ballot(k);
-                if (k) glist[w][g][rank_below(gm)] = (uint8_t)lane;
+                if (k) glist[w][g][rank_below(gm)] = (uint16_t)(lane * kRecBytes);
                 gcnt[g] = __popcll(gm);
                 if constexpr (kSentinel) {
-                    if (lane < kG) glist[w][g][gcnt[g] + lane] = (uint8_t)kWave;
+                    if (lane < kG) glist[w][g][gcnt[g] + lane] = (uint16_t)(kWave * kRecBytes);
                 }
             }
             wave_sync();
@@ -872,11 +876,12 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
                     pair_steps<V4, kG, false>(
                         gn, slot_s,
                         [&](int sl) { return kSentinel || sl < gn ? (int)glist[w][g][sl] : 0; },
-                        [&](int k, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
-                            r0 = stg[w][0][k];
-                            r1 = stg[w][1][k];
-                            r2 = stg[w][2][k];
-                            r3 = stg[w][3][k];
+                        [&](int off, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
+                            const char *rb = reinterpret_cast<const char *>(&stg[w][0][0]) + off;
+                            r0 = *reinterpret_cast<const V4 *>(rb);
+                            r1 = *reinterpret_cast<const V4 *>(rb + kRecStride);
+                            r2 = *reinterpret_cast<const V4 *>(rb + 2 * kRecStride);
+                            r3 = *reinterpret_cast<const V4 *>(rb + 3 * kRecStride);
                         },
                         [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
                             P::template pair<kStats, decltype(cls)::value>(
