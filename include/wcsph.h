@@ -223,9 +223,12 @@ typedef enum {
  * Launch shape of the interaction (an autotuner sets it): the kernel, the
  * waves per chunk and the targets per group; a wave step evaluates `group`
  * targets against 64/`group` candidates.  0 = the library's choice.  Per
- * precision, process-wide, host-side; it changes launch shapes only, never
- * results beyond summation order.  Not to be changed while another thread is
- * launching.
+ * precision, process-wide, host-side: besides sph_run_noalloc's scratch this
+ * is the library's only state outside the caller's buffers.  It changes
+ * launch shapes only, never results beyond summation order; each field is
+ * read and written atomically, so a launch on another thread sees either the
+ * old or the new value of each field (set it before launching for a
+ * consistent shape).
  */
 typedef struct sph_tuning {
     int32_t split_fp64;
@@ -265,7 +268,10 @@ int sph_get_density(const sph_params *p, const sph_state *s, double *rho, int32_
                     void *stream);
 
 /*
- * Cell-linked list (neighbour search set-up).  Hashes every position to its
+ * Cell-linked list (neighbour search set-up).  The neighbours of a particle
+ * are the particles within the compact support 2h of the Wendland kernel
+ * (eq. sphw, q <= 2; Section 2.2); with cells of edge >= 2h they all lie in
+ * the 27 cells around its own.  Hashes every position to its
  * cell (clamped to the grid), sorts the particles stably by cell row (fixed
  * y, z), then class (fluid before boundary), then cell x, then half of the
  * cell along y, then half along x (LSD radix sort of 32-bit keys), gathers

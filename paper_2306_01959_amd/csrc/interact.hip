@@ -38,6 +38,7 @@
 // accurate in FP32.  FP64: absolute positions, d = r_j - r_i, the same r^2.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <type_traits>
@@ -1576,23 +1577,27 @@ __global__ __launch_bounds__(1024) void k_chunk_reduce(const int4 *__restrict__ 
 // ================================================================ launch
 
 // interaction launch shape per precision: waves per chunk and targets per
-// group (0 = automatic)
-static int g_split[2] = {0, 0};
-static int g_group[2] = {0, 0};
-static int g_kernel[2] = {0, 0};
+// group (0 = automatic).  Host-side preferences set by sph_set_tuning (the
+// autotuner); atomics, so a thread that launches while another sets them
+// reads defined values (each field on its own).  They pick launch shapes
+// only, never results beyond summation order.
+static std::atomic<int> g_split[2] = {{0}, {0}};
+static std::atomic<int> g_group[2] = {{0}, {0}};
+static std::atomic<int> g_kernel[2] = {{0}, {0}};
 
 int set_kernel(int precision, int kernel) {
     if (precision != SPH_FP64 && precision != SPH_MIXED) return -1;
     if (kernel != SPH_KERNEL_AUTO && kernel != SPH_KERNEL_ROWS && kernel != SPH_KERNEL_GROUPS &&
         kernel != SPH_KERNEL_COOP && kernel != SPH_KERNEL_COOP2)
         return -1;
-    g_kernel[precision] = kernel;
+    g_kernel[precision].store(kernel, std::memory_order_relaxed);
     return 0;
 }
 
 int kernel_for(const Problem &P) {
     const int pr = P.precision == SPH_MIXED ? SPH_MIXED : SPH_FP64;
-    return g_kernel[pr] ? g_kernel[pr] : SPH_KERNEL_ROWS;
+    const int k = g_kernel[pr].load(std::memory_order_relaxed);
+    return k ? k : SPH_KERNEL_ROWS;
 }
 
 bool fused_writes_keys(const Problem &P) {
@@ -1612,19 +1617,20 @@ int chunk_for(const Problem &P) {
 int set_split(int precision, int split) {
     if (precision != SPH_FP64 && precision != SPH_MIXED) return -1;
     if (split != 0 && split != 1 && split != 3 && split != 9) return -1;
-    g_split[precision] = split;
+    g_split[precision].store(split, std::memory_order_relaxed);
     return 0;
 }
 
 int set_group(int precision, int group) {
     if (precision != SPH_FP64 && precision != SPH_MIXED) return -1;
     if (group != 0 && group != 8 && group != 16 && group != 64) return -1;
-    g_group[precision] = group;
+    g_group[precision].store(group, std::memory_order_relaxed);
     return 0;
 }
 
 int split_for(const Problem &P) {
-    const int s = g_split[P.precision == SPH_MIXED ? SPH_MIXED : SPH_FP64];
+    const int s = g_split[P.precision == SPH_MIXED ? SPH_MIXED : SPH_FP64].load(
+        std::memory_order_relaxed);
     if (s) return s;
     const int64_t max_chunks = (P.n + kChunk - 1) / kChunk + P.nrows;
     // enough waves to fill 256 CUs x 4 SIMDs several times over
@@ -1635,7 +1641,8 @@ int split_for(const Problem &P) {
 
 int group_for(const Problem &P) {
     const int pr = P.precision == SPH_MIXED ? SPH_MIXED : SPH_FP64;
-    if (g_group[pr]) return g_group[pr];
+    const int g = g_group[pr].load(std::memory_order_relaxed);
+    if (g) return g;
     return pr == SPH_MIXED ? 8 : 16;
 }
 
