@@ -135,6 +135,47 @@ def test_internal_energy(oracle_lib):
 
 # ------------------------------------------------------------- neighbours
 
+def test_cells_clamp_and_stable_order(oracle_lib):
+    """The cell routine: cell = floor((r - o) / cs) per axis, clamped into the
+    grid (R13: below the origin, beyond the far face and NaN all land in an
+    edge cell), and a stable counting sort by the linear cell
+    x + nx (y + ny z): start[] is the prefix count of the cell sizes and each
+    cell lists its particles in increasing index.  Hand-placed points with
+    known cells, then a random cloud against the definition."""
+    orc = oracle_lib
+    prm = scene.make_params(0.02, lo=(0, 0, 0), hi=(0.3, 0.2, 0.25))
+    p = orc.par(prm)
+    cs, nx, ny, nz = p.cs, p.nx, p.ny, p.nz
+    ox, oy, oz = p.ox, p.oy, p.oz
+    x = np.array([ox + 0.5 * cs, ox + 1.5 * cs, ox - 3.0, ox + 1e3, np.nan, ox + 1.5 * cs])
+    y = np.array([oy + 0.5 * cs, oy + 2.5 * cs, oy + 0.5 * cs, oy - 1.0, oy + 0.5 * cs,
+                  oy + 2.5 * cs])
+    z = np.array([oz + 0.5 * cs, oz + 0.5 * cs, oz + 1e3, oz + 0.5 * cs, oz + 0.5 * cs,
+                  oz + 0.5 * cs])
+    cx, cy, cz, start, order = orc.cells(p, x, y, z)
+    assert cx.tolist() == [0, 1, 0, nx - 1, 0, 1]
+    assert cy.tolist() == [0, 2, 0, 0, 0, 2]
+    assert cz.tolist() == [0, 0, nz - 1, 0, 0, 0]
+    # particles 0 and 4 share cell 0 (4 is NaN in x), 1 and 5 share a cell
+    lin = cx + nx * (cy + ny * cz.astype(np.int64))
+    assert order.tolist() == np.argsort(lin, kind="stable").tolist()
+    assert order[:2].tolist() == [0, 4]
+    rng = np.random.Generator(np.random.PCG64(11))
+    n = 3000
+    x = rng.uniform(ox - 0.05, ox + nx * cs + 0.05, n)
+    y = rng.uniform(oy - 0.05, oy + ny * cs + 0.05, n)
+    z = rng.uniform(oz - 0.05, oz + nz * cs + 0.05, n)
+    cx, cy, cz, start, order = orc.cells(p, x, y, z)
+    ex = np.clip(np.floor((x - ox) / cs), 0, nx - 1).astype(np.int64)
+    ey = np.clip(np.floor((y - oy) / cs), 0, ny - 1).astype(np.int64)
+    ez = np.clip(np.floor((z - oz) / cs), 0, nz - 1).astype(np.int64)
+    assert np.array_equal(cx, ex) and np.array_equal(cy, ey) and np.array_equal(cz, ez)
+    lin = ex + nx * (ey + ny * ez)
+    assert np.array_equal(order, np.argsort(lin, kind="stable"))
+    counts = np.bincount(lin, minlength=nx * ny * nz)
+    assert np.array_equal(start, np.concatenate([[0], np.cumsum(counts)]))
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_neighbour_sets_bruteforce(oracle_lib, seed):
     """Cell-list neighbour sets equal the O(N^2) definition bit-exactly,
