@@ -286,9 +286,12 @@ struct Mixed {
         const float dz = r0.w - t.a.z;
         const float rr = sq_sum_f32(dx, dy, dz);
         const int j = __float_as_int(r3.z);
-        // boundary-boundary pairs are never staged, so the support decides;
-        // the pair with itself (r = 0) contributes nothing to the sums and is
-        // left out only where the neighbours are counted per particle
+        // boundary-boundary pairs are never staged, so the support decides.
+        // The pair with itself (r = 0) adds zero to every sum but the delta
+        // term, where the fused difference leaves the rounding error of
+        // (rho_i - rho0) B_i (a relative 2^-24 of it, far inside the
+        // tolerance); it is left out only where neighbours are counted per
+        // particle
         const bool in = kStats ? valid && rr < (float)ip.r2max && j != ti
                                : valid && rr < (float)ip.r2max;
         cn.in += in ? 1u : 0u;
