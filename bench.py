@@ -355,6 +355,127 @@ def time_alpha_study(steps, hip, retune=False, graph=True, dp=0.005):
     return r
 
 
+# Algorithmic FP64 work of one explicit MPS neighbour pair with a field
+# (eqs. mpsw, mpspnd, mpsgrad, mpslap, mpssigmai2; FMA = 2, sqrt / division =
+# 1): displacement 3, r^2 5, weight 3, density 1, centroid sums 6, field
+# difference 1, Laplacian sum 2, gradient sums 12.
+FLOP_MPS = 33
+PEAK_FP64_TFLOPS = 78.6
+
+
+def _event_ms(fn, calls):
+    """Mean device time of `calls` calls of fn() between two events on the
+    current stream (the library's)."""
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(calls):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / calls
+
+
+def time_extras(sc, verlet_ms, steps=40, warmup=5, calls=20):
+    """What the library computes around the step, each on the headline
+    workload unless stated: the two-stage symplectic scheme (two
+    interactions per step), the gate-release dam break at dp = 0.005 m (a
+    moving boundary, the paper's Verlet scheme), the loads (force on the
+    obstacle's upstream face and on every wall particle, probe pressures and
+    their impulse), and the explicit MPS operators (r_e = 2.1 dp, cells of
+    edge r_e)."""
+    import torch
+    from paper_2306_01959_amd import lib, scene
+    dp = sc.params["dp"]
+    out = {}
+    # two-stage symplectic scheme, device-side dt
+    sim = lib.Simulation(sc, "mixed", scheme=lib.SCHEME_SYMPLECTIC)
+    sim.run(warmup, -1.0, 0)
+    ms = _event_ms(lambda: sim.run(steps, -1.0, warmup), 1) / steps
+    d, _ = sim.diagnostics()
+    assert d["n_nonfinite"] == 0, "non-finite state"
+    out["symplectic"] = {
+        "workload": "headline workload, two-stage symplectic predictor-corrector (two "
+                    "interactions and cell lists per step), mixed, device-side dt",
+        "steps": steps, "ms_per_step": ms, "value": sc.n / (ms * 1e-3),
+        "unit": "particle-steps/s", "over_verlet_step": ms / verlet_ms}
+    # loads at that state: the force sums and the probes synchronise the stream
+    face = (0.84, 0.84 + 2 * dp, 0.24, 0.36, 0.0, 0.16)
+    walls = (-10.0, 10.0, -10.0, 10.0, -10.0, 10.0)
+    probes = [[0.84 - dp, 0.3, z] for z in (0.02, 0.06, 0.10, 0.14)]
+    nf, _, _ = sim.neighbour_stats()
+    wall_pairs = int(nf[sc.is_boundary].sum())
+    loads = {"workload": "headline workload after the symplectic steps; host-synchronous calls"}
+    for name, box in (("face_force", face), ("wall_force", walls)):
+        f, cnt = sim.boundary_force(box)
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            sim.boundary_force(box)
+        us = (time.perf_counter() - t0) / calls * 1e6
+        loads[name] = {"us_per_call": us, "boundary_particles": cnt, "force_N": list(f)}
+    loads["wall_force"]["fluid_pairs"] = wall_pairs
+    loads["wall_force"]["pairs_per_s"] = wall_pairs / (loads["wall_force"]["us_per_call"] * 1e-6)
+    sim.probe_impulse(probes, reset=True)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        sim.probe_impulse(probes)
+    loads["probe_impulse"] = {"us_per_call": (time.perf_counter() - t0) / calls * 1e6,
+                              "probes": len(probes)}
+    out["loads"] = loads
+    del sim
+    torch.cuda.empty_cache()
+    # moving boundary: the gate release, the paper's Verlet scheme
+    gate = scene.gate_release(0.005, 7)
+    sim = lib.Simulation(gate, "mixed")
+    sim.run(warmup, -1.0, 0)
+    ms = _event_ms(lambda: sim.run(steps, -1.0, warmup), 1) / steps
+    out["gate_release"] = {
+        "workload": "gate-release dam break at dp = 0.005 m, gate lifted at 1.25 m/s, "
+                    "Verlet scheme, mixed, device-side dt",
+        "particles": gate.n, "steps": steps, "ms_per_step": ms,
+        "value": gate.n / (ms * 1e-3), "unit": "particle-steps/s"}
+    del sim
+    torch.cuda.empty_cache()
+    # explicit MPS operators on the headline particle set
+    re = 2.1 * dp
+    lo = [min(v.min(), 0.0) - 0.05 for v in (sc.x, sc.y, sc.z)]
+    hi = [max(v.max(), 0.0) + 0.05 for v in (sc.x, sc.y, sc.z)]
+    msc = sc.copy()
+    msc.params = scene.make_params(dp, h_factor=re / (2 * dp), lo=lo, hi=hi)
+    sim = lib.Simulation(msc, "fp64")
+    sim.build_cells()
+    nf, nb, _ = sim.neighbour_stats()   # the same set: r^2 < (2h)^2 = r_e^2
+    pairs = int(nf.sum() + nb.sum())
+    n0, lam = lib.mps_constants(dp, re)
+    m = lib.SphMps(re, n0, lam, 0.98, 0.2, dp)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    phi = torch.rand(sc.n, **f64)
+    pnd, lap, sig = (torch.empty(sc.n, **f64) for _ in range(3))
+    grad = torch.empty(3 * sc.n, **f64)
+    surf = torch.empty(sc.n, dtype=torch.int32, device="cuda")
+
+    def mps():
+        lib.check(sim.lib.sph_mps_operators(
+            C.byref(sim.params), C.byref(sim.state), sim.ws_ptr, C.byref(m), phi.data_ptr(),
+            pnd.data_ptr(), lap.data_ptr(), grad.data_ptr(), sig.data_ptr(), surf.data_ptr(),
+            sim._s()))
+    mps()
+    ms = _event_ms(mps, calls)
+    achieved = FLOP_MPS * pairs / (ms * 1e-3) / 1e12
+    out["mps_operators"] = {
+        "workload": "headline particle set, r_e = 2.1 dp, cells of edge r_e, FP64: particle "
+                    "number density, Laplacian and gradient of a field, centroid deviation, "
+                    "free-surface flags",
+        "ms_per_call": ms, "particles": sc.n, "neighbour_pairs": pairs,
+        "pairs_per_s": pairs / (ms * 1e-3),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "flop_model": f"{FLOP_MPS} FP64 per neighbour pair"}}
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo)."""
     try:
@@ -442,6 +563,8 @@ def main():
     ap.add_argument("--small-only", action="store_true",
                     help="only the dp = 0.01 m dam break, mixed (profiling its kernels alone)")
     ap.add_argument("--no-alpha", action="store_true", help="skip the alpha-study batch")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the symplectic, gate-release, loads and MPS legs")
     ap.add_argument("--alpha-only", action="store_true",
                     help="only the alpha-study batch (profiling its kernels alone)")
     args = ap.parse_args()
@@ -567,6 +690,8 @@ def main():
         out["ensemble"] = time_ensemble(args.ensemble_steps, hip, retune=args.retune)
     if not args.no_alpha:
         out["alpha_study"] = time_alpha_study(args.ensemble_steps, hip, retune=args.retune)
+    if not args.no_extras:
+        out["extras"] = time_extras(sc, mixed["ms_per_step"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, sc2)
     print(json.dumps(out), flush=True)
