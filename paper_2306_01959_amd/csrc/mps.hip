@@ -9,6 +9,13 @@
 // 0 < |r_j - r_i| < r_e (coincident particles, where w is unbounded, are left
 // out).  One thread per particle walks the fluid and the boundary halves of
 // its 27-cell stencil (the cells must be at least r_e wide); FP64 throughout.
+// A wave's particles are consecutive in cell order, so they usually share a
+// cell row and their stencil rows overlap: the wave then stages each stencil
+// row's candidates {x, y, z, phi} once in LDS (one coalesced load per
+// candidate instead of four gathers per lane) and every lane reads its own
+// window of them; a wave that spans two rows, or a row range too long for the
+// staging buffer, loads from memory as before.  Each lane visits the same
+// candidates in the same order either way, so the sums are identical.
 // The pressure Poisson solve of the method is not part of this library.
 #include <hip/hip_runtime.h>
 
@@ -45,48 +52,103 @@ __device__ __forceinline__ double mps_r2(double dx, double dy, double dz) {
     return (a + b) + c;
 }
 
-__global__ __launch_bounds__(256) void k_mps(MpsArgs a) {
+constexpr int kMpsThreads = 256;
+constexpr int kMpsStage = 256;  // candidates a wave stages per stencil row
+
+__global__ __launch_bounds__(kMpsThreads) void k_mps(MpsArgs a) {
+    __shared__ double4 stage[kMpsThreads / kWave][kMpsStage];
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+    // lanes past the end take part in the staging only (n >= 1); lane 0 is
+    // active in every wave that has an active lane
+    const bool act = i < a.n;
+    if (__ballot(act) == 0ull) return;  // the whole wave: no barrier follows
+    const int64_t ti = act ? i : a.n - 1;
     const Inst &ip = a.ip;
-    const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+    const double xi = a.x[ti], yi = a.y[ti], zi = a.z[ti];
     const int cx = mps_cell(xi, ip.ox, ip.cs, ip.nx);
     const int cy = mps_cell(yi, ip.oy, ip.cs, ip.ny);
     const int cz = mps_cell(zi, ip.oz, ip.cs, ip.nz);
     const double re = a.re, re2 = re * re;
     const bool field = a.phi != nullptr;
-    const double phii = field ? a.phi[i] : 0.0;
+    const double phii = field ? a.phi[ti] : 0.0;
+    // one cell row for the whole wave (its active lanes)?
+    const int row = cz * ip.ny + cy;
+    const int row0 = __builtin_amdgcn_readfirstlane(row);
+    const bool one_row = __ballot(act && row != row0) == 0ull;
+    int cxlo = act ? cx : ip.nx, cxhi = act ? cx : -1;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int lo = __shfl_xor(cxlo, off, kWave), hi = __shfl_xor(cxhi, off, kWave);
+        cxlo = lo < cxlo ? lo : cxlo;
+        cxhi = hi > cxhi ? hi : cxhi;
+    }
+    const int ulo = cxlo > 0 ? cxlo - 1 : 0, uhi = cxhi + 1 < ip.nx ? cxhi + 1 : ip.nx - 1;
+    // the stencil's centre row: lane 0's for the whole wave when they share it
+    // (then the lanes past the end follow it too)
+    const int cz0 = one_row ? __builtin_amdgcn_readfirstlane(cz) : cz;
+    const int cy0 = one_row ? __builtin_amdgcn_readfirstlane(cy) : cy;
     double sw = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     double sl = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    // (the particle itself is at r = 0 and is left out with the coincident ones)
+    auto visit = [&](double xj, double yj, double zj, double phj) {
+        const double rx = xj - xi, ry = yj - yi, rz = zj - zi;
+        const double r2 = mps_r2(rx, ry, rz);
+        if (!(r2 < re2) || !(r2 > 0.0)) return;
+        // one square root and one division per pair: w = r_e / r - 1 and
+        // 1 / r^2 from 1 / r (a few ulp from the textbook order)
+        const double ir = 1.0 / sqrt(r2);
+        const double w = re * ir - 1.0;
+        sw += w;
+        sx += rx * w;
+        sy += ry * w;
+        sz += rz * w;
+        if (field) {
+            const double d = phj - phii;
+            sl += d * w;
+            const double f = d * w * (ir * ir);
+            gx += f * rx;
+            gy += f * ry;
+            gz += f * rz;
+        }
+    };
     const int xl = cx > 0 ? cx - 1 : 0, xh = cx + 1 < ip.nx ? cx + 1 : ip.nx - 1;
     for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy) {
-            const int czn = cz + dz, cyn = cy + dy;
-            if (czn < 0 || czn >= ip.nz || cyn < 0 || cyn >= ip.ny) continue;
+            const int czn = cz0 + dz, cyn = cy0 + dy;
+            const bool in_grid = czn >= 0 && czn < ip.nz && cyn >= 0 && cyn < ip.ny;
             for (uint32_t half = 0; half < 2; ++half) {
-                const uint32_t hb =
-                    half_row_key(ip.cell_base, ip.nx, (uint32_t)(czn * ip.ny + cyn), half);
-                const uint32_t js = a.cell_start[hb + xl], je = a.cell_start[hb + xh + 1];
-                for (uint32_t j = js; j < je; ++j) {
-                    if ((int64_t)j == i) continue;
-                    const double rx = a.x[j] - xi, ry = a.y[j] - yi, rz = a.z[j] - zi;
-                    const double r2 = mps_r2(rx, ry, rz);
-                    if (!(r2 < re2) || !(r2 > 0.0)) continue;
-                    const double w = re / sqrt(r2) - 1.0;
-                    sw += w;
-                    sx += rx * w;
-                    sy += ry * w;
-                    sz += rz * w;
-                    if (field) {
-                        const double d = a.phi[j] - phii;
-                        sl += d * w;
-                        gx += d * rx * w / r2;
-                        gy += d * ry * w / r2;
-                        gz += d * rz * w / r2;
+                const uint32_t hb = in_grid ? half_row_key(ip.cell_base, ip.nx,
+                                                           (uint32_t)(czn * ip.ny + cyn), half)
+                                            : 0u;
+                uint32_t js = 0, je = 0;
+                if (in_grid && act) {
+                    js = a.cell_start[hb + xl];
+                    je = a.cell_start[hb + xh + 1];
+                }
+                if (one_row) {
+                    // wave-uniform: the same stencil row for every lane
+                    if (!in_grid) continue;
+                    const uint32_t u0 = a.cell_start[hb + ulo], u1 = a.cell_start[hb + uhi + 1];
+                    if (u1 - u0 <= (uint32_t)kMpsStage) {
+                        for (uint32_t k = lane; k < u1 - u0; k += kWave) {
+                            const uint32_t j = u0 + k;
+                            stage[wv][k] = make_double4(a.x[j], a.y[j], a.z[j],
+                                                       field ? a.phi[j] : 0.0);
+                        }
+                        wave_sync();
+                        for (uint32_t j = js; j < je; ++j) {
+                            const double4 c = stage[wv][j - u0];
+                            visit(c.x, c.y, c.z, c.w);
+                        }
+                        wave_sync();  // the next row overwrites the buffer
+                        continue;
                     }
                 }
+                for (uint32_t j = js; j < je; ++j)
+                    visit(a.x[j], a.y[j], a.z[j], field ? a.phi[j] : 0.0);
             }
         }
+    if (!act) return;
     const double sig = sw > 0.0 ? sqrt(mps_r2(sx, sy, sz)) / sw : 0.0;
     if (a.pnd) a.pnd[i] = sw;
     if (a.sigma) a.sigma[i] = sig;
@@ -122,7 +184,8 @@ int launch_mps(const Problem &P, const sph_state &s, const Ws &w, const sph_mps 
     a.gz = grad ? grad + 2 * s.n : nullptr;
     a.sigma = sigma;
     a.surface = surface;
-    hipLaunchKernelGGL(k_mps, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_mps, dim3((unsigned)((s.n + kMpsThreads - 1) / kMpsThreads)),
+                       dim3(kMpsThreads), 0, st, a);
     return launch_check("mps operators");
 }
 
