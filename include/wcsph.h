@@ -409,8 +409,9 @@ int sph_boundary_force(const sph_params *p, const sph_state *s, void *ws, const 
  * workspace by the trapezoidal rule over the samples of successive calls,
  * with the simulated time the steps have accumulated (sph_diag.time).  The
  * first call after sph_workspace_init, and any call with reset = 1, starts
- * the integral at this sample (impulse 0).  Successive calls must pass the
- * same probe points.  probes_xyz: host, 3 np finite values, 1 <= np <= 1024;
+ * the integral at this sample (impulse 0), and so does a call with a
+ * different number of probes.  Successive calls must pass the same probe
+ * points.  probes_xyz: host, 3 np finite values, 1 <= np <= 1024;
  * probe_p, impulse: host arrays of np doubles (Pa, Pa s).  Requires current
  * cells; synchronises the stream.
  */

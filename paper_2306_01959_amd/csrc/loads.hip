@@ -217,12 +217,13 @@ int launch_boundary_force(const Problem &P, const sph_state &s, const Ws &w, con
 }
 
 // I += (P_prev + P) / 2 (t - t_prev) for every probe, unless this is the
-// first sample since init or reset; then P_prev = P, t_prev = t.
+// first sample since init or reset, or the number of probes changed; then
+// the integrals restart at zero.  Then P_prev = P, t_prev = t.
 __global__ __launch_bounds__(kLoadThreads) void k_impulse(ImpulseState *imp, double *sum,
                                                           double *prev, const double *p, int np,
                                                           int reset, const InstState *ist) {
     const double t = ist[0].time;
-    const bool acc = !reset && imp->has_prev;
+    const bool acc = !reset && imp->has_prev && imp->np == np;
     const double dt = t - imp->t_prev;
     for (int a = threadIdx.x; a < np; a += kLoadThreads) {
         if (!acc) sum[a] = 0.0;

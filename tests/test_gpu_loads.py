@@ -112,3 +112,27 @@ def test_force_and_impulse_series(gpu, oracle_lib, precision):
     assert err[0] <= 0.01 * span[0], err / span
     assert np.abs(got_f[:, 1:] - ref_f[:, 1:]).max() <= 0.01 * span[0]
     assert (ierr <= 0.01).all(), ierr
+
+
+def test_impulse_restarts_when_probe_count_changes(gpu):
+    """The running integral belongs to one set of probes: a call with another
+    number of probes starts it again at zero (and so does reset), while the
+    same probes keep accumulating."""
+    wet = np.array([[0.2, 0.3, z] for z in (0.02, 0.06, 0.10, 0.14)])  # in the water
+    sim = gpu.Simulation(_scene(), "fp64")
+    sim.run(20, -1.0, 0)
+    sim.build_cells()
+    p0, i0 = sim.probe_impulse(wet, reset=True)
+    assert np.all(i0 == 0.0)
+    sim.run(20, -1.0, 20)
+    sim.build_cells()
+    p1, i1 = sim.probe_impulse(wet)
+    assert np.any(i1 != 0.0) and np.all(np.isfinite(i1))
+    _, i2 = sim.probe_impulse(wet[:3])
+    assert np.all(i2 == 0.0)
+    sim.run(5, -1.0, 40)
+    sim.build_cells()
+    _, i3 = sim.probe_impulse(wet[:3])
+    assert np.any(i3 != 0.0)
+    _, i4 = sim.probe_impulse(wet[:3], reset=True)
+    assert np.all(i4 == 0.0)
