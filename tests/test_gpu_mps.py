@@ -102,3 +102,30 @@ def test_mps_lattice_block(gpu, oracle_lib):
     inner = np.max(np.abs(np.stack([x, y, z], 1) - c), axis=1) < 3.0 * l0
     assert np.allclose(lap[inner], 6.0, rtol=1e-11)
     assert surf[z == z.max()].all() and not surf[inner].any()
+
+
+def test_mps_without_field_and_dense_rows(gpu, oracle_lib):
+    """phi = NULL: only the density, the centroid deviation and the flags,
+    identical to the run with a field; and a cloud eight times denser than
+    l0^-3, whose waves' stencil rows hold more candidates than one staging
+    buffer (they load from memory instead), against the oracle."""
+    l0 = 0.02
+    sc = _mps_scene(scene.config_scene(1), l0)
+    re = K_MPS * l0
+    n0, lam = oracle_lib.mps_lattice(l0, re)
+    sim = gpu.Simulation(sc, "fp64")
+    with_phi = sim.mps_operators(re, l0, phi=np.asarray(sc.z, np.float64))
+    without = sim.mps_operators(re, l0, phi=None)
+    assert "lap" not in without and "grad" not in without
+    for k in ("pnd", "sigma", "surface"):
+        assert np.array_equal(without[k], with_phi[k]), k
+    ref = oracle_lib.mps_operators(oracle_lib.par(sc.params), sc.x, sc.y, sc.z, None, re, n0,
+                                   lam, 0.98, 0.2, l0)
+    assert np.abs(without["pnd"] - ref[0]).max() < 1e-12 * n0
+    assert np.abs(without["sigma"] - ref[3]).max() < 1e-12 * l0
+    # dense: ~74 particles per cell of edge r_e, so a wave's row range of
+    # three or four cells holds about 220-300 candidates, either side of 256
+    l0 = 0.01
+    dense = scene.random_cloud(8000, 11, dp=l0, box=0.1)
+    _compare(gpu, oracle_lib, _mps_scene(dense, l0), l0,
+             np.random.default_rng(3).normal(size=dense.n), "dense cloud")
