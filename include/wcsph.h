@@ -15,6 +15,10 @@
  *   - dynamic boundary particles: they obey continuity and the equation of
  *     state but are not moved by the forces (a wall stays put, a gate moves
  *     with its prescribed velocity).
+ * Around that step, on the same cell list: a two-stage symplectic scheme
+ * (sph_params.scheme), the loads of Section 3 (force on wall particles,
+ * pressure impulse at probes), batches of independent systems, and the
+ * explicit operators of the MPS method (Section 2).
  *
  * Conventions for every entry point:
  *   - extern "C"; the return value is an sph_status (0 = success).  On
@@ -28,8 +32,11 @@
  *     The one exception is sph_run_noalloc, whose workspace is a static
  *     device array of the library.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Calls are
- *     asynchronous on that stream except sph_diagnostics, which
- *     synchronises it.
+ *     asynchronous on that stream except those that return host values
+ *     (sph_diagnostics, sph_batch_diagnostics, sph_boundary_force,
+ *     sph_probe_impulse) and those whose description says they synchronise
+ *     (sph_batch_workspace_init, sph_batch_run with SPH_RUN_GRAPH);
+ *     sph_mps_constants runs on the host only.
  *   - Particle arrays are structure-of-arrays of length n.  After
  *     sph_build_cells the arrays are in cell order (cell row, then fluid
  *     before boundary, then cell x); id[] carries each particle's original
