@@ -228,8 +228,12 @@ typedef enum {
 
 /*
  * Launch shape of the interaction (an autotuner sets it): the kernel, the
- * waves per chunk and the targets per group; a wave step evaluates `group`
- * targets against 64/`group` candidates.  0 = the library's choice.  Per
+ * waves per chunk, the targets per group (a wave step evaluates `group`
+ * targets against 64/`group` candidates) and the order in which workgroups
+ * take chunks: xcd_run = 1 in chunk order, 8 or 32 so that each of the
+ * chip's eight XCDs (which receive workgroups in turn) takes runs of that
+ * many consecutive chunks, which share candidates in its L2.  0 = the
+ * library's choice (xcd_run: 1).  Per
  * precision, process-wide, host-side: besides sph_run_noalloc's scratch this
  * is the library's only state outside the caller's buffers.  It changes
  * launch shapes only, never results beyond summation order; each field is
@@ -244,7 +248,8 @@ typedef struct sph_tuning {
     int32_t group_mixed;
     int32_t kernel_fp64;  /* sph_kernel */
     int32_t kernel_mixed;
-    int32_t reserved[2];  /* must be 0 */
+    int32_t xcd_run_fp64;  /* 0, 1, 8 or 32 */
+    int32_t xcd_run_mixed;
 } sph_tuning;
 
 int sph_set_tuning(const sph_tuning *t);

@@ -596,8 +596,6 @@ int sph_check_params(const sph_params *p) { return check_params(p); }
 
 int sph_set_tuning(const sph_tuning *t) {
     if (!t) return fail(SPH_E_INVAL, "tuning is NULL");
-    for (int k = 0; k < 2; ++k)
-        if (t->reserved[k] != 0) return fail(SPH_E_INVAL, "tuning reserved must be 0");
     auto split_ok = [](int v) { return v == 0 || v == 1 || v == 3 || v == 9; };
     auto group_ok = [](int v) { return v == 0 || v == 8 || v == 16 || v == 64; };
     auto kernel_ok = [](int v) {
@@ -610,12 +608,17 @@ int sph_set_tuning(const sph_tuning *t) {
         return fail(SPH_E_INVAL, "group must be 0, 8, 16 or 64");
     if (!kernel_ok(t->kernel_fp64) || !kernel_ok(t->kernel_mixed))
         return fail(SPH_E_INVAL, "kernel must be an sph_kernel value");
+    auto run_ok = [](int v) { return v == 0 || v == 1 || v == 8 || v == 32; };
+    if (!run_ok(t->xcd_run_fp64) || !run_ok(t->xcd_run_mixed))
+        return fail(SPH_E_INVAL, "xcd_run must be 0, 1, 8 or 32");
     set_split(SPH_FP64, t->split_fp64);
     set_split(SPH_MIXED, t->split_mixed);
     set_group(SPH_FP64, t->group_fp64);
     set_group(SPH_MIXED, t->group_mixed);
     set_kernel(SPH_FP64, t->kernel_fp64);
     set_kernel(SPH_MIXED, t->kernel_mixed);
+    set_xcd_run(SPH_FP64, t->xcd_run_fp64);
+    set_xcd_run(SPH_MIXED, t->xcd_run_mixed);
     return SPH_OK;
 }
 

@@ -392,9 +392,11 @@ int diag_blocks(int ninst);
 int set_split(int precision, int split);
 int set_group(int precision, int group);
 int set_kernel(int precision, int kernel);
+int set_xcd_run(int precision, int run);
 int split_for(const Problem &P);
 int group_for(const Problem &P);
 int kernel_for(const Problem &P);
+int xcd_run_for(const Problem &P);
 int chunk_for(const Problem &P);  // targets per chunk of the interaction launched for P
 
 // Cell id layout inside an instance: local = cx + nx * (cy + ny * cz).

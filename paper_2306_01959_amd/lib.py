@@ -64,7 +64,7 @@ class SphTuning(C.Structure):
     _fields_ = [("split_fp64", C.c_int32), ("split_mixed", C.c_int32),
                 ("group_fp64", C.c_int32), ("group_mixed", C.c_int32),
                 ("kernel_fp64", C.c_int32), ("kernel_mixed", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("xcd_run_fp64", C.c_int32), ("xcd_run_mixed", C.c_int32)]
 
 
 class SphState(C.Structure):
@@ -179,9 +179,12 @@ def check(rc: int) -> None:
 
 
 def set_tuning(split_fp64: int = 0, split_mixed: int = 0, group_fp64: int = 0,
-               group_mixed: int = 0, kernel_fp64: int = 0, kernel_mixed: int = 0) -> None:
+               group_mixed: int = 0, kernel_fp64: int = 0, kernel_mixed: int = 0,
+               xcd_run_fp64: int = 0, xcd_run_mixed: int = 0) -> None:
     """Process-wide interaction launch shape (0 = the library's choice)."""
     t = SphTuning()
+    t.xcd_run_fp64 = int(xcd_run_fp64)
+    t.xcd_run_mixed = int(xcd_run_mixed)
     t.split_fp64 = int(split_fp64)
     t.split_mixed = int(split_mixed)
     t.group_fp64 = int(group_fp64)

@@ -323,3 +323,24 @@ def test_mps_operators_rejected_before_launch(L):
     assert call(good, phi=None) == lib.SPH_E_INVAL                      # lap without phi
     st.cells_valid = 0
     assert call(good) == lib.SPH_E_STATE
+
+
+def test_tuning_validated_and_reported(L):
+    """sph_set_tuning is host-side: it accepts the documented values of every
+    field, rejects anything else without changing the current setting, and
+    sph_get_split reports the shape it set (no GPU needed)."""
+    p = params()
+    bad = [dict(split_mixed=2), dict(group_fp64=32), dict(kernel_mixed=9),
+           dict(xcd_run_fp64=4), dict(xcd_run_mixed=-1), dict(xcd_run_mixed=64)]
+    try:
+        lib.set_tuning(split_mixed=3, group_mixed=16, kernel_mixed=1, xcd_run_mixed=32)
+        for kw in bad:
+            with pytest.raises(lib.SphError) as e:
+                lib.set_tuning(**kw)
+            assert e.value.code == lib.SPH_E_INVAL, kw
+        p.precision = lib.SPH_MIXED
+        assert lib.get_split(p, 100000) == (3, 16, 1)
+        for run in (0, 1, 8, 32):
+            lib.set_tuning(xcd_run_fp64=run, xcd_run_mixed=run)
+    finally:
+        lib.set_tuning()

@@ -480,3 +480,30 @@ def test_every_launch_shape_matches(gpu, oracle_lib, developed, precision):
     for s_ in stats[1:]:
         for a_, b_ in zip(s_, stats[0]):
             assert np.array_equal(a_, b_)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_xcd_run_order_is_bitwise_neutral(gpu, developed, precision):
+    """The order in which workgroups take chunks (runs of 1, 8 or 32 chunks
+    per XCD) changes no result bit: each chunk's sums are its own.  Row-split
+    and group-per-wave kernels."""
+    params, st = developed
+    sc, prev = scene_from_oracle(st, params)
+    try:
+        for kernel, split, group in ((gpu.SPH_KERNEL_ROWS, 1, 16), (gpu.SPH_KERNEL_GROUPS, 1, 8),
+                                     (gpu.SPH_KERNEL_COOP, 1, 16)):
+            outs = []
+            for run in (1, 8, 32):
+                if precision == "fp64":
+                    gpu.set_tuning(split_fp64=split, group_fp64=group, kernel_fp64=kernel,
+                                   xcd_run_fp64=run)
+                else:
+                    gpu.set_tuning(split_mixed=split, group_mixed=group, kernel_mixed=kernel,
+                                   xcd_run_mixed=run)
+                sim = _sim(gpu, sc, precision, prev)
+                outs.append(sim.rates_by_id())
+            for o in outs[1:]:
+                for k in range(len(o)):
+                    assert np.array_equal(o[k], outs[0][k]), (kernel, k)
+    finally:
+        gpu.set_tuning()
