@@ -647,8 +647,8 @@ constexpr int kRanges = 18;
 // some XCDs the dry walls and others the dense water: 18 % slower).  run = 1
 // is the identity.  The autotuner picks run per problem: on the 5.8 M-particle
 // dam break runs of 32 cut the interaction's fetched bytes from 6.1 to
-// 2.5 GB per launch and its time by 1-2 %; on the ensemble, whose view fits
-// the last-level cache, they cost 2 %.
+// 2.5 GB per launch and the step by ~2 %; the 64-instance ensemble gains
+// ~2 % with runs of 8 (and nothing with 32).
 __device__ __forceinline__ uint32_t xcd_item(uint32_t b, uint32_t run) {
     const uint32_t x = b % (uint32_t)kXcds, k = b / (uint32_t)kXcds;
     return ((k / run) * (uint32_t)kXcds + x) * run + k % run;
