@@ -119,6 +119,15 @@ __device__ __forceinline__ double uni(double v) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// max(a, |b|) for a >= 0 in one instruction (the absolute value is an input
+// modifier of v_max_f32; written out because the compiler would first quiet
+// possible signalling NaNs); a NaN b is dropped, as IEEE maxNum does
+__device__ __forceinline__ float max_abs(float a, float b) {
+    float r;
+    asm("v_max_f32 %0, %1, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // max of two non-negative floats: their bit patterns order like integers (one
 // integer max, where fmaxf first quiets possible signalling NaNs)
 __device__ __forceinline__ float max_nonneg(float a, float b) {
@@ -306,16 +315,23 @@ struct Mixed {
         // evaluated on every lane (no branch); lanes outside the support
         // are zeroed through F and the |mu| select
         const float r = __builtin_amdgcn_sqrtf(rr);
-        const float q2 = fmaf(r, -0.5f * (float)ip.invh, 1.f);  // 1 - q/2
+        // 1 - q/2 clamped to [0, 1] (the clamp is an output modifier of the
+        // FMA): F vanishes outside the support without a select.  The clamp
+        // and the predicate can disagree only where F is within rounding of
+        // zero; counts and |mu| keep the exact predicate, and where
+        // neighbours are counted per particle (kStats) F follows it too.
+        // Idle lanes (valid false: kernels without sentinel records) are
+        // zeroed by a select, which folds away where valid is always true.
+        const float q2 =
+            __builtin_amdgcn_fmed3f(fmaf(r, -0.5f * (float)ip.invh, 1.f), 0.f, 1.f);
         const float Fr = q2 * q2 * q2;  // (1-q/2)^3; store() applies m 5 w_D/h^2
-        const float F = in ? Fr : 0.f;
+        const float F = kStats ? (in ? Fr : 0.f) : (valid ? Fr : 0.f);
         const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const float vr = vx * dx + vy * dy + vz * dz;               // u_ij . r_ij
         if constexpr (kCls == kBoundaryTargets) {
             // continuity over fluid j, and |mu| for the time step; nothing else
             const float mu = vr * __builtin_amdgcn_rcpf(rr + (float)ip.eta2);  // mu / h
-            const float amu = in ? fabsf(mu) : 0.f;
-            acc.mu = max_nonneg(acc.mu, amu);
+            acc.mu = max_abs(acc.mu, in ? mu : 0.f);
             acc.dr -= F * vr;
             return;
         }
@@ -325,8 +341,7 @@ struct Mixed {
         const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r2.x;  // rho_i + rho_j
         const float hvi = vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
         const float mu = hvi * rsum;
-        const float amu = in ? fabsf(mu) : 0.f;
-        acc.mu = max_nonneg(acc.mu, amu);
+        acc.mu = max_abs(acc.mu, in ? mu : 0.f);
         acc.dr -= F * vr;                                    // m (u_i - u_j) . grad_i W_ij
         const float Fd = kCls == kFluidTargets ? F : fi ? F : 0.f;
         acc.dr += fmaf(-t.c.y, r2.w, r2.z) * Fd;             // delta term
