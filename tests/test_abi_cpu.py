@@ -344,3 +344,25 @@ def test_tuning_validated_and_reported(L):
             lib.set_tuning(xcd_run_fp64=run, xcd_run_mixed=run)
     finally:
         lib.set_tuning()
+
+
+def test_autotune_table_shapes():
+    """Table entries of two, three and four values all name a full launch
+    shape (kernel, waves per chunk, targets per group, XCD run), and every
+    shipped entry is one the library accepts."""
+    from paper_2306_01959_amd import autotune
+    assert autotune.full_shape([3, 8]) == (1, 3, 8, 1)
+    assert autotune.full_shape([2, 1, 16]) == (2, 1, 16, 1)
+    assert autotune.full_shape([1, 1, 16, 32]) == (1, 1, 16, 32)
+    tab = autotune._load()
+    assert tab, "shipped table missing"
+    try:
+        for key, ent in tab.items():
+            k, split, group, run = autotune.full_shape(ent["shape"])
+            prec = key.split(":")[1] if key.startswith("ensemble") else key.split(":")[0]
+            assert prec in ("mixed", "fp64"), key
+            autotune.apply(prec, ent["shape"])      # raises SphError if rejected
+            assert run in autotune.XCD_RUNS
+    finally:
+        autotune._state.update(fp64=(0, 0, 0, 0), mixed=(0, 0, 0, 0))
+        lib.set_tuning()
