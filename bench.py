@@ -11,10 +11,13 @@ steps.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: particle-steps/s of the mixed step, the FP64 step on the
 same workload for the ratio, the interaction kernel's roofline (achieved
-algorithmic FP32 FLOP/s over HIP-event kernel time), the same pair for the
-dam break at dp = 0.01 m, the batched ensemble of 64 dam breaks (throughput,
-sort/reorder HBM bandwidth against peak) and the FP64 CPU oracle timed on this
-host.
+algorithmic FP32 FLOP/s over HIP-event kernel time, and the HBM bytes per
+launch from the committed counter summary), the same pair for the dam break at
+dp = 0.01 m, the batched ensemble of 64 dam breaks and the paper's
+artificial-viscosity study as a batch (throughput, sort/reorder HBM bandwidth
+against peak), the steps and calls around the step (symplectic scheme, gate
+release, loads on solids, MPS operators) and the FP64 CPU oracle timed on
+this host.
 """
 import argparse
 import ctypes as C
