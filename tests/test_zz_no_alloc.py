@@ -2,8 +2,8 @@
 workspace) against sph_run on a fresh workspace, through the C ABI.
 
 Both run the same kernels in the same launch shapes on the same inputs, so
-the states must agree bit for bit (which is stricter than the task's
-tolerances: FP64 1e-12, mixed 1e-5 relative L2).  Two calls in a row, the
+the states must agree bit for bit (stricter than the parity tolerances
+against the oracle: FP64 1e-12, mixed 1e-5 relative L2).  Two calls in a row, the
 second on a smaller system, so the second call runs on scratch the first
 one filled."""
 import numpy as np
