@@ -163,3 +163,35 @@ def test_ensemble_fullsize_graph_equals_eager(gpu, ensemble_scenes):
         assert da[k]["time"] == db[k]["time"]
         assert da[k]["n_nonfinite"] == 0
         assert da[k]["flags"] & gpu.FLAG_DT_CFL == 0
+
+
+def test_obstacle_dp00025_long_run(gpu):
+    """The headline workload's full 2000 steps (mixed, device-side time step,
+    the benchmark's launch shape), diagnostics every 100 steps: the mass is
+    the same bit for bit every time, nothing leaves the grid or turns
+    non-finite, no step exceeds its time-step bound, the total energy
+    (kinetic + potential + internal) stays within 2 % of its start, and the
+    surge front advances as the column collapses."""
+    sc = scene.config_scene(5)
+    try:
+        table_shape("mixed", sc)
+        sim = gpu.Simulation(sc, "mixed")
+        d0, _ = sim.diagnostics()
+        e0 = d0["e_kin"] + d0["e_pot"] + d0["e_int"]
+        fronts = [d0["x_front"]]
+        for k in range(20):
+            sim.run(100, -1.0, 100 * k)
+            d, _ = sim.diagnostics()
+            e = d["e_kin"] + d["e_pot"] + d["e_int"]
+            fronts.append(d["x_front"])
+            assert d["mass"] == d0["mass"] and d["n"] == d0["n"]
+            assert d["n_nonfinite"] == 0 and d["n_outside"] == 0
+            assert d["flags"] & gpu.FLAG_DT_CFL == 0
+            assert abs(e - e0) <= 0.02 * abs(e0), (k, e, e0)
+        print(f"\nconfiguration 5, 2000 mixed steps: t = {d['time']:.4f} s, front "
+              f"{fronts[0]:.3f} -> {fronts[-1]:.3f} m, energy {e0:.3f} -> {e:.3f} J, "
+              f"max |u| {d['umax']:.3f} m/s", flush=True)
+        assert fronts[-1] > fronts[0] + 0.05
+        assert np.all(np.diff(fronts) >= -1e-9)
+    finally:
+        gpu.set_tuning()
