@@ -195,3 +195,37 @@ def test_obstacle_dp00025_long_run(gpu):
         assert np.all(np.diff(fronts) >= -1e-9)
     finally:
         gpu.set_tuning()
+
+
+def test_ensemble_long_run(gpu, ensemble_scenes):
+    """The 64-instance batch's 500 steps in the benchmark's form (lagged dt,
+    fused update, graph replays): every instance keeps its mass bit for bit,
+    stays finite and in its grid, never steps past its lagged bound, does not
+    gain total energy (viscosity up to alpha = 0.1 dissipates some: a loss of
+    at most 10 %) and moves its front downstream."""
+    import torch
+    ens = gpu.Ensemble(ensemble_scenes, "mixed", stream=torch.cuda.Stream())
+    try:
+        tab = autotune._load()
+        ent = tab.get(f"ensemble:mixed:n={ens.n}:inst={ens.ninst}")
+        if ent is not None:
+            autotune.apply("mixed", ent["shape"])
+        d0 = ens.diagnostics()
+        ens.run(40, -1.0, 0, mode=gpu.RUN_LAGGED)
+        ens.run(480, -1.0, 40, mode=gpu.RUN_LAGGED | gpu.RUN_GRAPH)
+        d1 = ens.diagnostics()
+    finally:
+        gpu.set_tuning()
+    rel = []
+    for a, b in zip(d0, d1):
+        assert b["mass"] == a["mass"] and b["n"] == a["n"]
+        assert b["n_nonfinite"] == 0 and b["n_outside"] == 0
+        assert b["flags"] & gpu.FLAG_DT_CFL == 0
+        ea = a["e_kin"] + a["e_pot"] + a["e_int"]
+        eb = b["e_kin"] + b["e_pot"] + b["e_int"]
+        rel.append((eb - ea) / abs(ea))
+        assert b["x_front"] > a["x_front"]
+    rel = np.array(rel)
+    print(f"\nensemble, 520 steps: relative energy change {rel.min():.2e} .. {rel.max():.2e}",
+          flush=True)
+    assert rel.max() < 1e-3 and rel.min() > -0.1
