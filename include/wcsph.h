@@ -38,9 +38,9 @@
  *     (sph_batch_workspace_init, sph_batch_run with SPH_RUN_GRAPH);
  *     sph_mps_constants runs on the host only.
  *   - Particle arrays are structure-of-arrays of length n.  After
- *     sph_build_cells the arrays are in cell order (cell row, then fluid
- *     before boundary, then cell x); id[] carries each particle's original
- *     index.
+ *     sph_build_cells the arrays are in cell order (per system: fluid
+ *     before boundary, then cell row, then cell x); id[] carries each
+ *     particle's original index.
  *   - One state/workspace pair must not be used by two overlapping calls.
  */
 #ifndef WCSPH_H
@@ -233,8 +233,13 @@ typedef enum {
  * take chunks: xcd_run = 1 in chunk order, 8 or 32 so that each of the
  * chip's eight XCDs (which receive workgroups in turn) takes runs of that
  * many consecutive chunks, which share candidates in its L2.  0 = the
- * library's choice (xcd_run: 1).  Per
- * precision, process-wide, host-side: besides sph_run_noalloc's scratch this
+ * library's choice (xcd_run: 1).  full_gather = 1 turns off the fixed-wall
+ * shortcut of sph_run / sph_batch_run: from the third step of a call (and
+ * outside the two steps from each refresh), while no boundary particle has
+ * moved with the workspace, the boundary particles keep their sorted
+ * positions and the gather leaves them in place, copying only their
+ * densities; both give the same results bit for bit.  Per
+ * precision (full_gather: for both), process-wide, host-side: besides sph_run_noalloc's scratch this
  * is the library's only state outside the caller's buffers.  It changes
  * launch shapes only, never results beyond summation order; each field is
  * read and written atomically, so a launch on another thread sees either the
@@ -250,6 +255,7 @@ typedef struct sph_tuning {
     int32_t kernel_mixed;
     int32_t xcd_run_fp64;  /* 0, 1, 8 or 32 */
     int32_t xcd_run_mixed;
+    int32_t full_gather;   /* 0 or 1, see above */
 } sph_tuning;
 
 int sph_set_tuning(const sph_tuning *t);
@@ -284,9 +290,9 @@ int sph_get_density(const sph_params *p, const sph_state *s, double *rho, int32_
  * are the particles within the compact support 2h of the Wendland kernel
  * (eq. sphw, q <= 2; Section 2.2); with cells of edge >= 2h they all lie in
  * the 27 cells around its own.  Hashes every position to its
- * cell (clamped to the grid), sorts the particles stably by cell row (fixed
- * y, z), then class (fluid before boundary), then cell x, then half of the
- * cell along y, then half along x (LSD radix sort of 32-bit keys), gathers
+ * cell (clamped to the grid), sorts the particles stably by class (fluid
+ * before boundary), then cell row (fixed y, z), then cell x, then half of
+ * the cell along y, then half along x (LSD radix sort of 32-bit keys), gathers
  * every state array into that order (the *_alt buffers, then swaps the
  * pointers) and builds the cell table, the chunk list and the interaction
  * view (per-particle pressure, sound speed, 1/rho, and for SPH_MIXED the FP32

@@ -293,16 +293,18 @@ struct Marks {
 // refreshes sort on the cell key alone.  keys (KeysLeft): what the previous
 // step of this same run left (else the keys and counts are computed from the
 // positions here).
+// walls_in_place: the previous two steps of this call gathered every
+// particle, so this gather may leave fixed walls in place (WallsInPlace).
 static int build_cells(const Problem &P, sph_state &s, const Ws &w, hipStream_t st,
                        bool lagged = false, double dt = 0.0, const Marks &m = Marks(),
-                       bool full = true, int keys = kNoKeys) {
+                       bool full = true, int keys = kNoKeys, bool walls_in_place = false) {
     if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
     uint32_t *sorted = nullptr, *perm = nullptr;
     if (int rc = m.at(SPH_REGION_SORT, true, st)) return rc;
     if (int rc = launch_sort(P, s, w, st, full, keys, &sorted, &perm)) return rc;
     if (int rc = m.at(SPH_REGION_SORT, false, st)) return rc;
     if (int rc = m.at(SPH_REGION_REORDER, true, st)) return rc;
-    if (int rc = launch_reorder(P, s, w, sorted, perm, st)) return rc;
+    if (int rc = launch_reorder(P, s, w, sorted, perm, walls_in_place, st)) return rc;
     if (int rc = m.at(SPH_REGION_REORDER, false, st)) return rc;
     if (int rc = launch_chunks(P, w, lagged, dt, st)) return rc;
     s.cells_valid = 1;
@@ -345,14 +347,28 @@ static int symplectic_step(const Problem &P, sph_state &s, const Ws &w, double d
     return SPH_OK;
 }
 
+// Whether step `step` (index k within this call) may leave fixed walls in
+// place.  The boundary particles must already sit, in both buffers of the
+// state, at the positions this step's sort gives them: the call's first two
+// steps and the two steps from each refresh (which sorts the walls by their
+// sub-cell bits too, and so may reorder them) gather every particle.
+static bool walls_in_place_at(const Problem &P, int64_t k, int64_t step) {
+    const int64_t R = refresh_period(P);
+    return k >= 2 && step % R != 0 && step % R != 1 && walls_in_place_enabled(P);
+}
+
 // One step.  fused: the lagged-dt form, where the interaction also advances
-// the state (one kernel instead of interaction + update).
+// the state (one kernel instead of interaction + update).  k: the step's
+// index within this call.
 static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
-                    bool fused, hipStream_t st, const Marks &m = Marks(), int keys = kNoKeys) {
+                    bool fused, hipStream_t st, const Marks &m = Marks(), int keys = kNoKeys,
+                    int64_t k = 0) {
     if (P.scheme == SPH_SCHEME_SYMPLECTIC) return symplectic_step(P, s, w, dt, step, st, m);
     if (!s.cells_valid) {
         const bool full = step % refresh_period(P) == 0;
-        if (int rc = build_cells(P, s, w, st, fused, dt, m, full, keys)) return rc;
+        if (int rc = build_cells(P, s, w, st, fused, dt, m, full, keys,
+                                 walls_in_place_at(P, k, step)))
+            return rc;
     } else {
         if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
         if (int rc = launch_chunks(P, w, fused, dt, st)) return rc;  // fresh dt bound
@@ -420,16 +436,18 @@ static bool same_pointers(const sph_state &a, const sph_state &b) {
 // replay it `reps` times.  The state pointers must come back to where they
 // started, which the period guarantees.
 static int graph_steps(const Problem &P, sph_state &s, const Ws &w, double dt, int64_t step,
-                       int64_t len, int64_t reps, bool lagged, hipStream_t st) {
+                       int64_t len, int64_t reps, bool lagged, hipStream_t st, int64_t k0) {
     const sph_state s0 = s;
     if (int rc = hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed), "capture"))
         return rc;
     int rc = SPH_OK;
     // the first captured step computes its keys from the positions (a replay
-    // may follow anything); the later ones take what the step before left
+    // may follow anything); the later ones take what the step before left.
+    // k0: the index of the first captured step within the call.
     for (int64_t k = 0; k < len && rc == SPH_OK; ++k)
         rc = one_step(P, s, w, dt, step + k, lagged && step + k > 0, st, Marks(),
-                      k > 0 ? keys_after(P, lagged && step + k - 1 > 0) : kNoKeys);
+                      k > 0 ? keys_after(P, lagged && step + k - 1 > 0) : kNoKeys,
+                      k0 + k);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(st, &g);
     if (rc == SPH_OK) rc = hip_check(ec, "end capture");
@@ -467,7 +485,7 @@ static int run_steps(const Problem &P, sph_state &s, const Ws &w, int64_t nsteps
         if (L > 0 && idx > 0 && idx % L == 0 && nsteps - k >= L && !ev_begin) {
             const int64_t reps = (nsteps - k) / L;
             s.cells_valid = 0;  // every captured step rebuilds its cells
-            if (int rc = graph_steps(P, s, w, dt, idx, L, reps, lagged, st)) return rc;
+            if (int rc = graph_steps(P, s, w, dt, idx, L, reps, lagged, st, k)) return rc;
             k += reps * L;
             keys = keys_after(P, lagged);  // the graph's last step has index > 0
             continue;
@@ -478,7 +496,7 @@ static int run_steps(const Problem &P, sph_state &s, const Ws &w, int64_t nsteps
             m.e0 = static_cast<hipEvent_t>(ev_begin[k]);
             m.e1 = static_cast<hipEvent_t>(ev_end[k]);
         }
-        if (int rc = one_step(P, s, w, dt, idx, lagged && idx > 0, st, m, keys)) return rc;
+        if (int rc = one_step(P, s, w, dt, idx, lagged && idx > 0, st, m, keys, k)) return rc;
         keys = keys_after(P, lagged && idx > 0);
         ++k;
     }
@@ -611,6 +629,8 @@ int sph_set_tuning(const sph_tuning *t) {
     auto run_ok = [](int v) { return v == 0 || v == 1 || v == 8 || v == 32; };
     if (!run_ok(t->xcd_run_fp64) || !run_ok(t->xcd_run_mixed))
         return fail(SPH_E_INVAL, "xcd_run must be 0, 1, 8 or 32");
+    if (t->full_gather != 0 && t->full_gather != 1)
+        return fail(SPH_E_INVAL, "full_gather must be 0 or 1");
     set_split(SPH_FP64, t->split_fp64);
     set_split(SPH_MIXED, t->split_mixed);
     set_group(SPH_FP64, t->group_fp64);
@@ -619,6 +639,7 @@ int sph_set_tuning(const sph_tuning *t) {
     set_kernel(SPH_MIXED, t->kernel_mixed);
     set_xcd_run(SPH_FP64, t->xcd_run_fp64);
     set_xcd_run(SPH_MIXED, t->xcd_run_mixed);
+    set_full_gather(t->full_gather);
     return SPH_OK;
 }
 

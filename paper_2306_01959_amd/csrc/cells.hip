@@ -86,6 +86,15 @@ __device__ __forceinline__ void encode_keys(const EncodeArgs &e, int64_t base, i
     }
 }
 
+// ------------------------------------------------------ walls in place
+
+// The update flags moving boundary particles (DevScalars::walls_move), which
+// only the Verlet update does; the symplectic scheme always gathers every
+// particle.
+bool walls_in_place_enabled(const Problem &P) {
+    return P.scheme == SPH_SCHEME_VERLET && !full_gather();
+}
+
 // ------------------------------------------------------------ radix sort
 //
 // LSD radix sort of (32-bit key, 32-bit index) pairs, 8-bit digits.  Per
@@ -491,6 +500,7 @@ struct ReorderArgs {
     uint32_t *start;
     int64_t nkeys;
     uint32_t table_block0;
+    WallsInPlace wip;  // on: boundary particles stay (the sort left them in place)
 };
 
 // Offset of coordinate v from the centre of cell c, computed in FP64 with
@@ -500,6 +510,21 @@ __device__ __forceinline__ float cell_offset(double v, double o, int c, double c
     double t = v - o;
     double ctr = ((double)c + 0.5) * cs;
     return (float)(t - ctr);
+}
+
+// Tait pressure and sound speed of the mixed view from rho - rho0 (FP32).
+template <bool kGamma7>
+__device__ __forceinline__ void mixed_eos(const Inst &ip, float dr, double &P, double &cs) {
+    const double xr = (double)dr / ip.rho0;
+    if constexpr (kGamma7) {
+        const double q = xr * (7.0 + xr * (21.0 + xr * (35.0 + xr * (35.0 + xr * (21.0 + xr * (7.0 + xr))))));
+        P = ip.B * q;
+        cs = ip.c_const ? ip.c0 : ip.c0 * (1.0 + xr * (3.0 + xr * (3.0 + xr)));
+    } else {
+        const double l1p = log1p(xr);
+        P = ip.B * expm1(ip.gamma * l1p);
+        cs = ip.c_const ? ip.c0 : ip.c0 * exp(0.5 * (ip.gamma - 1.0) * l1p);
+    }
 }
 
 // Gathers the state into cell order and writes the interaction view:
@@ -513,6 +538,12 @@ __device__ __forceinline__ float cell_offset(double v, double o, int c, double c
 // transcendental calls and fewer registers.
 // The same launch also builds the cell table from the sorted keys (the two
 // are independent): blocks from table_block0 on compute its entries.
+// With fixed walls in place a boundary particle keeps its sorted position: both
+// buffers of x, u, um and id already hold its values there (the two steps
+// before gathered every particle, and a fixed wall's position and zero
+// velocity never change), so only the densities (which the update changed)
+// are copied and the view rewritten (u = 0: no boundary particle has moved,
+// or the sort would have ranked every particle).
 template <bool kMixed, bool kGamma7>
 __global__ void k_reorder(ReorderArgs a) {
     if (blockIdx.x >= a.table_block0) {
@@ -522,6 +553,42 @@ __global__ void k_reorder(ReorderArgs a) {
     }
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.n) return;
+    const uint32_t key = key_cell(a.keys[k]);
+    const Inst ip = a.I.get(a.I.of_cell(key_row_cell(key)));
+    uint32_t off = key - 2u * ip.cell_base;  // half cells + lrow nx + cx
+    const bool bhalf = off >= inst_cells(ip);
+    if (bhalf) off -= inst_cells(ip);
+    const uint32_t lrow = off / (uint32_t)ip.nx;
+    const int cx = (int)(off % (uint32_t)ip.nx);
+    const int cy = (int)(lrow % (uint32_t)ip.ny);
+    const int cz = (int)(lrow / (uint32_t)ip.ny);
+    if (bhalf && a.wip.on()) {
+        const double x = a.x[k], y = a.y[k], z = a.z[k];
+        if constexpr (kMixed) {
+            const float dr = static_cast<const float *>(a.rho)[k];
+            static_cast<float *>(a.rho2)[k] = dr;
+            static_cast<float *>(a.rhom2)[k] = static_cast<const float *>(a.rhom)[k];
+            double P, cs;
+            mixed_eos<kGamma7>(ip, dr, P, cs);
+            const double inv = 1.0 / (ip.rho0 + (double)dr);
+            static_cast<float4 *>(a.v0)[k] =
+                make_float4(cell_offset(x, ip.ox, cx, ip.cs), cell_offset(y, ip.oy, cy, ip.cs),
+                            cell_offset(z, ip.oz, cz, ip.cs), dr);
+            static_cast<float4 *>(a.v1)[k] = make_float4(0.f, 0.f, 0.f, (float)P);
+            static_cast<float2 *>(a.v2)[k] = make_float2((float)inv, -(float)cs);
+        } else {
+            const double rho = static_cast<const double *>(a.rho)[k];
+            static_cast<double *>(a.rho2)[k] = rho;
+            static_cast<double *>(a.rhom2)[k] = static_cast<const double *>(a.rhom)[k];
+            const double r = rho / ip.rho0;
+            const double P = ip.B * (pow(r, ip.gamma) - 1.0);
+            const double cs = ip.c_const ? ip.c0 : ip.c0 * pow(r, 0.5 * (ip.gamma - 1.0));
+            static_cast<double4 *>(a.v0)[k] = make_double4(x, y, z, rho);
+            static_cast<double4 *>(a.v1)[k] = make_double4(0.0, 0.0, 0.0, P);
+            static_cast<double2 *>(a.v2)[k] = make_double2(1.0 / rho, -cs);
+        }
+        return;
+    }
     const uint32_t src = a.perm[k];
     const double x = a.x[src], y = a.y[src], z = a.z[src];
     const double ux = a.ux[src], uy = a.uy[src], uz = a.uz[src];
@@ -537,28 +604,12 @@ __global__ void k_reorder(ReorderArgs a) {
     a.uzm2[k] = a.uzm[src];
     a.id2[k] = id;
     const bool bnd = (id >> 31) != 0;
-    const uint32_t key = key_cell(a.keys[k]);
-    const Inst ip = a.I.get(a.I.of_cell(key_row_cell(key)));
     if constexpr (kMixed) {
         const float dr = static_cast<const float *>(a.rho)[src];
         static_cast<float *>(a.rho2)[k] = dr;
         static_cast<float *>(a.rhom2)[k] = static_cast<const float *>(a.rhom)[src];
-        const uint32_t off = key - 2u * ip.cell_base;  // (2 lrow + half) nx + cx
-        const uint32_t lrow = off / (2u * (uint32_t)ip.nx);
-        const int cx = (int)(off % (uint32_t)ip.nx);
-        const int cy = (int)(lrow % (uint32_t)ip.ny);
-        const int cz = (int)(lrow / (uint32_t)ip.ny);
-        const double xr = (double)dr / ip.rho0;
         double P, cs;
-        if constexpr (kGamma7) {
-            const double q = xr * (7.0 + xr * (21.0 + xr * (35.0 + xr * (35.0 + xr * (21.0 + xr * (7.0 + xr))))));
-            P = ip.B * q;
-            cs = ip.c_const ? ip.c0 : ip.c0 * (1.0 + xr * (3.0 + xr * (3.0 + xr)));
-        } else {
-            const double l1p = log1p(xr);
-            P = ip.B * expm1(ip.gamma * l1p);
-            cs = ip.c_const ? ip.c0 : ip.c0 * exp(0.5 * (ip.gamma - 1.0) * l1p);
-        }
+        mixed_eos<kGamma7>(ip, dr, P, cs);
         const double inv = 1.0 / (ip.rho0 + (double)dr);
         float4 v0 = make_float4(cell_offset(x, ip.ox, cx, ip.cs), cell_offset(y, ip.oy, cy, ip.cs),
                                 cell_offset(z, ip.oz, cz, ip.cs), dr);
@@ -584,7 +635,7 @@ __global__ void k_reorder(ReorderArgs a) {
 }
 
 int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *keys,
-                   const uint32_t *perm, hipStream_t st) {
+                   const uint32_t *perm, bool walls_in_place, hipStream_t st) {
     ReorderArgs a;
     a.perm = perm;
     a.keys = keys;
@@ -604,6 +655,8 @@ int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *
     a.start = w.cell_start();
     a.nkeys = 2 * w.L.ncells;
     a.table_block0 = (uint32_t)((s.n + 255) / 256);
+    a.wip.walls = &w.scalars()->walls_move;
+    a.wip.allow = walls_in_place && walls_in_place_enabled(P) ? 1 : 0;
     const int blocks = (int)(a.table_block0 + (a.nkeys + 1 + 255) / 256);
     bool g7 = true;
     for (const Inst &ip : P.host) g7 = g7 && ip.gamma == 7.0;
@@ -647,7 +700,7 @@ __device__ __forceinline__ void half_row(const Insts &I, int64_t r, int &inst, i
     inst = I.of_row((uint32_t)(r >> 1));
     const Inst ip = I.get(inst);
     lhalf = (int)(r - 2 * (int64_t)ip.row_base);
-    k0 = half_row_key(ip.cell_base, ip.nx, (uint32_t)lhalf >> 1, (uint32_t)lhalf & 1u);
+    k0 = half_row_key(ip, (uint32_t)lhalf >> 1, (uint32_t)lhalf & 1u);
     nx = ip.nx;
 }
 

@@ -91,6 +91,9 @@ struct DevScalars {
     unsigned int nchunks;            // interaction chunks of the current cells
     unsigned int dt_cfl_violation;   // a step used dt > dt_cfl
     unsigned long long pairs[3];     // interacting pairs since init: FF + FB, 0, BF
+    unsigned int walls_move;         // some step with this workspace moved a boundary
+                                     // particle (nonzero velocity); never cleared
+    unsigned int pad;
 };
 
 // Lanes below this one in the wave.
@@ -158,14 +161,20 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Sort keys.  Every cell row (fixed cy, cz) of an instance is split into a
-// fluid half-row and a boundary half-row, cells x-fastest within each, so a
-// run of cells of one row holds its fluid particles contiguously and its
-// boundary particles contiguously.  The key of cell x of half-row `half`
-// (0 fluid, 1 boundary) of local row `lrow` is half_row_key(...) + x; an
-// instance's keys fill [2 cell_base, 2 (cell_base + its cells)).
-__host__ __device__ __forceinline__ uint32_t half_row_key(uint32_t cell_base, uint32_t nx,
-                                                          uint32_t lrow, uint32_t half) {
-    return 2u * cell_base + (2u * lrow + half) * nx;
+// fluid half-row and a boundary half-row, cells x-fastest within each.  An
+// instance's keys fill [2 cell_base, 2 (cell_base + its cells)): first its
+// fluid half-rows, row by row, then its boundary half-rows in the same order,
+// so a run of cells of one row holds its fluid particles contiguously and its
+// boundary particles contiguously, and all of an instance's boundary
+// particles follow all of its fluid ones (a fixed wall's particles then keep
+// their sorted positions from step to step).  The key of cell x of half-row
+// `half` (0 fluid, 1 boundary) of local row `lrow` is half_row_key(...) + x.
+__host__ __device__ __forceinline__ uint32_t inst_cells(const Inst &ip) {
+    return (uint32_t)ip.nx * (uint32_t)ip.ny * (uint32_t)ip.nz;
+}
+__host__ __device__ __forceinline__ uint32_t half_row_key(const Inst &ip, uint32_t lrow,
+                                                          uint32_t half) {
+    return 2u * ip.cell_base + half * inst_cells(ip) + lrow * (uint32_t)ip.nx;
 }
 // a global cell of the cell key's row (enough to find the key's instance)
 __host__ __device__ __forceinline__ uint32_t key_row_cell(uint32_t key) { return key >> 1; }
@@ -205,7 +214,7 @@ __device__ __forceinline__ uint32_t sort_key(const Inst &ip, double x, double y,
     const int cy = axis_cell(y, ip.oy, ip.cs, ip.ny, uy);
     const int cz = axis_cell(z, ip.oz, ip.cs, ip.nz, uz);
     const uint32_t lrow = (uint32_t)cz * (uint32_t)ip.ny + (uint32_t)cy;
-    const uint32_t cell = half_row_key(ip.cell_base, ip.nx, lrow, id >> 31) + (uint32_t)cx;
+    const uint32_t cell = half_row_key(ip, lrow, id >> 31) + (uint32_t)cx;
     return (cell << kSubBits) | (uy << 1) | ux;
 }
 
@@ -245,6 +254,21 @@ struct Insts {
         return lo;
     }
 };
+
+// Fixed walls in place.  While no boundary particle moves, the boundary
+// particles of an instance keep their sorted positions from step to step
+// (they follow all of the instance's fluid particles in key order, and their
+// keys do not change), so the sort gives them the identity permutation and a
+// step's gather may leave them where they are: it copies only what the
+// update changed (the densities) and rewrites their view.
+struct WallsInPlace {
+    const unsigned int *walls;  // DevScalars::walls_move
+    int allow;                  // the host allows it for this step
+    // (the flag only changes inside an update, so every kernel of a step
+    // gets the same answer)
+    __device__ __forceinline__ bool on() const { return allow != 0 && *walls == 0u; }
+};
+
 
 // A problem: one or more instances sharing precision and particle arrays.
 struct Problem {
@@ -342,8 +366,13 @@ bool fused_writes_keys(const Problem &P);
 // exclusive scan of m values from `in` (left intact) to `out`; tot:
 // ceil(m / kScanSpan) values of scratch
 int launch_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tot, hipStream_t st);
+// walls_in_place: the two steps before gathered every particle, so this
+// gather may leave fixed walls in place (WallsInPlace; the kernel decides
+// from the device flag)
 int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *keys,
-                   const uint32_t *perm, hipStream_t st);
+                   const uint32_t *perm, bool walls_in_place, hipStream_t st);
+// steps of P may leave fixed walls in place (scheme and tuning)
+bool walls_in_place_enabled(const Problem &P);
 // lagged: also fix this step's dt from the previous interaction's bound (or dt > 0)
 int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStream_t st);
 // fuse: the interaction also advances every target (time update of step
@@ -393,6 +422,8 @@ int set_split(int precision, int split);
 int set_group(int precision, int group);
 int set_kernel(int precision, int kernel);
 int set_xcd_run(int precision, int run);
+void set_full_gather(int on);
+int full_gather();
 int split_for(const Problem &P);
 int group_for(const Problem &P);
 int kernel_for(const Problem &P);

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_partial(DiagArgs a) {
                     const int czn = cz + dz, cyn = cy + dy;
                     if (czn < 0 || czn >= ip.nz || cyn < 0 || cyn >= ip.ny) continue;
                     // the fluid half of the stencil row
-                    const uint32_t hb = half_row_key(ip.cell_base, ip.nx, czn * ip.ny + cyn, 0);
+                    const uint32_t hb = half_row_key(ip, czn * ip.ny + cyn, 0);
                     const int xl = cx > 0 ? cx - 1 : 0, xh = cx + 1 < ip.nx ? cx + 1 : ip.nx - 1;
                     const uint32_t js = a.cell_start[hb + xl], je = a.cell_start[hb + xh + 1];
                     for (uint32_t j = js; j < je && !found; ++j) found = near(j, i, x, y, z);
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_probes(DiagArgs a, const doubl
             const int czn = cz + dz, cyn = cy + dy;
             if (czn < 0 || czn >= ip.nz || cyn < 0 || cyn >= ip.ny) continue;
             // the fluid half of the stencil row
-            const uint32_t hb = half_row_key(ip.cell_base, ip.nx, czn * ip.ny + cyn, 0);
+            const uint32_t hb = half_row_key(ip, czn * ip.ny + cyn, 0);
             const int xl = cx > 0 ? cx - 1 : 0, xh = cx + 1 < ip.nx ? cx + 1 : ip.nx - 1;
             const uint32_t js = a.cell_start[hb + xl], je = a.cell_start[hb + xh + 1];
             for (uint32_t j = js + threadIdx.x; j < je; j += kDiagThreads) {

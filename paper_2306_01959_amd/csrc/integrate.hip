@@ -112,8 +112,9 @@ int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int
                      hipStream_t st, int hist_shift) {
     IntegrateArgs a;
     a.n = s.n;
-    a.state = StateArrays{s.x,   s.y,   s.z,   s.ux,  s.uy,   s.uz,
-                          s.uxm, s.uym, s.uzm, s.rho, s.rhom, s.id, w.keys_next()};
+    a.state = StateArrays{s.x,   s.y,   s.z,   s.ux,  s.uy,   s.uz,  s.uxm,
+                          s.uym, s.uzm, s.rho, s.rhom, s.id, w.keys_next(),
+                          &w.scalars()->walls_move};
     a.rates = w.base + w.L.rates;
     a.I = insts_of(P, w);
     a.sc = w.scalars();
@@ -363,6 +364,8 @@ __global__ void k_ws_init(DevScalars *sc, InstState *ist, int ninst, ImpulseStat
         sc->nchunks = 0;
         sc->dt_cfl_violation = 0;
         sc->pairs[0] = sc->pairs[1] = sc->pairs[2] = 0;
+        sc->walls_move = 0;
+        sc->pad = 0;
     }
     for (int k = t; k < ninst; k += blockDim.x) {
         ist[k].dt_min_bits = 0x7ff0000000000000ull;  // +inf: no bound yet

@@ -1,8 +1,8 @@
 // Pairwise WCSPH interaction (Section 2.2, eqs. sphu, pi, cpmu, sphw,
 // sphrho, tait) and the per-particle time-step bound (eq. sphdt).
 //
-// Work decomposition.  Particles are sorted by cell row (fixed cy, cz), then
-// fluid before boundary, then cell x.  A chunk is up to 64 consecutive sorted
+// Work decomposition.  Particles are sorted by class (fluid before
+// boundary), then cell row (fixed cy, cz), then cell x.  A chunk is up to 64 consecutive sorted
 // particles of one half-row (the fluid or the boundary particles of a row),
 // so it is all fluid or all boundary.  Its candidates are the nine stencil
 // rows (cy+dy, cz+dz) over cells [cx_first - 1, cx_last + 1], each split
@@ -686,7 +686,7 @@ __device__ __forceinline__ void stencil_range(const InteractArgs &a, const Inst 
     je = 0;
     hb = 0;
     if (czn >= 0 && czn < ip.nz && cyn >= 0 && cyn < ip.ny && !((lh & 1) && half)) {
-        hb = (int)half_row_key(ip.cell_base, ip.nx, (uint32_t)(czn * ip.ny + cyn), (uint32_t)half);
+        hb = (int)half_row_key(ip, (uint32_t)(czn * ip.ny + cyn), (uint32_t)half);
         const int xlo = cxa - 1 < 0 ? 0 : cxa - 1;
         const int xhi = cxb + 1 >= ip.nx ? ip.nx - 1 : cxb + 1;
         js = (int)a.cell_start[hb + xlo];
@@ -789,7 +789,7 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
     const int cs0 = uni(ch.x), cs1 = uni(ch.y), lh = uni(ch.z), inst = uni(ch.w);
     const Inst ip = a.I.get(inst);
     const int ntgt = cs1 - cs0;
-    const int rowbase = (int)half_row_key(ip.cell_base, ip.nx, lh >> 1, lh & 1);
+    const int rowbase = (int)half_row_key(ip, lh >> 1, lh & 1);
     const int cxa = uni((int)key_cell(a.keys[cs0]) - rowbase);
     const int cxb = uni((int)key_cell(a.keys[cs1 - 1]) - rowbase);
 
@@ -1111,7 +1111,7 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed ? 4 : 3))) void k_interact_g(Intera
         const int cs0 = uni(ch.x), cs1 = uni(ch.y), lh = uni(ch.z), inst = uni(ch.w);
         const Inst ip = a.I.get(inst);
         const int ntgt = cs1 - cs0;
-        const int rowbase = (int)half_row_key(ip.cell_base, ip.nx, lh >> 1, lh & 1);
+        const int rowbase = (int)half_row_key(ip, lh >> 1, lh & 1);
         const int cxa = uni((int)key_cell(a.keys[cs0]) - rowbase);
         const int cxb = uni((int)key_cell(a.keys[cs1 - 1]) - rowbase);
 
@@ -1310,7 +1310,7 @@ __global__ __launch_bounds__(kWave *kCW) void k_interact_c(InteractArgs a) {
     const int4 ch = a.chunks[chunk];
     const int cs0 = uni(ch.x), cs1 = uni(ch.y), lh = uni(ch.z), inst = uni(ch.w);
     const Inst ip = a.I.get(inst);
-    const int rowbase = (int)half_row_key(ip.cell_base, ip.nx, lh >> 1, lh & 1);
+    const int rowbase = (int)half_row_key(ip, lh >> 1, lh & 1);
     const int cxa = uni((int)key_cell(a.keys[cs0]) - rowbase);
     const int cxb = uni((int)key_cell(a.keys[cs1 - 1]) - rowbase);
     const int g0 = cs0 + w * kT;                    // this wave's first target
@@ -1639,6 +1639,11 @@ int xcd_run_for(const Problem &P) {
     return r ? r : 1;
 }
 
+// nonzero: every step gathers every particle (no fluid-only sort)
+static std::atomic<int> g_full_gather{0};
+void set_full_gather(int on) { g_full_gather.store(on ? 1 : 0, std::memory_order_relaxed); }
+int full_gather() { return g_full_gather.load(std::memory_order_relaxed); }
+
 int set_kernel(int precision, int kernel) {
     if (precision != SPH_FP64 && precision != SPH_MIXED) return -1;
     if (kernel != SPH_KERNEL_AUTO && kernel != SPH_KERNEL_ROWS && kernel != SPH_KERNEL_GROUPS &&
@@ -1838,7 +1843,8 @@ int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream
     a.st_nb = st_nb;
     a.st_hash = st_hash;
     a.state = StateArrays{s.x,   s.y,   s.z,   s.ux,   s.uy,  s.uz,
-                          s.uxm, s.uym, s.uzm, s.rho,  s.rhom, s.id, w.keys_next()};
+                          s.uxm, s.uym, s.uzm, s.rho,  s.rhom, s.id, w.keys_next(),
+                          &w.scalars()->walls_move};
     a.step = step;
     const bool stats = st_nf != nullptr;
     // chunks of <= csz targets: at most ceil(particles / csz) + 1 per half-row

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kLoadThreads) void k_boundary_force(ForceArgs a) {
     const int cy = a.cy0 + (int)blockIdx.x % a.nby;
     const int cz = a.cz0 + (int)blockIdx.x / a.nby;
     // this row's boundary particles in the box's cells
-    const uint32_t hb = half_row_key(ip.cell_base, ip.nx, (uint32_t)(cz * ip.ny + cy), 1);
+    const uint32_t hb = half_row_key(ip, (uint32_t)(cz * ip.ny + cy), 1);
     const uint32_t i0 = a.cell_start[hb + a.cx0], i1 = a.cell_start[hb + a.cx1 + 1];
     const double h = ip.h, m = ip.mass, eta2 = ip.eta2;
     const double inv_h = 1.0 / h, fk = 5.0 * ip.wd / (h * h);
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kLoadThreads) void k_boundary_force(ForceArgs a) {
             for (int dy = -1; dy <= 1; ++dy) {
                 const int czn = cz + dz, cyn = cy + dy;
                 if (czn < 0 || czn >= ip.nz || cyn < 0 || cyn >= ip.ny) continue;
-                const uint32_t fb = half_row_key(ip.cell_base, ip.nx, (uint32_t)(czn * ip.ny + cyn), 0);
+                const uint32_t fb = half_row_key(ip, (uint32_t)(czn * ip.ny + cyn), 0);
                 const int xl = pcx > 0 ? pcx - 1 : 0, xh = pcx + 1 < ip.nx ? pcx + 1 : ip.nx - 1;
                 const uint32_t js = a.cell_start[fb + xl], je = a.cell_start[fb + xh + 1];
                 for (uint32_t j = js; j < je; ++j) {

@@ -117,9 +117,8 @@ __global__ __launch_bounds__(kMpsThreads) void k_mps(MpsArgs a) {
             const int czn = cz0 + dz, cyn = cy0 + dy;
             const bool in_grid = czn >= 0 && czn < ip.nz && cyn >= 0 && cyn < ip.ny;
             for (uint32_t half = 0; half < 2; ++half) {
-                const uint32_t hb = in_grid ? half_row_key(ip.cell_base, ip.nx,
-                                                           (uint32_t)(czn * ip.ny + cyn), half)
-                                            : 0u;
+                const uint32_t hb =
+                    in_grid ? half_row_key(ip, (uint32_t)(czn * ip.ny + cyn), half) : 0u;
                 uint32_t js = 0, je = 0;
                 if (in_grid && act) {
                     js = a.cell_start[hb + xl];

@@ -27,6 +27,8 @@ struct StateArrays {
     void *rhom;
     const uint32_t *id;
     uint32_t *keys_next;  // or null
+    unsigned int *walls_move;  // DevScalars::walls_move: set when a boundary
+                               // particle has a nonzero velocity
 };
 
 // Returns the key written (0 without kKeys).
@@ -50,7 +52,10 @@ __device__ __forceinline__ uint32_t advance(const StateArrays &s, const Inst &ip
     const uint32_t id = s.id[i];
     if ((id >> 31) != 0) {
         // boundary: keeps its velocity (zero for a fixed wall, the prescribed
-        // one of a moving gate) and moves with it
+        // one of a moving gate) and moves with it.  Any nonzero bit (-0 too)
+        // marks a moving wall: later steps then sort and gather every particle.
+        if ((__double_as_longlong(ux) | __double_as_longlong(uy) | __double_as_longlong(uz)) != 0)
+            *s.walls_move = 1u;
         s.uxm[i] = ux;
         s.uym[i] = uy;
         s.uzm[i] = uz;

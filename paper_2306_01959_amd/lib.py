@@ -64,7 +64,8 @@ class SphTuning(C.Structure):
     _fields_ = [("split_fp64", C.c_int32), ("split_mixed", C.c_int32),
                 ("group_fp64", C.c_int32), ("group_mixed", C.c_int32),
                 ("kernel_fp64", C.c_int32), ("kernel_mixed", C.c_int32),
-                ("xcd_run_fp64", C.c_int32), ("xcd_run_mixed", C.c_int32)]
+                ("xcd_run_fp64", C.c_int32), ("xcd_run_mixed", C.c_int32),
+                ("full_gather", C.c_int32)]
 
 
 class SphState(C.Structure):
@@ -180,9 +181,12 @@ def check(rc: int) -> None:
 
 def set_tuning(split_fp64: int = 0, split_mixed: int = 0, group_fp64: int = 0,
                group_mixed: int = 0, kernel_fp64: int = 0, kernel_mixed: int = 0,
-               xcd_run_fp64: int = 0, xcd_run_mixed: int = 0) -> None:
-    """Process-wide interaction launch shape (0 = the library's choice)."""
+               xcd_run_fp64: int = 0, xcd_run_mixed: int = 0, full_gather: int = 0) -> None:
+    """Process-wide interaction launch shape (0 = the library's choice);
+    full_gather = 1: every step sorts and gathers every particle (the same
+    results as the default, which leaves fixed walls in place)."""
     t = SphTuning()
+    t.full_gather = int(full_gather)
     t.xcd_run_fp64 = int(xcd_run_fp64)
     t.xcd_run_mixed = int(xcd_run_mixed)
     t.split_fp64 = int(split_fp64)
@@ -291,6 +295,10 @@ class _System:
 
     # -- read-back ----------------------------------------------------------
     def ids(self) -> np.ndarray:
+        """Original index of every particle, in the current (cell) order;
+        synchronises the device first (the library may run on another stream
+        than torch's, whose copy would not wait for it)."""
+        self.sync()
         raw = self._cur("id").cpu().numpy().view(np.uint32)
         return (raw & np.uint32(0x7FFFFFFF)).astype(np.int64)
 

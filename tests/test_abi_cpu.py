@@ -331,7 +331,8 @@ def test_tuning_validated_and_reported(L):
     sph_get_split reports the shape it set (no GPU needed)."""
     p = params()
     bad = [dict(split_mixed=2), dict(group_fp64=32), dict(kernel_mixed=9),
-           dict(xcd_run_fp64=4), dict(xcd_run_mixed=-1), dict(xcd_run_mixed=64)]
+           dict(xcd_run_fp64=4), dict(xcd_run_mixed=-1), dict(xcd_run_mixed=64),
+           dict(full_gather=2), dict(full_gather=-1)]
     try:
         lib.set_tuning(split_mixed=3, group_mixed=16, kernel_mixed=1, xcd_run_mixed=32)
         for kw in bad:
@@ -342,6 +343,8 @@ def test_tuning_validated_and_reported(L):
         assert lib.get_split(p, 100000) == (3, 16, 1)
         for run in (0, 1, 8, 32):
             lib.set_tuning(xcd_run_fp64=run, xcd_run_mixed=run)
+        for full in (0, 1):
+            lib.set_tuning(full_gather=full)
     finally:
         lib.set_tuning()
 

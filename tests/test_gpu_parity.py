@@ -49,13 +49,13 @@ def _sim(gpu, sc, precision, prev=None, **kw):
 # ---------------------------------------------------------------- cells
 
 def _sort_keys(sc_or_xyz, prm, isb, full):
-    """The library's sort key from FP64 positions: cell row, class, cell x,
+    """The library's sort key from FP64 positions: class, cell row, cell x,
     then (full) the upper-half flags along y and x."""
     x, y, z = sc_or_xyz
     (cx, cy, cz), _ = bruteforce.cells_and_offsets(x, y, z, prm["origin"], prm["cell_size"],
                                                    prm["dims"])
-    nx, ny = prm["dims"][0], prm["dims"][1]
-    key = (2 * (cy + ny * cz) + isb) * nx + cx
+    nx, ny, nz = prm["dims"]
+    key = isb * (nx * ny * nz) + (cy + ny * cz) * nx + cx
     if not full:
         return key
     ux = bruteforce.upper_half(x, prm["origin"][0], prm["cell_size"], prm["dims"][0])
@@ -65,7 +65,7 @@ def _sort_keys(sc_or_xyz, prm, isb, full):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_build_cells_invariants(gpu, precision):
-    """sph_build_cells sorts on the full key (cell row, class, cell x, the
+    """sph_build_cells sorts on the full key (class, cell row, cell x, the
     halves of the cell along y and x), stably."""
     s = scene.config_scene(1)
     sim = _sim(gpu, s, precision)
