@@ -234,6 +234,11 @@ SORT_BYTES_FIRST_KEYS = 16  # pass 0 when the previous (fused) step wrote the ke
 SORT_BYTES_PASS = 20    # later passes: + the index read
 REORDER_BYTES = 4 + 4 + 84 + 84 + 40  # perm + key in, state gathered (84 B) and written,
                                       # interaction view written (40 B)
+REORDER_BYTES_WALL = 4 + 24 + 8 + 8 + 40  # a fixed wall's particle left in place: key,
+                                          # x, y, z and both densities in, both densities
+                                          # and the view out
+WALLS_FULL_STEPS = 2  # steps per refresh period that gather every particle (the
+                      # refresh and the step after it)
 TABLE_BYTES = 4 + 4 + 4  # per cell-table entry (same launch as the reorder): its previous
                          # value read as the search hint, one key probed, the entry written
 
@@ -275,14 +280,17 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False, scene
     kern = {}
     for name, region in (("sort", lib.REGION_SORT), ("reorder", lib.REGION_REORDER),
                          ("interact", lib.REGION_INTERACT), ("step", lib.REGION_STEP)):
-        # from the second step on: the first one reuses the cells the
-        # diagnostics built and has no sort or reorder of its own
-        ev = Events(hip, 21, every=2, start=1)
-        ens.run_profiled(21, -1.0, step, ev.begin, ev.end, region=region, mode=mode)
+        # one whole refresh period from a refresh step, every step (the mix
+        # of the graph replays: the refresh and the step after it gather
+        # every particle, the others leave the fixed walls in place); the
+        # first step rebuilds its cells (not those the diagnostics built)
+        ens.state.cells_valid = 0
+        ev = Events(hip, period)
+        ens.run_profiled(period, -1.0, step, ev.begin, ev.end, region=region, mode=mode)
         torch.cuda.synchronize()
         kern[name] = ev.mean_ms()
         ev.close()
-        step += 21
+        step += period
     assert all(d["n_nonfinite"] == 0 for d in d1), "non-finite state"
     n = ens.n
     # sort key: 2 x (cells) keys of the cell list plus 2 sub-cell bits; the
@@ -297,7 +305,11 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False, scene
     first = SORT_BYTES_FIRST_KEYS if keys_written else SORT_BYTES_FIRST
     sort_bytes = n * (first + SORT_BYTES_PASS * (passes - 1))
     cells = sum(int(np.prod(s.params["dims"])) for s in scenes)
-    reorder_bytes = n * REORDER_BYTES + (2 * cells + 1) * TABLE_BYTES
+    n_wall = sum(int(s.is_boundary.sum()) for s in scenes)
+    in_place = (period - WALLS_FULL_STEPS) / period   # share of steps with walls in place
+    reorder_bytes = ((n - n_wall) * REORDER_BYTES
+                     + n_wall * (in_place * REORDER_BYTES_WALL + (1 - in_place) * REORDER_BYTES)
+                     + (2 * cells + 1) * TABLE_BYTES)
     alg_bytes = n * (ALG_KEY_BYTES + 2 * STATE_BYTES["mixed"]) + CELL_TABLE_BYTES * cells
     pairs = [(d1[0][k] - d0[0][k]) / steps for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
     flop = FLOP_FF * pairs[0] + FLOP_FB * pairs[1] + FLOP_BF * pairs[2]
@@ -332,7 +344,9 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False, scene
                      bytes_model="design bytes",
                      first_pass_keys="written by the fused update" if keys_written
                      else "computed from the positions"),
-        "reorder": dict(bw(reorder_bytes, kern["reorder"]), bytes_model="design bytes"),
+        "reorder": dict(bw(reorder_bytes, kern["reorder"]), bytes_model="design bytes",
+                        wall_particles=n_wall,
+                        steps_with_walls_in_place=f"{period - WALLS_FULL_STEPS} of {period}"),
         "interact": {"kernel_ms": kern["interact"], "achieved": flop / (kern["interact"] * 1e-3)
                      / 1e12, "unit": "TFLOP/s", "peak": PEAK_FP32_TFLOPS,
                      "flop_per_launch": flop},
