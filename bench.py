@@ -234,11 +234,9 @@ SORT_BYTES_FIRST_KEYS = 16  # pass 0 when the previous (fused) step wrote the ke
 SORT_BYTES_PASS = 20    # later passes: + the index read
 REORDER_BYTES = 4 + 4 + 84 + 84 + 40  # perm + key in, state gathered (84 B) and written,
                                       # interaction view written (40 B)
-REORDER_BYTES_WALL = 4 + 24 + 8 + 8 + 40  # a fixed wall's particle left in place: key,
-                                          # x, y, z and both densities in, both densities
-                                          # and the view out
-WALLS_FULL_STEPS = 2  # steps per refresh period that gather every particle (the
-                      # refresh and the step after it)
+REORDER_BYTES_WALL = 4 + 8 + 8 + 16  # a fixed wall's particle left in place (mixed):
+                                     # key and both densities in, both densities and the
+                                     # view's density part out
 TABLE_BYTES = 4 + 4 + 4  # per cell-table entry (same launch as the reorder): its previous
                          # value read as the search hint, one key probed, the entry written
 
@@ -280,17 +278,16 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False, scene
     kern = {}
     for name, region in (("sort", lib.REGION_SORT), ("reorder", lib.REGION_REORDER),
                          ("interact", lib.REGION_INTERACT), ("step", lib.REGION_STEP)):
-        # one whole refresh period from a refresh step, every step (the mix
-        # of the graph replays: the refresh and the step after it gather
-        # every particle, the others leave the fixed walls in place); the
-        # first step rebuilds its cells (not those the diagnostics built)
-        ens.state.cells_valid = 0
-        ev = Events(hip, period)
-        ens.run_profiled(period, -1.0, step, ev.begin, ev.end, region=region, mode=mode)
+        # one whole refresh period of steady-state steps: a call's first two
+        # steps gather every particle (the fixed walls stay in place from
+        # the third on, as in the graph replays), so the period sampled is
+        # steps 2 .. period + 1 of the call
+        ev = Events(hip, period + 2, start=2)
+        ens.run_profiled(period + 2, -1.0, step, ev.begin, ev.end, region=region, mode=mode)
         torch.cuda.synchronize()
         kern[name] = ev.mean_ms()
         ev.close()
-        step += period
+        step += period + 2
     assert all(d["n_nonfinite"] == 0 for d in d1), "non-finite state"
     n = ens.n
     # sort key: 2 x (cells) keys of the cell list plus 2 sub-cell bits; the
@@ -306,9 +303,7 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False, scene
     sort_bytes = n * (first + SORT_BYTES_PASS * (passes - 1))
     cells = sum(int(np.prod(s.params["dims"])) for s in scenes)
     n_wall = sum(int(s.is_boundary.sum()) for s in scenes)
-    in_place = (period - WALLS_FULL_STEPS) / period   # share of steps with walls in place
-    reorder_bytes = ((n - n_wall) * REORDER_BYTES
-                     + n_wall * (in_place * REORDER_BYTES_WALL + (1 - in_place) * REORDER_BYTES)
+    reorder_bytes = ((n - n_wall) * REORDER_BYTES + n_wall * REORDER_BYTES_WALL
                      + (2 * cells + 1) * TABLE_BYTES)
     alg_bytes = n * (ALG_KEY_BYTES + 2 * STATE_BYTES["mixed"]) + CELL_TABLE_BYTES * cells
     pairs = [(d1[0][k] - d0[0][k]) / steps for k in ("pairs_ff", "pairs_fb", "pairs_bf")]
@@ -346,7 +341,7 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False, scene
                      else "computed from the positions"),
         "reorder": dict(bw(reorder_bytes, kern["reorder"]), bytes_model="design bytes",
                         wall_particles=n_wall,
-                        steps_with_walls_in_place=f"{period - WALLS_FULL_STEPS} of {period}"),
+                        walls="left in place (steady state: a call's steps 2 on)"),
         "interact": {"kernel_ms": kern["interact"], "achieved": flop / (kern["interact"] * 1e-3)
                      / 1e12, "unit": "TFLOP/s", "peak": PEAK_FP32_TFLOPS,
                      "flop_per_launch": flop},

@@ -234,11 +234,10 @@ typedef enum {
  * chip's eight XCDs (which receive workgroups in turn) takes runs of that
  * many consecutive chunks, which share candidates in its L2.  0 = the
  * library's choice (xcd_run: 1).  full_gather = 1 turns off the fixed-wall
- * shortcut of sph_run / sph_batch_run: from the third step of a call (and
- * outside the two steps from each refresh), while no boundary particle has
- * moved with the workspace, the boundary particles keep their sorted
- * positions and the gather leaves them in place, copying only their
- * densities; both give the same results bit for bit.  Per
+ * shortcut of sph_run / sph_batch_run: from the third step of a call, while
+ * no boundary particle has moved with the workspace, the boundary particles
+ * keep their sorted positions and the gather leaves them in place, copying
+ * only their densities; both give the same results bit for bit.  Per
  * precision (full_gather: for both), process-wide, host-side: besides sph_run_noalloc's scratch this
  * is the library's only state outside the caller's buffers.  It changes
  * launch shapes only, never results beyond summation order; each field is
@@ -292,7 +291,8 @@ int sph_get_density(const sph_params *p, const sph_state *s, double *rho, int32_
  * the 27 cells around its own.  Hashes every position to its
  * cell (clamped to the grid), sorts the particles stably by class (fluid
  * before boundary), then cell row (fixed y, z), then cell x, then half of
- * the cell along y, then half along x (LSD radix sort of 32-bit keys), gathers
+ * the cell along y, then half along x (fluid particles only; LSD radix sort
+ * of 32-bit keys), gathers
  * every state array into that order (the *_alt buffers, then swaps the
  * pointers) and builds the cell table, the chunk list and the interaction
  * view (per-particle pressure, sound speed, 1/rho, and for SPH_MIXED the FP32
@@ -508,9 +508,10 @@ typedef struct sph_batch {
                             soon as its sums are complete: one fused kernel
                             instead of interaction + update */
 #define SPH_RUN_GRAPH 2  /* capture a period of steps (lcm of 4 and every
-                            N_s, at most 400) in a HIP graph and replay it;
-                            the stream must not be NULL; the call then
-                            synchronises the stream before it returns */
+                            N_s, at most 400) from the call's third step in
+                            a HIP graph and replay it; the stream must not
+                            be NULL; the call then synchronises the stream
+                            before it returns */
 
 /* Workspace bytes of a batch; SPH_E_RANGE if the sum of particles reaches
  * 2^31 or the sum of cells 2^29. */

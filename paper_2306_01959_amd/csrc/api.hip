@@ -69,8 +69,8 @@ WsLayout make_layout(const Problem &P) {
     L.chunks = take(sizeof(int4) * (size_t)L.max_chunks);
     L.chunk_out = take(sizeof(ChunkOut) * (size_t)L.max_chunks);
     L.view0 = take(L.view_elem * (size_t)n);
-    L.view1 = take(L.view_elem * (size_t)n);
-    L.view2 = take((mixed ? 8 : 16) * (size_t)n);
+    L.view1 = take((mixed ? 8 : 32) * (size_t)n);
+    L.view2 = take(16 * (size_t)n);
     L.rates = take(5 * L.rate_elem * (size_t)n);
     L.scalars = take(sizeof(DevScalars));
     L.inst_tab = take(sizeof(Inst) * (size_t)L.ninst);
@@ -295,9 +295,11 @@ struct Marks {
 // positions here).
 // walls_in_place: the previous two steps of this call gathered every
 // particle, so this gather may leave fixed walls in place (WallsInPlace).
+// zero_hist: the step's fused interaction counts the next sort's digits.
 static int build_cells(const Problem &P, sph_state &s, const Ws &w, hipStream_t st,
                        bool lagged = false, double dt = 0.0, const Marks &m = Marks(),
-                       bool full = true, int keys = kNoKeys, bool walls_in_place = false) {
+                       bool full = true, int keys = kNoKeys, bool walls_in_place = false,
+                       bool zero_hist = false) {
     if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
     uint32_t *sorted = nullptr, *perm = nullptr;
     if (int rc = m.at(SPH_REGION_SORT, true, st)) return rc;
@@ -306,7 +308,7 @@ static int build_cells(const Problem &P, sph_state &s, const Ws &w, hipStream_t 
     if (int rc = m.at(SPH_REGION_REORDER, true, st)) return rc;
     if (int rc = launch_reorder(P, s, w, sorted, perm, walls_in_place, st)) return rc;
     if (int rc = m.at(SPH_REGION_REORDER, false, st)) return rc;
-    if (int rc = launch_chunks(P, w, lagged, dt, st)) return rc;
+    if (int rc = launch_chunks(P, w, lagged, dt, st, zero_hist)) return rc;
     s.cells_valid = 1;
     return SPH_OK;
 }
@@ -347,14 +349,12 @@ static int symplectic_step(const Problem &P, sph_state &s, const Ws &w, double d
     return SPH_OK;
 }
 
-// Whether step `step` (index k within this call) may leave fixed walls in
-// place.  The boundary particles must already sit, in both buffers of the
-// state, at the positions this step's sort gives them: the call's first two
-// steps and the two steps from each refresh (which sorts the walls by their
-// sub-cell bits too, and so may reorder them) gather every particle.
-static bool walls_in_place_at(const Problem &P, int64_t k, int64_t step) {
-    const int64_t R = refresh_period(P);
-    return k >= 2 && step % R != 0 && step % R != 1 && walls_in_place_enabled(P);
+// Whether step k of this call may leave fixed walls in place.  The boundary
+// particles must already sit, in both buffers of the state, at the positions
+// this step's sort gives them (refreshes included: boundary keys carry no
+// sub-cell bits), so the call's first two steps gather every particle.
+static bool walls_in_place_at(const Problem &P, int64_t k) {
+    return k >= 2 && walls_in_place_enabled(P);
 }
 
 // One step.  fused: the lagged-dt form, where the interaction also advances
@@ -364,27 +364,31 @@ static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int6
                     bool fused, hipStream_t st, const Marks &m = Marks(), int keys = kNoKeys,
                     int64_t k = 0) {
     if (P.scheme == SPH_SCHEME_SYMPLECTIC) return symplectic_step(P, s, w, dt, step, st, m);
+    // the next step's sort: on every key bit at a refresh, else from kSubBits;
+    // a fused interaction that writes its keys may also count its first digits
+    const int next_low = (step + 1) % refresh_period(P) == 0 ? 0 : kSubBits;
+    const bool count = fused && fused_counts_digits(P);
     if (!s.cells_valid) {
         const bool full = step % refresh_period(P) == 0;
-        if (int rc = build_cells(P, s, w, st, fused, dt, m, full, keys,
-                                 walls_in_place_at(P, k, step)))
+        if (int rc = build_cells(P, s, w, st, fused, dt, m, full, keys, walls_in_place_at(P, k),
+                                 count))
             return rc;
     } else {
         if (int rc = m.at(SPH_REGION_STEP, true, st)) return rc;
-        if (int rc = launch_chunks(P, w, fused, dt, st)) return rc;  // fresh dt bound
+        if (int rc = launch_chunks(P, w, fused, dt, st, count)) return rc;  // fresh dt bound
     }
     // the interaction region ends with the kernel (before the reduction of
     // its chunk records)
     if (int rc = m.at(SPH_REGION_INTERACT, true, st)) return rc;
     hipEvent_t after = m.region == SPH_REGION_INTERACT ? m.e1 : nullptr;
     if (!m.e0) after = nullptr;
-    if (int rc = launch_interact(P, s, w, st, nullptr, nullptr, nullptr, fused, step, after))
+    if (int rc = launch_interact(P, s, w, st, nullptr, nullptr, nullptr, fused, step, after,
+                                 count ? next_low : -1))
         return rc;
     if (fused) {
         after_fused_step(s);
     } else {
         // the update also counts the first digits of the next step's sort
-        const int next_low = (step + 1) % refresh_period(P) == 0 ? 0 : kSubBits;
         if (int rc = launch_integrate(P, s, w, dt, step, st, next_low)) return rc;
     }
     if (int rc = m.at(SPH_REGION_STEP, false, st)) return rc;
@@ -394,10 +398,10 @@ static int one_step(const Problem &P, sph_state &s, const Ws &w, double dt, int6
 
 // What a step leaves for the next sort (KeysLeft): the update kernel writes
 // the keys and counts their first digits; a fused interaction may write the
-// keys.
+// keys, and the row-split one with them count their first digits too.
 static int keys_after(const Problem &P, bool fused) {
     if (P.scheme == SPH_SCHEME_SYMPLECTIC) return kNoKeys;
-    if (!fused) return kKeysCounted;
+    if (!fused || fused_counts_digits(P)) return kKeysCounted;
     return fused_writes_keys(P) ? kKeysOnly : kNoKeys;
 }
 
@@ -482,7 +486,10 @@ static int run_steps(const Problem &P, sph_state &s, const Ws &w, int64_t nsteps
     int keys = kNoKeys;
     while (k < nsteps) {
         const int64_t idx = step0 + k;
-        if (L > 0 && idx > 0 && idx % L == 0 && nsteps - k >= L && !ev_begin) {
+        // graphs of L steps from the call's third step on (after the two steps
+        // that gather every particle): the step-dependent choices (Euler
+        // reset, refresh) and the buffers repeat with period L from any step
+        if (L > 0 && k >= 2 && nsteps - k >= L && !ev_begin) {
             const int64_t reps = (nsteps - k) / L;
             s.cells_valid = 0;  // every captured step rebuilds its cells
             if (int rc = graph_steps(P, s, w, dt, idx, L, reps, lagged, st, k)) return rc;

@@ -496,10 +496,10 @@ struct ReorderArgs {
     // view
     void *v0, *v1, *v2;
     Insts I;
-    // cell table, built by the blocks from table_block0 on
+    // cell table, built by the first table_blocks blocks
     uint32_t *start;
     int64_t nkeys;
-    uint32_t table_block0;
+    uint32_t table_blocks;
     WallsInPlace wip;  // on: boundary particles stay (the sort left them in place)
 };
 
@@ -528,8 +528,9 @@ __device__ __forceinline__ void mixed_eos(const Inst &ip, float dr, double &P, d
 }
 
 // Gathers the state into cell order and writes the interaction view:
-// mixed: {offset from the cell centre (FP32), rho - rho0}, {u (FP32), P},
-// {1/rho, +-c}; FP64: {r, rho}, {u, P}, {1/rho, +-c}; c < 0 marks a boundary
+// mixed: {offset from the cell centre (FP32), u_x}, {u_y, u_z}, {rho - rho0,
+// P, 1/rho, +-c} (what a fixed wall changes from step to step is in the last
+// vector alone); FP64: {r, rho}, {u, P}, {1/rho, +-c}; c < 0 marks a boundary
 // particle.  P from the Tait equation, c the Tait sound speed (or c0).
 // Mixed precision takes them from x = (rho - rho0) / rho0 in FP64 without
 // cancellation: (1 + x)^gamma - 1 = expm1(gamma log1p(x)); kGamma7 (every
@@ -537,24 +538,20 @@ __device__ __forceinline__ void mixed_eos(const Inst &ip, float dr, double &P, d
 // binomial instead, x (7 + 21 x + ... + x^6) and c0 (1 + x)^3, which needs no
 // transcendental calls and fewer registers.
 // The same launch also builds the cell table from the sorted keys (the two
-// are independent): blocks from table_block0 on compute its entries.
+// are independent): its first table_blocks blocks compute the entries (they
+// are latency-bound searches, dispatched first so that they overlap the
+// gather).
 // With fixed walls in place a boundary particle keeps its sorted position: both
 // buffers of x, u, um and id already hold its values there (the two steps
 // before gathered every particle, and a fixed wall's position and zero
 // velocity never change), so only the densities (which the update changed)
-// are copied and the view rewritten (u = 0: no boundary particle has moved,
-// or the sort would have ranked every particle).
+// are copied and the view's density-dependent part rewritten (mixed: the
+// offsets and zero velocity stay from the step before, at the same position;
+// FP64: the whole view, u = 0).  reorder_one: position k, with its key's
+// cell and its instance.
 template <bool kMixed, bool kGamma7>
-__global__ void k_reorder(ReorderArgs a) {
-    if (blockIdx.x >= a.table_block0) {
-        const int64_t c = (int64_t)(blockIdx.x - a.table_block0) * blockDim.x + threadIdx.x;
-        if (c <= a.nkeys) cell_table_entry(a.keys, a.n, c, a.start);
-        return;
-    }
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n) return;
-    const uint32_t key = key_cell(a.keys[k]);
-    const Inst ip = a.I.get(a.I.of_cell(key_row_cell(key)));
+__device__ __forceinline__ void reorder_one(const ReorderArgs &a, int64_t k, uint32_t key,
+                                            const Inst &ip) {
     uint32_t off = key - 2u * ip.cell_base;  // half cells + lrow nx + cx
     const bool bhalf = off >= inst_cells(ip);
     if (bhalf) off -= inst_cells(ip);
@@ -563,20 +560,17 @@ __global__ void k_reorder(ReorderArgs a) {
     const int cy = (int)(lrow % (uint32_t)ip.ny);
     const int cz = (int)(lrow / (uint32_t)ip.ny);
     if (bhalf && a.wip.on()) {
-        const double x = a.x[k], y = a.y[k], z = a.z[k];
         if constexpr (kMixed) {
+            // the view's offsets and (zero) velocity are those of the step
+            // before; the update also wrote both density levels to the
+            // destination buffers
             const float dr = static_cast<const float *>(a.rho)[k];
-            static_cast<float *>(a.rho2)[k] = dr;
-            static_cast<float *>(a.rhom2)[k] = static_cast<const float *>(a.rhom)[k];
             double P, cs;
             mixed_eos<kGamma7>(ip, dr, P, cs);
             const double inv = 1.0 / (ip.rho0 + (double)dr);
-            static_cast<float4 *>(a.v0)[k] =
-                make_float4(cell_offset(x, ip.ox, cx, ip.cs), cell_offset(y, ip.oy, cy, ip.cs),
-                            cell_offset(z, ip.oz, cz, ip.cs), dr);
-            static_cast<float4 *>(a.v1)[k] = make_float4(0.f, 0.f, 0.f, (float)P);
-            static_cast<float2 *>(a.v2)[k] = make_float2((float)inv, -(float)cs);
+            static_cast<float4 *>(a.v2)[k] = make_float4(dr, (float)P, (float)inv, -(float)cs);
         } else {
+            const double x = a.x[k], y = a.y[k], z = a.z[k];
             const double rho = static_cast<const double *>(a.rho)[k];
             static_cast<double *>(a.rho2)[k] = rho;
             static_cast<double *>(a.rhom2)[k] = static_cast<const double *>(a.rhom)[k];
@@ -611,13 +605,12 @@ __global__ void k_reorder(ReorderArgs a) {
         double P, cs;
         mixed_eos<kGamma7>(ip, dr, P, cs);
         const double inv = 1.0 / (ip.rho0 + (double)dr);
-        float4 v0 = make_float4(cell_offset(x, ip.ox, cx, ip.cs), cell_offset(y, ip.oy, cy, ip.cs),
-                                cell_offset(z, ip.oz, cz, ip.cs), dr);
-        float4 v1 = make_float4((float)ux, (float)uy, (float)uz, (float)P);
-        float2 v2 = make_float2((float)inv, bnd ? -(float)cs : (float)cs);
-        static_cast<float4 *>(a.v0)[k] = v0;
-        static_cast<float4 *>(a.v1)[k] = v1;
-        static_cast<float2 *>(a.v2)[k] = v2;
+        static_cast<float4 *>(a.v0)[k] =
+            make_float4(cell_offset(x, ip.ox, cx, ip.cs), cell_offset(y, ip.oy, cy, ip.cs),
+                        cell_offset(z, ip.oz, cz, ip.cs), (float)ux);
+        static_cast<float2 *>(a.v1)[k] = make_float2((float)uy, (float)uz);
+        static_cast<float4 *>(a.v2)[k] =
+            make_float4(dr, (float)P, (float)inv, bnd ? -(float)cs : (float)cs);
     } else {
         const double rho = static_cast<const double *>(a.rho)[src];
         static_cast<double *>(a.rho2)[k] = rho;
@@ -632,6 +625,19 @@ __global__ void k_reorder(ReorderArgs a) {
         static_cast<double4 *>(a.v1)[k] = v1;
         static_cast<double2 *>(a.v2)[k] = v2;
     }
+}
+
+template <bool kMixed, bool kGamma7>
+__global__ void k_reorder(ReorderArgs a) {
+    if (blockIdx.x < a.table_blocks) {
+        const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (c <= a.nkeys) cell_table_entry(a.keys, a.n, c, a.start);
+        return;
+    }
+    int64_t k = (int64_t)(blockIdx.x - a.table_blocks) * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const uint32_t key = key_cell(a.keys[k]);
+    reorder_one<kMixed, kGamma7>(a, k, key, a.I.get(a.I.of_cell(key_row_cell(key))));
 }
 
 int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *keys,
@@ -654,10 +660,10 @@ int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *
     a.I = insts_of(P, w);
     a.start = w.cell_start();
     a.nkeys = 2 * w.L.ncells;
-    a.table_block0 = (uint32_t)((s.n + 255) / 256);
+    a.table_blocks = (uint32_t)((a.nkeys + 1 + 255) / 256);
     a.wip.walls = &w.scalars()->walls_move;
     a.wip.allow = walls_in_place && walls_in_place_enabled(P) ? 1 : 0;
-    const int blocks = (int)(a.table_block0 + (a.nkeys + 1 + 255) / 256);
+    const int blocks = (int)(a.table_blocks + (s.n + 255) / 256);
     bool g7 = true;
     for (const Inst &ip : P.host) g7 = g7 && ip.gamma == 7.0;
     if (P.precision == SPH_MIXED && g7)
@@ -759,8 +765,10 @@ __device__ __forceinline__ uint32_t half_row_chunks(const uint32_t *__restrict__
 __global__ __launch_bounds__(256) void k_row_counts(const uint32_t *__restrict__ start, Insts I,
                                                     int64_t nhalf, uint32_t csz,
                                                     uint32_t *__restrict__ cnt, DevScalars *sc,
-                                                    InstState *ist, int lagged, double dt_arg) {
+                                                    InstState *ist, int lagged, double dt_arg,
+                                                    uint32_t *__restrict__ zero, int64_t nzero) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < nzero) zero[g] = 0u;  // digit counts the fused interaction adds to
     if (g == 0 && lagged) sc->steps += 1;
     constexpr unsigned long long kInf = 0x7ff0000000000000ull;
     if (g < I.n) {
@@ -834,14 +842,18 @@ __global__ __launch_bounds__(256) void k_row_chunks(const uint32_t *__restrict__
     if (r == nhalf - 1 && lane == 0) sc->nchunks = f + nch;
 }
 
-int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStream_t st) {
+int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStream_t st,
+                  bool zero_hist) {
     const int64_t nhalf = 2 * w.L.nrows;
-    const int64_t threads = std::max<int64_t>(nhalf * kWave, (int64_t)P.host.size());
+    const int64_t nzero = zero_hist ? (int64_t)kRadix * w.L.ntiles : 0;
+    const int64_t threads =
+        std::max<int64_t>(std::max<int64_t>(nhalf * kWave, (int64_t)P.host.size()), nzero);
     const int blocks = (int)((threads + 255) / 256);
     const Insts I = insts_of(P, w);
     const uint32_t csz = (uint32_t)chunk_for(P);
     hipLaunchKernelGGL(k_row_counts, dim3(blocks), dim3(256), 0, st, w.cell_start(), I, nhalf,
-                       csz, w.row_cnt(), w.scalars(), w.inst_state(), (int)lagged, dt);
+                       csz, w.row_cnt(), w.scalars(), w.inst_state(), (int)lagged, dt, w.hist(),
+                       nzero);
     if (int rc = launch_check("chunk counts")) return rc;
     const dim3 grid((unsigned)((nhalf * kWave + 255) / 256));
     if (nhalf <= kRowScanMax) {

@@ -185,7 +185,10 @@ __host__ __device__ __forceinline__ uint32_t key_row_cell(uint32_t key) { return
 // consecutive particles are compact (about 1.4 x 1.3 x 1.3 spacings on the
 // lattice instead of 3.3 x 1.6 x 0.2): more of a group's evaluated pairs lie
 // inside the support.  Steps between refreshes sort on the cell key alone
-// (stable, so the cells keep the order of the last full sort).
+// (stable, so the cells keep the order of the last full sort).  Boundary
+// particles take zeros there: a refresh never reorders them within a cell,
+// so a fixed wall's particles keep their sorted positions through refreshes
+// too (their groups only compute continuity, where compactness matters little).
 constexpr int kSubBits = 2;
 __host__ __device__ __forceinline__ uint32_t key_cell(uint32_t key) { return key >> kSubBits; }
 
@@ -214,8 +217,9 @@ __device__ __forceinline__ uint32_t sort_key(const Inst &ip, double x, double y,
     const int cy = axis_cell(y, ip.oy, ip.cs, ip.ny, uy);
     const int cz = axis_cell(z, ip.oz, ip.cs, ip.nz, uz);
     const uint32_t lrow = (uint32_t)cz * (uint32_t)ip.ny + (uint32_t)cy;
-    const uint32_t cell = half_row_key(ip, lrow, id >> 31) + (uint32_t)cx;
-    return (cell << kSubBits) | (uy << 1) | ux;
+    const uint32_t bnd = id >> 31;
+    const uint32_t cell = half_row_key(ip, lrow, bnd) + (uint32_t)cx;
+    return (cell << kSubBits) | (bnd ? 0u : (uy << 1) | ux);
 }
 
 // Device-side access to the instances: a table in the workspace (batches) or
@@ -260,7 +264,8 @@ struct Insts {
 // (they follow all of the instance's fluid particles in key order, and their
 // keys do not change), so the sort gives them the identity permutation and a
 // step's gather may leave them where they are: it copies only what the
-// update changed (the densities) and rewrites their view.
+// update changed (the densities) and rewrites the density-dependent part of
+// their view.
 struct WallsInPlace {
     const unsigned int *walls;  // DevScalars::walls_move
     int allow;                  // the host allows it for this step
@@ -311,7 +316,7 @@ struct WsLayout {
     size_t loads = 0;        // boundary-force partial sums: 4 doubles per cell row
     size_t impulse = 0;      // ImpulseState, then 2 x kMaxProbes doubles
     size_t total = 0;
-    size_t view_elem = 0;    // bytes of one view record (first two arrays)
+    size_t view_elem = 0;    // bytes of one view record in the first array
     size_t rate_elem = 0;    // bytes of one rate value
 };
 
@@ -373,16 +378,23 @@ int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *
                    const uint32_t *perm, bool walls_in_place, hipStream_t st);
 // steps of P may leave fixed walls in place (scheme and tuning)
 bool walls_in_place_enabled(const Problem &P);
-// lagged: also fix this step's dt from the previous interaction's bound (or dt > 0)
-int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStream_t st);
+// lagged: also fix this step's dt from the previous interaction's bound (or dt > 0);
+// zero_hist: also clear the sort's digit counts (w.hist())
+int launch_chunks(const Problem &P, const Ws &w, bool lagged, double dt, hipStream_t st,
+                  bool zero_hist = false);
 // fuse: the interaction also advances every target (time update of step
 // `step`) with the dt already stored per instance, instead of storing rates.
 // after_kernel (optional): recorded between the interaction kernel and the
 // per-instance reduction of its chunk records.
+// count_shift >= 0 (fused, where fused_counts_digits): the update also adds
+// the next sort's first-pass digit counts (from that bit) to w.hist(), which
+// launch_chunks(zero_hist) cleared.
 int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st,
                     int32_t *st_nf = nullptr, int32_t *st_nb = nullptr,
                     uint32_t *st_hash = nullptr, bool fuse = false, int64_t step = 0,
-                    hipEvent_t after_kernel = nullptr);
+                    hipEvent_t after_kernel = nullptr, int count_shift = -1);
+// the fused interaction launched for P can also count the next sort's digits
+bool fused_counts_digits(const Problem &P);
 int launch_export_rates(const Problem &P, const Ws &w, double *ax, double *ay, double *az,
                         double *drho, double *mumax, hipStream_t st);
 // hist_shift >= 0: the update also counts the digits (from that bit) of the

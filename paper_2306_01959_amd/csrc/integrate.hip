@@ -114,7 +114,7 @@ int launch_integrate(const Problem &P, sph_state &s, const Ws &w, double dt, int
     a.n = s.n;
     a.state = StateArrays{s.x,   s.y,   s.z,   s.ux,  s.uy,   s.uz,  s.uxm,
                           s.uym, s.uzm, s.rho, s.rhom, s.id, w.keys_next(),
-                          &w.scalars()->walls_move};
+                          &w.scalars()->walls_move, s.rho_alt, s.rhom_alt};
     a.rates = w.base + w.L.rates;
     a.I = insts_of(P, w);
     a.sc = w.scalars();

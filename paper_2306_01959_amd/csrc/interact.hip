@@ -64,7 +64,26 @@ struct InteractArgs {
     StateArrays state;           // fused update: the state to advance
     long long step;              // fused update: step index (selects the Euler reset)
     uint32_t xcd_run;            // chunks per XCD run (1: workgroups in chunk order)
+    // fused update that writes the next sort's keys: with hist, also the
+    // digit counts (from bit hist_shift) of its first pass per sort tile
+    // (tiles of 2^tile_log2 positions; the counts start at zero)
+    uint32_t *hist;
+    int hist_shift, ntiles, tile_log2;
 };
+
+// Adds the keys of a wave's targets (one per lane, consecutive positions
+// `it`) to the next sort's first-pass digit counts: equal (digit, tile) come
+// in runs of consecutive lanes (nearly sorted keys), one atomic per run.  All
+// lanes of the wave call it.
+__device__ __forceinline__ void count_next_digit(const InteractArgs &a, bool act, int it,
+                                                 uint32_t key) {
+    const uint32_t slot =
+        act ? ((key >> a.hist_shift) & (kRadix - 1)) * (uint32_t)a.ntiles +
+                  ((uint32_t)it >> a.tile_log2)
+            : 0xffffffffu;
+    const uint64_t starts = run_starts(slot);
+    if (act && ((starts >> __lane_id()) & 1ull)) atomicAdd(&a.hist[slot], run_length(starts));
+}
 
 __device__ __forceinline__ float sq_sum_f32(float dx, float dy, float dz) {
 #pragma clang fp contract(off)
@@ -195,9 +214,12 @@ struct Mixed {
         float4 a, b, c;
         __device__ bool fluid() const { return c.x > 0.f; }
     };
+    // view: v0 {o_x, o_y, o_z, u_x}, v1 {u_y, u_z}, v2 {rho - rho0, P, 1/rho,
+    // +-c}; only v2 changes for a fixed wall's particle
     struct Cand {
-        float4 v0, v1;
-        float2 v2;
+        float4 v0;
+        float2 v1;
+        float4 v2;
         uint32_t key;  // global cell (raw: nothing is computed from a load
                        // before it is needed, so the next batch's loads stay
                        // in flight while the current batch is processed)
@@ -208,19 +230,19 @@ struct Mixed {
                                   bool &fi) {
         // an absent target sits far away (+1e15 m): no record is within its
         // support, not even a sentinel (which sits at -1e15 m)
-        float4 v0 = make_float4(1e15f, 1e15f, 1e15f, 0.f), v1 = make_float4(0.f, 0.f, 0.f, 0.f);
-        float2 v2 = make_float2(1.f, 1.f);
+        float4 v0 = make_float4(1e15f, 1e15f, 1e15f, 0.f), v2 = make_float4(0.f, 0.f, 1.f, 1.f);
+        float2 v1 = make_float2(0.f, 0.f);
         int cix = cxa;
         if (act) {
             v0 = static_cast<const float4 *>(a.v0)[i];
-            v1 = static_cast<const float4 *>(a.v1)[i];
-            v2 = static_cast<const float2 *>(a.v2)[i];
+            v1 = static_cast<const float2 *>(a.v1)[i];
+            v2 = static_cast<const float4 *>(a.v2)[i];
             cix = (int)key_cell(a.keys[i]) - rowbase;
         }
-        fi = act && v2.y > 0.f;
+        fi = act && v2.w > 0.f;
         t0 = make_float4(v0.x, v0.y, v0.z, (float)cix);
-        t1 = v1;
-        t2 = make_float4(fi ? v2.x : 0.f, v0.w, -(float)(ip.alpha * ip.h) * fabsf(v2.y), 0.f);
+        t1 = make_float4(v0.w, v1.x, v1.y, v2.y);
+        t2 = make_float4(fi ? v2.z : 0.f, v2.x, -(float)(ip.alpha * ip.h) * fabsf(v2.w), 0.f);
         const float csf = (float)ip.cs;
         bx = v0.x + (float)(cix - cxa) * csf;
         by = v0.y;
@@ -233,8 +255,8 @@ struct Mixed {
         c.ok = j < je;
         const int jj = c.ok ? j : 0;
         c.v0 = static_cast<const float4 *>(a.v0)[jj];
-        c.v1 = static_cast<const float4 *>(a.v1)[jj];
-        c.v2 = static_cast<const float2 *>(a.v2)[jj];
+        c.v1 = static_cast<const float2 *>(a.v1)[jj];
+        c.v2 = static_cast<const float4 *>(a.v2)[jj];
         c.key = key_cell(a.keys[jj]);
     }
     // position of a candidate in the chunk frame (cell cxa of the chunk's
@@ -252,7 +274,7 @@ struct Mixed {
         qy = r0.z;
         qz = r0.w;
     }
-    __device__ static bool cand_fluid(const Cand &c) { return c.v2.y > 0.f; }
+    __device__ static bool cand_fluid(const Cand &c) { return c.v2.w > 0.f; }
     __device__ static bool rec_fluid(const float4 &r3) { return r3.y > 0.f; }
     // a record that lies outside every target's support (at -1e15 m; every
     // term stays finite and is zeroed through F)
@@ -271,15 +293,15 @@ struct Mixed {
                                  int j, int dy, int dz, float4 *rec0, float4 *rec1, float4 *rec2,
                                  float4 *rec3) {
         const float csf = (float)ip.cs;
-        const float invr = c.v2.x;
-        const bool fj = c.v2.y > 0.f;
+        const float invr = c.v2.z;
+        const bool fj = c.v2.w > 0.f;
         const float kd = (fj || ip.delta_all) ? (float)ip.kdelta : 0.f;
         const float B = kd * invr;
         *rec0 = make_float4(c.v0.x, (float)((int)c.key - nbase), c.v0.y + (float)dy * csf,
                             c.v0.z + (float)dz * csf);
-        *rec1 = make_float4(c.v1.x, c.v1.y, c.v1.z, c.v1.w * invr);
-        *rec2 = make_float4(c.v0.w, invr, c.v0.w * B, B);
-        *rec3 = make_float4(-(float)(ip.alpha * ip.h) * fabsf(c.v2.y), c.v2.y, __int_as_float(j), 0.f);
+        *rec1 = make_float4(c.v0.w, c.v1.x, c.v1.y, c.v2.y * invr);
+        *rec2 = make_float4(c.v2.x, invr, c.v2.x * B, B);
+        *rec3 = make_float4(-(float)(ip.alpha * ip.h) * fabsf(c.v2.w), c.v2.w, __int_as_float(j), 0.f);
     }
     // one (target, record) pair; `valid` is false for idle lanes; kCls: the
     // class of every target (kAnyTargets: read per target)
@@ -1039,6 +1061,7 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
         }
     }
     double bound = __longlong_as_double(0x7ff0000000000000ll);
+    uint32_t nkey = 0;
     if (act) {
         double fax, fay, faz;
         P::store(a, ip, it, fi_own, sx, sy, sz, sd, sm, !kFuse, bound, fax, fay, faz);
@@ -1054,8 +1077,12 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
             const double dt = a.ist[inst].dt_last;
             const bool euler =
                 a.step == 0 || (ip.verlet_ns > 0 && a.step % ip.verlet_ns == 0);
-            wcsph::advance<P::kMixed, kFusedKeys<P, kT>>(a.state, ip, it, dt, euler, fax, fay, faz, (double)sd);
+            nkey = wcsph::advance<P::kMixed, kFusedKeys<P, kT>>(a.state, ip, it, dt, euler, fax,
+                                                                fay, faz, (double)sd);
         }
+    }
+    if constexpr (kFuse && kFusedKeys<P, kT>) {
+        if (a.hist) count_next_digit(a, act, it, nkey);
     }
     bound = group_min(bound, kWave);
     // each fluid target met itself once (in the stencil row of its own cell)
@@ -1666,6 +1693,11 @@ bool fused_writes_keys(const Problem &P) {
     return k == SPH_KERNEL_GROUPS || (k == SPH_KERNEL_ROWS && group_for(P) >= 16);
 }
 
+bool fused_counts_digits(const Problem &P) {
+    // the row-split kernel with kFusedKeys (one target per lane of wave 0)
+    return P.precision == SPH_MIXED && kernel_for(P) == SPH_KERNEL_ROWS && group_for(P) >= 16;
+}
+
 int chunk_for(const Problem &P) {
     const int k = kernel_for(P);
     if (k == SPH_KERNEL_GROUPS) return group_for(P);
@@ -1817,9 +1849,15 @@ static void launch_prec(int kernel, int split, int group, uint32_t nb, bool stat
 
 int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream_t st,
                     int32_t *st_nf, int32_t *st_nb, uint32_t *st_hash, bool fuse,
-                    int64_t step, hipEvent_t after_kernel) {
+                    int64_t step, hipEvent_t after_kernel, int count_shift) {
     InteractArgs a;
     a.xcd_run = (uint32_t)xcd_run_for(P);
+    const bool count = fuse && count_shift >= 0 && st_nf == nullptr && fused_counts_digits(P);
+    a.hist = count ? w.hist() : nullptr;
+    a.hist_shift = count_shift;
+    a.ntiles = (int)w.L.ntiles;
+    a.tile_log2 = 0;
+    while (((int64_t)1 << a.tile_log2) < sort_tile(s.n)) ++a.tile_log2;
     a.chunks = w.chunks();
     a.sc = w.scalars();
     a.ist = w.inst_state();
@@ -1844,7 +1882,7 @@ int launch_interact(const Problem &P, const sph_state &s, const Ws &w, hipStream
     a.st_hash = st_hash;
     a.state = StateArrays{s.x,   s.y,   s.z,   s.ux,   s.uy,  s.uz,
                           s.uxm, s.uym, s.uzm, s.rho,  s.rhom, s.id, w.keys_next(),
-                          &w.scalars()->walls_move};
+                          &w.scalars()->walls_move, s.rho_alt, s.rhom_alt};
     a.step = step;
     const bool stats = st_nf != nullptr;
     // chunks of <= csz targets: at most ceil(particles / csz) + 1 per half-row

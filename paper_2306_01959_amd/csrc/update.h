@@ -29,6 +29,10 @@ struct StateArrays {
     uint32_t *keys_next;  // or null
     unsigned int *walls_move;  // DevScalars::walls_move: set when a boundary
                                // particle has a nonzero velocity
+    // the other buffers of rho and rhom (the next gather's destinations), or
+    // null: a boundary particle's two levels are also written there, so a
+    // gather that leaves fixed walls in place need not copy them
+    void *rho_alt, *rhom_alt;
 };
 
 // Returns the key written (0 without kKeys).
@@ -37,20 +41,32 @@ __device__ __forceinline__ uint32_t advance(const StateArrays &s, const Inst &ip
                                             double dt, bool euler, double ax, double ay,
                                             double az, double dr) {
     const double w = euler ? dt : 2.0 * dt;
+    const uint32_t id = s.id[i];
+    const bool bnd = (id >> 31) != 0;
     if constexpr (kMixed) {
-        const double cur = (double)static_cast<const float *>(s.rho)[i];
+        const float curf = static_cast<const float *>(s.rho)[i];
+        const double cur = (double)curf;
         float *pm = static_cast<float *>(s.rhom);
         const double base = euler ? cur : (double)pm[i];
-        pm[i] = (float)(base + w * dr);
+        const float nxt = (float)(base + w * dr);
+        pm[i] = nxt;
+        if (bnd && s.rho_alt) {  // after the level swap: rho = new, rhom = current
+            static_cast<float *>(s.rho_alt)[i] = nxt;
+            static_cast<float *>(s.rhom_alt)[i] = curf;
+        }
     } else {
         const double cur = static_cast<const double *>(s.rho)[i];
         double *pm = static_cast<double *>(s.rhom);
         const double base = euler ? cur : pm[i];
-        pm[i] = base + w * dr;
+        const double nxt = base + w * dr;
+        pm[i] = nxt;
+        if (bnd && s.rho_alt) {
+            static_cast<double *>(s.rho_alt)[i] = nxt;
+            static_cast<double *>(s.rhom_alt)[i] = cur;
+        }
     }
     const double ux = s.ux[i], uy = s.uy[i], uz = s.uz[i];
-    const uint32_t id = s.id[i];
-    if ((id >> 31) != 0) {
+    if (bnd) {
         // boundary: keeps its velocity (zero for a fixed wall, the prescribed
         // one of a moving gate) and moves with it.  Any nonzero bit (-0 too)
         // marks a moving wall: later steps then sort and gather every particle.

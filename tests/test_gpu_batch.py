@@ -173,8 +173,8 @@ def test_batch_lagged_mixed_fixed_dt_vs_oracle(gpu, oracle_lib, scenes):
 
 @pytest.mark.parametrize("mode", ["lagged", "plain"])
 def test_graph_replay_equals_eager(gpu, scenes, mode):
-    """100 steps: 40 eager, then one 40-step graph replayed, then 20 eager;
-    bit-identical to 100 eager steps."""
+    """100 steps: 2 eager, then a 40-step graph replayed twice, then 18
+    eager; bit-identical to 100 eager steps."""
     import torch
     base = gpu.RUN_LAGGED if mode == "lagged" else 0
     a = gpu.Ensemble(scenes, "mixed")

@@ -146,7 +146,8 @@ def test_ensemble_fullsize_rates(gpu, oracle_lib, ensemble_scenes):
 
 def test_ensemble_fullsize_graph_equals_eager(gpu, ensemble_scenes):
     """80 steps of the benchmark's ensemble form (lagged dt, fused update):
-    40 eager, then one 40-step graph replayed once, against 80 eager steps."""
+    2 eager, then a 40-step graph replayed once, then 38 eager, against 80
+    eager steps."""
     import torch
     a = gpu.Ensemble(ensemble_scenes, "mixed")
     a.run(80, -1.0, 0, mode=gpu.RUN_LAGGED)

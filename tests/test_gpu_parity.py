@@ -50,7 +50,8 @@ def _sim(gpu, sc, precision, prev=None, **kw):
 
 def _sort_keys(sc_or_xyz, prm, isb, full):
     """The library's sort key from FP64 positions: class, cell row, cell x,
-    then (full) the upper-half flags along y and x."""
+    then (full) the upper-half flags along y and x (zero for boundary
+    particles)."""
     x, y, z = sc_or_xyz
     (cx, cy, cz), _ = bruteforce.cells_and_offsets(x, y, z, prm["origin"], prm["cell_size"],
                                                    prm["dims"])
@@ -60,7 +61,7 @@ def _sort_keys(sc_or_xyz, prm, isb, full):
         return key
     ux = bruteforce.upper_half(x, prm["origin"][0], prm["cell_size"], prm["dims"][0])
     uy = bruteforce.upper_half(y, prm["origin"][1], prm["cell_size"], prm["dims"][1])
-    return key * 4 + uy * 2 + ux
+    return key * 4 + np.where(isb, 0, uy * 2 + ux)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
