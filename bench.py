@@ -229,14 +229,16 @@ CELL_TABLE_BYTES = 4
 # The bytes this design moves (design overhead over the algorithmic ones):
 SORT_BYTES_FIRST = 44   # pass 0: histogram reads x, y, z, id and writes the key; scatter
                         # reads the key, writes key + index
+SORT_BYTES_FIRST_COUNTED = 12  # pass 0 when the previous (fused row-split) step wrote
+                               # the keys and counted their digits: scatter only
 SORT_BYTES_FIRST_KEYS = 16  # pass 0 when the previous (fused) step wrote the keys:
                             # histogram reads the key; scatter as above
 SORT_BYTES_PASS = 20    # later passes: + the index read
 REORDER_BYTES = 4 + 4 + 84 + 84 + 40  # perm + key in, state gathered (84 B) and written,
                                       # interaction view written (40 B)
-REORDER_BYTES_WALL = 4 + 8 + 8 + 16  # a fixed wall's particle left in place (mixed):
-                                     # key and both densities in, both densities and the
-                                     # view's density part out
+REORDER_BYTES_WALL = 4 + 4 + 16  # a fixed wall's particle left in place (mixed): key
+                                 # and density in, the view's density part out (the
+                                 # update wrote both levels to the destination)
 TABLE_BYTES = 4 + 4 + 4  # per cell-table entry (same launch as the reorder): its previous
                          # value read as the search hint, one key probed, the entry written
 
@@ -299,7 +301,9 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False, scene
     # fixed (mixed: wave per group, or row split with groups of 16 or more);
     # the sampled steps follow a fused step
     keys_written = shape[0] == 2 or (shape[0] == 1 and shape[2] >= 16)
-    first = SORT_BYTES_FIRST_KEYS if keys_written else SORT_BYTES_FIRST
+    counted = shape[0] == 1 and shape[2] >= 16   # the row-split kernel also counts
+    first = (SORT_BYTES_FIRST_COUNTED if counted else
+             SORT_BYTES_FIRST_KEYS if keys_written else SORT_BYTES_FIRST)
     sort_bytes = n * (first + SORT_BYTES_PASS * (passes - 1))
     cells = sum(int(np.prod(s.params["dims"])) for s in scenes)
     n_wall = sum(int(s.is_boundary.sum()) for s in scenes)
@@ -337,7 +341,8 @@ def time_ensemble(steps, hip, n_inst=64, seed=4, graph=True, retune=False, scene
         # each launch sequence against the bytes this design moves
         "sort": dict(bw(sort_bytes, kern["sort"]), passes=passes, key_bits=key_bits,
                      bytes_model="design bytes",
-                     first_pass_keys="written by the fused update" if keys_written
+                     first_pass_keys=("written and counted by the fused update" if counted
+                                      else "written by the fused update") if keys_written
                      else "computed from the positions"),
         "reorder": dict(bw(reorder_bytes, kern["reorder"]), bytes_model="design bytes",
                         wall_particles=n_wall,
