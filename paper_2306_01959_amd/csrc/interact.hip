@@ -85,12 +85,11 @@ __device__ __forceinline__ void count_next_digit(const InteractArgs &a, bool act
     if (act && ((starts >> __lane_id()) & 1ull)) atomicAdd(&a.hist[slot], run_length(starts));
 }
 
+// r^2 of the mixed path's neighbour predicate: fma(dz, dz, fma(dy, dy, dx dx)),
+// each operation rounded once (three instructions; the FP32 brute force of
+// the tests takes the same steps)
 __device__ __forceinline__ float sq_sum_f32(float dx, float dy, float dz) {
-#pragma clang fp contract(off)
-    float a = dx * dx;
-    float b = dy * dy;
-    float c = dz * dz;
-    return (a + b) + c;
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
 __device__ __forceinline__ double sq_sum_f64(double dx, double dy, double dz) {

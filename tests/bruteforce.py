@@ -9,15 +9,40 @@ Two predicates, each the plain definition of "j is a neighbour of i"
   cell coordinate c (floor((x - origin)/cs), clamped to the grid) and an FP32
   offset o from that cell's centre, computed in float64 and rounded once.  The
   displacement is d = fl32(fl32(o_j + (c_j - c_i) cs32) - o_i) per axis and
-  r^2 = fl32(fl32(fl32(dx^2) + fl32(dy^2)) + fl32(dz^2)), compared with
-  fl32(4h^2).  This is the decision the mixed-precision path takes, so the two
-  sets are compared bit-exactly.
+  r^2 = fma32(dz, dz, fma32(dy, dy, fl32(dx^2))) with fma32 a fused
+  multiply-add rounded once to FP32, compared with fl32(4h^2).  This is the
+  decision the mixed-precision path takes, so the two sets are compared
+  bit-exactly.
 """
 from __future__ import annotations
 
 from typing import Sequence, Set, Tuple
 
 import numpy as np
+
+
+def fma32(a, b, c) -> np.ndarray:
+    """a * b + c for float32 arrays, rounded once to float32 (to nearest,
+    ties to even).  The product is exact in float64; the float64 sum s and its
+    exact error e (Knuth's two-sum) give the exact value s + e, and rounding s
+    to float32 is already correct unless s lies exactly halfway between two
+    float32 values with e != 0, where e decides the side."""
+    a, b, c = (np.asarray(v, np.float32) for v in (a, b, c))
+    p = a.astype(np.float64) * b.astype(np.float64)
+    c64 = c.astype(np.float64)
+    s = p + c64
+    bb = s - p
+    e = (p - (s - bb)) + (c64 - bb)
+    r = s.astype(np.float32)
+    rd = r.astype(np.float64)
+    # the float32 neighbour of r on s's side, and the midpoint between them
+    other = np.nextafter(r, np.where(s > rd, np.float32(np.inf), np.float32(-np.inf)))
+    mid = (rd + other.astype(np.float64)) * 0.5
+    fix = (s != rd) & (s == mid) & (e != 0)
+    up = e > 0          # the exact value lies above the midpoint
+    hi = np.maximum(r, other)
+    lo = np.minimum(r, other)
+    return np.where(fix, np.where(up, hi, lo), r).astype(np.float32)
 
 
 def pairs_fp64(x, y, z, h: float) -> Set[Tuple[int, int]]:
@@ -73,7 +98,7 @@ def pairs_mixed(x, y, z, h: float, origin, cs: float, dims, stencil: bool = Fals
         shifted = (o[None, :].astype(np.float64) + dc * cs32).astype(np.float32)
         d.append(shifted - o[:, None])            # float32 - float32
     dx, dy, dz = d
-    r2 = (dx * dx + dy * dy) + dz * dz             # all float32
+    r2 = fma32(dz, dz, fma32(dy, dy, dx * dx))     # all float32
     assert r2.dtype == np.float32
     ok = r2 < np.float32(4.0 * h * h)
     near = ((np.abs(cx[None, :] - cx[:, None]) <= 1)
