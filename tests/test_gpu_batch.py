@@ -217,3 +217,41 @@ def test_lagged_step_without_bound_is_flagged(gpu, scenes):
     dg = ens.diagnostics()
     assert dg[0]["flags"] & gpu.FLAG_DT_CFL
     assert dg[0]["dt_last"] == 0.0
+
+
+def test_fused_step_counts_feed_the_sort(gpu):
+    """The lagged fused row-split interaction (groups of 16) writes the next
+    sort's keys and counts their first digits per sort tile, so the sort after
+    it launches no histogram of its own.  That sort's order must be the stable
+    sort, by cell key, of the positions the fused step left, in the order
+    before it: each instance's fluid then its boundary particles, cell row by
+    cell row, cell x by cell x (step 5 is no refresh: no sub-cell bits)."""
+    from tests import bruteforce
+    scenes = scene.ensemble(6, master_seed=31, dps=(0.02, 0.015))
+    gpu.set_tuning(kernel_mixed=1, split_mixed=1, group_mixed=16)
+    try:
+        a = gpu.Ensemble(scenes, "mixed")
+        a.run(5, -1.0, 0, mode=gpu.RUN_LAGGED)   # steps 1..4 fused
+        ids_a = a.ids()
+        x = a._cur("x").cpu().numpy()
+        y = a._cur("y").cpu().numpy()
+        z = a._cur("z").cpu().numpy()
+        b = gpu.Ensemble(scenes, "mixed")
+        b.run(6, -1.0, 0, mode=gpu.RUN_LAGGED)   # step 5 sorts what step 4 counted
+        ids_b = b.ids()
+    finally:
+        gpu.set_tuning()
+    counts = np.array([s.n for s in scenes])
+    offsets = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    inst = np.searchsorted(offsets, ids_a, side="right") - 1
+    isb = np.concatenate([s.is_boundary for s in scenes])[ids_a]
+    key = np.zeros(ids_a.size, np.int64)
+    cell_base = 0
+    for k, s in enumerate(scenes):
+        m = inst == k
+        nx, ny, nz = s.params["dims"]
+        (cx, cy, cz), _ = bruteforce.cells_and_offsets(x[m], y[m], z[m], s.params["origin"],
+                                                       s.params["cell_size"], s.params["dims"])
+        key[m] = 2 * cell_base + isb[m] * (nx * ny * nz) + (cy + ny * cz) * nx + cx
+        cell_base += nx * ny * nz
+    assert np.array_equal(ids_b, ids_a[np.argsort(key, kind="stable")])
