@@ -138,14 +138,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t *__re
     for (int d = tid; d < kRadix; d += kSortThreads) hist[(int64_t)d * ntiles + tile] = h[d];
 }
 
-// Exclusive scan (the (digit, tile) counts, the chunks per half-row).  A
-// block of 1024 threads scans a span of kScanSpan values (4 consecutive
-// values per thread, wave prefix sums by shuffles, one LDS exchange of the
-// 16 wave totals).  Up to kScanRedundantSpans spans: one launch, block b
-// sums the input before its span itself.  Up to kScanSumSpans: span totals,
-// then block b sums the totals before it and scans its span.  Beyond: span
-// totals -> scan of the totals (one block) -> spans scanned with their
-// offsets, all spans in parallel.
+// Exclusive scans (per digit over the tiles for the sort, the chunks per
+// half-row).  A block of 1024 threads scans a span of kScanSpan values (4
+// consecutive values per thread, wave prefix sums by shuffles, one LDS
+// exchange of the 16 wave totals).  launch_scan: up to kScanRedundantSpans
+// spans, one launch, block b sums the input before its span itself; up to
+// kScanSumSpans, span totals, then block b sums the totals before it and
+// scans its span; beyond, span totals -> scan of the totals (one block) ->
+// spans scanned with their offsets, all spans in parallel.
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = __lane_id();
@@ -269,6 +269,22 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_spans_sum(const uint32_t 
     span_scan(in, out, m, (int64_t)blockIdx.x * kScanSpan, offset, wsum);
 }
 
+// The sort's (digit, tile) counts, digit-major: block d scans digit d's row
+// of ntiles counts (its tiles in order, a span at a time) and writes the
+// row's total.  The scatter adds the totals of the digits below its own, so
+// one launch serves any number of tiles.
+__global__ __launch_bounds__(kScanThreads) void k_scan_rows(const uint32_t *__restrict__ in,
+                                                            uint32_t *__restrict__ out,
+                                                            int64_t ntiles,
+                                                            uint32_t *__restrict__ tot) {
+    __shared__ uint32_t wsum[kScanThreads / kWave + 1];
+    const int64_t row = (int64_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < ntiles; base += kScanSpan)
+        carry += span_scan(in + row, out + row, ntiles, base, carry, wsum);
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
 int launch_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tot, hipStream_t st) {
     const int64_t spans = (m + kScanSpan - 1) / kScanSpan;
     if (spans <= kScanRedundantSpans) {
@@ -293,17 +309,19 @@ int launch_scan(const uint32_t *in, uint32_t *out, int64_t m, uint32_t *tot, hip
 // [w 64 kItems, (w + 1) 64 kItems) (input order = wave, item, lane), loads
 // them all up front, and ranks them item by item against a per-wave digit
 // count in LDS that only this wave touches (no workgroup barrier per item).
-// One barrier later the per-wave counts become start slots (the tile's
-// offset per digit from the scan, then the waves in order), and every key
-// goes to its slot + rank.
+// One barrier later the per-wave counts become start slots (per digit: the
+// keys of all smaller digits, plus its keys in the tiles before this one from
+// the row scan, then the waves in order), and every key goes to its slot +
+// rank.
 template <int kItems>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ hist,
-    int ntiles) {
+    const uint32_t *__restrict__ dtot, int ntiles) {
     constexpr int kWaves = kSortThreads / kWave;
     static_assert(kSortThreads == kRadix, "one thread per digit for the start slots");
     __shared__ uint32_t wcnt[kWaves][kRadix];  // per-wave counts, then start slots
+    __shared__ uint32_t wtot[kWaves];           // digit totals summed per wave
     const int tid = threadIdx.x;
     const int w = tid / kWave, lane = tid % kWave;
     for (int d = lane; d < kRadix; d += kWave) wcnt[w][d] = 0u;
@@ -347,10 +365,18 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
         if (ok && r == 0) wcnt[w][d] = before + cnt;
         wave_sync();
     }
+    // the keys of all smaller digits come first: an exclusive scan of the
+    // digit totals over the block (by waves, then the wave totals; loaded
+    // here, as a load issued before the keys' would delay their wait)
+    const uint32_t dt = dtot[tid];
+    const uint32_t dincl = wave_incl_scan(dt);
+    if (lane == kWave - 1) wtot[w] = dincl;
     __syncthreads();
     {
         const int d = tid;
-        uint32_t run = hist[(int64_t)d * ntiles + tile];
+        uint32_t run = hist[(int64_t)d * ntiles + tile] + (dincl - dt);
+#pragma unroll
+        for (int k = 0; k < kWaves - 1; ++k) run += k < w ? wtot[k] : 0u;
 #pragma unroll
         for (int k = 0; k < kWaves; ++k) {
             const uint32_t c = wcnt[k][d];
@@ -411,14 +437,16 @@ int launch_sort(const Problem &P, const sph_state &s, const Ws &w, hipStream_t s
                 hipLaunchKernelGGL((k_sort_hist<kSortItemsLarge, false>), dim3(ntiles),
                                    dim3(kSortThreads), 0, st, kin, n, shift, w.hist(), ntiles, e);
         }
-        if (int rc = launch_scan(w.hist(), w.hist_off(), (int64_t)kRadix * ntiles, w.scan_tot(), st))
-            return rc;
+        hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(kScanThreads), 0, st, w.hist(),
+                           w.hist_off(), (int64_t)ntiles, w.hist_tot());
         if (small)
             hipLaunchKernelGGL(k_sort_scatter<kSortItemsSmall>, dim3(ntiles), dim3(kSortThreads),
-                               0, st, kin, vin, kout, vout, n, shift, w.hist_off(), ntiles);
+                               0, st, kin, vin, kout, vout, n, shift, w.hist_off(), w.hist_tot(),
+                               ntiles);
         else
             hipLaunchKernelGGL(k_sort_scatter<kSortItemsLarge>, dim3(ntiles), dim3(kSortThreads),
-                               0, st, kin, vin, kout, vout, n, shift, w.hist_off(), ntiles);
+                               0, st, kin, vin, kout, vout, n, shift, w.hist_off(), w.hist_tot(),
+                               ntiles);
         if (int rc = launch_check("radix sort")) return rc;
         kin = kout;
         kout = kother;

@@ -300,7 +300,8 @@ struct WsLayout {
     size_t keys_next = 0;    // the next sort's input keys (written by the update)
     size_t sorted_keys = 0;  // where the sort leaves the keys (keys)
     size_t hist = 0;         // (digit, tile) counts of a sort pass
-    size_t hist_off = 0;     // their exclusive scan: first output slot per (digit, tile)
+    size_t hist_off = 0;     // per digit, exclusive scan of its counts over the tiles
+    size_t hist_tot = 0;     // per digit, its count over all tiles
     size_t scan_tot = 0;     // span totals of a scan (counts of the sort, chunks per row)
     size_t row_cnt = 0;      // chunks per row
     size_t row_first = 0;    // first chunk of each row
@@ -338,6 +339,7 @@ struct Ws {
     uint32_t *row_first() const { return at<uint32_t>(L.row_first); }
     uint32_t *row_cnt() const { return at<uint32_t>(L.row_cnt); }
     uint32_t *hist_off() const { return at<uint32_t>(L.hist_off); }
+    uint32_t *hist_tot() const { return at<uint32_t>(L.hist_tot); }
     uint32_t *cell_start() const { return at<uint32_t>(L.cell_start); }
     int4 *chunks() const { return at<int4>(L.chunks); }
     ChunkOut *chunk_out() const { return at<ChunkOut>(L.chunk_out); }
