@@ -727,11 +727,29 @@ int launch_reorder(const Problem &P, sph_state &s, const Ws &w, const uint32_t *
 // the caller's dt, else Cr times the lagged bound (eq. sphdt one step late);
 // with no bound yet, dt = 0 and the CFL flag is raised.
 
-// Global half-row r (row r / 2, half r % 2): its instance, local half-row
-// and the key of its cell x = 0.
+// Instance of global row `row`, the same in every lane of the wave (all
+// lanes active): the instances' first rows do not decrease, so the answer is
+// the number of instances starting at or below `row`, less one; the wave
+// reads 64 of them at a time and counts with a ballot (one load latency
+// instead of a binary search's chain of dependent loads).
+__device__ __forceinline__ int of_row_wave(const Insts &I, uint32_t row) {
+    if (I.n == 1) return 0;
+    const int lane = threadIdx.x % kWave;
+    int below = 0;
+    for (int b = 0; b < I.n; b += kWave) {
+        const int k = b + lane;
+        const int c = __popcll(__ballot(k < I.n && I.tab[k < I.n ? k : 0].row_base <= row));
+        below += c;
+        if (c < kWave) break;  // (uniform) every later instance starts above `row`
+    }
+    return below - 1;
+}
+
+// Global half-row r (row r / 2, half r % 2; the same in every lane of the
+// wave): its instance, local half-row and the key of its cell x = 0.
 __device__ __forceinline__ void half_row(const Insts &I, int64_t r, int &inst, int &lhalf,
                                          uint32_t &k0, int &nx) {
-    inst = I.of_row((uint32_t)(r >> 1));
+    inst = of_row_wave(I, (uint32_t)(r >> 1));
     const Inst ip = I.get(inst);
     lhalf = (int)(r - 2 * (int64_t)ip.row_base);
     k0 = half_row_key(ip, (uint32_t)lhalf >> 1, (uint32_t)lhalf & 1u);

@@ -229,7 +229,7 @@ struct Insts {
     Inst one;
     int n;
     __device__ __forceinline__ Inst get(int k) const { return tab ? tab[k] : one; }
-    // instance of an original particle id / global cell id / global row
+    // instance of an original particle id / global cell id
     __device__ __forceinline__ int of_id(uint32_t id) const {
         if (n == 1) return 0;
         int lo = 0, hi = n - 1;
@@ -245,15 +245,6 @@ struct Insts {
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (tab[mid].cell_base <= cell) lo = mid; else hi = mid - 1;
-        }
-        return lo;
-    }
-    __device__ __forceinline__ int of_row(uint32_t row) const {
-        if (n == 1) return 0;
-        int lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tab[mid].row_base <= row) lo = mid; else hi = mid - 1;
         }
         return lo;
     }
