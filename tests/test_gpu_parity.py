@@ -104,15 +104,31 @@ def test_step_between_refreshes_sorts_cells_only(gpu):
 
 
 def test_build_cells_large_sort(gpu):
-    """700k particles: the counts scan of the radix sort runs on many spans
-    in parallel (not one block); the order must still be the stable sort by
-    the full key."""
+    """700k particles: many sort tiles per digit, scanned per digit over the
+    tiles, each scatter adding the smaller digits' totals; the order must
+    still be the stable sort by the full key."""
     sc = scene.random_cloud(700_000, 3, dp=0.002, box=0.2)
     sim = _sim(gpu, sc, "mixed")
     sim.build_cells()
     sim.sync()
     ids = sim.ids()
     key = _sort_keys((sc.x, sc.y, sc.z), sc.params, sc.is_boundary, True)
+    assert np.array_equal(ids, np.argsort(key, kind="stable"))
+
+
+def test_sort_digit_rows_longer_than_one_scan_span(gpu):
+    """17 M particles: more than 4096 sort tiles of 4096 keys, so each digit's
+    row of per-tile counts is longer than one block's scan span and its scan
+    carries from span to span; the order must be the stable sort by the full
+    key."""
+    n = 17_000_000
+    sc = scene.random_cloud(n, 5, dp=0.002, box=0.6)
+    sim = _sim(gpu, sc, "mixed")
+    sim.build_cells()
+    sim.sync()
+    ids = sim.ids()
+    key = _sort_keys((sc.x, sc.y, sc.z), sc.params, sc.is_boundary, True)
+    assert -(-n // 4096) > 4096
     assert np.array_equal(ids, np.argsort(key, kind="stable"))
 
 
