@@ -62,8 +62,7 @@ WsLayout make_layout(const Problem &P) {
     L.hist = take(4 * (size_t)kRadix * (size_t)L.ntiles);
     L.hist_off = take(4 * (size_t)kRadix * (size_t)L.ntiles);
     L.hist_tot = take(4 * (size_t)kRadix);
-    const size_t scanned = std::max((size_t)kRadix * (size_t)L.ntiles, (size_t)(2 * L.nrows));
-    L.scan_tot = take(4 * ((scanned + kScanSpan - 1) / kScanSpan));
+    L.scan_tot = take(4 * (((size_t)(2 * L.nrows) + kScanSpan - 1) / kScanSpan));
     L.row_cnt = take(4 * (size_t)(2 * L.nrows));  // per half-row
     L.row_first = take(4 * (size_t)(2 * L.nrows));
     L.cell_start = take(4 * (size_t)(2 * L.ncells + 1));

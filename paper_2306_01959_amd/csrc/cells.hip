@@ -98,8 +98,8 @@ bool walls_in_place_enabled(const Problem &P) {
 // ------------------------------------------------------------ radix sort
 //
 // LSD radix sort of (32-bit key, 32-bit index) pairs, 8-bit digits.  Per
-// pass: tile histograms -> one exclusive scan over (digit, tile) -> stable
-// scatter.  Ranks inside a tile come from wave-wide digit matching (eight
+// pass: tile histograms -> an exclusive scan of each digit's counts over the
+// tiles -> stable scatter (which adds the smaller digits' totals).  Ranks inside a tile come from wave-wide digit matching (eight
 // ballots), so a tile's keys keep their input order: the sort is stable and
 // deterministic.
 

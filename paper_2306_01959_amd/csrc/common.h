@@ -293,7 +293,7 @@ struct WsLayout {
     size_t hist = 0;         // (digit, tile) counts of a sort pass
     size_t hist_off = 0;     // per digit, exclusive scan of its counts over the tiles
     size_t hist_tot = 0;     // per digit, its count over all tiles
-    size_t scan_tot = 0;     // span totals of a scan (counts of the sort, chunks per row)
+    size_t scan_tot = 0;     // span totals of the chunks-per-half-row scan
     size_t row_cnt = 0;      // chunks per row
     size_t row_first = 0;    // first chunk of each row
     size_t cell_start = 0;
