@@ -773,14 +773,20 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
     // support) and each group's list is padded with it up to a whole pair
     // step, so a step tests neither its slot nor its target
     constexpr bool kSentinel = P::kMixed;
-    __shared__ V4 stg[kSplit][4][kWave + 1];           // staged candidate records (per wave)
+    // staged records collect over batches and are paired once another batch
+    // might not fit, so batches with few survivors share the group setup and
+    // the padding of each group's list to whole pair steps: mixed precision
+    // with one wave per chunk has room for 88 records (what the LDS of 16
+    // blocks per CU leaves), elsewhere every batch is paired at once
+    constexpr int kCap = (P::kMixed && kSplit == 1) ? 88 : kWave;
+    __shared__ V4 stg[kSplit][4][kCap + 1];            // staged candidate records (per wave)
     __shared__ V4 tgt[3][kWave];                       // the chunk's targets
     __shared__ R gbox[kG][6];                          // group bounding boxes, chunk frame
     // per group: the staged records that reach it, as byte offsets into the
     // wave's staging region (a pair step adds them to a constant base)
-    __shared__ uint16_t glist[kSplit][kG][kWave + kG];
+    __shared__ uint16_t glist[kSplit][kG][kCap + kG];
     constexpr int kRecBytes = (int)sizeof(V4);
-    constexpr int kRecStride = (kWave + 1) * kRecBytes;  // between the four record arrays
+    constexpr int kRecStride = (kCap + 1) * kRecBytes;  // between the four record arrays
     __shared__ int4 rows[kSplit][kRows];
     // after its loop a wave reuses its own staging region for its per-target
     // sums (5 values of R and 3 int32 per target fit in 4 V4 per lane)
@@ -857,8 +863,8 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
         rows[w][lane] = make_int4(js, je, hb, code);
     }
     if constexpr (kSentinel) {
-        if (lane == 0) P::sentinel(&stg[w][0][kWave], &stg[w][1][kWave], &stg[w][2][kWave],
-                                   &stg[w][3][kWave]);
+        if (lane == 0) P::sentinel(&stg[w][0][kCap], &stg[w][1][kCap], &stg[w][2][kCap],
+                                   &stg[w][3][kCap]);
     }
     __syncthreads();  // targets, group boxes, rows (and the sentinel) are in LDS
 
@@ -873,13 +879,97 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
     Acc<R> acc[kG];
     Stats sts[kG];
 
+    // Staged records not yet paired (uniform): [0, fill) of the wave's region.
+    int fill = 0;
+    // Pairs the staged records: per group the records that can reach the
+    // group's box, then the pair steps over them.
+    auto flush = [&]() __attribute__((always_inline)) {
+        wave_sync();  // the staged records
+        const int cnt = fill;
+        fill = 0;
+        if (cnt == 0) return;
+        int gcnt[kG];
+#pragma unroll
+        for (int g = 0; g < kG; ++g) gcnt[g] = 0;
+#pragma unroll
+        for (int r0 = 0; r0 < kCap; r0 += kWave) {
+            if (r0 >= cnt) break;  // (uniform)
+            const int r = r0 + lane;
+            R px = 0, py = 0, pz = 0;
+            bool rf = false;
+            if (r < cnt) {
+                const V4 q0 = stg[w][0][r];
+                const V4 q3 = stg[w][3][r];
+                P::rec_pos(a, ip, q0, cxa, px, py, pz);
+                rf = P::rec_fluid(q3);
+            }
+#pragma unroll
+            for (int g = 0; g < kG; ++g) {
+                const uint64_t gbits = kT == 64 ? ~0ull : (((1ull << (kT % 64)) - 1) << (g * kT % 64));
+                const bool gf = (fluid_tgts & gbits) != 0ull;
+                const R ex = fmax(fmax(gbox[g][0] - px, px - gbox[g][1]), (R)0);
+                const R ey = fmax(fmax(gbox[g][2] - py, py - gbox[g][3]), (R)0);
+                const R ez = fmax(fmax(gbox[g][4] - pz, pz - gbox[g][5]), (R)0);
+                const bool k = r < cnt && (ex * ex + ey * ey + ez * ez) <= cull2 && (gf || rf);
+                const uint64_t gm = __ballot(k);
+                if (k) glist[w][g][gcnt[g] + rank_below(gm)] = (uint16_t)(r * kRecBytes);
+                gcnt[g] = uni(gcnt[g] + (int)__popcll(gm));
+            }
+        }
+        if constexpr (kSentinel) {
+#pragma unroll
+            for (int g = 0; g < kG; ++g)
+                if (lane < kG) glist[w][g][gcnt[g] + lane] = (uint16_t)(kCap * kRecBytes);
+        }
+        wave_sync();
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+            if (gcnt[g] == 0) continue;
+            const int tidx = g * kT + t_in_g;
+            typename P::T tg;
+            tg.a = tgt[0][tidx];
+            tg.b = tgt[1][tidx];
+            tg.c = tgt[2][tidx];
+            const int ti = cs0 + tidx;
+            const int gn = gcnt[g];
+            auto steps = [&](auto cls) __attribute__((always_inline)) {
+                pair_steps<V4, kG, false>(
+                    gn, slot_s,
+                    [&](int sl) { return kSentinel || sl < gn ? (int)glist[w][g][sl] : 0; },
+                    [&](int off, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
+                        const char *rb = reinterpret_cast<const char *>(&stg[w][0][0]) + off;
+                        r0 = *reinterpret_cast<const V4 *>(rb);
+                        r1 = *reinterpret_cast<const V4 *>(rb + kRecStride);
+                        r2 = *reinterpret_cast<const V4 *>(rb + 2 * kRecStride);
+                        r3 = *reinterpret_cast<const V4 *>(rb + 3 * kRecStride);
+                    },
+                    [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
+                        P::template pair<kStats, decltype(cls)::value>(
+                            a, ip, tg, ti, kSentinel || (sl < gn && tidx < ntgt), r0, r1, r2,
+                            r3, acc[g], cn, sts[g]);
+                    });
+            };
+            // a pair body per target class (the chunk is all fluid or all
+            // boundary) where the occupancy is fixed by the launch
+            // attributes; elsewhere one body for both (two would cost this
+            // kernel's occupancy)
+            if constexpr (P::kMixed && kT >= 16) {
+                if (any_fluid)
+                    steps(std::integral_constant<int, kFluidTargets>{});
+                else
+                    steps(std::integral_constant<int, kBoundaryTargets>{});
+            } else {
+                steps(std::integral_constant<int, kAnyTargets>{});
+            }
+        }
+        wave_sync();  // before the next records are staged over these
+    };
     // One batch of 64 candidates (row q, first index jb): cull against the
-    // chunk box, compact into LDS, per group the records that reach it, then
-    // the pairs.
+    // chunk box and append the survivors to the staged records; pair them
+    // when another batch might not fit.
     auto process = [&](const typename P::Cand &cur, int q, int jb) __attribute__((always_inline)) {
         const int4 rq = rows[w][q];
         const int dy = (rq.w & 3) - 1, dz = (rq.w >> 2) - 1;
-        // cull against the chunk box, compact the survivors into LDS
         bool keep = false;
         if (cur.ok) {
             R qx, qy, qz;
@@ -891,81 +981,12 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
         }
         const uint64_t m = __ballot(keep);
         if (keep) {
-            const int slot = rank_below(m);
+            const int slot = fill + rank_below(m);  // < kCap: fill <= kCap - kWave here
             P::stage(a, ip, cur, rq.z, jb + lane, dy, dz, &stg[w][0][slot], &stg[w][1][slot],
                      &stg[w][2][slot], &stg[w][3][slot]);
         }
-        wave_sync();
-        const int cnt = __popcll(m);
-        if (cnt > 0) {
-            // per group: the staged records that can reach the group's box
-            R px = 0, py = 0, pz = 0;
-            bool rf = false;
-            if (lane < cnt) {
-                const V4 r0 = stg[w][0][lane];
-                const V4 r3 = stg[w][3][lane];
-                P::rec_pos(a, ip, r0, cxa, px, py, pz);
-                rf = P::rec_fluid(r3);
-            }
-            int gcnt[kG];
-#pragma unroll
-            for (int g = 0; g < kG; ++g) {
-                const uint64_t gbits = kT == 64 ? ~0ull : (((1ull << (kT % 64)) - 1) << (g * kT % 64));
-                const bool gf = (fluid_tgts & gbits) != 0ull;
-                const R ex = fmax(fmax(gbox[g][0] - px, px - gbox[g][1]), (R)0);
-                const R ey = fmax(fmax(gbox[g][2] - py, py - gbox[g][3]), (R)0);
-                const R ez = fmax(fmax(gbox[g][4] - pz, pz - gbox[g][5]), (R)0);
-                const bool k = lane < cnt && (ex * ex + ey * ey + ez * ez) <= cull2 && (gf || rf);
-                const uint64_t gm = __ballot(k);
-                if (k) glist[w][g][rank_below(gm)] = (uint16_t)(lane * kRecBytes);
-                gcnt[g] = __popcll(gm);
-                if constexpr (kSentinel) {
-                    if (lane < kG) glist[w][g][gcnt[g] + lane] = (uint16_t)(kWave * kRecBytes);
-                }
-            }
-            wave_sync();
-#pragma unroll
-            for (int g = 0; g < kG; ++g) {
-                if (gcnt[g] == 0) continue;
-                const int tidx = g * kT + t_in_g;
-                typename P::T tg;
-                tg.a = tgt[0][tidx];
-                tg.b = tgt[1][tidx];
-                tg.c = tgt[2][tidx];
-                const int ti = cs0 + tidx;
-                const int gn = gcnt[g];
-                auto steps = [&](auto cls) __attribute__((always_inline)) {
-                    pair_steps<V4, kG, false>(
-                        gn, slot_s,
-                        [&](int sl) { return kSentinel || sl < gn ? (int)glist[w][g][sl] : 0; },
-                        [&](int off, V4 &r0, V4 &r1, V4 &r2, V4 &r3) {
-                            const char *rb = reinterpret_cast<const char *>(&stg[w][0][0]) + off;
-                            r0 = *reinterpret_cast<const V4 *>(rb);
-                            r1 = *reinterpret_cast<const V4 *>(rb + kRecStride);
-                            r2 = *reinterpret_cast<const V4 *>(rb + 2 * kRecStride);
-                            r3 = *reinterpret_cast<const V4 *>(rb + 3 * kRecStride);
-                        },
-                        [&](int sl, const V4 &r0, const V4 &r1, const V4 &r2, const V4 &r3) {
-                            P::template pair<kStats, decltype(cls)::value>(
-                                a, ip, tg, ti, kSentinel || (sl < gn && tidx < ntgt), r0, r1,
-                                r2, r3, acc[g], cn, sts[g]);
-                        });
-                };
-                // a pair body per target class (the chunk is all fluid or all
-                // boundary) where the occupancy is fixed by the launch
-                // attributes; elsewhere one body for both (two would cost
-                // this kernel's occupancy)
-                if constexpr (P::kMixed && kT >= 16) {
-                    if (any_fluid)
-                        steps(std::integral_constant<int, kFluidTargets>{});
-                    else
-                        steps(std::integral_constant<int, kBoundaryTargets>{});
-                } else {
-                    steps(std::integral_constant<int, kAnyTargets>{});
-                }
-            }
-        }
-        wave_sync();
+        fill = uni(fill + (int)__popcll(m));
+        if (fill > kCap - kWave) flush();
     };
     // the batch after (q, jb): the next 64 of the row, else the next non-empty row
     auto next_batch = [&](int q, int jb, int &q2, int &jb2) __attribute__((always_inline)) {
@@ -998,6 +1019,7 @@ __attribute__((amdgpu_waves_per_eu(P::kMixed && kT >= 16 ? 4 : 1))) void k_inter
         load_batch(qa, ja, ca);
         process(cb, qb, jbb);
     }
+    flush();
 
     // sum the kG lanes that share a target (fixed shuffle tree); each wave's
     // per-target sums go to LDS
