@@ -208,7 +208,7 @@ struct Mixed {
     using V4 = float4;
     static constexpr bool kMixed = true;
     // target: {o_x, o_y, o_z, own cell x}, {u, P}, {1/rho (0 for boundary),
-    // rho - rho0, -alpha |c|, -}
+    // rho - rho0, -alpha |c|, 2 rho0 + (rho - rho0) in FP32}
     struct T {
         float4 a, b, c;
         __device__ bool fluid() const { return c.x > 0.f; }
@@ -241,7 +241,8 @@ struct Mixed {
         fi = act && v2.w > 0.f;
         t0 = make_float4(v0.x, v0.y, v0.z, (float)cix);
         t1 = make_float4(v0.w, v1.x, v1.y, v2.y);
-        t2 = make_float4(fi ? v2.z : 0.f, v2.x, -(float)(ip.alpha * ip.h) * fabsf(v2.w), 0.f);
+        t2 = make_float4(fi ? v2.z : 0.f, v2.x, -(float)(ip.alpha * ip.h) * fabsf(v2.w),
+                         (float)(2.0 * ip.rho0) + v2.x);
         const float csf = (float)ip.cs;
         bx = v0.x + (float)(cix - cxa) * csf;
         by = v0.y;
@@ -359,7 +360,7 @@ struct Mixed {
         // one reciprocal for mu / h = vr / (r^2 + eta^2) and the viscosity's
         // mu / (h (rho_i + rho_j)) = hvi; the factor h is in the -alpha |c|
         // terms of target and record, and store() applies it to max |mu|
-        const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r2.x;  // rho_i + rho_j
+        const float rsum = t.c.w + r2.x;  // rho_i + rho_j (t.c.w: the target's part)
         const float hvi = vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
         const float mu = hvi * rsum;
         acc.mu = max_abs(acc.mu, in ? mu : 0.f);
@@ -409,7 +410,7 @@ struct Mixed {
         const float F = valid ? q2 * q2 * q2 : 0.f;
         const float vx = r1.x - t.b.x, vy = r1.y - t.b.y, vz = r1.z - t.b.z;
         const float vr = vx * dx + vy * dy + vz * dz;
-        const float rsum = ((float)(2.0 * ip.rho0) + t.c.y) + r2.x;  // rho_i + rho_j
+        const float rsum = t.c.w + r2.x;  // rho_i + rho_j (t.c.w: the target's part)
         const float hvi = vr * __builtin_amdgcn_rcpf((rr + (float)ip.eta2) * rsum);
         const float mu = hvi * rsum;
         acc.mu = valid ? max_nonneg(acc.mu, fabsf(mu)) : acc.mu;
