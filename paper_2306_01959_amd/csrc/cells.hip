@@ -99,9 +99,9 @@ bool walls_in_place_enabled(const Problem &P) {
 //
 // LSD radix sort of (32-bit key, 32-bit index) pairs, 8-bit digits.  Per
 // pass: tile histograms -> an exclusive scan of each digit's counts over the
-// tiles -> stable scatter (which adds the smaller digits' totals).  Ranks inside a tile come from wave-wide digit matching (eight
-// ballots), so a tile's keys keep their input order: the sort is stable and
-// deterministic.
+// tiles -> stable scatter (which adds the smaller digits' totals).  Ranks
+// inside a tile come from wave-wide digit matching (eight ballots), so a
+// tile's keys keep their input order: the sort is stable and deterministic.
 
 // kEncode: the first pass, which computes the keys (encode_key) and stores
 // them instead of reading them.
