@@ -131,6 +131,25 @@ def test_batch_run_equals_single(gpu, shape, scenes, precision):
         assert dg[k]["dt_last"] == d1["dt_last"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_of_more_than_64_instances(gpu, shape, precision):
+    """70 instances: the chunk-list kernels find a half-row's instance 64
+    instances at a time, so half-rows of the instances past the first 64 take
+    a second round; the first, the 64th and the last instance each equal the
+    same system run alone."""
+    scs = scene.ensemble(70, master_seed=5, dps=DPS)
+    ens = gpu.Ensemble(scs, precision)
+    ens.run(6, -1.0, 0)
+    got = ens.fetch()
+    for k in (0, 63, 64, 69):
+        sim = gpu.Simulation(scs[k], precision)
+        sim.run(6, -1.0, 0)
+        ref = sim.fetch()
+        o, c = ens.offsets[k], ens.counts[k]
+        for key in ("x", "y", "z", "ux", "uz", "rho"):
+            assert np.array_equal(got[key][o:o + c], ref[key]), (k, key)
+
+
 def test_batch_lagged_fp64_vs_oracle(gpu, oracle_lib, scenes):
     """45 fused steps with the lagged CFL dt (crossing the Euler reset at
     step 40) against the oracle's lagged-dt run of every instance."""
